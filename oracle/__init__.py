@@ -1,0 +1,275 @@
+"""FP64 CPU oracle for Milne-Eddington genetic-algorithm Stokes inversion.
+
+TEST INFRASTRUCTURE ONLY.  The oracle is the plain, slow reference the HIP path
+is checked against (Harker & Mighell, "A GPU-Computing Approach to Solar Stokes
+Profile Inversion": Sec. 3 genetic algorithm, Sec. 4.2 16-bit genes, Sec. 5
+Milne-Eddington synthesis and chi-square).  Only ``tests/``, the smoke check and
+the CPU-baseline leg of ``bench.py`` may import it.  It shares no code with the
+HIP library in ``paper_1208_0302_amd`` and never imports it.
+
+The C sources next to this file are compiled with gcc (OpenMP over pixels) into
+``liboracle.so``; ``build()`` does that and ``lib()`` builds on first use when
+the shared object is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = [os.path.join(_HERE, f) for f in ("oracle_me.c", "oracle_ga.c")]
+_LOCK = threading.Lock()
+_LIB = None
+
+NPAR = 9
+MAXCOMP = 64
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc -O2 -fopenmp into liboracle.so."""
+    if not force and os.path.exists(_SO):
+        return _SO
+    tmp = _SO + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+           "-D_GNU_SOURCE", "-o", tmp] + _SRC + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _SO)
+    return _SO
+
+
+class Line(C.Structure):
+    _fields_ = [
+        ("lambda0", C.c_double),
+        ("ncomp", C.c_int32),
+        ("q", C.c_int32 * MAXCOMP),
+        ("shift", C.c_double * MAXCOMP),
+        ("strength", C.c_double * MAXCOMP),
+        ("start", C.c_double),
+        ("step", C.c_double),
+        ("nlam", C.c_int32),
+    ]
+
+
+_dp = C.POINTER(C.c_double)
+_u16p = C.POINTER(C.c_uint16)
+_i32p = C.POINTER(C.c_int32)
+_u32p = C.POINTER(C.c_uint32)
+_linep = C.POINTER(Line)
+
+
+def lib():
+    global _LIB
+    with _LOCK:
+        if _LIB is None:
+            newest_src = max(os.path.getmtime(s) for s in _SRC + [os.path.join(_HERE, "oracle.h")])
+            if not os.path.exists(_SO) or os.path.getmtime(_SO) < newest_src:
+                build()
+            L = C.CDLL(_SO)
+            L.oracle_faddeeva.argtypes = [C.c_double, C.c_double, _dp, _dp]
+            L.oracle_lande_ls.argtypes = [C.c_double] * 3
+            L.oracle_lande_ls.restype = C.c_double
+            L.oracle_wigner3j.argtypes = [C.c_double] * 6
+            L.oracle_wigner3j.restype = C.c_double
+            L.oracle_zeeman.argtypes = [C.c_double] * 4 + [_i32p, _dp, _dp, C.c_int]
+            L.oracle_zeeman.restype = C.c_int
+            L.oracle_me_synth.argtypes = [_dp, C.c_int64, _linep, C.c_int, _dp, _dp]
+            L.oracle_chi2.argtypes = [_dp, C.c_int64, C.c_int, _linep, C.c_int, _dp, _dp, _dp, _dp]
+            L.oracle_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+            L.oracle_rng_word.argtypes = [C.c_uint64] + [C.c_uint32] * 5
+            L.oracle_rng_word.restype = C.c_uint32
+            L.oracle_decode.argtypes = [_u16p, _dp, _dp, _dp]
+            L.oracle_ga_init.argtypes = [C.c_uint64, C.c_uint32, C.c_int, _u16p]
+            L.oracle_ga_step.argtypes = [_u16p, _dp, C.c_int, C.c_int, C.c_double, C.c_double,
+                                         C.c_uint64, C.c_uint32, C.c_uint32,
+                                         _u16p, _i32p, _i32p, _u16p, _i32p]
+            L.oracle_ga_step.restype = C.c_int
+            L.oracle_ga_invert.argtypes = [_dp, _dp, _dp, C.c_int64, _linep, C.c_int, _dp, _dp,
+                                           C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                           C.c_uint64, C.c_uint32, _dp, _dp, _i32p, _u16p, _dp]
+            L.oracle_ga_invert.restype = C.c_int
+            L.oracle_num_threads.restype = C.c_int
+            _LIB = L
+    return _LIB
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(t)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# --------------------------------------------------------------------------- #
+# special functions and atomic data
+
+def faddeeva(x, y):
+    """w(x + i y) elementwise (numpy broadcasting); complex128."""
+    x, y = np.broadcast_arrays(np.asarray(x, np.float64), np.asarray(y, np.float64))
+    out = np.empty(x.shape, np.complex128)
+    re, im = C.c_double(), C.c_double()
+    L = lib()
+    for idx in np.ndindex(x.shape):
+        L.oracle_faddeeva(float(x[idx]), float(y[idx]), C.byref(re), C.byref(im))
+        out[idx] = complex(re.value, im.value)
+    return out
+
+
+def lande_ls(S, Lq, J):
+    return lib().oracle_lande_ls(float(S), float(Lq), float(J))
+
+
+def wigner3j(j1, j2, j3, m1, m2, m3):
+    return lib().oracle_wigner3j(*(float(v) for v in (j1, j2, j3, m1, m2, m3)))
+
+
+def zeeman(Jl, gl, Ju, gu):
+    """Components (q, shift, strength) of the J_l -> J_u transition."""
+    q = np.zeros(MAXCOMP, np.int32)
+    s = np.zeros(MAXCOMP, np.float64)
+    st = np.zeros(MAXCOMP, np.float64)
+    n = lib().oracle_zeeman(float(Jl), float(gl), float(Ju), float(gu),
+                            _ptr(q, _i32p), _ptr(s, _dp), _ptr(st, _dp), MAXCOMP)
+    if n < 0:
+        raise ValueError("invalid transition")
+    return q[:n].copy(), s[:n].copy(), st[:n].copy()
+
+
+def make_line(lambda0, Jl, gl, Ju, gu, start, step, nlam) -> Line:
+    q, s, st = zeeman(Jl, gl, Ju, gu)
+    ln = Line()
+    ln.lambda0 = float(lambda0)
+    ln.ncomp = len(q)
+    for i in range(len(q)):
+        ln.q[i] = int(q[i])
+        ln.shift[i] = float(s[i])
+        ln.strength[i] = float(st[i])
+    ln.start = float(start)
+    ln.step = float(step)
+    ln.nlam = int(nlam)
+    return ln
+
+
+def _lines_array(lines):
+    arr = (Line * len(lines))(*lines)
+    return arr, C.cast(arr, _linep)
+
+
+def total_samples(lines):
+    return sum(int(l.nlam) for l in lines)
+
+
+# --------------------------------------------------------------------------- #
+# forward model and merit function
+
+def me_synth(params, lines, mu=None):
+    """Stokes [n, 4, L] for params [n, 9] (FP64)."""
+    p = _f64(params).reshape(-1, NPAR)
+    n = p.shape[0]
+    L = total_samples(lines)
+    out = np.empty((n, 4, L), np.float64)
+    arr, lp = _lines_array(lines)
+    m = None if mu is None else _f64(np.broadcast_to(mu, (n,)))
+    lib().oracle_me_synth(_ptr(p, _dp), n, lp, len(lines),
+                          None if m is None else _ptr(m, _dp), _ptr(out, _dp))
+    return out
+
+
+def chi2(params, obs, sigma, lines, mu=None):
+    """chi-square [npix, pop] of params [npix, pop, 9] against obs [npix, 4, L]."""
+    p = _f64(params)
+    npix, pop = p.shape[0], p.shape[1]
+    o = _f64(obs)
+    s = _f64(sigma)
+    out = np.empty((npix, pop), np.float64)
+    arr, lp = _lines_array(lines)
+    m = None if mu is None else _f64(np.broadcast_to(mu, (npix,)))
+    lib().oracle_chi2(_ptr(p, _dp), npix, pop, lp, len(lines), _ptr(o, _dp), _ptr(s, _dp),
+                      None if m is None else _ptr(m, _dp), _ptr(out, _dp))
+    return out
+
+
+# --------------------------------------------------------------------------- #
+# random stream and genetic operators
+
+def philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(ctr, np.uint32)
+    k = np.ascontiguousarray(key, np.uint32)
+    out = np.empty(4, np.uint32)
+    lib().oracle_philox4x32_10(_ptr(c, _u32p), _ptr(k, _u32p), _ptr(out, _u32p))
+    return out
+
+
+def rng_word(seed, pixel, gen, indiv, purpose, n):
+    return lib().oracle_rng_word(int(seed), int(pixel), int(gen), int(indiv), int(purpose), int(n))
+
+
+def decode(genes, lo, hi):
+    g = np.ascontiguousarray(genes, np.uint16).reshape(-1, NPAR)
+    lo = _f64(lo)
+    hi = _f64(hi)
+    out = np.empty(g.shape, np.float64)
+    for i in range(g.shape[0]):
+        lib().oracle_decode(_ptr(g[i], _u16p), _ptr(lo, _dp), _ptr(hi, _dp), _ptr(out[i], _dp))
+    return out.reshape(np.shape(genes))
+
+
+def ga_init(seed, pixel, pop):
+    g = np.empty((pop, NPAR), np.uint16)
+    lib().oracle_ga_init(int(seed), int(pixel), int(pop), _ptr(g, _u16p))
+    return g
+
+
+def ga_step(genes_in, fitness, k, p_cross, p_mut, seed, pixel, gen):
+    """One generation; returns dict(genes, parents, xpoint, masks, elite)."""
+    g = np.ascontiguousarray(genes_in, np.uint16)
+    pop = g.shape[0]
+    f = _f64(fitness)
+    out = np.empty_like(g)
+    parents = np.empty((pop, 2), np.int32)
+    xp = np.empty(pop, np.int32)
+    masks = np.empty_like(g)
+    e = C.c_int32()
+    rc = lib().oracle_ga_step(_ptr(g, _u16p), _ptr(f, _dp), pop, int(k), float(p_cross),
+                              float(p_mut), int(seed), int(pixel), int(gen), _ptr(out, _u16p),
+                              _ptr(parents, _i32p), _ptr(xp, _i32p), _ptr(masks, _u16p),
+                              C.byref(e))
+    if rc != 0:
+        raise ValueError("oracle_ga_step rejected its arguments")
+    return dict(genes=out, parents=parents, xpoint=xp, masks=masks, elite=int(e.value))
+
+
+def ga_invert(obs, sigma, lines, lo, hi, pop, generations, k, p_cross, p_mut, seed,
+              mu=None, pixel_base=0, want_population=False):
+    o = _f64(obs)
+    s = _f64(sigma)
+    npix = o.shape[0]
+    lo = _f64(lo)
+    hi = _f64(hi)
+    bp = np.empty((npix, NPAR), np.float64)
+    bc = np.empty(npix, np.float64)
+    st = np.empty(npix, np.int32)
+    fg = np.empty((npix, pop, NPAR), np.uint16) if want_population else None
+    ff = np.empty((npix, pop), np.float64) if want_population else None
+    arr, lp = _lines_array(lines)
+    m = None if mu is None else _f64(np.broadcast_to(mu, (npix,)))
+    rc = lib().oracle_ga_invert(
+        _ptr(o, _dp), _ptr(s, _dp), None if m is None else _ptr(m, _dp), npix, lp, len(lines),
+        _ptr(lo, _dp), _ptr(hi, _dp), int(pop), int(generations), int(k), float(p_cross),
+        float(p_mut), int(seed), int(pixel_base), _ptr(bp, _dp), _ptr(bc, _dp), _ptr(st, _i32p),
+        None if fg is None else _ptr(fg, _u16p), None if ff is None else _ptr(ff, _dp))
+    if rc != 0:
+        raise ValueError("oracle_ga_invert rejected its arguments")
+    res = dict(params=bp, chi2=bc, status=st)
+    if want_population:
+        res.update(genes=fg, fitness=ff)
+    return res
+
+
+def num_threads():
+    return lib().oracle_num_threads()

@@ -1,0 +1,113 @@
+/*
+ * FP64 CPU oracle for Milne-Eddington genetic-algorithm Stokes inversion.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, plain reference that the
+ * HIP path is checked against.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it; the product path never does.
+ * It shares no code, header, table or constant generator with the HIP library.
+ *
+ * Method: Harker & Mighell, "A GPU-Computing Approach to Solar Stokes Profile
+ * Inversion" (GENESIS).  Section references below are to that paper.
+ *
+ * Parameter vector of one model atmosphere (9 doubles, this order):
+ *   0 B      field strength [G]
+ *   1 incl   inclination psi to the line of sight [deg]
+ *   2 azim   azimuth chi [deg]
+ *   3 vlos   line-of-sight velocity [km/s], positive = redshift; it moves the
+ *            line centre to lambda0 * (1 + vlos / c)   (stands in for the
+ *            paper's free line-centre wavelength, Sec. 5 model vector)
+ *   4 dopp   Doppler width Delta lambda_D [Angstrom]
+ *   5 damp   damping parameter a
+ *   6 eta0   line-to-continuum opacity ratio
+ *   7 S0     source function at tau = 0
+ *   8 S1     source function gradient (S1 = S0 * beta0 of Sec. 5)
+ *
+ * Parity of the genetic operators: the end-to-end inversion is a stochastic
+ * heuristic and its result is "parity unpinned" (it is checked through
+ * recovered-parameter accuracy, chi-square against the truth's chi-square and
+ * determinism); the integer steps (Philox, tournament, crossover, mutation)
+ * are pinned and compared bit-exactly.
+ */
+#ifndef GENESIS_ORACLE_H
+#define GENESIS_ORACLE_H
+
+#include <stdint.h>
+
+#define ORACLE_NPAR 9
+#define ORACLE_MAXCOMP 64
+
+typedef struct {
+    double lambda0;                    /* rest wavelength [Angstrom] */
+    int32_t ncomp;                     /* Zeeman components */
+    int32_t q[ORACLE_MAXCOMP];         /* M_lower - M_upper */
+    double shift[ORACLE_MAXCOMP];      /* g_l M_l - g_u M_u, units of Delta lambda_B */
+    double strength[ORACLE_MAXCOMP];   /* relative strength, each q group sums to 1 */
+    double start;                      /* first wavelength sample [Angstrom] */
+    double step;                       /* sample spacing [Angstrom] */
+    int32_t nlam;                      /* samples for this line */
+} oracle_line;
+
+/* Faddeeva function w(x + i y) = exp(-z^2) erfc(-i z), y >= 0 (Sec. 5: Voigt
+ * H = Re w and Faraday-Voigt L = Im w).  Valid for 0 <= y <= 1.5 to ~1e-14
+ * absolute; returns NaN outside that strip. */
+void oracle_faddeeva(double x, double y, double *re, double *im);
+
+/* LS-coupling Lande factor of a term 2S+1 L_J; returns 0 for J = 0. */
+double oracle_lande_ls(double S, double L, double J);
+/* Wigner 3j symbol by the Racah sum (integer or half-integer arguments). */
+double oracle_wigner3j(double j1, double j2, double j3, double m1, double m2, double m3);
+/* Full Zeeman pattern of a J_l -> J_u dipole transition (Sec. 5: computed once
+ * per inversion).  Writes up to cap components; returns the count or -1. */
+int oracle_zeeman(double Jl, double gl, double Ju, double gu,
+                  int32_t *q, double *shift, double *strength, int cap);
+
+/* Stokes synthesis (Sec. 5, Unno-Rachkovsky solution).  par [n][9]; mu [n] or
+ * NULL (= 1); out [n][4][L] with L = sum of nlam, lines concatenated. */
+void oracle_me_synth(const double *par, int64_t n, const oracle_line *lines, int nlines,
+                     const double *mu, double *out);
+
+/* Merit function (Sec. 5, chi-square equation) with w_i = 1/sigma_i:
+ * chi2 = 1/nu sum_i sum_j (O - M)^2 / sigma_i^2, nu = 4L - 9.
+ * par [npix][pop][9], obs [npix][4][L], sigma [npix][4], chi2 [npix][pop]. */
+void oracle_chi2(const double *par, int64_t npix, int pop, const oracle_line *lines, int nlines,
+                 const double *obs, const double *sigma, const double *mu, double *chi2);
+
+/* Philox4x32-10 (Salmon et al. 2011). */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* Word n of the random stream (seed, pixel, generation, individual, purpose). */
+uint32_t oracle_rng_word(uint64_t seed, uint32_t pixel, uint32_t gen, uint32_t indiv,
+                         uint32_t purpose, uint32_t n);
+
+/* Decoding operator E^-1 (Sec. 3, decode equation) for 16-bit genes. */
+void oracle_decode(const uint16_t *genes, const double *lo, const double *hi, double *par);
+
+/* Generation-0 population: genes [pop][9]. */
+void oracle_ga_init(uint64_t seed, uint32_t pixel, int pop, uint16_t *genes);
+
+/* One generation of the operators S, R, M of the standard GA (Sec. 3,
+ * Algorithm 1) with elitism.  Produces generation `gen` (>= 1) from the
+ * population genes_in [pop][9] and its fitness fit [pop].
+ * Outputs: genes_out [pop][9]; parents [pop][2]; xpoint [pop] (0 = no
+ * crossover); masks [pop][9] (mutation XOR masks); *elite.
+ * Returns 0, or -1 on invalid arguments. */
+int oracle_ga_step(const uint16_t *genes_in, const double *fit, int pop, int k,
+                   double p_cross, double p_mut, uint64_t seed, uint32_t pixel, uint32_t gen,
+                   uint16_t *genes_out, int32_t *parents, int32_t *xpoint, uint16_t *masks,
+                   int32_t *elite);
+
+/* Full inversion of npix pixels (Algorithm 1 run for G generations after the
+ * initial evaluation).  Pixel p uses RNG pixel id pixel_base + p.
+ * best_params [npix][9], best_chi2 [npix], status [npix] (0 ok, 1 non-finite
+ * observation, 2 sigma <= 0 or non-finite); final_genes [npix][pop][9] and
+ * final_fit [npix][pop] may be NULL.  Returns 0 or -1. */
+int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, int64_t npix,
+                     const oracle_line *lines, int nlines, const double *lo, const double *hi,
+                     int pop, int generations, int k, double p_cross, double p_mut,
+                     uint64_t seed, uint32_t pixel_base,
+                     double *best_params, double *best_chi2, int32_t *status,
+                     uint16_t *final_genes, double *final_fit);
+
+/* Threads the OpenMP loops would use. */
+int oracle_num_threads(void);
+
+#endif

@@ -1,0 +1,123 @@
+"""Seeded synthetic inputs shared by the oracle tests, the HIP tests and the
+benchmark.
+
+This module holds line data, wavelength grids, parameter priors and random
+draws only.  It contains none of the inversion method's arithmetic (no Zeeman
+pattern, no profile, no synthesis, no genetic operator): the forward model that
+turns truth parameters into observed Stokes profiles lives on each side of the
+comparison separately.
+
+Line data are Fe I multiplet 816 of Table 1 (Sec. 2).  Lande factors are the
+LS-coupling values of the listed terms: 5P2 = 11/6, 5D2 = 3/2, 5P1 = 5/2,
+5D0 has J = 0.  The lower level is the 5P term.
+
+Priors follow the synthetic workloads used throughout the tests and the
+benchmark: B U(0, 3000) G, inclination U(0, 180) deg, azimuth U(0, 180) deg,
+v_los N(0, 1.5) km/s clipped to +-7.5, Doppler width U(20, 50) mA, damping
+U(0, 0.5), eta0 U(1, 30), S0 U(0, 0.5), S1 U(0.5, 1); noise sigma = 1e-3 Ic
+with Ic = S0 + mu S1.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+PARAM_NAMES = ("B", "incl", "azim", "vlos", "dopp", "damp", "eta0", "S0", "S1")
+NPAR = 9
+
+# GA search box = prior box (v_los box at +-5 sigma of its normal prior)
+PRIOR_LO = np.array([0.0, 0.0, 0.0, -7.5, 0.020, 0.0, 1.0, 0.0, 0.5])
+PRIOR_HI = np.array([3000.0, 180.0, 180.0, 7.5, 0.050, 0.5, 30.0, 0.5, 1.0])
+
+# Table 1 lines: rest wavelength [A] and (J, g) of lower and upper level
+FE6301 = dict(name="FeI6301.5", lambda0=6301.5091, Jl=2.0, gl=11.0 / 6.0, Ju=2.0, gu=1.5,
+              terms=((2, 1, 2), (2, 2, 2)))   # (S, L, J) of lower, upper
+FE6302 = dict(name="FeI6302.5", lambda0=6302.5017, Jl=1.0, gl=2.5, Ju=0.0, gu=0.0,
+              terms=((2, 1, 1), (2, 2, 0)))
+TABLE1_GEFF = {"FeI6301.5": 1.667, "FeI6302.5": 2.500}
+
+
+def grid(line: dict, nlam: int, half_width: float = 0.4):
+    """Wavelength grid of one line: nlam samples over lambda0 +- half_width,
+    end points included.  Returns (start, step) in Angstrom."""
+    start = line["lambda0"] - half_width
+    step = 2.0 * half_width / (nlam - 1)
+    return start, step
+
+
+def line_set(name: str):
+    """Named line/grid sets of the synthetic workloads:
+    'tiny'  -- one line (6302.5) x 100 samples;
+    'slit'  -- both lines x 128 samples."""
+    if name == "tiny":
+        return [(FE6302, 100)]
+    if name == "slit":
+        return [(FE6301, 128), (FE6302, 128)]
+    if name == "slit1":
+        return [(FE6302, 128)]
+    raise KeyError(name)
+
+
+def draw_truth(npix: int, seed: int) -> np.ndarray:
+    """Truth parameters [npix, 9] drawn iid from the priors (float64)."""
+    rng = np.random.Generator(np.random.Philox(key=seed))
+    p = np.empty((npix, NPAR))
+    p[:, 0] = rng.uniform(0.0, 3000.0, npix)
+    p[:, 1] = rng.uniform(0.0, 180.0, npix)
+    p[:, 2] = rng.uniform(0.0, 180.0, npix)
+    p[:, 3] = np.clip(rng.normal(0.0, 1.5, npix), -7.5, 7.5)
+    p[:, 4] = rng.uniform(0.020, 0.050, npix)
+    p[:, 5] = rng.uniform(0.0, 0.5, npix)
+    p[:, 6] = rng.uniform(1.0, 30.0, npix)
+    p[:, 7] = rng.uniform(0.0, 0.5, npix)
+    p[:, 8] = rng.uniform(0.5, 1.0, npix)
+    return p
+
+
+def draw_uniform_box(n: int, seed: int, lo=PRIOR_LO, hi=PRIOR_HI) -> np.ndarray:
+    """Parameters [n, 9] uniform in a box (used for parity sweeps)."""
+    rng = np.random.Generator(np.random.Philox(key=seed + 7919))
+    u = rng.uniform(size=(n, NPAR))
+    return np.asarray(lo) + (np.asarray(hi) - np.asarray(lo)) * u
+
+
+def sigma_for(truth: np.ndarray, mu=None, rel: float = 1e-3) -> np.ndarray:
+    """Per-pixel, per-Stokes noise sigma [npix, 4] = rel * (S0 + mu S1)."""
+    m = 1.0 if mu is None else np.asarray(mu, np.float64)
+    ic = truth[:, 7] + m * truth[:, 8]
+    return np.repeat((rel * ic)[:, None], 4, axis=1)
+
+
+def std_normal(shape, seed: int) -> np.ndarray:
+    """Standard-normal draws for additive observation noise."""
+    rng = np.random.Generator(np.random.Philox(key=seed + 104729))
+    return rng.standard_normal(shape)
+
+
+def random_genes(npix: int, pop: int, seed: int) -> np.ndarray:
+    """Arbitrary 16-bit genotypes [npix, pop, 9] (inputs of operator tests)."""
+    rng = np.random.Generator(np.random.Philox(key=seed + 31337))
+    return rng.integers(0, 65536, size=(npix, pop, NPAR), dtype=np.uint16)
+
+
+def random_fitness(npix: int, pop: int, seed: int, ties: bool = True, nans: bool = False):
+    """Fitness values [npix, pop] as float32-representable numbers, with
+    deliberate ties (and optionally NaNs) so that tie-breaking is exercised."""
+    rng = np.random.Generator(np.random.Philox(key=seed + 2718))
+    f = rng.gamma(2.0, 1.0, size=(npix, pop)).astype(np.float32)
+    if ties:
+        idx = rng.integers(0, pop, size=(npix, pop // 4))
+        src = rng.integers(0, pop, size=(npix, pop // 4))
+        for p in range(npix):
+            f[p, idx[p]] = f[p, src[p]]
+    if nans:
+        idx = rng.integers(0, pop, size=(npix, max(1, pop // 16)))
+        for p in range(npix):
+            f[p, idx[p]] = np.nan
+    return f.astype(np.float64)
+
+
+def disc_mask(n: int = 2048, radius: float = 1024.0) -> np.ndarray:
+    """Boolean on-disc mask of an n x n grid, centre ((n-1)/2, (n-1)/2)."""
+    c = (n - 1) / 2.0
+    y, x = np.mgrid[0:n, 0:n]
+    return (x - c) ** 2 + (y - c) ** 2 <= radius ** 2
