@@ -1,0 +1,219 @@
+/*
+ * genesis.h -- C ABI of the MI355X (gfx950) library libgenesis_hip.so:
+ * population-parallel genetic-algorithm inversion of solar Stokes profiles
+ * under the Milne-Eddington model.
+ *
+ * Method: Harker & Mighell, "A GPU-Computing Approach to Solar Stokes Profile
+ * Inversion" (GENESIS).  Section numbers below refer to that paper.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Array pointers are DEVICE memory owned by the caller unless stated.
+ *    Struct pointers (lines, grids, bounds, config) are HOST memory, read
+ *    during the call only.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *    asynchronous on that stream; the library allocates nothing on the
+ *    device and keeps no device state between calls.
+ *  - Return value: 0 on success or a negative ME_E* code; the message of the
+ *    last failure on the calling thread is returned by me_last_error().  No
+ *    C++ exception crosses this boundary.  On error nothing is launched.
+ *  - Parameter vector of one Milne-Eddington atmosphere, GENESIS_NPAR = 9
+ *    values in this order (Sec. 5 model vector; v_los stands in for the free
+ *    line-centre wavelength and S1 = S0 beta0 for the source gradient):
+ *      0 B [G]   1 inclination [deg]   2 azimuth [deg]   3 v_los [km/s]
+ *      4 Doppler width [Angstrom]   5 damping a   6 eta0   7 S0   8 S1
+ *  - Stokes arrays are [n][4][L] (I, Q, U, V), L = sum of grid[l].n over the
+ *    lines, lines concatenated in the order given.  Observations are
+ *    [npix][4][L]; noise is sigma [npix][4] with chi-square weights
+ *    w_i = 1/sigma_i (Sec. 5 merit function, weights constant over
+ *    wavelength).  mu (cosine of the heliocentric angle) is [npix] or NULL
+ *    for mu = 1.
+ *  - Genes are uint16 [.][9], one 16-bit gene per parameter (Sec. 4.2);
+ *    bit 0 of the paper's bit string is the most significant bit.
+ */
+#ifndef GENESIS_H
+#define GENESIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GENESIS_ABI_VERSION 1
+#define GENESIS_NPAR 9
+#define GENESIS_MAX_COMP 32   /* Zeeman components per line */
+#define GENESIS_MAX_LINES 4
+#define GENESIS_MAX_POP 1024
+#define GENESIS_MAX_K 8       /* tournament size */
+
+enum {
+    ME_OK = 0,
+    ME_EINVAL = -1, /* invalid argument (shape, range, NULL pointer) */
+    ME_ENOMEM = -2, /* workspace too small / shared memory limit exceeded */
+    ME_EHIP = -3,   /* a HIP runtime call failed */
+    ME_EBUSY = -4   /* resource in use */
+};
+
+/* Zeeman pattern of one spectral line (Sec. 5: the full pattern of the
+ * transition is computed once, at the start of an inversion).  Component c
+ * has q[c] = M_lower - M_upper in {-1, 0, +1}, wavelength shift
+ * shift[c] * Delta_lambda_B with shift = g_l M_l - g_u M_u and
+ * Delta_lambda_B = 4.6686e-13 lambda0^2 B [Angstrom], and relative strength
+ * strength[c]; strengths of each q group sum to 1. */
+typedef struct {
+    double lambda0_A;
+    int32_t ncomp;
+    int32_t q[GENESIS_MAX_COMP];
+    double shift[GENESIS_MAX_COMP];
+    double strength[GENESIS_MAX_COMP];
+} me_line;
+
+/* Wavelength samples of one line: lambda_j = start_A + j step_A, j < n. */
+typedef struct {
+    double start_A;
+    double step_A;
+    int32_t n;
+} me_grid;
+
+/* Search box u_j <= p_j <= v_j of the nine parameters (Sec. 3). */
+typedef struct {
+    double lo[GENESIS_NPAR];
+    double hi[GENESIS_NPAR];
+} me_bounds;
+
+/* Genetic-algorithm configuration (Sec. 3, Algorithm 1).
+ *  pop          population size, 2 .. GENESIS_MAX_POP
+ *  generations  G >= 0 iterations after the initial evaluation
+ *  tournament_k contestants per tournament, 1 .. min(pop, GENESIS_MAX_K)
+ *  p_cross      probability of single-point crossover of a pair
+ *  p_mut        mean per-bit mutation probability r; bit k (0 = MSB) flips
+ *               with probability 2 r (k + 1) / 17
+ *  seed         key of the counter-based random stream
+ *  pixel_base   pixel p of the call draws random numbers as pixel
+ *               pixel_base + p, so a map split into calls reproduces the
+ *               single-call result. */
+typedef struct {
+    int32_t pop;
+    int32_t generations;
+    int32_t tournament_k;
+    int32_t reserved0;
+    float p_cross;
+    float p_mut;
+    uint64_t seed;
+    uint32_t pixel_base;
+    int32_t reserved[7];
+} ga_config;
+
+/* Message of the last failure on this thread ("" if none). */
+const char *me_last_error(void);
+int genesis_abi_version(void);
+
+/* ---- line data (host only, no device work) ------------------------------ */
+
+/* Full Zeeman pattern of the dipole transition J_l -> J_u with Lande
+ * factors g_l, g_u (Sec. 5; Table 1 lists the two Fe I lines).
+ * Returns 0, or ME_EINVAL for |J_u - J_l| > 1, J_l = J_u = 0, half-integer
+ * mismatch or more than GENESIS_MAX_COMP components. */
+int me_line_from_terms(double lambda0_A, double Jl, double gl, double Ju, double gu,
+                       me_line *out);
+/* Effective triplet: three components at shifts -geff, 0, +geff. */
+int me_line_triplet(double lambda0_A, double geff, me_line *out);
+
+/* ---- forward model (Sec. 5) --------------------------------------------- */
+
+/* Stokes synthesis: params [n][9] -> stokes [n][4][L] by the analytic
+ * Unno-Rachkovsky solution I = S0 e + mu S1 (1 + eta0 Phi)^-1 e with the
+ * Voigt and Faraday-Voigt profiles over every Zeeman component.
+ * FP32: rational Voigt approximation (max error 1.6e-8) in FP32 arithmetic.
+ * n may be 0.  ME_EINVAL on NULL arrays (n > 0), nlines out of range, a grid
+ * with n < 1, or an invalid line. */
+int me_synth(const float *params, int64_t n, const me_line *lines, const me_grid *grids,
+             int32_t nlines, const float *mu, float *stokes, void *stream);
+/* FP64 arithmetic with the Weideman N = 36 Faddeeva approximation. */
+int me_synth_f64(const double *params, int64_t n, const me_line *lines, const me_grid *grids,
+                 int32_t nlines, const double *mu, double *stokes, void *stream);
+
+/* Merit function F (Sec. 5 chi-square): for pixel p and individual i,
+ * chi2[p][i] = 1/nu sum_s sum_j ((obs[p][s][j] - M[s][j]) / sigma[p][s])^2,
+ * nu = 4L - 9, M synthesised from params [npix][pop][9].  Accumulation:
+ * per-Stokes sums of squared residuals over j ascending (FP32 in me_chi2,
+ * FP64 in me_chi2_f64), then sum_s sum / sigma_s^2, then / nu.
+ * Pixels with non-finite observations or sigma <= 0 give NaN. */
+int me_chi2(const float *params, int64_t npix, int32_t pop, const float *obs, const float *sigma,
+            const float *mu, const me_line *lines, const me_grid *grids, int32_t nlines,
+            float *chi2, void *stream);
+int me_chi2_f64(const double *params, int64_t npix, int32_t pop, const double *obs,
+                const double *sigma, const double *mu, const me_line *lines,
+                const me_grid *grids, int32_t nlines, double *chi2, void *stream);
+
+/* ---- genetic operators (Sec. 3, Sec. 4.2) ------------------------------- */
+
+/* Generation-0 population genes [npix][pop][9]: gene j of individual i of
+ * pixel p = high 16 bits of word j of the random stream
+ * (seed, pixel_base + p, generation 0, individual i, purpose 0). */
+int ga_init(int64_t npix, const ga_config *cfg, uint16_t *genes, void *stream);
+
+/* Decoding operator E^-1 (Sec. 3 decode equation):
+ * p_j = lo_j + (hi_j - lo_j) g_j / 65535, genes [n][9] -> params [n][9]. */
+int ga_decode(const uint16_t *genes, int64_t n, const me_bounds *bounds, float *params,
+              void *stream);
+
+/* Evaluation F[E^-1(G)]: fitness [npix][pop] of genes [npix][pop][9]; the
+ * same arithmetic as the fused loop of ga_invert. */
+int ga_evaluate(const uint16_t *genes, int64_t npix, int32_t pop, const me_bounds *bounds,
+                const float *obs, const float *sigma, const float *mu, const me_line *lines,
+                const me_grid *grids, int32_t nlines, float *fitness, void *stream);
+int ga_evaluate_f64(const uint16_t *genes, int64_t npix, int32_t pop, const me_bounds *bounds,
+                    const double *obs, const double *sigma, const double *mu,
+                    const me_line *lines, const me_grid *grids, int32_t nlines,
+                    double *fitness, void *stream);
+
+/* One generation of selection S, recombination R and mutation M with
+ * elitism, producing generation `generation` (>= 1) of every pixel from
+ * genes_in [npix][pop][9] and its fitness [npix][pop].
+ *  - elite (best fitness, ties to the lowest index, NaN = +inf) -> slot 0;
+ *  - slot c >= 1 is child (c-1)%2 of pair (c-1)/2: two tournaments of k
+ *    distinct contestants (Floyd sampling), single-point crossover of the
+ *    144-bit string with probability p_cross at a point in [1, 143], then a
+ *    per-bit XOR mutation mask.
+ * Outputs genes_out [npix][pop][9]; optional (NULL to skip): parents
+ * [npix][pop][2], xpoint [npix][pop] (0 = no crossover), masks
+ * [npix][pop][9], elite [npix].  genes_in and genes_out must not overlap. */
+int ga_step(const uint16_t *genes_in, const float *fitness, int64_t npix, const ga_config *cfg,
+            int32_t generation, uint16_t *genes_out, int32_t *parents, int32_t *xpoint,
+            uint16_t *masks, int32_t *elite, void *stream);
+int ga_step_f64(const uint16_t *genes_in, const double *fitness, int64_t npix,
+                const ga_config *cfg, int32_t generation, uint16_t *genes_out, int32_t *parents,
+                int32_t *xpoint, uint16_t *masks, int32_t *elite, void *stream);
+
+/* ---- the whole inversion (Algorithm 1, device resident) ----------------- */
+
+/* Device workspace ga_invert needs (bytes); currently 0: the population,
+ * its fitness and the pixel's observation live in on-chip memory. */
+size_t ga_workspace_bytes(int64_t npix, const ga_config *cfg);
+
+/* Invert npix pixels: create P0, evaluate, then G times select, recombine,
+ * mutate, decode and evaluate; one workgroup per pixel, one individual per
+ * lane, a single launch.  Outputs best_params [npix][9] (decoded best
+ * genotype of the last generation), best_chi2 [npix], status [npix]
+ * (0 ok, 1 non-finite observation, 2 sigma <= 0 or non-finite; outputs NaN
+ * for status != 0) -- status may be NULL; final_genes [npix][pop][9] and
+ * final_fitness [npix][pop] may be NULL.  workspace/ws_bytes may be NULL/0. */
+int ga_invert(const float *obs, const float *sigma, const float *mu, int64_t npix,
+              const me_line *lines, const me_grid *grids, int32_t nlines,
+              const me_bounds *bounds, const ga_config *cfg, float *best_params,
+              float *best_chi2, int32_t *status, uint16_t *final_genes, float *final_fitness,
+              void *workspace, size_t ws_bytes, void *stream);
+int ga_invert_f64(const double *obs, const double *sigma, const double *mu, int64_t npix,
+                  const me_line *lines, const me_grid *grids, int32_t nlines,
+                  const me_bounds *bounds, const ga_config *cfg, double *best_params,
+                  double *best_chi2, int32_t *status, uint16_t *final_genes,
+                  double *final_fitness, void *workspace, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GENESIS_H */

@@ -5,7 +5,7 @@ is checked against (Harker & Mighell, "A GPU-Computing Approach to Solar Stokes
 Profile Inversion": Sec. 3 genetic algorithm, Sec. 4.2 16-bit genes, Sec. 5
 Milne-Eddington synthesis and chi-square).  Only ``tests/``, the smoke check and
 the CPU-baseline leg of ``bench.py`` may import it.  It shares no code with the
-HIP library in ``paper_1208_0302_amd`` and never imports it.
+HIP library and never imports it.
 
 The C sources next to this file are compiled with gcc (OpenMP over pixels) into
 ``liboracle.so``; ``build()`` does that and ``lib()`` builds on first use when

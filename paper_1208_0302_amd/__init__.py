@@ -1,0 +1,341 @@
+"""Python binding of libgenesis_hip.so (C ABI in include/genesis.h).
+
+Genetic-algorithm Milne-Eddington inversion of solar Stokes profiles on
+MI355X (gfx950), after Harker & Mighell, "A GPU-Computing Approach to Solar
+Stokes Profile Inversion".  This module only marshals arguments: every step of
+the computation runs in the library's HIP kernels.  PyTorch supplies device
+memory and the current stream.  There is no CPU fallback: if the shared object
+is missing, loading fails with an error that says how to build it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+import threading
+from typing import Optional, Sequence
+
+import torch
+
+from . import build as _build
+
+NPAR = 9
+MAX_COMP = 32
+MAX_LINES = 4
+MAX_POP = 1024
+MAX_K = 8
+
+ME_OK, ME_EINVAL, ME_ENOMEM, ME_EHIP, ME_EBUSY = 0, -1, -2, -3, -4
+
+
+class GenesisError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("genesis error %d: %s" % (code, msg))
+        self.code = code
+
+
+class MeLine(C.Structure):
+    _fields_ = [("lambda0_A", C.c_double), ("ncomp", C.c_int32),
+                ("q", C.c_int32 * MAX_COMP), ("shift", C.c_double * MAX_COMP),
+                ("strength", C.c_double * MAX_COMP)]
+
+
+class MeGrid(C.Structure):
+    _fields_ = [("start_A", C.c_double), ("step_A", C.c_double), ("n", C.c_int32)]
+
+
+class MeBounds(C.Structure):
+    _fields_ = [("lo", C.c_double * NPAR), ("hi", C.c_double * NPAR)]
+
+
+class GaConfigC(C.Structure):
+    _fields_ = [("pop", C.c_int32), ("generations", C.c_int32), ("tournament_k", C.c_int32),
+                ("reserved0", C.c_int32), ("p_cross", C.c_float), ("p_mut", C.c_float),
+                ("seed", C.c_uint64), ("pixel_base", C.c_uint32), ("reserved", C.c_int32 * 7)]
+
+
+@dataclasses.dataclass
+class GAConfig:
+    """Genetic-algorithm settings (Sec. 3, Algorithm 1)."""
+    pop: int = 128
+    generations: int = 200
+    tournament_k: int = 4
+    p_cross: float = 0.85
+    p_mut: float = 0.05
+    seed: int = 0
+    pixel_base: int = 0
+
+    def c(self) -> GaConfigC:
+        cfg = GaConfigC()
+        cfg.pop = self.pop
+        cfg.generations = self.generations
+        cfg.tournament_k = self.tournament_k
+        cfg.p_cross = self.p_cross
+        cfg.p_mut = self.p_mut
+        cfg.seed = self.seed
+        cfg.pixel_base = self.pixel_base
+        return cfg
+
+
+_LOCK = threading.Lock()
+_LIB = None
+
+_vp = C.c_void_p
+_i64 = C.c_int64
+_i32 = C.c_int32
+_lp = C.POINTER(MeLine)
+_gp = C.POINTER(MeGrid)
+_bp = C.POINTER(MeBounds)
+_cp = C.POINTER(GaConfigC)
+
+_SIGS = {
+    "me_last_error": ([], C.c_char_p),
+    "genesis_abi_version": ([], C.c_int),
+    "me_line_from_terms": ([C.c_double] * 5 + [_lp], C.c_int),
+    "me_line_triplet": ([C.c_double, C.c_double, _lp], C.c_int),
+    "me_synth": ([_vp, _i64, _lp, _gp, _i32, _vp, _vp, _vp], C.c_int),
+    "me_synth_f64": ([_vp, _i64, _lp, _gp, _i32, _vp, _vp, _vp], C.c_int),
+    "me_chi2": ([_vp, _i64, _i32, _vp, _vp, _vp, _lp, _gp, _i32, _vp, _vp], C.c_int),
+    "me_chi2_f64": ([_vp, _i64, _i32, _vp, _vp, _vp, _lp, _gp, _i32, _vp, _vp], C.c_int),
+    "ga_init": ([_i64, _cp, _vp, _vp], C.c_int),
+    "ga_decode": ([_vp, _i64, _bp, _vp, _vp], C.c_int),
+    "ga_evaluate": ([_vp, _i64, _i32, _bp, _vp, _vp, _vp, _lp, _gp, _i32, _vp, _vp], C.c_int),
+    "ga_evaluate_f64": ([_vp, _i64, _i32, _bp, _vp, _vp, _vp, _lp, _gp, _i32, _vp, _vp],
+                        C.c_int),
+    "ga_step": ([_vp, _vp, _i64, _cp, _i32, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "ga_step_f64": ([_vp, _vp, _i64, _cp, _i32, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "ga_workspace_bytes": ([_i64, _cp], C.c_size_t),
+    "ga_invert": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _cp, _vp, _vp, _vp, _vp, _vp, _vp,
+                   C.c_size_t, _vp], C.c_int),
+    "ga_invert_f64": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _cp, _vp, _vp, _vp, _vp, _vp,
+                       _vp, C.c_size_t, _vp], C.c_int),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def lib_path() -> str:
+    return _build.SO
+
+
+def lib():
+    """Load libgenesis_hip.so (fails loudly if it has not been built)."""
+    global _LIB
+    with _LOCK:
+        if _LIB is None:
+            if not os.path.exists(_build.SO):
+                raise RuntimeError(
+                    "libgenesis_hip.so is not built; run `python -m paper_1208_0302_amd.build` "
+                    "(or __graft_entry__.build()) first")
+            L = C.CDLL(_build.SO)
+            for name, (args, res) in _SIGS.items():
+                f = getattr(L, name)
+                f.argtypes = args
+                f.restype = res
+            _LIB = L
+    return _LIB
+
+
+def _check(rc):
+    if rc != ME_OK:
+        raise GenesisError(rc, lib().me_last_error().decode())
+
+
+# --------------------------------------------------------------------------- #
+# line data (host only)
+
+def line_from_terms(lambda0_A, Jl, gl, Ju, gu) -> MeLine:
+    ln = MeLine()
+    _check(lib().me_line_from_terms(float(lambda0_A), float(Jl), float(gl), float(Ju), float(gu),
+                                    C.byref(ln)))
+    return ln
+
+
+def line_triplet(lambda0_A, geff) -> MeLine:
+    ln = MeLine()
+    _check(lib().me_line_triplet(float(lambda0_A), float(geff), C.byref(ln)))
+    return ln
+
+
+def grid(start_A, step_A, n) -> MeGrid:
+    return MeGrid(float(start_A), float(step_A), int(n))
+
+
+def bounds(lo, hi) -> MeBounds:
+    b = MeBounds()
+    for j in range(NPAR):
+        b.lo[j] = float(lo[j])
+        b.hi[j] = float(hi[j])
+    return b
+
+
+def _lines(lines: Sequence[MeLine], grids: Sequence[MeGrid]):
+    if len(lines) != len(grids):
+        raise ValueError("one grid per line")
+    la = (MeLine * len(lines))(*lines)
+    ga = (MeGrid * len(grids))(*grids)
+    return la, ga, len(lines)
+
+
+def total_samples(grids: Sequence[MeGrid]) -> int:
+    return sum(int(g.n) for g in grids)
+
+
+# --------------------------------------------------------------------------- #
+# tensor plumbing
+
+def _stream(t: torch.Tensor):
+    return _vp(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _dev(t: Optional[torch.Tensor], dtype, name, shape=None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    return t
+
+
+def _ptr(t):
+    return None if t is None else _vp(t.data_ptr())
+
+
+def _real(t: torch.Tensor):
+    if t.dtype not in (torch.float32, torch.float64):
+        raise TypeError("float32 or float64 tensor expected")
+    return t.dtype
+
+
+# --------------------------------------------------------------------------- #
+# forward model
+
+def me_synth(params: torch.Tensor, lines, grids, mu=None, out=None):
+    """Stokes [n, 4, L] from params [n, 9] (Sec. 5 analytic solution)."""
+    dt = _real(params)
+    n = params.shape[0]
+    L = total_samples(grids)
+    _dev(params, dt, "params", (n, NPAR))
+    _dev(mu, dt, "mu", (n,))
+    if out is None:
+        out = torch.empty((n, 4, L), dtype=dt, device=params.device)
+    _dev(out, dt, "out", (n, 4, L))
+    la, ga, nl = _lines(lines, grids)
+    f = lib().me_synth if dt == torch.float32 else lib().me_synth_f64
+    _check(f(_ptr(params), n, la, ga, nl, _ptr(mu), _ptr(out), _stream(params)))
+    return out
+
+
+def me_chi2(params, obs, sigma, lines, grids, mu=None, out=None):
+    """chi-square [npix, pop] of params [npix, pop, 9] (Sec. 5 merit function)."""
+    dt = _real(params)
+    npix, pop = params.shape[0], params.shape[1]
+    L = total_samples(grids)
+    _dev(params, dt, "params", (npix, pop, NPAR))
+    _dev(obs, dt, "obs", (npix, 4, L))
+    _dev(sigma, dt, "sigma", (npix, 4))
+    _dev(mu, dt, "mu", (npix,))
+    if out is None:
+        out = torch.empty((npix, pop), dtype=dt, device=params.device)
+    _dev(out, dt, "out", (npix, pop))
+    la, ga, nl = _lines(lines, grids)
+    f = lib().me_chi2 if dt == torch.float32 else lib().me_chi2_f64
+    _check(f(_ptr(params), npix, pop, _ptr(obs), _ptr(sigma), _ptr(mu), la, ga, nl, _ptr(out),
+             _stream(params)))
+    return out
+
+
+# --------------------------------------------------------------------------- #
+# genetic operators
+
+def ga_init(npix: int, cfg: GAConfig, device="cuda"):
+    genes = torch.empty((npix, cfg.pop, NPAR), dtype=torch.uint16, device=device)
+    c = cfg.c()
+    _check(lib().ga_init(npix, C.byref(c), _ptr(genes), _stream(genes)))
+    return genes
+
+
+def ga_decode(genes: torch.Tensor, bnds: MeBounds):
+    _dev(genes, torch.uint16, "genes")
+    n = genes.numel() // NPAR
+    out = torch.empty(genes.shape, dtype=torch.float32, device=genes.device)
+    _check(lib().ga_decode(_ptr(genes), n, C.byref(bnds), _ptr(out), _stream(genes)))
+    return out
+
+
+def ga_evaluate(genes, bnds: MeBounds, obs, sigma, lines, grids, mu=None, out=None):
+    dt = _real(obs)
+    npix, pop = genes.shape[0], genes.shape[1]
+    L = total_samples(grids)
+    _dev(genes, torch.uint16, "genes", (npix, pop, NPAR))
+    _dev(obs, dt, "obs", (npix, 4, L))
+    _dev(sigma, dt, "sigma", (npix, 4))
+    _dev(mu, dt, "mu", (npix,))
+    if out is None:
+        out = torch.empty((npix, pop), dtype=dt, device=genes.device)
+    _dev(out, dt, "out", (npix, pop))
+    la, ga, nl = _lines(lines, grids)
+    f = lib().ga_evaluate if dt == torch.float32 else lib().ga_evaluate_f64
+    _check(f(_ptr(genes), npix, pop, C.byref(bnds), _ptr(obs), _ptr(sigma), _ptr(mu), la, ga, nl,
+             _ptr(out), _stream(genes)))
+    return out
+
+
+def ga_step(genes_in, fitness, cfg: GAConfig, generation: int, diagnostics=True):
+    """One generation of S, R, M with elitism; returns a dict of tensors."""
+    dt = _real(fitness)
+    npix, pop = genes_in.shape[0], genes_in.shape[1]
+    if pop != cfg.pop:
+        raise ValueError("genes have pop %d, config says %d" % (pop, cfg.pop))
+    _dev(genes_in, torch.uint16, "genes_in", (npix, pop, NPAR))
+    _dev(fitness, dt, "fitness", (npix, pop))
+    dev = genes_in.device
+    out = torch.empty_like(genes_in)
+    res = dict(genes=out)
+    if diagnostics:
+        res.update(parents=torch.empty((npix, pop, 2), dtype=torch.int32, device=dev),
+                   xpoint=torch.empty((npix, pop), dtype=torch.int32, device=dev),
+                   masks=torch.empty_like(genes_in),
+                   elite=torch.empty((npix,), dtype=torch.int32, device=dev))
+    c = cfg.c()
+    f = lib().ga_step if dt == torch.float32 else lib().ga_step_f64
+    _check(f(_ptr(genes_in), _ptr(fitness), npix, C.byref(c), int(generation), _ptr(out),
+             _ptr(res.get("parents")), _ptr(res.get("xpoint")), _ptr(res.get("masks")),
+             _ptr(res.get("elite")), _stream(genes_in)))
+    return res
+
+
+def ga_workspace_bytes(npix: int, cfg: GAConfig) -> int:
+    c = cfg.c()
+    return int(lib().ga_workspace_bytes(npix, C.byref(c)))
+
+
+def ga_invert(obs, sigma, lines, grids, bnds: MeBounds, cfg: GAConfig, mu=None,
+              want_population=False, want_status=True):
+    """Whole inversion (Algorithm 1) in one launch; returns a dict of tensors."""
+    dt = _real(obs)
+    npix = obs.shape[0]
+    L = total_samples(grids)
+    _dev(obs, dt, "obs", (npix, 4, L))
+    _dev(sigma, dt, "sigma", (npix, 4))
+    _dev(mu, dt, "mu", (npix,))
+    dev = obs.device
+    res = dict(params=torch.empty((npix, NPAR), dtype=dt, device=dev),
+               chi2=torch.empty((npix,), dtype=dt, device=dev))
+    if want_status:
+        res["status"] = torch.empty((npix,), dtype=torch.int32, device=dev)
+    if want_population:
+        res["genes"] = torch.empty((npix, cfg.pop, NPAR), dtype=torch.uint16, device=dev)
+        res["fitness"] = torch.empty((npix, cfg.pop), dtype=dt, device=dev)
+    la, ga, nl = _lines(lines, grids)
+    c = cfg.c()
+    f = lib().ga_invert if dt == torch.float32 else lib().ga_invert_f64
+    _check(f(_ptr(obs), _ptr(sigma), _ptr(mu), npix, la, ga, nl, C.byref(bnds), C.byref(c),
+             _ptr(res["params"]), _ptr(res["chi2"]), _ptr(res.get("status")),
+             _ptr(res.get("genes")), _ptr(res.get("fitness")), None, 0, _stream(obs)))
+    return res

@@ -1,0 +1,920 @@
+// libgenesis_hip.so: kernels and C ABI (declared in include/genesis.h).
+//
+// Harker & Mighell, "A GPU-Computing Approach to Solar Stokes Profile
+// Inversion": genetic algorithm (Sec. 3, Algorithm 1), 16-bit genes
+// (Sec. 4.2), Milne-Eddington synthesis and chi-square (Sec. 5).
+//
+// The paper runs only the fitness evaluation on the GPU (one block per
+// individual, one thread per wavelength) and the genetic operators on the
+// host.  Here the whole loop is device resident: ga_invert is one launch,
+// one workgroup per pixel, one individual per lane, population and fitness
+// in LDS, random numbers from a counter-based stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "genesis_device.h"
+
+using namespace genesis;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int check_launch(const char *what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(ME_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return ME_OK;
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+constexpr int kMaxGrid = 1 << 30;
+constexpr size_t kMaxLds = 64 * 1024;
+
+int grid_for(int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>(n, 1), kMaxGrid); }
+int block_for_pop(int pop) { return ((pop + 63) / 64) * 64; }
+
+// ---- line data ---------------------------------------------------------
+
+bool twice_int(double x, int *out)
+{
+    const double t = 2.0 * x, r = std::floor(t + 0.5);
+    if (!std::isfinite(x) || std::fabs(t - r) > 1e-9)
+        return false;
+    *out = (int)r;
+    return true;
+}
+
+// Relative strength of the component M_l -> M_u = M_l - q of a dipole
+// transition between the lower level J_l and the upper level J_u
+// (closed forms of Condon & Shortley for J_u = J_l + 1, J_l, J_l - 1;
+// normalised per q group by the caller).  Arguments are doubled integers.
+double cs_strength(int TJl, int TJu, int TM, int q)
+{
+    const double J = 0.5 * TJl, M = 0.5 * TM;
+    if (TJu == TJl + 2) {
+        if (q == 0)
+            return (J + 1) * (J + 1) - M * M;
+        if (q == -1)
+            return (J + M + 1) * (J + M + 2);
+        return (J - M + 1) * (J - M + 2);
+    }
+    if (TJu == TJl) {
+        if (q == 0)
+            return M * M;
+        if (q == -1)
+            return (J - M) * (J + M + 1);
+        return (J + M) * (J - M + 1);
+    }
+    // J_u = J_l - 1
+    if (q == 0)
+        return J * J - M * M;
+    if (q == -1)
+        return (J - M) * (J - M - 1);
+    return (J + M) * (J + M - 1);
+}
+
+template <typename Real>
+int pack_lines(const me_line *lines, const me_grid *grids, int nlines, DevLines<Real> &out)
+{
+    if (!lines || !grids)
+        return fail(ME_EINVAL, "lines and grids must not be NULL");
+    if (nlines < 1 || nlines > GENESIS_MAX_LINES)
+        return fail(ME_EINVAL, "nlines = %d outside [1, %d]", nlines, GENESIS_MAX_LINES);
+    std::memset(&out, 0, sizeof out);
+    out.nlines = nlines;
+    int off = 0;
+    for (int l = 0; l < nlines; ++l) {
+        const me_line &ln = lines[l];
+        const me_grid &gd = grids[l];
+        if (!(ln.lambda0_A > 0) || !std::isfinite(ln.lambda0_A))
+            return fail(ME_EINVAL, "line %d: lambda0 must be positive", l);
+        if (ln.ncomp < 1 || ln.ncomp > GENESIS_MAX_COMP)
+            return fail(ME_EINVAL, "line %d: ncomp = %d outside [1, %d]", l, ln.ncomp,
+                        GENESIS_MAX_COMP);
+        if (gd.n < 1 || !std::isfinite(gd.start_A) || !std::isfinite(gd.step_A))
+            return fail(ME_EINVAL, "line %d: invalid wavelength grid", l);
+        DevLine<Real> &d = out.l[l];
+        d.off0 = (Real)(gd.start_A - ln.lambda0_A);
+        d.step = (Real)gd.step_A;
+        d.dop_kms = (Real)(ln.lambda0_A / kCkms);
+        d.zee_G = (Real)(kZeeman * ln.lambda0_A * ln.lambda0_A);
+        d.nlam = gd.n;
+        d.off = off;
+        int n = 0;
+        int cnt[3] = {0, 0, 0};
+        for (int g = -1; g <= 1; ++g)
+            for (int c = 0; c < ln.ncomp; ++c) {
+                if (ln.q[c] < -1 || ln.q[c] > 1)
+                    return fail(ME_EINVAL, "line %d component %d: q must be -1, 0 or 1", l, c);
+                if (!std::isfinite(ln.shift[c]) || !std::isfinite(ln.strength[c]))
+                    return fail(ME_EINVAL, "line %d component %d: non-finite data", l, c);
+                if (ln.q[c] != g)
+                    continue;
+                d.s[n] = (Real)ln.shift[c];
+                d.w[n] = (Real)ln.strength[c];
+                ++n;
+                ++cnt[g + 1];
+            }
+        d.nb = cnt[0];
+        d.np = cnt[1];
+        d.nr = cnt[2];
+        off += gd.n;
+        if (off > (1 << 20))
+            return fail(ME_EINVAL, "too many wavelength samples");
+    }
+    out.L = off;
+    return ME_OK;
+}
+
+int pack_bounds(const me_bounds *b, Bounds &out)
+{
+    if (!b)
+        return fail(ME_EINVAL, "bounds must not be NULL");
+    for (int j = 0; j < GENESIS_NPAR; ++j) {
+        if (!std::isfinite(b->lo[j]) || !std::isfinite(b->hi[j]) || b->lo[j] > b->hi[j])
+            return fail(ME_EINVAL, "bounds of parameter %d: need finite lo <= hi", j);
+        out.lo[j] = b->lo[j];
+        out.span[j] = b->hi[j] - b->lo[j];
+    }
+    if (!(b->lo[4] > 0))
+        return fail(ME_EINVAL, "Doppler width bound must be positive");
+    if (b->lo[5] < 0)
+        return fail(ME_EINVAL, "damping bound must be >= 0");
+    return ME_OK;
+}
+
+int pack_ga(const ga_config *cfg, GaConst &ga)
+{
+    if (!cfg)
+        return fail(ME_EINVAL, "config must not be NULL");
+    if (cfg->pop < 2 || cfg->pop > GENESIS_MAX_POP)
+        return fail(ME_EINVAL, "pop = %d outside [2, %d]", cfg->pop, GENESIS_MAX_POP);
+    if (cfg->tournament_k < 1 || cfg->tournament_k > std::min(cfg->pop, GENESIS_MAX_K))
+        return fail(ME_EINVAL, "tournament_k = %d outside [1, min(pop, %d)]", cfg->tournament_k,
+                    GENESIS_MAX_K);
+    if (cfg->generations < 0)
+        return fail(ME_EINVAL, "generations must be >= 0");
+    const double pc = cfg->p_cross, pm = cfg->p_mut;
+    if (!(pc >= 0.0 && pc <= 1.0) || !(pm >= 0.0 && pm <= 1.0))
+        return fail(ME_EINVAL, "p_cross and p_mut must lie in [0, 1]");
+    ga.pop = cfg->pop;
+    ga.k = cfg->tournament_k;
+    ga.thr_cross = (uint64_t)std::floor(pc * 4294967296.0);
+    for (int kb = 0; kb < 16; ++kb) {
+        double t = std::floor(2.0 * pm * (double)(kb + 1) / 17.0 * 65536.0 + 0.5);
+        if (t > 65536.0)
+            t = 65536.0;
+        ga.mut_thr[kb] = (uint32_t)t;
+    }
+    ga.key.k0 = (uint32_t)(cfg->seed & 0xFFFFFFFFu);
+    ga.key.k1 = (uint32_t)(cfg->seed >> 32);
+    ga.pixel_base = cfg->pixel_base;
+    return ME_OK;
+}
+
+// ---- kernels -----------------------------------------------------------
+
+template <typename Real>
+struct StokesSink {
+    Real *out;  // [4][L] of one profile
+    int L;
+    __device__ __forceinline__ void operator()(int j, Real I, Real Q, Real U, Real V)
+    {
+        out[j] = I;
+        out[L + j] = Q;
+        out[2 * L + j] = U;
+        out[3 * L + j] = V;
+    }
+};
+
+template <typename Real>
+__global__ __launch_bounds__(256) void k_me_synth(const Real *__restrict__ params, int64_t n,
+                                                  DevLines<Real> ls, const Real *__restrict__ mu,
+                                                  Real *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    double p[GENESIS_NPAR];
+#pragma unroll
+    for (int j = 0; j < GENESIS_NPAR; ++j)
+        p[j] = (double)params[i * GENESIS_NPAR + j];
+    Model<Real> m;
+    model_setup(p, mu ? (double)mu[i] : 1.0, m);
+    StokesSink<Real> s{out + i * 4 * (int64_t)ls.L, ls.L};
+    synthesize(m, ls, s);
+}
+
+// Stage one pixel's observation into LDS as [L] x (I, Q, U, V) and return
+// its status (0 ok, 1 non-finite observation, 2 bad sigma); w2 = 1/sigma^2.
+template <typename Real>
+__device__ __forceinline__ int stage_pixel(const Real *__restrict__ obs_p,
+                                           const Real *__restrict__ sig_p, int L,
+                                           Vec4<Real> *obs_s, Real (&w2)[4])
+{
+    int bad = 0;
+    for (int j = threadIdx.x; j < L; j += blockDim.x) {
+        Vec4<Real> o;
+        o.x = obs_p[j];
+        o.y = obs_p[L + j];
+        o.z = obs_p[2 * L + j];
+        o.w = obs_p[3 * L + j];
+        bad |= !(isfinite(o.x) && isfinite(o.y) && isfinite(o.z) && isfinite(o.w));
+        obs_s[j] = o;
+    }
+    bad = __syncthreads_or(bad);
+    int bad_sig = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const Real sg = sig_p[s];
+        bad_sig |= !(sg > (Real)0 && isfinite(sg));
+        w2[s] = (Real)1 / (sg * sg);
+    }
+    return bad ? 1 : (bad_sig ? 2 : 0);
+}
+
+// Fitness of every individual of every pixel: from params (me_chi2) or from
+// genes through the decoding operator (ga_evaluate).
+template <typename Real, bool FROM_GENES>
+__global__ __launch_bounds__(1024) void k_fitness(const Real *__restrict__ params,
+                                                  const uint16_t *__restrict__ genes, Bounds b,
+                                                  int64_t npix, int pop,
+                                                  const Real *__restrict__ obs,
+                                                  const Real *__restrict__ sigma,
+                                                  const Real *__restrict__ mu, DevLines<Real> ls,
+                                                  Real *__restrict__ out)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    Vec4<Real> *obs_s = reinterpret_cast<Vec4<Real> *>(smem);
+    const int L = ls.L;
+    const Real inv_nu = (Real)(1.0 / (4.0 * L - GENESIS_NPAR));
+    for (int64_t p = blockIdx.x; p < npix; p += gridDim.x) {
+        Real w2[4];
+        const int st = stage_pixel(obs + p * 4 * (int64_t)L, sigma + p * 4, L, obs_s, w2);
+        const double m_mu = mu ? (double)mu[p] : 1.0;
+        for (int i = threadIdx.x; i < pop; i += blockDim.x) {
+            double par[GENESIS_NPAR];
+            const int64_t row = (p * pop + i) * GENESIS_NPAR;
+            if (FROM_GENES) {
+                uint32_t g[GENESIS_NPAR];
+#pragma unroll
+                for (int j = 0; j < GENESIS_NPAR; ++j)
+                    g[j] = genes[row + j];
+                decode(g, b, par);
+            } else {
+#pragma unroll
+                for (int j = 0; j < GENESIS_NPAR; ++j)
+                    par[j] = (double)params[row + j];
+            }
+            Real c = (Real)NAN;
+            if (st == 0) {
+                Model<Real> m;
+                model_setup(par, m_mu, m);
+                c = chi2_of(m, ls, obs_s, w2, inv_nu);
+            }
+            out[p * pop + i] = c;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_ga_init(int64_t npix, int pop, Key key, uint32_t pixel_base,
+                          uint16_t *__restrict__ genes)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= npix * pop)
+        return;
+    const int64_t p = t / pop;
+    const int i = (int)(t - p * pop);
+    const uint32_t pix = pixel_base + (uint32_t)p;
+#pragma unroll
+    for (int blk = 0; blk < 3; ++blk) {
+        const uint4 w = philox(pix, 0u, (uint32_t)i, (kInit << 24) | (uint32_t)blk, key);
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (4 * blk + q < GENESIS_NPAR)
+                genes[t * GENESIS_NPAR + 4 * blk + q] = (uint16_t)(ws[q] >> 16);
+    }
+}
+
+template <typename Real>
+__global__ void k_decode(const uint16_t *__restrict__ genes, int64_t n, Bounds b,
+                         Real *__restrict__ params)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    uint32_t g[GENESIS_NPAR];
+#pragma unroll
+    for (int j = 0; j < GENESIS_NPAR; ++j)
+        g[j] = genes[i * GENESIS_NPAR + j];
+    double p[GENESIS_NPAR];
+    decode(g, b, p);
+#pragma unroll
+    for (int j = 0; j < GENESIS_NPAR; ++j)
+        params[i * GENESIS_NPAR + j] = (Real)p[j];
+}
+
+// LDS of the GA kernels: observation [L] x 4, fitness [pop], argmin
+// scratch, and two gene buffers [9][pop] (parents, children).
+template <typename Real>
+struct GaLds {
+    Vec4<Real> *obs;
+    Real *fit, *red_f;
+    int *red_i;
+    uint16_t *genes;  // two buffers [9][pop] back to back
+};
+
+__host__ __device__ inline size_t align16(size_t o) { return (o + 15) & ~(size_t)15; }
+
+template <typename Real>
+__host__ __device__ inline size_t ga_lds_bytes(int L, int pop)
+{
+    size_t o = align16(sizeof(Vec4<Real>) * (size_t)L);
+    o = align16(o + sizeof(Real) * (size_t)pop);
+    o += (sizeof(Real) + sizeof(int)) * 16;
+    o = align16(o + 2 * sizeof(uint16_t) * GENESIS_NPAR * (size_t)pop);
+    return o;
+}
+
+template <typename Real>
+__device__ __forceinline__ GaLds<Real> ga_lds(unsigned char *base, int L, int pop)
+{
+    GaLds<Real> s;
+    size_t o = 0;
+    s.obs = reinterpret_cast<Vec4<Real> *>(base);
+    o = align16(sizeof(Vec4<Real>) * (size_t)L);
+    s.fit = reinterpret_cast<Real *>(base + o);
+    o = align16(o + sizeof(Real) * (size_t)pop);
+    s.red_f = reinterpret_cast<Real *>(base + o);
+    o += sizeof(Real) * 16;
+    s.red_i = reinterpret_cast<int *>(base + o);
+    o += sizeof(int) * 16;
+    s.genes = reinterpret_cast<uint16_t *>(base + o);
+    return s;
+}
+
+// Child sink writing into an LDS gene buffer [9][pop].
+struct LdsChild {
+    uint16_t *dst;
+    int pop, c;
+    __device__ __forceinline__ void meta(int, int, int) {}
+    __device__ __forceinline__ void gene(int j, uint32_t g, uint32_t)
+    {
+        dst[j * pop + c] = (uint16_t)g;
+    }
+};
+
+// Child sink writing the step outputs to global memory.
+struct GlobalChild {
+    uint16_t *genes, *masks;  // row of this child [9]
+    int32_t *parents, *xpoint;
+    __device__ __forceinline__ void meta(int a, int b, int x)
+    {
+        if (parents) {
+            parents[0] = a;
+            parents[1] = b;
+        }
+        if (xpoint)
+            *xpoint = x;
+    }
+    __device__ __forceinline__ void gene(int j, uint32_t g, uint32_t m)
+    {
+        genes[j] = (uint16_t)g;
+        if (masks)
+            masks[j] = (uint16_t)m;
+    }
+};
+
+template <typename Real>
+struct StepArgs {
+    const uint16_t *genes_in;
+    const Real *fitness;
+    int64_t npix;
+    uint32_t gen;
+    GaConst ga;
+    uint16_t *genes_out;
+    int32_t *parents, *xpoint, *elite;
+    uint16_t *masks;
+};
+
+template <typename Real>
+__global__ __launch_bounds__(1024) void k_ga_step(StepArgs<Real> a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int pop = a.ga.pop;
+    const GaLds<Real> s = ga_lds<Real>(smem, 0, pop);
+    const int tid = threadIdx.x;
+    for (int64_t p = blockIdx.x; p < a.npix; p += gridDim.x) {
+        for (int i = tid; i < pop; i += blockDim.x) {
+            s.fit[i] = a.fitness[p * pop + i];
+#pragma unroll
+            for (int j = 0; j < GENESIS_NPAR; ++j)
+                s.genes[j * pop + i] = a.genes_in[(p * pop + i) * GENESIS_NPAR + j];
+        }
+        __syncthreads();
+        const int e = block_argmin(s.fit, pop, s.red_f, s.red_i);
+        const uint32_t pix = a.ga.pixel_base + (uint32_t)p;
+        if (tid < pop) {
+            const int64_t row = p * pop + tid;
+            GlobalChild out{a.genes_out + row * GENESIS_NPAR,
+                            a.masks ? a.masks + row * GENESIS_NPAR : nullptr,
+                            a.parents ? a.parents + row * 2 : nullptr,
+                            a.xpoint ? a.xpoint + row : nullptr};
+            if (tid == 0) {
+                out.meta(e, e, 0);
+                for (int j = 0; j < GENESIS_NPAR; ++j)
+                    out.gene(j, s.genes[j * pop + e], 0u);
+                if (a.elite)
+                    a.elite[p] = e;
+            } else {
+                make_child(tid, pix, a.gen, s.fit, s.genes, a.ga, out);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename Real>
+struct InvertArgs {
+    const Real *obs, *sigma, *mu;
+    int64_t npix;
+    int32_t generations;
+    DevLines<Real> ls;
+    Bounds b;
+    GaConst ga;
+    Real *best_params, *best_chi2, *final_fitness;
+    int32_t *status;
+    uint16_t *final_genes;
+};
+
+template <typename Real>
+__device__ __forceinline__ Real evaluate_lds(const uint16_t *genes_s, int pop, int i,
+                                             const Bounds &b, double mu,
+                                             const DevLines<Real> &ls, const Vec4<Real> *obs_s,
+                                             const Real (&w2)[4], Real inv_nu)
+{
+    uint32_t g[GENESIS_NPAR];
+#pragma unroll
+    for (int j = 0; j < GENESIS_NPAR; ++j)
+        g[j] = genes_s[j * pop + i];
+    double par[GENESIS_NPAR];
+    decode(g, b, par);
+    Model<Real> m;
+    model_setup(par, mu, m);
+    return chi2_of(m, ls, obs_s, w2, inv_nu);
+}
+
+// The whole of Algorithm 1 for one pixel per workgroup: the population
+// lives in LDS (two buffers: parents and children), lane i owns
+// individual i.
+template <typename Real>
+__global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real> a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int pop = a.ga.pop;
+    const int L = a.ls.L;
+    const GaLds<Real> s = ga_lds<Real>(smem, L, pop);
+    const int tid = threadIdx.x;
+    const bool active = tid < pop;
+    const Real inv_nu = (Real)(1.0 / (4.0 * L - GENESIS_NPAR));
+    for (int64_t p = blockIdx.x; p < a.npix; p += gridDim.x) {
+        Real w2[4];
+        const int st = stage_pixel(a.obs + p * 4 * (int64_t)L, a.sigma + p * 4, L, s.obs, w2);
+        if (st != 0) {
+            if (tid == 0) {
+                for (int j = 0; j < GENESIS_NPAR; ++j)
+                    a.best_params[p * GENESIS_NPAR + j] = (Real)NAN;
+                a.best_chi2[p] = (Real)NAN;
+                if (a.status)
+                    a.status[p] = st;
+            }
+            if (active) {
+                if (a.final_fitness)
+                    a.final_fitness[p * pop + tid] = (Real)NAN;
+                if (a.final_genes)
+                    for (int j = 0; j < GENESIS_NPAR; ++j)
+                        a.final_genes[(p * pop + tid) * GENESIS_NPAR + j] = 0;
+            }
+            __syncthreads();
+            continue;
+        }
+        const double mu = a.mu ? (double)a.mu[p] : 1.0;
+        const uint32_t pix = a.ga.pixel_base + (uint32_t)p;
+        const int gstride = GENESIS_NPAR * pop;
+        int cur = 0;  // offset of the current generation's gene buffer
+        if (active) {
+#pragma unroll
+            for (int blk = 0; blk < 3; ++blk) {
+                const uint4 w = philox(pix, 0u, (uint32_t)tid, (kInit << 24) | (uint32_t)blk,
+                                       a.ga.key);
+                const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (4 * blk + q < GENESIS_NPAR)
+                        s.genes[(4 * blk + q) * pop + tid] = (uint16_t)(ws[q] >> 16);
+            }
+        }
+        Real f = (Real)0;
+        for (int t = 0;; ++t) {
+            // evaluate generation t (each lane reads only its own genes)
+            if (active) {
+                f = evaluate_lds(s.genes + cur, pop, tid, a.b, mu, a.ls, s.obs, w2, inv_nu);
+                s.fit[tid] = f;
+            }
+            __syncthreads();
+            if (t == a.generations)
+                break;
+            const int e = block_argmin(s.fit, pop, s.red_f, s.red_i);
+            if (active) {
+                LdsChild out{s.genes + (gstride - cur), pop, tid};
+                if (tid == 0) {
+                    for (int j = 0; j < GENESIS_NPAR; ++j)
+                        out.gene(j, s.genes[cur + j * pop + e], 0u);
+                } else {
+                    make_child(tid, pix, (uint32_t)(t + 1), s.fit, s.genes + cur, a.ga, out);
+                }
+            }
+            __syncthreads();
+            cur = gstride - cur;
+        }
+        const int e = block_argmin(s.fit, pop, s.red_f, s.red_i);
+        if (tid == 0) {
+            uint32_t gb[GENESIS_NPAR];
+            for (int j = 0; j < GENESIS_NPAR; ++j)
+                gb[j] = s.genes[cur + j * pop + e];
+            double par[GENESIS_NPAR];
+            decode(gb, a.b, par);
+            for (int j = 0; j < GENESIS_NPAR; ++j)
+                a.best_params[p * GENESIS_NPAR + j] = (Real)par[j];
+            a.best_chi2[p] = s.fit[e];
+            if (a.status)
+                a.status[p] = 0;
+        }
+        if (active) {
+            if (a.final_fitness)
+                a.final_fitness[p * pop + tid] = f;
+            if (a.final_genes)
+                for (int j = 0; j < GENESIS_NPAR; ++j)
+                    a.final_genes[(p * pop + tid) * GENESIS_NPAR + j] = s.genes[cur + j * pop + tid];
+        }
+        __syncthreads();
+    }
+}
+
+// ---- host wrappers -----------------------------------------------------
+
+template <typename Real>
+int synth_impl(const Real *params, int64_t n, const me_line *lines, const me_grid *grids,
+               int nlines, const Real *mu, Real *stokes, void *stream)
+{
+    DevLines<Real> ls;
+    if (int rc = pack_lines(lines, grids, nlines, ls))
+        return rc;
+    if (n < 0)
+        return fail(ME_EINVAL, "n must be >= 0");
+    if (n == 0)
+        return ME_OK;
+    if (!params || !stokes)
+        return fail(ME_EINVAL, "params and stokes must not be NULL");
+    const int bs = 256;
+    const int64_t blocks = (n + bs - 1) / bs;
+    if (blocks > kMaxGrid)
+        return fail(ME_EINVAL, "n too large");
+    hipLaunchKernelGGL(k_me_synth<Real>, dim3((unsigned)blocks), dim3(bs), 0, as_stream(stream),
+                       params, n, ls, mu, stokes);
+    return check_launch("me_synth");
+}
+
+template <typename Real, bool FROM_GENES>
+int fitness_impl(const Real *params, const uint16_t *genes, const me_bounds *bounds, int64_t npix,
+                 int pop, const Real *obs, const Real *sigma, const Real *mu,
+                 const me_line *lines, const me_grid *grids, int nlines, Real *out, void *stream)
+{
+    DevLines<Real> ls;
+    if (int rc = pack_lines(lines, grids, nlines, ls))
+        return rc;
+    Bounds b{};
+    if (FROM_GENES)
+        if (int rc = pack_bounds(bounds, b))
+            return rc;
+    if (npix < 0 || pop < 1 || pop > GENESIS_MAX_POP)
+        return fail(ME_EINVAL, "npix >= 0 and 1 <= pop <= %d required", GENESIS_MAX_POP);
+    if (4 * ls.L <= GENESIS_NPAR)
+        return fail(ME_EINVAL, "need 4 L > 9 wavelength samples for nu > 0");
+    if (npix == 0)
+        return ME_OK;
+    if (!(FROM_GENES ? (const void *)genes : (const void *)params) || !obs || !sigma || !out)
+        return fail(ME_EINVAL, "NULL array argument");
+    const size_t lds = sizeof(Vec4<Real>) * (size_t)ls.L;
+    if (lds > kMaxLds)
+        return fail(ME_ENOMEM, "observation of %d samples exceeds LDS", ls.L);
+    hipLaunchKernelGGL((k_fitness<Real, FROM_GENES>), dim3(grid_for(npix)),
+                       dim3(block_for_pop(pop)), lds, as_stream(stream), params, genes, b, npix,
+                       pop, obs, sigma, mu, ls, out);
+    return check_launch("fitness");
+}
+
+template <typename Real>
+int step_impl(const uint16_t *genes_in, const Real *fitness, int64_t npix, const ga_config *cfg,
+              int32_t generation, uint16_t *genes_out, int32_t *parents, int32_t *xpoint,
+              uint16_t *masks, int32_t *elite, void *stream)
+{
+    StepArgs<Real> a{};
+    if (int rc = pack_ga(cfg, a.ga))
+        return rc;
+    if (generation < 1)
+        return fail(ME_EINVAL, "generation must be >= 1 (generation 0 is ga_init)");
+    if (npix < 0)
+        return fail(ME_EINVAL, "npix must be >= 0");
+    if (npix == 0)
+        return ME_OK;
+    if (!genes_in || !fitness || !genes_out)
+        return fail(ME_EINVAL, "NULL array argument");
+    const size_t bytes = (size_t)npix * cfg->pop * GENESIS_NPAR * sizeof(uint16_t);
+    const char *gi = (const char *)genes_in, *go = (const char *)genes_out;
+    if (gi < go + bytes && go < gi + bytes)
+        return fail(ME_EINVAL, "genes_in and genes_out overlap");
+    a.genes_in = genes_in;
+    a.fitness = fitness;
+    a.npix = npix;
+    a.gen = (uint32_t)generation;
+    a.genes_out = genes_out;
+    a.parents = parents;
+    a.xpoint = xpoint;
+    a.masks = masks;
+    a.elite = elite;
+    const size_t lds = ga_lds_bytes<Real>(0, cfg->pop);
+    hipLaunchKernelGGL(k_ga_step<Real>, dim3(grid_for(npix)), dim3(block_for_pop(cfg->pop)), lds,
+                       as_stream(stream), a);
+    return check_launch("ga_step");
+}
+
+template <typename Real>
+int invert_impl(const Real *obs, const Real *sigma, const Real *mu, int64_t npix,
+                const me_line *lines, const me_grid *grids, int nlines, const me_bounds *bounds,
+                const ga_config *cfg, Real *best_params, Real *best_chi2, int32_t *status,
+                uint16_t *final_genes, Real *final_fitness, void *stream)
+{
+    InvertArgs<Real> a{};
+    if (int rc = pack_lines(lines, grids, nlines, a.ls))
+        return rc;
+    if (int rc = pack_bounds(bounds, a.b))
+        return rc;
+    if (int rc = pack_ga(cfg, a.ga))
+        return rc;
+    if (npix < 0)
+        return fail(ME_EINVAL, "npix must be >= 0");
+    if (4 * a.ls.L <= GENESIS_NPAR)
+        return fail(ME_EINVAL, "need 4 L > 9 wavelength samples for nu > 0");
+    const size_t lds = ga_lds_bytes<Real>(a.ls.L, cfg->pop);
+    if (lds > kMaxLds)
+        return fail(ME_ENOMEM, "L = %d, pop = %d need %zu B of LDS (> %zu)", a.ls.L, cfg->pop,
+                    lds, kMaxLds);
+    if (npix == 0)
+        return ME_OK;
+    if (!obs || !sigma || !best_params || !best_chi2)
+        return fail(ME_EINVAL, "NULL array argument");
+    a.obs = obs;
+    a.sigma = sigma;
+    a.mu = mu;
+    a.npix = npix;
+    a.generations = cfg->generations;
+    a.best_params = best_params;
+    a.best_chi2 = best_chi2;
+    a.status = status;
+    a.final_genes = final_genes;
+    a.final_fitness = final_fitness;
+    hipLaunchKernelGGL(k_ga_invert<Real>, dim3(grid_for(npix)), dim3(block_for_pop(cfg->pop)),
+                       lds, as_stream(stream), a);
+    return check_launch("ga_invert");
+}
+
+}  // namespace
+
+// ---- C ABI -------------------------------------------------------------
+
+extern "C" {
+
+const char *me_last_error(void) { return g_err.c_str(); }
+
+int genesis_abi_version(void) { return GENESIS_ABI_VERSION; }
+
+int me_line_from_terms(double lambda0_A, double Jl, double gl, double Ju, double gu,
+                       me_line *out)
+{
+    if (!out)
+        return fail(ME_EINVAL, "out must not be NULL");
+    int TJl, TJu;
+    if (!twice_int(Jl, &TJl) || !twice_int(Ju, &TJu) || TJl < 0 || TJu < 0)
+        return fail(ME_EINVAL, "J values must be non-negative integers or half-integers");
+    if (std::abs(TJl - TJu) > 2 || ((TJl - TJu) & 1) || (TJl == 0 && TJu == 0))
+        return fail(ME_EINVAL, "J_l = %g -> J_u = %g is not a dipole transition", Jl, Ju);
+    if (!(lambda0_A > 0) || !std::isfinite(gl) || !std::isfinite(gu))
+        return fail(ME_EINVAL, "invalid line data");
+    me_line ln;
+    std::memset(&ln, 0, sizeof ln);
+    ln.lambda0_A = lambda0_A;
+    double sum[3] = {0, 0, 0};
+    int n = 0;
+    for (int TM = -TJl; TM <= TJl; TM += 2) {
+        for (int q = -1; q <= 1; ++q) {
+            const int TMu = TM - 2 * q;
+            if (TMu < -TJu || TMu > TJu)
+                continue;
+            const double s = cs_strength(TJl, TJu, TM, q);
+            if (s <= 0.0)
+                continue;
+            if (n >= GENESIS_MAX_COMP)
+                return fail(ME_EINVAL, "more than %d Zeeman components", GENESIS_MAX_COMP);
+            ln.q[n] = q;
+            ln.shift[n] = gl * 0.5 * TM - gu * 0.5 * TMu;
+            ln.strength[n] = s;
+            sum[q + 1] += s;
+            ++n;
+        }
+    }
+    for (int c = 0; c < n; ++c)
+        ln.strength[c] /= sum[ln.q[c] + 1];
+    ln.ncomp = n;
+    *out = ln;
+    return ME_OK;
+}
+
+int me_line_triplet(double lambda0_A, double geff, me_line *out)
+{
+    if (!out)
+        return fail(ME_EINVAL, "out must not be NULL");
+    if (!(lambda0_A > 0) || !std::isfinite(geff))
+        return fail(ME_EINVAL, "invalid line data");
+    me_line ln;
+    std::memset(&ln, 0, sizeof ln);
+    ln.lambda0_A = lambda0_A;
+    ln.ncomp = 3;
+    for (int c = 0; c < 3; ++c) {
+        ln.q[c] = c - 1;
+        ln.shift[c] = (c - 1) * geff;
+        ln.strength[c] = 1.0;
+    }
+    *out = ln;
+    return ME_OK;
+}
+
+int me_synth(const float *params, int64_t n, const me_line *lines, const me_grid *grids,
+             int32_t nlines, const float *mu, float *stokes, void *stream)
+{
+    return synth_impl<float>(params, n, lines, grids, nlines, mu, stokes, stream);
+}
+
+int me_synth_f64(const double *params, int64_t n, const me_line *lines, const me_grid *grids,
+                 int32_t nlines, const double *mu, double *stokes, void *stream)
+{
+    return synth_impl<double>(params, n, lines, grids, nlines, mu, stokes, stream);
+}
+
+int me_chi2(const float *params, int64_t npix, int32_t pop, const float *obs, const float *sigma,
+            const float *mu, const me_line *lines, const me_grid *grids, int32_t nlines,
+            float *chi2, void *stream)
+{
+    return fitness_impl<float, false>(params, nullptr, nullptr, npix, pop, obs, sigma, mu, lines,
+                                      grids, nlines, chi2, stream);
+}
+
+int me_chi2_f64(const double *params, int64_t npix, int32_t pop, const double *obs,
+                const double *sigma, const double *mu, const me_line *lines,
+                const me_grid *grids, int32_t nlines, double *chi2, void *stream)
+{
+    return fitness_impl<double, false>(params, nullptr, nullptr, npix, pop, obs, sigma, mu, lines,
+                                       grids, nlines, chi2, stream);
+}
+
+int ga_init(int64_t npix, const ga_config *cfg, uint16_t *genes, void *stream)
+{
+    GaConst ga;
+    if (int rc = pack_ga(cfg, ga))
+        return rc;
+    if (npix < 0)
+        return fail(ME_EINVAL, "npix must be >= 0");
+    if (npix == 0)
+        return ME_OK;
+    if (!genes)
+        return fail(ME_EINVAL, "genes must not be NULL");
+    const int64_t n = npix * cfg->pop;
+    const int bs = 256;
+    const int64_t blocks = (n + bs - 1) / bs;
+    if (blocks > kMaxGrid)
+        return fail(ME_EINVAL, "npix * pop too large");
+    hipLaunchKernelGGL(k_ga_init, dim3((unsigned)blocks), dim3(bs), 0, as_stream(stream), npix,
+                       cfg->pop, ga.key, ga.pixel_base, genes);
+    return check_launch("ga_init");
+}
+
+int ga_decode(const uint16_t *genes, int64_t n, const me_bounds *bounds, float *params,
+              void *stream)
+{
+    Bounds b;
+    if (int rc = pack_bounds(bounds, b))
+        return rc;
+    if (n < 0)
+        return fail(ME_EINVAL, "n must be >= 0");
+    if (n == 0)
+        return ME_OK;
+    if (!genes || !params)
+        return fail(ME_EINVAL, "NULL array argument");
+    const int bs = 256;
+    const int64_t blocks = (n + bs - 1) / bs;
+    if (blocks > kMaxGrid)
+        return fail(ME_EINVAL, "n too large");
+    hipLaunchKernelGGL(k_decode<float>, dim3((unsigned)blocks), dim3(bs), 0, as_stream(stream),
+                       genes, n, b, params);
+    return check_launch("ga_decode");
+}
+
+int ga_evaluate(const uint16_t *genes, int64_t npix, int32_t pop, const me_bounds *bounds,
+                const float *obs, const float *sigma, const float *mu, const me_line *lines,
+                const me_grid *grids, int32_t nlines, float *fitness, void *stream)
+{
+    return fitness_impl<float, true>(nullptr, genes, bounds, npix, pop, obs, sigma, mu, lines,
+                                     grids, nlines, fitness, stream);
+}
+
+int ga_evaluate_f64(const uint16_t *genes, int64_t npix, int32_t pop, const me_bounds *bounds,
+                    const double *obs, const double *sigma, const double *mu,
+                    const me_line *lines, const me_grid *grids, int32_t nlines,
+                    double *fitness, void *stream)
+{
+    return fitness_impl<double, true>(nullptr, genes, bounds, npix, pop, obs, sigma, mu, lines,
+                                      grids, nlines, fitness, stream);
+}
+
+int ga_step(const uint16_t *genes_in, const float *fitness, int64_t npix, const ga_config *cfg,
+            int32_t generation, uint16_t *genes_out, int32_t *parents, int32_t *xpoint,
+            uint16_t *masks, int32_t *elite, void *stream)
+{
+    return step_impl<float>(genes_in, fitness, npix, cfg, generation, genes_out, parents, xpoint,
+                            masks, elite, stream);
+}
+
+int ga_step_f64(const uint16_t *genes_in, const double *fitness, int64_t npix,
+                const ga_config *cfg, int32_t generation, uint16_t *genes_out, int32_t *parents,
+                int32_t *xpoint, uint16_t *masks, int32_t *elite, void *stream)
+{
+    return step_impl<double>(genes_in, fitness, npix, cfg, generation, genes_out, parents, xpoint,
+                             masks, elite, stream);
+}
+
+size_t ga_workspace_bytes(int64_t npix, const ga_config *cfg)
+{
+    (void)npix;
+    (void)cfg;
+    return 0;
+}
+
+int ga_invert(const float *obs, const float *sigma, const float *mu, int64_t npix,
+              const me_line *lines, const me_grid *grids, int32_t nlines,
+              const me_bounds *bounds, const ga_config *cfg, float *best_params,
+              float *best_chi2, int32_t *status, uint16_t *final_genes, float *final_fitness,
+              void *workspace, size_t ws_bytes, void *stream)
+{
+    (void)workspace;
+    (void)ws_bytes;
+    return invert_impl<float>(obs, sigma, mu, npix, lines, grids, nlines, bounds, cfg,
+                              best_params, best_chi2, status, final_genes, final_fitness, stream);
+}
+
+int ga_invert_f64(const double *obs, const double *sigma, const double *mu, int64_t npix,
+                  const me_line *lines, const me_grid *grids, int32_t nlines,
+                  const me_bounds *bounds, const ga_config *cfg, double *best_params,
+                  double *best_chi2, int32_t *status, uint16_t *final_genes,
+                  double *final_fitness, void *workspace, size_t ws_bytes, void *stream)
+{
+    (void)workspace;
+    (void)ws_bytes;
+    return invert_impl<double>(obs, sigma, mu, npix, lines, grids, nlines, bounds, cfg,
+                               best_params, best_chi2, status, final_genes, final_fitness,
+                               stream);
+}
+
+}  // extern "C"

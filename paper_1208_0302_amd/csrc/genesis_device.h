@@ -1,0 +1,508 @@
+// Device building blocks of the gfx950 inversion kernels: counter-based
+// random stream, Faddeeva approximations, Milne-Eddington synthesis and the
+// genetic operators.  Section numbers refer to Harker & Mighell, "A
+// GPU-Computing Approach to Solar Stokes Profile Inversion".
+//
+// Mapping: one workgroup per pixel, one GA individual per lane.  Every lane
+// walks the same wavelength/component loop (trip counts are wavefront
+// uniform, component tables live in kernel arguments and are read with
+// scalar loads), the pixel's observation is broadcast from LDS, so the inner
+// loop is pure VALU work on per-lane registers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/genesis.h"
+#include "voigt_rational.h"
+#include "weideman36.h"
+
+namespace genesis {
+
+constexpr double kCkms = 299792.458;      // speed of light [km/s]
+constexpr double kZeeman = 4.6686e-13;    // Delta lambda_B / (lambda0^2 B) [1/(A G)]
+constexpr double kPi = 3.14159265358979323846;
+
+// ------------------------------------------------------------------------
+// Lines as the kernels see them.  Components are grouped b (q = -1),
+// p (q = 0), r (q = +1) so that the inner loops need no per-component branch.
+template <typename Real>
+struct DevLine {
+    Real off0;     // first sample minus lambda0 [A]
+    Real step;     // sample spacing [A]
+    Real dop_kms;  // lambda0 / c [A per km/s]
+    Real zee_G;    // 4.6686e-13 lambda0^2 [A per G]
+    int32_t nlam, off, nb, np, nr, pad_;
+    Real s[GENESIS_MAX_COMP];  // shift in units of Delta lambda_B
+    Real w[GENESIS_MAX_COMP];  // strength
+};
+
+template <typename Real>
+struct DevLines {
+    int32_t nlines, L;
+    DevLine<Real> l[GENESIS_MAX_LINES];
+};
+
+template <typename Real>
+struct alignas(4 * sizeof(Real)) Vec4 {
+    Real x, y, z, w;
+};
+
+// ------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).  Word n of the stream
+// (seed, pixel, generation, individual, purpose) is component n % 4 of the
+// block with counter (pixel, generation, individual, purpose << 24 | n / 4).
+struct Key {
+    uint32_t k0, k1;
+};
+
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        Key key)
+{
+    uint32_t k0 = key.k0, k1 = key.k1;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ uint32_t pick(uint4 b, uint32_t i)
+{
+    return i == 0 ? b.x : i == 1 ? b.y : i == 2 ? b.z : b.w;
+}
+
+// uniform integer in [0, m]: multiply-high, no rejection
+__device__ __forceinline__ uint32_t uniform_upto(uint32_t word, uint32_t m)
+{
+    return (uint32_t)(((uint64_t)word * ((uint64_t)m + 1u)) >> 32);
+}
+
+enum Purpose : uint32_t { kInit = 0, kTournament = 1, kCross = 2, kMutate = 3 };
+
+// ------------------------------------------------------------------------
+// Faddeeva function w(v + i a) -> (H, L) = (Re w, Im w) (Sec. 5: Voigt and
+// Faraday-Voigt profiles).
+//
+// FP32: w = P(Z)/Q(Z), Z = a - i v, real coefficients (deg 7 / 8), fitted on
+// Re Z = 0 (maximum error 1.6e-8, which bounds the error for every a >= 0).
+// Expanding around Z = a once per individual gives polynomials in u = v^2:
+//   P(a - i v) = EP(u) - i v OP(u),  Q(a - i v) = EQ(u) - i v OQ(u),
+// so one profile evaluation costs 14 FMAs of Horner plus one reciprocal:
+//   H = (EP EQ + u OP OQ) / (EQ^2 + u OQ^2),  L = v (EP OQ - OP EQ) / (...).
+struct VoigtF32 {
+    float ep[4], op[4], eq[5], oq[4];
+};
+
+// Taylor shift of a real polynomial: c(x) -> c(x + a), in place.
+template <int N>
+__device__ __forceinline__ void taylor_shift(double (&c)[N], double a)
+{
+#pragma unroll
+    for (int i = 0; i < N - 1; ++i)
+#pragma unroll
+        for (int j = N - 2; j >= i; --j)
+            c[j] = fma(a, c[j + 1], c[j]);
+}
+
+__device__ __forceinline__ VoigtF32 voigt_setup_f32(double a)
+{
+    double p[GENESIS_VR_NP], q[GENESIS_VR_NQ];
+#pragma unroll
+    for (int i = 0; i < GENESIS_VR_NP; ++i)
+        p[i] = genesis_vr_p[i];
+#pragma unroll
+    for (int i = 0; i < GENESIS_VR_NQ; ++i)
+        q[i] = genesis_vr_q[i];
+    taylor_shift(p, a);
+    taylor_shift(q, a);
+    VoigtF32 c;
+    // (-i v)^(2m) = (-1)^m u^m ; (-i v)^(2m+1) = -i v (-1)^m u^m
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const double sg = (m & 1) ? -1.0 : 1.0;
+        c.ep[m] = (float)(sg * p[2 * m]);
+        c.op[m] = (float)(sg * p[2 * m + 1]);
+        c.eq[m] = (float)(sg * q[2 * m]);
+        c.oq[m] = (float)(sg * q[2 * m + 1]);
+    }
+    c.eq[4] = (float)q[8];
+    return c;
+}
+
+__device__ __forceinline__ void voigt_f32(const VoigtF32 &c, float v, float &H, float &L)
+{
+    const float u = v * v;
+    const float ep = fmaf(fmaf(fmaf(c.ep[3], u, c.ep[2]), u, c.ep[1]), u, c.ep[0]);
+    const float op = fmaf(fmaf(fmaf(c.op[3], u, c.op[2]), u, c.op[1]), u, c.op[0]);
+    const float eq = fmaf(fmaf(fmaf(fmaf(c.eq[4], u, c.eq[3]), u, c.eq[2]), u, c.eq[1]), u, c.eq[0]);
+    const float oq = fmaf(fmaf(fmaf(c.oq[3], u, c.oq[2]), u, c.oq[1]), u, c.oq[0]);
+    const float den = fmaf(eq, eq, u * (oq * oq));
+    const float rc = __builtin_amdgcn_rcpf(den);
+    H = fmaf(ep, eq, u * (op * oq)) * rc;
+    L = (v * fmaf(ep, oq, -(op * eq))) * rc;
+}
+
+// FP64: Weideman's expansion with N = 36 (error ~2e-15).
+__device__ __forceinline__ void voigt_f64(double a, double v, double &H, double &L)
+{
+    const double WL = GENESIS_WD_L;
+    // d = L - i z with z = v + i a  ->  d = (WL + a) - i v ; r = 1/d
+    const double dr = WL + a, di = -v;
+    const double inv = 1.0 / fma(dr, dr, di * di);
+    const double rr = dr * inv, ri = -di * inv;
+    // Z = (L + i z) r = ((WL - a) + i v) r
+    const double nr = WL - a, ni = v;
+    const double Zr = fma(nr, rr, -(ni * ri));
+    const double Zi = fma(nr, ri, ni * rr);
+    double pr = genesis_wd_c[GENESIS_WD_N - 1], pi = 0.0;
+#pragma unroll
+    for (int n = GENESIS_WD_N - 2; n >= 0; --n) {
+        const double tr = fma(pr, Zr, fma(-pi, Zi, genesis_wd_c[n]));
+        const double ti = fma(pr, Zi, pi * Zr);
+        pr = tr;
+        pi = ti;
+    }
+    // w = r (2 p r + 1/sqrt(pi))
+    const double tr = fma(2.0, fma(pr, rr, -(pi * ri)), 0.56418958354775628695);
+    const double ti = 2.0 * fma(pr, ri, pi * rr);
+    H = fma(tr, rr, -(ti * ri));
+    L = fma(tr, ri, ti * rr);
+}
+
+// ------------------------------------------------------------------------
+// Per-individual constants of the Milne-Eddington model (Sec. 5).
+template <typename Real>
+struct Model;
+
+template <>
+struct Model<float> {
+    float B, inv_dop, vlos;
+    float cI1, cI2, cQ, cU, cV;  // eta0/2 folded into the geometry factors
+    float S0, muS1;
+    VoigtF32 vc;
+};
+
+template <>
+struct Model<double> {
+    double B, inv_dop, vlos, a;
+    double cI1, cI2, cQ, cU, cV;
+    double S0, muS1;
+};
+
+// Geometry factors of the propagation matrix (absorption eta and
+// magneto-optical rho share them):
+//   eta_I = eta0/2 [phi_p sin^2(g) + (phi_b + phi_r)(1 + cos^2(g))/2]
+//   eta_Q = eta0/2 [phi_p - (phi_b + phi_r)/2] sin^2(g) cos(2 chi)
+//   eta_U = eta0/2 [phi_p - (phi_b + phi_r)/2] sin^2(g) sin(2 chi)
+//   eta_V = eta0/2 (phi_r - phi_b) cos(g)
+template <typename Real>
+__device__ __forceinline__ void model_common(const double (&p)[GENESIS_NPAR], double mu,
+                                             Model<Real> &m)
+{
+    const double g = p[1] * (kPi / 180.0), chi = p[2] * (kPi / 180.0);
+    double sg, cg, s2x, c2x;
+    sincos(g, &sg, &cg);
+    sincos(2.0 * chi, &s2x, &c2x);
+    const double h = 0.5 * p[6];
+    const double sg2 = sg * sg;
+    m.B = (Real)p[0];
+    m.inv_dop = (Real)(1.0 / p[4]);
+    m.vlos = (Real)p[3];
+    m.cI1 = (Real)(h * sg2);
+    m.cI2 = (Real)(0.5 * h * (1.0 + cg * cg));
+    m.cQ = (Real)(h * sg2 * c2x);
+    m.cU = (Real)(h * sg2 * s2x);
+    m.cV = (Real)(h * cg);
+    m.S0 = (Real)p[7];
+    m.muS1 = (Real)(mu * p[8]);
+}
+
+__device__ __forceinline__ void model_setup(const double (&p)[GENESIS_NPAR], double mu,
+                                            Model<float> &m)
+{
+    model_common(p, mu, m);
+    m.vc = voigt_setup_f32(p[5]);
+}
+
+__device__ __forceinline__ void model_setup(const double (&p)[GENESIS_NPAR], double mu,
+                                            Model<double> &m)
+{
+    model_common(p, mu, m);
+    m.a = p[5];
+}
+
+__device__ __forceinline__ void profile(const Model<float> &m, float v, float &H, float &L)
+{
+    voigt_f32(m.vc, v, H, L);
+}
+
+__device__ __forceinline__ void profile(const Model<double> &m, double v, double &H, double &L)
+{
+    voigt_f64(m.a, v, H, L);
+}
+
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
+// Walk every wavelength of every line and hand (j, I, Q, U, V) to `sink`.
+// Unno-Rachkovsky closed form with k = 1 + eta_I,
+//   Pi = eta.rho, Delta = k^2 (k^2 - |eta|^2 + |rho|^2) - Pi^2,
+//   I = S0 + mu S1 k (k^2 + |rho|^2) / Delta,
+//   Q = -mu S1 [k^2 eta_Q + k (eta_V rho_U - eta_U rho_V) + rho_Q Pi] / Delta
+//   (U, V by cyclic permutation Q -> U -> V),
+// i.e. S0 e + mu S1 K^-1 e for K = 1 + eta0 Phi.
+template <typename Real, typename Sink>
+__device__ __forceinline__ void synthesize(const Model<Real> &m, const DevLines<Real> &ls,
+                                           Sink &sink)
+{
+    for (int l = 0; l < ls.nlines; ++l) {
+        const DevLine<Real> &ln = ls.l[l];
+        const Real xb = (ln.off0 - m.vlos * ln.dop_kms) * m.inv_dop;
+        const Real xs = ln.step * m.inv_dop;
+        const Real zb = ln.zee_G * m.B * m.inv_dop;
+        const int e_b = ln.nb, e_p = ln.nb + ln.np, e_r = ln.nb + ln.np + ln.nr;
+        for (int j = 0; j < ln.nlam; ++j) {
+            const Real x0 = fma((Real)j, xs, xb);
+            Real hb = 0, lb = 0, hp = 0, lp = 0, hr = 0, lr = 0;
+            for (int c = 0; c < e_b; ++c) {
+                Real H, L;
+                profile(m, fma(-ln.s[c], zb, x0), H, L);
+                hb = fma(ln.w[c], H, hb);
+                lb = fma(ln.w[c], L, lb);
+            }
+            for (int c = e_b; c < e_p; ++c) {
+                Real H, L;
+                profile(m, fma(-ln.s[c], zb, x0), H, L);
+                hp = fma(ln.w[c], H, hp);
+                lp = fma(ln.w[c], L, lp);
+            }
+            for (int c = e_p; c < e_r; ++c) {
+                Real H, L;
+                profile(m, fma(-ln.s[c], zb, x0), H, L);
+                hr = fma(ln.w[c], H, hr);
+                lr = fma(ln.w[c], L, lr);
+            }
+            const Real hs = hb + hr, ls_ = lb + lr;
+            const Real ht = fma((Real)-0.5, hs, hp), lt = fma((Real)-0.5, ls_, lp);
+            const Real eI = fma(m.cI1, hp, m.cI2 * hs);
+            const Real eQ = m.cQ * ht, eU = m.cU * ht, eV = m.cV * (hr - hb);
+            const Real rQ = m.cQ * lt, rU = m.cU * lt, rV = m.cV * (lr - lb);
+            const Real k = (Real)1 + eI;
+            const Real k2 = k * k;
+            const Real e2 = fma(eQ, eQ, fma(eU, eU, eV * eV));
+            const Real r2 = fma(rQ, rQ, fma(rU, rU, rV * rV));
+            const Real Pi = fma(eQ, rQ, fma(eU, rU, eV * rV));
+            const Real D = fma(k2, k2 - e2 + r2, -(Pi * Pi));
+            const Real rD = m.muS1 * recip(D);
+            const Real I = fma(k * (k2 + r2), rD, m.S0);
+            const Real Q = -fma(k2, eQ, fma(k, fma(eV, rU, -(eU * rV)), rQ * Pi)) * rD;
+            const Real U = -fma(k2, eU, fma(k, fma(eQ, rV, -(eV * rQ)), rU * Pi)) * rD;
+            const Real V = -fma(k2, eV, fma(k, fma(eU, rQ, -(eQ * rU)), rV * Pi)) * rD;
+            sink(ln.off + j, I, Q, U, V);
+        }
+    }
+}
+
+// chi-square accumulator against an observation staged in LDS as
+// [L] x (I, Q, U, V): per-Stokes sums of squared residuals, combined with the
+// weights 1/sigma^2 at the end (Sec. 5 merit function).
+template <typename Real>
+struct Chi2Sink {
+    const Vec4<Real> *obs;
+    Real sI, sQ, sU, sV;
+    __device__ __forceinline__ void operator()(int j, Real I, Real Q, Real U, Real V)
+    {
+        const Vec4<Real> o = obs[j];
+        const Real dI = o.x - I, dQ = o.y - Q, dU = o.z - U, dV = o.w - V;
+        sI = fma(dI, dI, sI);
+        sQ = fma(dQ, dQ, sQ);
+        sU = fma(dU, dU, sU);
+        sV = fma(dV, dV, sV);
+    }
+};
+
+template <typename Real>
+__device__ __forceinline__ Real chi2_of(const Model<Real> &m, const DevLines<Real> &ls,
+                                        const Vec4<Real> *obs_lds, const Real (&w2)[4],
+                                        Real inv_nu)
+{
+    Chi2Sink<Real> s{obs_lds, 0, 0, 0, 0};
+    synthesize(m, ls, s);
+    return fma(w2[0], s.sI, fma(w2[1], s.sQ, fma(w2[2], s.sU, w2[3] * s.sV))) * inv_nu;
+}
+
+// ------------------------------------------------------------------------
+// Decoding operator E^-1 (Sec. 3): p = lo + (hi - lo) g / 65535, in FP64.
+struct Bounds {
+    double lo[GENESIS_NPAR], span[GENESIS_NPAR];
+};
+
+__device__ __forceinline__ void decode(const uint32_t (&g)[GENESIS_NPAR], const Bounds &b,
+                                       double (&p)[GENESIS_NPAR])
+{
+#pragma unroll
+    for (int j = 0; j < GENESIS_NPAR; ++j)
+        p[j] = b.lo[j] + b.span[j] * (double)g[j] / 65535.0;
+}
+
+// ------------------------------------------------------------------------
+// Genetic operators (Sec. 3; genes as 16-bit integers, Sec. 4.2).
+struct GaConst {
+    int32_t pop, k;
+    uint64_t thr_cross;          // crossover iff word < thr_cross (thr in [0, 2^32])
+    uint32_t mut_thr[16];        // bit k (0 = MSB) flips iff 16-bit uniform < mut_thr[k]
+    Key key;
+    uint32_t pixel_base;
+};
+
+// fitness order: NaN reads as +infinity, ties go to the lower index
+template <typename Real>
+__device__ __forceinline__ Real fit_key(Real f)
+{
+    return isnan(f) ? (Real)INFINITY : f;
+}
+
+template <typename Real>
+__device__ __forceinline__ bool before(Real fa, int ia, Real fb, int ib)
+{
+    return fa < fb || (fa == fb && ia < ib);
+}
+
+// Tournament of k distinct contestants drawn by Floyd's algorithm from the
+// words which*k .. which*k + k - 1 of stream (pixel, gen, pair, 1).
+template <typename Real>
+__device__ __forceinline__ int tournament(const Real *fit_s, int pop, int k, Key key,
+                                          uint32_t pixel, uint32_t gen, uint32_t pair, int which)
+{
+    int chosen[GENESIS_MAX_K];
+    int best = 0;
+    Real bestf = (Real)INFINITY;
+    uint32_t blk_id = 0xFFFFFFFFu;
+    uint4 blk = make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < GENESIS_MAX_K; ++i) {
+        if (i < k) {
+            const uint32_t n = (uint32_t)(which * k + i);
+            if ((n >> 2) != blk_id) {
+                blk_id = n >> 2;
+                blk = philox(pixel, gen, pair, (kTournament << 24) | blk_id, key);
+            }
+            const int j = pop - k + i;
+            int t = (int)uniform_upto(pick(blk, n & 3u), (uint32_t)j);
+            bool seen = false;
+#pragma unroll
+            for (int c = 0; c < GENESIS_MAX_K; ++c)
+                if (c < i && chosen[c] == t)
+                    seen = true;
+            t = seen ? j : t;
+            chosen[i] = t;
+            const Real f = fit_key(fit_s[t]);
+            if (i == 0 || before(f, t, bestf, best)) {
+                best = t;
+                bestf = f;
+            }
+        }
+    }
+    return best;
+}
+
+__device__ __forceinline__ uint32_t first_parent_mask(int j, int x)
+{
+    const int lo = j * 16;
+    if (x >= lo + 16)
+        return 0xFFFFu;
+    if (x <= lo)
+        return 0u;
+    return (0xFFFFu << (16 - (x - lo))) & 0xFFFFu;
+}
+
+// Child of slot c >= 1 (child (c-1)%2 of pair (c-1)/2) of generation gen.
+// genes_s is the parent population in LDS as [9][pop]; `out` receives
+// out.meta(parent A, parent B, crossover point) and out.gene(j, gene, mask).
+template <typename Real, typename Out>
+__device__ __forceinline__ void make_child(int c, uint32_t pixel, uint32_t gen,
+                                           const Real *fit_s, const uint16_t *genes_s,
+                                           const GaConst &ga, Out &out)
+{
+    const int pop = ga.pop;
+    const uint32_t pair = (uint32_t)((c - 1) >> 1);
+    const bool second = ((c - 1) & 1) != 0;
+    const int A = tournament(fit_s, pop, ga.k, ga.key, pixel, gen, pair, 0);
+    const int B = tournament(fit_s, pop, ga.k, ga.key, pixel, gen, pair, 1);
+    const uint4 cw = philox(pixel, gen, pair, kCross << 24, ga.key);
+    const bool cross = (uint64_t)cw.x < ga.thr_cross;
+    const int x = cross ? 1 + (int)uniform_upto(cw.y, GENESIS_NPAR * 16 - 2) : 0;
+    const int first = second ? B : A, other = second ? A : B;
+    out.meta(A, B, x);
+#pragma unroll 1
+    for (int j = 0; j < GENESIS_NPAR; ++j) {
+        const uint32_t m = cross ? first_parent_mask(j, x) : 0xFFFFu;
+        const uint32_t g1 = genes_s[j * pop + first], g2 = genes_s[j * pop + other];
+        const uint32_t child = (g1 & m) | (g2 & (~m & 0xFFFFu));
+        // mutation: block 2j + h of stream (pixel, gen, c, 3) holds the 16-bit
+        // uniforms of bits 8h .. 8h + 7 of gene j (low half of a word first)
+        uint32_t mk = 0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint4 b = philox(pixel, gen, (uint32_t)c,
+                                   (kMutate << 24) | (uint32_t)(2 * j + h), ga.key);
+            const uint32_t wds[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int kb = 8 * h + q;
+                const uint32_t wd = wds[q >> 1];
+                const uint32_t u16 = (q & 1) ? (wd >> 16) : (wd & 0xFFFFu);
+                mk |= (u16 < ga.mut_thr[kb]) ? (1u << (15 - kb)) : 0u;
+            }
+        }
+        out.gene(j, child ^ mk, mk);
+    }
+}
+
+// Block-wide argmin of fit_s[0 .. pop) (NaN = +inf, ties to the lower index);
+// every thread gets the result.  red_f/red_i: LDS scratch of one entry per
+// wavefront.
+template <typename Real>
+__device__ __forceinline__ int block_argmin(const Real *fit_s, int pop, Real *red_f, int *red_i)
+{
+    const int tid = threadIdx.x;
+    Real f = tid < pop ? fit_key(fit_s[tid]) : (Real)INFINITY;
+    int idx = tid < pop ? tid : 0x7FFFFFFF;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const Real f2 = __shfl_xor(f, off);
+        const int i2 = __shfl_xor(idx, off);
+        if (before(f2, i2, f, idx)) {
+            f = f2;
+            idx = i2;
+        }
+    }
+    if ((tid & 63) == 0) {
+        red_f[tid >> 6] = f;
+        red_i[tid >> 6] = idx;
+    }
+    __syncthreads();
+    const int nw = (int)(blockDim.x >> 6);
+    f = red_f[0];
+    idx = red_i[0];
+    for (int w = 1; w < nw; ++w)
+        if (before(red_f[w], red_i[w], f, idx)) {
+            f = red_f[w];
+            idx = red_i[w];
+        }
+    return idx;
+}
+
+}  // namespace genesis
