@@ -1,0 +1,217 @@
+"""Benchmark: GA Milne-Eddington inversion of a synthetic slit row on one MI355X.
+
+One step = one ga_invert launch over the whole workload (every pixel runs the
+full genetic algorithm: init, evaluate, then G generations of selection,
+crossover, mutation, decode and evaluate).  Inputs are resident in HBM before
+the timed region.  Prints ONE JSON line.
+
+Workload (default, 'slit'): 2048 pixels x 2 lines (Fe I 6301.5 full 12-component
+pattern, Fe I 6302.5 triplet) x 128 samples over +-0.4 A, FP32, population 128,
+200 generations, tournament 4, mutation rate 0.05, crossover 0.85; truth drawn
+from the priors, observations synthesised by the library's forward model
+(noise-free, so that the recovered-parameter accuracy can be gated).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pixel inversions/s at fixed param accuracy; ME evals/s vs VALU peak; p99 tile ms"
+
+# Algorithmic FP32 work of the implemented formulas (FMA = 2 flops, reciprocal
+# = 1): per Zeeman component and wavelength (reduced wavelength, rational
+# Faddeeva in v^2, accumulation) and per wavelength (propagation matrix,
+# Unno-Rachkovsky closed form, chi-square terms).
+FLOP_PER_COMP_LAMBDA = 48
+FLOP_PER_LAMBDA = 86
+PEAK_FP32_VALU = 157.3e12     # MI355X published FP32 vector peak
+PEAK_FP64_VALU = 78.6e12
+
+
+def workload(name):
+    import synth_inputs as si
+    if name == "slit":
+        return dict(name=name, npix=2048, lines="slit", pop=128, generations=200, k=4,
+                    p_mut=0.05, p_cross=0.85, seed=0, dtype="f32")
+    if name == "tiny":
+        return dict(name=name, npix=64, lines="tiny", pop=64, generations=100, k=4,
+                    p_mut=0.05, p_cross=0.85, seed=0, dtype="f64")
+    raise SystemExit("unknown workload %s" % name)
+
+
+def flops_per_eval(lines):
+    f = 0
+    for ln, g in lines:
+        f += g.n * (ln.ncomp * FLOP_PER_COMP_LAMBDA + FLOP_PER_LAMBDA)
+    return f
+
+
+def describe(w, lines):
+    parts = []
+    for ln, g in lines:
+        parts.append("%.4f A (%d comp) x %d" % (ln.lambda0_A, ln.ncomp, g.n))
+    return ("%s: %d px x [%s], pop %d, G %d, k %d, p_mut %.2f, p_cross %.2f, %s"
+            % (w["name"], w["npix"], "; ".join(parts), w["pop"], w["generations"], w["k"],
+               w["p_mut"], w["p_cross"], w["dtype"].upper()))
+
+
+def cpu_baseline(w, truth, olines, budget_s=20.0):
+    """The FP64 oracle's GA on a bounded sample of the same workload, on the
+    host cores: `nthr` pixels (their observations synthesised by the oracle
+    itself), generations chosen so the run takes roughly `budget_s`; scaled
+    to full inversions per second."""
+    import oracle
+    import synth_inputs as si
+    nthr = oracle.num_threads()
+    npx = min(max(nthr, 1), w["npix"])
+    obs_np = oracle.me_synth(truth[:npx], olines)
+    sig_np = si.sigma_for(truth[:npx])
+    # probe: one generation
+    t0 = time.perf_counter()
+    oracle.ga_invert(obs_np[:npx], sig_np[:npx], olines, si.PRIOR_LO, si.PRIOR_HI,
+                     pop=w["pop"], generations=0, k=w["k"], p_cross=w["p_cross"],
+                     p_mut=w["p_mut"], seed=w["seed"])
+    t_gen = time.perf_counter() - t0
+    gs = int(max(0, min(w["generations"], budget_s / max(t_gen, 1e-6) - 1)))
+    t0 = time.perf_counter()
+    oracle.ga_invert(obs_np[:npx], sig_np[:npx], olines, si.PRIOR_LO, si.PRIOR_HI,
+                     pop=w["pop"], generations=gs, k=w["k"], p_cross=w["p_cross"],
+                     p_mut=w["p_mut"], seed=w["seed"])
+    dt = time.perf_counter() - t0
+    frac = (gs + 1) / (w["generations"] + 1)
+    return {"value": npx * frac / dt, "unit": "pixels/s", "cores": nthr, "kind": "oracle",
+            "sample": "%d pixels x %d of %d generations (pop %d) of the same workload, FP64 "
+                      "oracle with OpenMP over pixels, %.1f s; rate scaled by (G+1)"
+                      % (npx, gs + 1, w["generations"] + 1, w["pop"], dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="slit")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (3 times) so that "
+                         "HBM byte counters can be scaled against a kernel of known traffic")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; pixels are independent, so N GPUs would "
+              "each invert their own share (see the design notes). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.calibrate_copy_mib:
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}), flush=True)
+        return
+    import paper_1208_0302_amd as g
+    import synth_inputs as si
+
+    w = workload(args.workload)
+    dev = torch.device("cuda:0")
+    dt = torch.float32 if w["dtype"] == "f32" else torch.float64
+    specs = si.line_set(w["lines"])
+    lines, grids = [], []
+    for ln, n in specs:
+        start, step = si.grid(ln, n)
+        lines.append(g.line_from_terms(ln["lambda0"], ln["Jl"], ln["gl"], ln["Ju"], ln["gu"]))
+        grids.append(g.grid(start, step, n))
+    truth = si.draw_truth(w["npix"], seed=w["seed"])
+    truth_t = torch.tensor(truth, dtype=dt, device=dev)
+    obs = g.me_synth(truth_t, lines, grids)                     # noise-free observations
+    sig = torch.tensor(si.sigma_for(truth), dtype=dt, device=dev)
+    b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
+    cfg = g.GAConfig(pop=w["pop"], generations=w["generations"], tournament_k=w["k"],
+                     p_cross=w["p_cross"], p_mut=w["p_mut"], seed=w["seed"])
+    torch.cuda.synchronize()
+
+    for i in range(args.warmup):
+        res = g.ga_invert(obs, sig, lines, grids, b, cfg)
+        print("warmup %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream(dev)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        evs[i][0].record(stream)
+        res = g.ga_invert(obs, sig, lines, grids, b, cfg)
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = np.array([a.elapsed_time(z) for a, z in evs])
+    print("steps done: kernel ms %s" % np.round(kern_ms, 3).tolist(), file=sys.stderr, flush=True)
+
+    # accuracy on the noise-free truth (the gate: p90 |dB| <= 10 G)
+    bp = res["params"].double().cpu().numpy()
+    dB = np.abs(bp[:, 0] - truth[:, 0])
+    acc = {"p50_abs_dB_G": float(np.percentile(dB, 50)),
+           "p90_abs_dB_G": float(np.percentile(dB, 90)),
+           "p99_abs_dB_G": float(np.percentile(dB, 99)),
+           "gate_p90_dB_le_10G": bool(np.percentile(dB, 90) <= 10.0),
+           "median_chi2": float(res["chi2"].double().median().item())}
+
+    npix = w["npix"]
+    evals = npix * w["pop"] * (w["generations"] + 1)
+    fpe = flops_per_eval(list(zip(lines, grids)))
+    flop_launch = evals * fpe
+    mean_s = float(kern_ms.mean()) / 1e3
+    achieved = flop_launch / mean_s
+    peak = PEAK_FP32_VALU if dt == torch.float32 else PEAK_FP64_VALU
+    out = {
+        "metric": METRIC,
+        "value": npix * args.steps / wall,
+        "unit": "pixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": w["dtype"],
+        "data": "synthetic (truth from the priors, noise-free observations from the forward model)",
+        "config": {"workload": describe(w, list(zip(lines, grids))), "npix": npix,
+                   "pop": w["pop"], "generations": w["generations"], "seed": w["seed"]},
+        "me_evals_per_s": evals * args.steps / wall,
+        "tile_ms_p50": float(np.percentile(kern_ms, 50)),
+        "tile_ms_p99": float(np.percentile(kern_ms, 99)),
+        "accuracy": acc,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "kernel": "k_ga_invert<%s>" % ("float" if dt == torch.float32 else "double"),
+                     "flop_per_eval": fpe, "evals_per_launch": evals},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        olines = []
+        for ln, n in specs:
+            start, step = si.grid(ln, n)
+            olines.append(oracle.make_line(ln["lambda0"], ln["Jl"], ln["gl"], ln["Ju"], ln["gu"],
+                                           start, step, n))
+        out["cpu_baseline"] = cpu_baseline(w, truth, olines, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -3,7 +3,10 @@
 Forward model: FP32 within 1e-5 of the continuum intensity Ic = S0 + mu S1 at
 every sample (the FP32 rational Voigt approximation is good to 1.6e-8 and its
 FP32 evaluation to ~4e-7, which moves profiles by < 1e-6 Ic), FP64 within
-1e-12 Ic.  Integer genetic operators: bit-exact.  The whole inversion: the
+1e-10 Ic: the oracle forms lambda_j - lambda_c from absolute wavelengths near
+6302 A, whose FP64 rounding (ulp 9e-13 A) over the narrowest Doppler width
+(0.02 A) moves v by 4.5e-11, and |dI/dv| <= 0.92 mu S1.  Integer genetic
+operators: bit-exact.  The whole inversion: the
 fused single-launch loop equals the step-by-step composition of the library's
 own operator entry points bit for bit, and every number it reports agrees with
 the oracle re-evaluated on it.
@@ -24,7 +27,7 @@ if gpu_available():
 
 DEV = "cuda"
 FWD_TOL_F32 = 1e-5
-FWD_TOL_F64 = 1e-12
+FWD_TOL_F64 = 1e-10
 
 
 def _setup(kind, nlam=None):
@@ -310,8 +313,13 @@ def test_f64_loop_tracks_the_oracle():
     same = [np.array_equal(r["genes"][p].cpu().numpy(), ref["genes"][p]) for p in range(16)]
     print("pixels with identical final populations: %d / 16" % sum(same))
     assert sum(same) >= 12
+    # identical genotypes: chi-square within the FP64 forward-model bound
+    bp = r["params"].cpu().numpy()
+    L = obs.shape[-1]
+    models = oracle.me_synth(bp, olines)[:, None]
+    tol = _chi2_tol(obs, models, sig, _ic(truth), 4 * L - 9, FWD_TOL_F64)[:, 0]
     for p in np.nonzero(same)[0]:
-        assert abs(r["chi2"][p].item() - ref["chi2"][p]) <= 1e-10 * max(ref["chi2"][p], 1.0)
+        assert abs(r["chi2"][p].item() - ref["chi2"][p]) <= tol[p]
 
 
 @pytest.mark.parametrize("kind", ["tiny", "slit"])
