@@ -105,53 +105,73 @@ struct VoigtF32 {
     float ep[4], op[4], eq[5], oq[4];
 };
 
-// Taylor shift of a real polynomial: c(x) -> c(x + a), in place.
+// Coefficients of c(x + a) = sum_k r_k x^k: r_k = sum_{m >= k} C(m, k) c_m a^(m-k),
+// each evaluated by its own Horner scheme in a (few live registers).
 template <int N>
-__device__ __forceinline__ void taylor_shift(double (&c)[N], double a)
+struct ShiftTable {
+    double t[N][N];  // t[k][m - k] = C(m, k) c_m
+};
+
+template <int N>
+constexpr ShiftTable<N> shift_table(const double (&c)[N])
 {
+    ShiftTable<N> s{};
+    for (int k = 0; k < N; ++k) {
+        double binom = 1.0;  // C(m, k) for m = k
+        for (int m = k; m < N; ++m) {
+            s.t[k][m - k] = binom * c[m];
+            binom = binom * (double)(m + 1) / (double)(m + 1 - k);
+        }
+    }
+    return s;
+}
+
+constexpr double kVrP[GENESIS_VR_NP] = {GENESIS_VR_P_INIT};
+constexpr double kVrQ[GENESIS_VR_NQ] = {GENESIS_VR_Q_INIT};
+constexpr ShiftTable<GENESIS_VR_NP> kShiftP = shift_table(kVrP);
+constexpr ShiftTable<GENESIS_VR_NQ> kShiftQ = shift_table(kVrQ);
+
+template <int N>
+__device__ __forceinline__ float shifted(const ShiftTable<N> &s, int k, double a)
+{
+    double r = s.t[k][N - 1 - k];
 #pragma unroll
-    for (int i = 0; i < N - 1; ++i)
-#pragma unroll
-        for (int j = N - 2; j >= i; --j)
-            c[j] = fma(a, c[j + 1], c[j]);
+    for (int i = N - 2 - k; i >= 0; --i)
+        r = fma(r, a, s.t[k][i]);
+    return (float)r;
 }
 
 __device__ __forceinline__ VoigtF32 voigt_setup_f32(double a)
 {
-    double p[GENESIS_VR_NP], q[GENESIS_VR_NQ];
-#pragma unroll
-    for (int i = 0; i < GENESIS_VR_NP; ++i)
-        p[i] = genesis_vr_p[i];
-#pragma unroll
-    for (int i = 0; i < GENESIS_VR_NQ; ++i)
-        q[i] = genesis_vr_q[i];
-    taylor_shift(p, a);
-    taylor_shift(q, a);
     VoigtF32 c;
     // (-i v)^(2m) = (-1)^m u^m ; (-i v)^(2m+1) = -i v (-1)^m u^m
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        const double sg = (m & 1) ? -1.0 : 1.0;
-        c.ep[m] = (float)(sg * p[2 * m]);
-        c.op[m] = (float)(sg * p[2 * m + 1]);
-        c.eq[m] = (float)(sg * q[2 * m]);
-        c.oq[m] = (float)(sg * q[2 * m + 1]);
+        const float sg = (m & 1) ? -1.0f : 1.0f;
+        c.ep[m] = sg * shifted(kShiftP, 2 * m, a);
+        c.op[m] = sg * shifted(kShiftP, 2 * m + 1, a);
+        c.eq[m] = sg * shifted(kShiftQ, 2 * m, a);
+        c.oq[m] = sg * shifted(kShiftQ, 2 * m + 1, a);
     }
-    c.eq[4] = (float)q[8];
+    c.eq[4] = shifted(kShiftQ, 8, a);
     return c;
 }
 
-__device__ __forceinline__ void voigt_f32(const VoigtF32 &c, float v, float &H, float &L)
+// h += w H(v), l += w L(v): 13 FMAs of Horner, one reciprocal, and the
+// strength folded into the reciprocal; u OQ is shared by numerator and
+// denominator.
+__device__ __forceinline__ void voigt_acc_f32(const VoigtF32 &c, float v, float w, float &h,
+                                              float &l)
 {
     const float u = v * v;
     const float ep = fmaf(fmaf(fmaf(c.ep[3], u, c.ep[2]), u, c.ep[1]), u, c.ep[0]);
     const float op = fmaf(fmaf(fmaf(c.op[3], u, c.op[2]), u, c.op[1]), u, c.op[0]);
     const float eq = fmaf(fmaf(fmaf(fmaf(c.eq[4], u, c.eq[3]), u, c.eq[2]), u, c.eq[1]), u, c.eq[0]);
     const float oq = fmaf(fmaf(fmaf(c.oq[3], u, c.oq[2]), u, c.oq[1]), u, c.oq[0]);
-    const float den = fmaf(eq, eq, u * (oq * oq));
-    const float rc = __builtin_amdgcn_rcpf(den);
-    H = fmaf(ep, eq, u * (op * oq)) * rc;
-    L = (v * fmaf(ep, oq, -(op * eq))) * rc;
+    const float uoq = u * oq;
+    const float wr = w * __builtin_amdgcn_rcpf(fmaf(eq, eq, oq * uoq));
+    h = fmaf(fmaf(ep, eq, op * uoq), wr, h);
+    l = fmaf(v * fmaf(ep, oq, -(op * eq)), wr, l);
 }
 
 // FP64: Weideman's expansion with N = 36 (error ~2e-15).
@@ -181,6 +201,14 @@ __device__ __forceinline__ void voigt_f64(double a, double v, double &H, double 
     L = fma(tr, ri, ti * rr);
 }
 
+__device__ __forceinline__ void voigt_acc_f64(double a, double v, double w, double &h, double &l)
+{
+    double H, L;
+    voigt_f64(a, v, H, L);
+    h = fma(w, H, h);
+    l = fma(w, L, l);
+}
+
 // ------------------------------------------------------------------------
 // Per-individual constants of the Milne-Eddington model (Sec. 5).
 template <typename Real>
@@ -189,7 +217,7 @@ struct Model;
 template <>
 struct Model<float> {
     float B, inv_dop, vlos;
-    float cI1, cI2, cQ, cU, cV;  // eta0/2 folded into the geometry factors
+    float cI1, cI2, cQ, cU, cV, c2;  // eta0/2 folded in; c2 = cQ^2 + cU^2
     float S0, muS1;
     VoigtF32 vc;
 };
@@ -197,7 +225,7 @@ struct Model<float> {
 template <>
 struct Model<double> {
     double B, inv_dop, vlos, a;
-    double cI1, cI2, cQ, cU, cV;
+    double cI1, cI2, cQ, cU, cV, c2;
     double S0, muS1;
 };
 
@@ -225,6 +253,7 @@ __device__ __forceinline__ void model_common(const double (&p)[GENESIS_NPAR], do
     m.cQ = (Real)(h * sg2 * c2x);
     m.cU = (Real)(h * sg2 * s2x);
     m.cV = (Real)(h * cg);
+    m.c2 = (Real)(h * sg2 * h * sg2);
     m.S0 = (Real)p[7];
     m.muS1 = (Real)(mu * p[8]);
 }
@@ -232,7 +261,24 @@ __device__ __forceinline__ void model_common(const double (&p)[GENESIS_NPAR], do
 __device__ __forceinline__ void model_setup(const double (&p)[GENESIS_NPAR], double mu,
                                             Model<float> &m)
 {
-    model_common(p, mu, m);
+    // FP32 model: angles, geometry and Voigt coefficients in FP32 after the
+    // FP64 decode (keeps the per-individual set-up register-light)
+    float sg, cg, s2x, c2x;
+    sincosf((float)(p[1] * (kPi / 180.0)), &sg, &cg);
+    sincosf((float)(p[2] * (kPi / 90.0)), &s2x, &c2x);
+    const float h = 0.5f * (float)p[6];
+    const float sg2 = sg * sg;
+    m.B = (float)p[0];
+    m.inv_dop = (float)(1.0 / p[4]);
+    m.vlos = (float)p[3];
+    m.cI1 = h * sg2;
+    m.cI2 = 0.5f * h * fmaf(cg, cg, 1.0f);
+    m.cQ = h * sg2 * c2x;
+    m.cU = h * sg2 * s2x;
+    m.cV = h * cg;
+    m.c2 = (h * sg2) * (h * sg2);
+    m.S0 = (float)p[7];
+    m.muS1 = (float)(mu * p[8]);
     m.vc = voigt_setup_f32(p[5]);
 }
 
@@ -243,75 +289,104 @@ __device__ __forceinline__ void model_setup(const double (&p)[GENESIS_NPAR], dou
     m.a = p[5];
 }
 
-__device__ __forceinline__ void profile(const Model<float> &m, float v, float &H, float &L)
+__device__ __forceinline__ void profile_acc(const Model<float> &m, float v, float w, float &h,
+                                            float &l)
 {
-    voigt_f32(m.vc, v, H, L);
+    voigt_acc_f32(m.vc, v, w, h, l);
 }
 
-__device__ __forceinline__ void profile(const Model<double> &m, double v, double &H, double &L)
+__device__ __forceinline__ void profile_acc(const Model<double> &m, double v, double w,
+                                            double &h, double &l)
 {
-    voigt_f64(m.a, v, H, L);
+    voigt_acc_f64(m.a, v, w, h, l);
 }
 
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
-// Walk every wavelength of every line and hand (j, I, Q, U, V) to `sink`.
+// Components of one Zeeman group at wavelength offset x0 (reduced units):
+// accumulate strength-weighted H and L.  N >= 0: compile-time count (the
+// component table then sits in scalar registers for the whole line);
+// N < 0: runtime count n.
+template <int N, typename Real>
+__device__ __forceinline__ void group(const Model<Real> &m, const DevLine<Real> &ln, int c0,
+                                      int n, Real x0, Real zb, Real &h, Real &l)
+{
+    if constexpr (N >= 0) {
+#pragma unroll
+        for (int c = 0; c < N; ++c)
+            profile_acc(m, fma(-ln.s[c0 + c], zb, x0), ln.w[c0 + c], h, l);
+    } else {
+        for (int c = c0; c < c0 + n; ++c)
+            profile_acc(m, fma(-ln.s[c], zb, x0), ln.w[c], h, l);
+    }
+}
+
+// One line: every wavelength, handing (j, I, Q, U, V) to `sink`.
 // Unno-Rachkovsky closed form with k = 1 + eta_I,
 //   Pi = eta.rho, Delta = k^2 (k^2 - |eta|^2 + |rho|^2) - Pi^2,
 //   I = S0 + mu S1 k (k^2 + |rho|^2) / Delta,
 //   Q = -mu S1 [k^2 eta_Q + k (eta_V rho_U - eta_U rho_V) + rho_Q Pi] / Delta
 //   (U, V by cyclic permutation Q -> U -> V),
-// i.e. S0 e + mu S1 K^-1 e for K = 1 + eta0 Phi.
+// i.e. S0 e + mu S1 K^-1 e for K = 1 + eta0 Phi.  Because eta_Q, eta_U,
+// rho_Q, rho_U share the azimuth factors (eta_Q = cQ h_t, rho_Q = cQ l_t,
+// eta_U = cU h_t, rho_U = cU l_t), eta_U rho_Q - eta_Q rho_U = 0 and, with
+// c2 = cQ^2 + cU^2, X = eta_V l_t - h_t rho_V, A = k^2 h_t + l_t Pi:
+//   |eta|^2 = c2 h_t^2 + eta_V^2, |rho|^2 = c2 l_t^2 + rho_V^2,
+//   Pi = c2 h_t l_t + eta_V rho_V,
+//   Q = -mu S1 (cQ A + cU k X) / Delta, U = -mu S1 (cU A - cQ k X) / Delta,
+//   V = -mu S1 (k^2 eta_V + rho_V Pi) / Delta.
+template <int NB, int NP, int NR, typename Real, typename Sink>
+__device__ __forceinline__ void synth_line(const Model<Real> &m, const DevLine<Real> &ln,
+                                           Sink &sink)
+{
+    const Real xb = (ln.off0 - m.vlos * ln.dop_kms) * m.inv_dop;
+    const Real xs = ln.step * m.inv_dop;
+    const Real zb = ln.zee_G * m.B * m.inv_dop;
+    const int nb = NB >= 0 ? NB : ln.nb, np = NP >= 0 ? NP : ln.np;
+    const int nr = NR >= 0 ? NR : ln.nr;
+    for (int j = 0; j < ln.nlam; ++j) {
+        const Real x0 = fma((Real)j, xs, xb);
+        Real hb = 0, lb = 0, hp = 0, lp = 0, hr = 0, lr = 0;
+        group<NB>(m, ln, 0, nb, x0, zb, hb, lb);
+        group<NP>(m, ln, nb, np, x0, zb, hp, lp);
+        group<NR>(m, ln, nb + np, nr, x0, zb, hr, lr);
+        const Real hs = hb + hr, ls_ = lb + lr;
+        const Real ht = fma((Real)-0.5, hs, hp), lt = fma((Real)-0.5, ls_, lp);
+        const Real eI = fma(m.cI1, hp, m.cI2 * hs);
+        const Real eV = m.cV * (hr - hb), rV = m.cV * (lr - lb);
+        const Real k = (Real)1 + eI;
+        const Real k2 = k * k;
+        const Real e2 = fma(ht * ht, m.c2, eV * eV);
+        const Real r2 = fma(lt * lt, m.c2, rV * rV);
+        const Real Pi = fma(ht * lt, m.c2, eV * rV);
+        const Real D = fma(k2, k2 - e2 + r2, -(Pi * Pi));
+        const Real nrD = -(m.muS1 * recip(D));
+        const Real I = fma(-(k * (k2 + r2)), nrD, m.S0);
+        const Real X = fma(eV, lt, -(ht * rV));
+        const Real kX = k * X;
+        const Real A = fma(k2, ht, lt * Pi);
+        const Real Q = fma(m.cQ, A, m.cU * kX) * nrD;
+        const Real U = fma(m.cU, A, -(m.cQ * kX)) * nrD;
+        const Real V = fma(k2, eV, rV * Pi) * nrD;
+        sink(ln.off + j, I, Q, U, V);
+    }
+}
+
+// Every line; the two Zeeman patterns of the Fe I 6302 pair (a triplet and
+// the 4 + 4 + 4 pattern of 6301.5) get compile-time component counts.
 template <typename Real, typename Sink>
 __device__ __forceinline__ void synthesize(const Model<Real> &m, const DevLines<Real> &ls,
                                            Sink &sink)
 {
     for (int l = 0; l < ls.nlines; ++l) {
         const DevLine<Real> &ln = ls.l[l];
-        const Real xb = (ln.off0 - m.vlos * ln.dop_kms) * m.inv_dop;
-        const Real xs = ln.step * m.inv_dop;
-        const Real zb = ln.zee_G * m.B * m.inv_dop;
-        const int e_b = ln.nb, e_p = ln.nb + ln.np, e_r = ln.nb + ln.np + ln.nr;
-        for (int j = 0; j < ln.nlam; ++j) {
-            const Real x0 = fma((Real)j, xs, xb);
-            Real hb = 0, lb = 0, hp = 0, lp = 0, hr = 0, lr = 0;
-            for (int c = 0; c < e_b; ++c) {
-                Real H, L;
-                profile(m, fma(-ln.s[c], zb, x0), H, L);
-                hb = fma(ln.w[c], H, hb);
-                lb = fma(ln.w[c], L, lb);
-            }
-            for (int c = e_b; c < e_p; ++c) {
-                Real H, L;
-                profile(m, fma(-ln.s[c], zb, x0), H, L);
-                hp = fma(ln.w[c], H, hp);
-                lp = fma(ln.w[c], L, lp);
-            }
-            for (int c = e_p; c < e_r; ++c) {
-                Real H, L;
-                profile(m, fma(-ln.s[c], zb, x0), H, L);
-                hr = fma(ln.w[c], H, hr);
-                lr = fma(ln.w[c], L, lr);
-            }
-            const Real hs = hb + hr, ls_ = lb + lr;
-            const Real ht = fma((Real)-0.5, hs, hp), lt = fma((Real)-0.5, ls_, lp);
-            const Real eI = fma(m.cI1, hp, m.cI2 * hs);
-            const Real eQ = m.cQ * ht, eU = m.cU * ht, eV = m.cV * (hr - hb);
-            const Real rQ = m.cQ * lt, rU = m.cU * lt, rV = m.cV * (lr - lb);
-            const Real k = (Real)1 + eI;
-            const Real k2 = k * k;
-            const Real e2 = fma(eQ, eQ, fma(eU, eU, eV * eV));
-            const Real r2 = fma(rQ, rQ, fma(rU, rU, rV * rV));
-            const Real Pi = fma(eQ, rQ, fma(eU, rU, eV * rV));
-            const Real D = fma(k2, k2 - e2 + r2, -(Pi * Pi));
-            const Real rD = m.muS1 * recip(D);
-            const Real I = fma(k * (k2 + r2), rD, m.S0);
-            const Real Q = -fma(k2, eQ, fma(k, fma(eV, rU, -(eU * rV)), rQ * Pi)) * rD;
-            const Real U = -fma(k2, eU, fma(k, fma(eQ, rV, -(eV * rQ)), rU * Pi)) * rD;
-            const Real V = -fma(k2, eV, fma(k, fma(eU, rQ, -(eQ * rU)), rV * Pi)) * rD;
-            sink(ln.off + j, I, Q, U, V);
-        }
+        if (ln.nb == 1 && ln.np == 1 && ln.nr == 1)
+            synth_line<1, 1, 1>(m, ln, sink);
+        else if (ln.nb == 4 && ln.np == 4 && ln.nr == 4)
+            synth_line<4, 4, 4>(m, ln, sink);
+        else
+            synth_line<-1, -1, -1>(m, ln, sink);
     }
 }
 
