@@ -212,6 +212,26 @@ int ga_invert_f64(const double *obs, const double *sigma, const double *mu, int6
                   double *best_chi2, int32_t *status, uint16_t *final_genes,
                   double *final_fitness, void *workspace, size_t ws_bytes, void *stream);
 
+/* ---- FP64 refinement of a solution (non-linear least squares) ----------- */
+
+/* Levenberg-Marquardt refinement in FP64 of one model per pixel, the local
+ * least-squares polish of the genetic algorithm's best individual (the
+ * machinery the paper uses for its non-magnetic pre-fit, Sec. 5.3, applied
+ * here to the full model and the Sec. 5 chi-square).  In normalised
+ * coordinates x_j = (p_j - lo_j)/(hi_j - lo_j), kept in [0, 1]: forward-
+ * difference Jacobian (step 1e-7), normal equations, damped Cholesky steps
+ * (lambda from 1e-3, /10 on success, x10 on failure, at most 10 trials per
+ * iteration); stops after `iterations` or an iteration without progress.
+ * params_in [npix][9] (need not lie inside the box: it is clamped);
+ * outputs params_out [npix][9], chi2_out [npix] (FP64 model, same merit
+ * function), iters_done [npix] (may be NULL).  Bounds need hi > lo for all
+ * nine parameters.  Pixels with non-finite observations or sigma <= 0 give
+ * NaN. */
+int me_refine_f64(const double *obs, const double *sigma, const double *mu, int64_t npix,
+                  const me_line *lines, const me_grid *grids, int32_t nlines,
+                  const me_bounds *bounds, const double *params_in, int32_t iterations,
+                  double *params_out, double *chi2_out, int32_t *iters_done, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,7 +22,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = [os.path.join(_HERE, f) for f in ("oracle_me.c", "oracle_ga.c")]
+_SRC = [os.path.join(_HERE, f) for f in ("oracle_me.c", "oracle_ga.c", "oracle_lm.c")]
 _LOCK = threading.Lock()
 _LIB = None
 
@@ -92,6 +92,9 @@ def lib():
                                            C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                            C.c_uint64, C.c_uint32, _dp, _dp, _i32p, _u16p, _dp]
             L.oracle_ga_invert.restype = C.c_int
+            L.oracle_lm_refine.argtypes = [_dp, _dp, _dp, C.c_int64, _linep, C.c_int, _dp, _dp,
+                                           _dp, C.c_int, _dp, _dp, _i32p]
+            L.oracle_lm_refine.restype = C.c_int
             L.oracle_num_threads.restype = C.c_int
             _LIB = L
     return _LIB
@@ -269,6 +272,28 @@ def ga_invert(obs, sigma, lines, lo, hi, pop, generations, k, p_cross, p_mut, se
     if want_population:
         res.update(genes=fg, fitness=ff)
     return res
+
+
+def lm_refine(obs, sigma, lines, lo, hi, params_in, iterations, mu=None):
+    """FP64 Levenberg-Marquardt refinement; returns dict(params, chi2, iters)."""
+    o = _f64(obs)
+    s = _f64(sigma)
+    npix = o.shape[0]
+    p0 = _f64(params_in).reshape(npix, NPAR)
+    lo = _f64(lo)
+    hi = _f64(hi)
+    po = np.empty((npix, NPAR), np.float64)
+    co = np.empty(npix, np.float64)
+    it = np.empty(npix, np.int32)
+    arr, lp = _lines_array(lines)
+    m = None if mu is None else _f64(np.broadcast_to(mu, (npix,)))
+    rc = lib().oracle_lm_refine(_ptr(o, _dp), _ptr(s, _dp), None if m is None else _ptr(m, _dp),
+                                npix, lp, len(lines), _ptr(lo, _dp), _ptr(hi, _dp),
+                                _ptr(p0, _dp), int(iterations), _ptr(po, _dp), _ptr(co, _dp),
+                                _ptr(it, _i32p))
+    if rc != 0:
+        raise ValueError("oracle_lm_refine rejected its arguments")
+    return dict(params=po, chi2=co, iters=it)
 
 
 def num_threads():

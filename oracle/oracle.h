@@ -107,6 +107,15 @@ int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, i
                      double *best_params, double *best_chi2, int32_t *status,
                      uint16_t *final_genes, double *final_fit);
 
+/* Levenberg-Marquardt refinement in FP64 (see oracle_lm.c for the exact
+ * steps): params_in [npix][9] -> params_out [npix][9], chi2_out [npix],
+ * iters_done [npix] (may be NULL).  Pixels with non-finite observations or
+ * sigma <= 0 give NaN.  Returns 0 or -1 (iterations < 0 or empty bounds). */
+int oracle_lm_refine(const double *obs, const double *sigma, const double *mu, int64_t npix,
+                     const oracle_line *lines, int nlines, const double *lo, const double *hi,
+                     const double *params_in, int iterations, double *params_out,
+                     double *chi2_out, int32_t *iters_done);
+
 /* Threads the OpenMP loops would use. */
 int oracle_num_threads(void);
 

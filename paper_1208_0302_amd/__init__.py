@@ -109,6 +109,8 @@ _SIGS = {
                    C.c_size_t, _vp], C.c_int),
     "ga_invert_f64": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _cp, _vp, _vp, _vp, _vp, _vp,
                        _vp, C.c_size_t, _vp], C.c_int),
+    "me_refine_f64": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _i32, _vp, _vp, _vp, _vp],
+                      C.c_int),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -338,4 +340,25 @@ def ga_invert(obs, sigma, lines, grids, bnds: MeBounds, cfg: GAConfig, mu=None,
     _check(f(_ptr(obs), _ptr(sigma), _ptr(mu), npix, la, ga, nl, C.byref(bnds), C.byref(c),
              _ptr(res["params"]), _ptr(res["chi2"]), _ptr(res.get("status")),
              _ptr(res.get("genes")), _ptr(res.get("fitness")), None, 0, _stream(obs)))
+    return res
+
+
+def me_refine_f64(obs, sigma, lines, grids, bnds: MeBounds, params_in, iterations=50, mu=None):
+    """FP64 Levenberg-Marquardt refinement of params_in [npix, 9]; returns a
+    dict(params, chi2, iters).  obs, sigma, mu and params_in are float64."""
+    npix = obs.shape[0]
+    L = total_samples(grids)
+    _dev(obs, torch.float64, "obs", (npix, 4, L))
+    _dev(sigma, torch.float64, "sigma", (npix, 4))
+    _dev(mu, torch.float64, "mu", (npix,))
+    _dev(params_in, torch.float64, "params_in", (npix, NPAR))
+    dev = obs.device
+    res = dict(params=torch.empty((npix, NPAR), dtype=torch.float64, device=dev),
+               chi2=torch.empty((npix,), dtype=torch.float64, device=dev),
+               iters=torch.empty((npix,), dtype=torch.int32, device=dev))
+    la, ga, nl = _lines(lines, grids)
+    _check(lib().me_refine_f64(_ptr(obs), _ptr(sigma), _ptr(mu), npix, la, ga, nl,
+                               C.byref(bnds), _ptr(params_in), int(iterations),
+                               _ptr(res["params"]), _ptr(res["chi2"]), _ptr(res["iters"]),
+                               _stream(obs)))
     return res

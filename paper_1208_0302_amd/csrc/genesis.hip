@@ -584,6 +584,288 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real> a)
     }
 }
 
+
+// ---- FP64 Levenberg-Marquardt refinement --------------------------------
+//
+// One workgroup of kRefineThreads per pixel, one wavelength per thread.  In
+// normalised coordinates x_j = (p_j - lo_j)/(hi_j - lo_j) in [0, 1]: forward
+// differences with step h = 1e-7 (backwards at the upper edge) give the
+// Jacobian; A = J^T J and g = J^T r are reduced over the workgroup; thread 0
+// solves (A + lambda diag(A)) d = g by Cholesky (d_j = 0 where A_jj = 0);
+// the trial x' = clamp(x + d) is accepted if chi2 drops (lambda /= 10, floor
+// 1e-12), else lambda *= 10 (cap 1e12), at most 10 trials per iteration;
+// lambda starts at 1e-3; the loop stops after an iteration without an
+// accepted trial.
+constexpr int kRefineThreads = 256;
+constexpr int kNA = GENESIS_NPAR * (GENESIS_NPAR + 1) / 2;  // packed upper triangle of A
+
+struct RefineArgs {
+    const double *obs, *sigma, *mu, *params_in;
+    int64_t npix;
+    int32_t iterations;
+    DevLines<double> ls;
+    double lo[GENESIS_NPAR], span[GENESIS_NPAR];
+    double *params_out, *chi2_out;
+    int32_t *iters_done;
+};
+
+struct RefineShared {
+    double x[GENESIS_NPAR], xt[GENESIS_NPAR];
+    double red[kRefineThreads / 64][kNA + GENESIS_NPAR + 1];
+    double tot[kNA + GENESIS_NPAR + 1];
+    double lam, chi2;
+    int flag;
+};
+
+__device__ __forceinline__ void model_from_x(const RefineArgs &a, const double *x, double mu,
+                                             Model<double> &m)
+{
+    double p[GENESIS_NPAR];
+#pragma unroll
+    for (int j = 0; j < GENESIS_NPAR; ++j)
+        p[j] = a.lo[j] + a.span[j] * x[j];
+    model_setup(p, mu, m);
+}
+
+// Sum `n` per-thread values over the workgroup into sh.tot[0 .. n)
+// (fixed order: wavefront butterflies, then wavefronts in index order).
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N], RefineShared &sh)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1)
+            v[i] += __shfl_xor(v[i], off);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            sh.red[w][i] = v[i];
+    __syncthreads();
+    if (threadIdx.x < N) {
+        double t = 0.0;
+        for (int k = 0; k < kRefineThreads / 64; ++k)
+            t += sh.red[k][threadIdx.x];
+        sh.tot[threadIdx.x] = t;
+    }
+    __syncthreads();
+}
+
+// chi2 * nu contribution of this thread's wavelengths at normalised x
+__device__ __forceinline__ double chi2_part(const RefineArgs &a, const double *x, double mu,
+                                            const Vec4<double> *obs_s, const double (&w2)[4])
+{
+    Model<double> m;
+    model_from_x(a, x, mu, m);
+    double acc = 0.0;
+    for (int l = 0; l < a.ls.nlines; ++l) {
+        const DevLine<double> &ln = a.ls.l[l];
+        for (int jj = threadIdx.x; jj < ln.nlam; jj += kRefineThreads) {
+            double I, Q, U, V;
+            stokes_at(m, ln, jj, I, Q, U, V);
+            const Vec4<double> o = obs_s[ln.off + jj];
+            const double dI = o.x - I, dQ = o.y - Q, dU = o.z - U, dV = o.w - V;
+            acc += w2[0] * dI * dI + w2[1] * dQ * dQ + w2[2] * dU * dU + w2[3] * dV * dV;
+        }
+    }
+    return acc;
+}
+
+__device__ bool cholesky9(double (&M)[GENESIS_NPAR][GENESIS_NPAR], const double (&g)[GENESIS_NPAR],
+                          double (&d)[GENESIS_NPAR])
+{
+    double Lm[GENESIS_NPAR][GENESIS_NPAR];
+    for (int i = 0; i < GENESIS_NPAR; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double s = M[i][j];
+            for (int k = 0; k < j; ++k)
+                s -= Lm[i][k] * Lm[j][k];
+            if (i == j) {
+                if (!(s > 0.0))
+                    return false;
+                Lm[i][i] = sqrt(s);
+            } else {
+                Lm[i][j] = s / Lm[j][j];
+            }
+        }
+    double y[GENESIS_NPAR];
+    for (int i = 0; i < GENESIS_NPAR; ++i) {
+        double s = g[i];
+        for (int k = 0; k < i; ++k)
+            s -= Lm[i][k] * y[k];
+        y[i] = s / Lm[i][i];
+    }
+    for (int i = GENESIS_NPAR - 1; i >= 0; --i) {
+        double s = y[i];
+        for (int k = i + 1; k < GENESIS_NPAR; ++k)
+            s -= Lm[k][i] * d[k];
+        d[i] = s / Lm[i][i];
+    }
+    return true;
+}
+
+__global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int L = a.ls.L;
+    Vec4<double> *obs_s = reinterpret_cast<Vec4<double> *>(smem);
+    __shared__ RefineShared sh;
+    const int tid = threadIdx.x;
+    const double inv_nu = 1.0 / (4.0 * L - GENESIS_NPAR);
+    const double h = 1e-7;
+    for (int64_t p = blockIdx.x; p < a.npix; p += gridDim.x) {
+        double w2[4];
+        const int st = stage_pixel(a.obs + p * 4 * (int64_t)L, a.sigma + p * 4, L, obs_s, w2);
+        if (st != 0) {
+            if (tid == 0) {
+                for (int j = 0; j < GENESIS_NPAR; ++j)
+                    a.params_out[p * GENESIS_NPAR + j] = NAN;
+                a.chi2_out[p] = NAN;
+                if (a.iters_done)
+                    a.iters_done[p] = 0;
+            }
+            __syncthreads();
+            continue;
+        }
+        const double mu = a.mu ? a.mu[p] : 1.0;
+        const double sig[4] = {a.sigma[p * 4], a.sigma[p * 4 + 1], a.sigma[p * 4 + 2],
+                               a.sigma[p * 4 + 3]};
+        if (tid < GENESIS_NPAR) {
+            const double v = (a.params_in[p * GENESIS_NPAR + tid] - a.lo[tid]) / a.span[tid];
+            sh.x[tid] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+        }
+        if (tid == 0)
+            sh.lam = 1e-3;
+        __syncthreads();
+        {
+            double c[1] = {chi2_part(a, sh.x, mu, obs_s, w2)};
+            block_sum(c, sh);
+            if (tid == 0)
+                sh.chi2 = sh.tot[0];
+            __syncthreads();
+        }
+        int it = 0;
+        for (; it < a.iterations; ++it) {
+            // ---- Jacobian and normal equations
+            double acc[kNA + GENESIS_NPAR];
+#pragma unroll
+            for (int i = 0; i < kNA + GENESIS_NPAR; ++i)
+                acc[i] = 0.0;
+            double hx[GENESIS_NPAR];
+#pragma unroll
+            for (int j = 0; j < GENESIS_NPAR; ++j)
+                hx[j] = (sh.x[j] + h <= 1.0) ? h : -h;
+            for (int l = 0; l < a.ls.nlines; ++l) {
+                const DevLine<double> &ln = a.ls.l[l];
+                for (int jj = tid; jj < ln.nlam; jj += kRefineThreads) {
+                    double M0[4], Jm[GENESIS_NPAR][4];
+                    {
+                        Model<double> m;
+                        model_from_x(a, sh.x, mu, m);
+                        stokes_at(m, ln, jj, M0[0], M0[1], M0[2], M0[3]);
+                    }
+                    for (int k = 0; k < GENESIS_NPAR; ++k) {
+                        double xk[GENESIS_NPAR];
+#pragma unroll
+                        for (int j = 0; j < GENESIS_NPAR; ++j)
+                            xk[j] = sh.x[j] + (j == k ? hx[k] : 0.0);
+                        Model<double> m;
+                        model_from_x(a, xk, mu, m);
+                        double Mk[4];
+                        stokes_at(m, ln, jj, Mk[0], Mk[1], Mk[2], Mk[3]);
+#pragma unroll
+                        for (int s4 = 0; s4 < 4; ++s4)
+                            Jm[k][s4] = (Mk[s4] - M0[s4]) / (hx[k] * sig[s4]);
+                    }
+                    const Vec4<double> o = obs_s[ln.off + jj];
+                    const double r[4] = {(o.x - M0[0]) / sig[0], (o.y - M0[1]) / sig[1],
+                                         (o.z - M0[2]) / sig[2], (o.w - M0[3]) / sig[3]};
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) {
+                        int q = 0;
+#pragma unroll
+                        for (int i = 0; i < GENESIS_NPAR; ++i) {
+#pragma unroll
+                            for (int j = i; j < GENESIS_NPAR; ++j)
+                                acc[q++] += Jm[i][s4] * Jm[j][s4];
+                        }
+#pragma unroll
+                        for (int i = 0; i < GENESIS_NPAR; ++i)
+                            acc[kNA + i] += Jm[i][s4] * r[s4];
+                    }
+                }
+            }
+            block_sum(acc, sh);
+            // ---- damped trials
+            bool accepted = false;
+            for (int trial = 0; trial < 10; ++trial) {
+                if (tid == 0) {
+                    double Mx[GENESIS_NPAR][GENESIS_NPAR], g[GENESIS_NPAR], d[GENESIS_NPAR];
+                    int q = 0;
+                    for (int i = 0; i < GENESIS_NPAR; ++i)
+                        for (int j = i; j < GENESIS_NPAR; ++j, ++q)
+                            Mx[i][j] = Mx[j][i] = sh.tot[q];
+                    for (int i = 0; i < GENESIS_NPAR; ++i)
+                        g[i] = sh.tot[kNA + i];
+                    for (int i = 0; i < GENESIS_NPAR; ++i) {
+                        const double aii = Mx[i][i];
+                        if (aii == 0.0) {
+                            for (int j = 0; j < GENESIS_NPAR; ++j)
+                                Mx[i][j] = Mx[j][i] = 0.0;
+                            Mx[i][i] = 1.0;
+                            g[i] = 0.0;
+                        } else {
+                            Mx[i][i] = aii + sh.lam * aii;
+                        }
+                    }
+                    sh.flag = cholesky9(Mx, g, d) ? 1 : 0;
+                    if (sh.flag)
+                        for (int j = 0; j < GENESIS_NPAR; ++j) {
+                            const double v = sh.x[j] + d[j];
+                            sh.xt[j] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+                        }
+                    else
+                        sh.lam = fmin(sh.lam * 10.0, 1e12);
+                }
+                __syncthreads();
+                if (!sh.flag) {
+                    __syncthreads();
+                    continue;
+                }
+                double c[1] = {chi2_part(a, sh.xt, mu, obs_s, w2)};
+                block_sum(c, sh);
+                if (tid == 0) {
+                    if (sh.tot[0] < sh.chi2) {
+                        for (int j = 0; j < GENESIS_NPAR; ++j)
+                            sh.x[j] = sh.xt[j];
+                        sh.chi2 = sh.tot[0];
+                        sh.lam = fmax(sh.lam / 10.0, 1e-12);
+                        sh.flag = 2;
+                    } else {
+                        sh.lam = fmin(sh.lam * 10.0, 1e12);
+                    }
+                }
+                __syncthreads();
+                accepted = sh.flag == 2;
+                __syncthreads();
+                if (accepted)
+                    break;
+            }
+            if (!accepted)
+                break;
+        }
+        if (tid < GENESIS_NPAR)
+            a.params_out[p * GENESIS_NPAR + tid] = a.lo[tid] + a.span[tid] * sh.x[tid];
+        if (tid == 0) {
+            a.chi2_out[p] = sh.chi2 * inv_nu;
+            if (a.iters_done)
+                a.iters_done[p] = it;
+        }
+        __syncthreads();
+    }
+}
+
 // ---- host wrappers -----------------------------------------------------
 
 template <typename Real>
@@ -712,6 +994,50 @@ int invert_impl(const Real *obs, const Real *sigma, const Real *mu, int64_t npix
     return check_launch("ga_invert");
 }
 
+
+int refine_impl(const double *obs, const double *sigma, const double *mu, int64_t npix,
+                const me_line *lines, const me_grid *grids, int nlines, const me_bounds *bounds,
+                const double *params_in, int iterations, double *params_out, double *chi2_out,
+                int32_t *iters_done, void *stream)
+{
+    RefineArgs a{};
+    if (int rc = pack_lines(lines, grids, nlines, a.ls))
+        return rc;
+    Bounds b;
+    if (int rc = pack_bounds(bounds, b))
+        return rc;
+    for (int j = 0; j < GENESIS_NPAR; ++j) {
+        if (!(b.span[j] > 0))
+            return fail(ME_EINVAL, "refinement needs hi > lo for every parameter (%d)", j);
+        a.lo[j] = b.lo[j];
+        a.span[j] = b.span[j];
+    }
+    if (iterations < 0)
+        return fail(ME_EINVAL, "iterations must be >= 0");
+    if (npix < 0)
+        return fail(ME_EINVAL, "npix must be >= 0");
+    if (4 * a.ls.L <= GENESIS_NPAR)
+        return fail(ME_EINVAL, "need 4 L > 9 wavelength samples for nu > 0");
+    const size_t lds = sizeof(Vec4<double>) * (size_t)a.ls.L;
+    if (lds + sizeof(RefineShared) > kMaxLds)
+        return fail(ME_ENOMEM, "observation of %d samples exceeds LDS", a.ls.L);
+    if (npix == 0)
+        return ME_OK;
+    if (!obs || !sigma || !params_in || !params_out || !chi2_out)
+        return fail(ME_EINVAL, "NULL array argument");
+    a.obs = obs;
+    a.sigma = sigma;
+    a.mu = mu;
+    a.params_in = params_in;
+    a.npix = npix;
+    a.iterations = iterations;
+    a.params_out = params_out;
+    a.chi2_out = chi2_out;
+    a.iters_done = iters_done;
+    hipLaunchKernelGGL(k_refine_f64, dim3(grid_for(npix)), dim3(kRefineThreads), lds,
+                       as_stream(stream), a);
+    return check_launch("me_refine_f64");
+}
 }  // namespace
 
 // ---- C ABI -------------------------------------------------------------
@@ -915,6 +1241,15 @@ int ga_invert_f64(const double *obs, const double *sigma, const double *mu, int6
     return invert_impl<double>(obs, sigma, mu, npix, lines, grids, nlines, bounds, cfg,
                                best_params, best_chi2, status, final_genes, final_fitness,
                                stream);
+}
+
+int me_refine_f64(const double *obs, const double *sigma, const double *mu, int64_t npix,
+                  const me_line *lines, const me_grid *grids, int32_t nlines,
+                  const me_bounds *bounds, const double *params_in, int32_t iterations,
+                  double *params_out, double *chi2_out, int32_t *iters_done, void *stream)
+{
+    return refine_impl(obs, sigma, mu, npix, lines, grids, nlines, bounds, params_in, iterations,
+                       params_out, chi2_out, iters_done, stream);
 }
 
 }  // extern "C"

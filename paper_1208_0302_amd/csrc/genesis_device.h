@@ -322,7 +322,7 @@ __device__ __forceinline__ void group(const Model<Real> &m, const DevLine<Real> 
     }
 }
 
-// One line: every wavelength, handing (j, I, Q, U, V) to `sink`.
+// Stokes vector at one wavelength from the strength-weighted group profiles:
 // Unno-Rachkovsky closed form with k = 1 + eta_I,
 //   Pi = eta.rho, Delta = k^2 (k^2 - |eta|^2 + |rho|^2) - Pi^2,
 //   I = S0 + mu S1 k (k^2 + |rho|^2) / Delta,
@@ -336,6 +336,32 @@ __device__ __forceinline__ void group(const Model<Real> &m, const DevLine<Real> 
 //   Pi = c2 h_t l_t + eta_V rho_V,
 //   Q = -mu S1 (cQ A + cU k X) / Delta, U = -mu S1 (cU A - cQ k X) / Delta,
 //   V = -mu S1 (k^2 eta_V + rho_V Pi) / Delta.
+template <typename Real>
+__device__ __forceinline__ void unno_rachkovsky(const Model<Real> &m, Real hb, Real lb, Real hp,
+                                                Real lp, Real hr, Real lr, Real &I, Real &Q,
+                                                Real &U, Real &V)
+{
+    const Real hs = hb + hr, ls_ = lb + lr;
+    const Real ht = fma((Real)-0.5, hs, hp), lt = fma((Real)-0.5, ls_, lp);
+    const Real eI = fma(m.cI1, hp, m.cI2 * hs);
+    const Real eV = m.cV * (hr - hb), rV = m.cV * (lr - lb);
+    const Real k = (Real)1 + eI;
+    const Real k2 = k * k;
+    const Real e2 = fma(ht * ht, m.c2, eV * eV);
+    const Real r2 = fma(lt * lt, m.c2, rV * rV);
+    const Real Pi = fma(ht * lt, m.c2, eV * rV);
+    const Real D = fma(k2, k2 - e2 + r2, -(Pi * Pi));
+    const Real nrD = -(m.muS1 * recip(D));
+    I = fma(-(k * (k2 + r2)), nrD, m.S0);
+    const Real X = fma(eV, lt, -(ht * rV));
+    const Real kX = k * X;
+    const Real A = fma(k2, ht, lt * Pi);
+    Q = fma(m.cQ, A, m.cU * kX) * nrD;
+    U = fma(m.cU, A, -(m.cQ * kX)) * nrD;
+    V = fma(k2, eV, rV * Pi) * nrD;
+}
+
+// One line: every wavelength, handing (j, I, Q, U, V) to `sink`.
 template <int NB, int NP, int NR, typename Real, typename Sink>
 __device__ __forceinline__ void synth_line(const Model<Real> &m, const DevLine<Real> &ln,
                                            Sink &sink)
@@ -351,24 +377,8 @@ __device__ __forceinline__ void synth_line(const Model<Real> &m, const DevLine<R
         group<NB>(m, ln, 0, nb, x0, zb, hb, lb);
         group<NP>(m, ln, nb, np, x0, zb, hp, lp);
         group<NR>(m, ln, nb + np, nr, x0, zb, hr, lr);
-        const Real hs = hb + hr, ls_ = lb + lr;
-        const Real ht = fma((Real)-0.5, hs, hp), lt = fma((Real)-0.5, ls_, lp);
-        const Real eI = fma(m.cI1, hp, m.cI2 * hs);
-        const Real eV = m.cV * (hr - hb), rV = m.cV * (lr - lb);
-        const Real k = (Real)1 + eI;
-        const Real k2 = k * k;
-        const Real e2 = fma(ht * ht, m.c2, eV * eV);
-        const Real r2 = fma(lt * lt, m.c2, rV * rV);
-        const Real Pi = fma(ht * lt, m.c2, eV * rV);
-        const Real D = fma(k2, k2 - e2 + r2, -(Pi * Pi));
-        const Real nrD = -(m.muS1 * recip(D));
-        const Real I = fma(-(k * (k2 + r2)), nrD, m.S0);
-        const Real X = fma(eV, lt, -(ht * rV));
-        const Real kX = k * X;
-        const Real A = fma(k2, ht, lt * Pi);
-        const Real Q = fma(m.cQ, A, m.cU * kX) * nrD;
-        const Real U = fma(m.cU, A, -(m.cQ * kX)) * nrD;
-        const Real V = fma(k2, eV, rV * Pi) * nrD;
+        Real I, Q, U, V;
+        unno_rachkovsky(m, hb, lb, hp, lp, hr, lr, I, Q, U, V);
         sink(ln.off + j, I, Q, U, V);
     }
 }
@@ -388,6 +398,22 @@ __device__ __forceinline__ void synthesize(const Model<Real> &m, const DevLines<
         else
             synth_line<-1, -1, -1>(m, ln, sink);
     }
+}
+
+// Stokes vector of one model at sample jj of one line (used where each lane
+// owns a wavelength instead of an individual).
+template <typename Real>
+__device__ __forceinline__ void stokes_at(const Model<Real> &m, const DevLine<Real> &ln, int jj,
+                                          Real &I, Real &Q, Real &U, Real &V)
+{
+    const Real xb = (ln.off0 - m.vlos * ln.dop_kms) * m.inv_dop;
+    const Real x0 = fma((Real)jj, ln.step * m.inv_dop, xb);
+    const Real zb = ln.zee_G * m.B * m.inv_dop;
+    Real hb = 0, lb = 0, hp = 0, lp = 0, hr = 0, lr = 0;
+    group<-1>(m, ln, 0, ln.nb, x0, zb, hb, lb);
+    group<-1>(m, ln, ln.nb, ln.np, x0, zb, hp, lp);
+    group<-1>(m, ln, ln.nb + ln.np, ln.nr, x0, zb, hr, lr);
+    unno_rachkovsky(m, hb, lb, hp, lp, hr, lr, I, Q, U, V);
 }
 
 // chi-square accumulator against an observation staged in LDS as

@@ -1,0 +1,108 @@
+"""GPU FP64 Levenberg-Marquardt refinement against the oracle's refinement and
+the noise-free truth."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth_inputs as si
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a HIP device")]
+if gpu_available():
+    import paper_1208_0302_amd as g
+
+DEV = "cuda"
+LO, HI = si.PRIOR_LO, si.PRIOR_HI
+
+
+def _setup(kind):
+    lines, grids, olines = [], [], []
+    for ln, n in si.line_set(kind):
+        st, sp = si.grid(ln, n)
+        lines.append(g.line_from_terms(ln["lambda0"], ln["Jl"], ln["gl"], ln["Ju"], ln["gu"]))
+        grids.append(g.grid(st, sp, n))
+        olines.append(oracle.make_line(ln["lambda0"], ln["Jl"], ln["gl"], ln["Ju"], ln["gu"],
+                                       st, sp, n))
+    return lines, grids, olines
+
+
+def _start(truth, seed, scale):
+    rng = np.random.default_rng(seed)
+    return np.clip(truth + (HI - LO) * rng.normal(0, scale, truth.shape), LO, HI)
+
+
+def _t(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device=DEV)
+
+
+@pytest.mark.parametrize("noise", [False, True])
+def test_refine_matches_oracle(noise):
+    lines, grids, olines = _setup("slit")
+    truth = si.draw_truth(10, 12)
+    obs = oracle.me_synth(truth, olines)
+    sig = si.sigma_for(truth)
+    if noise:
+        obs = obs + sig[:, :, None] * si.std_normal(obs.shape, 12)
+    p0 = _start(truth, 13, 0.01)
+    b = g.bounds(LO, HI)
+    r = g.me_refine_f64(_t(obs), _t(sig), lines, grids, b, _t(p0), iterations=40)
+    ref = oracle.lm_refine(obs, sig, olines, LO, HI, p0, 40)
+    gp = r["params"].cpu().numpy()
+    gc = r["chi2"].cpu().numpy()
+    dx = np.abs(gp - ref["params"]) / (HI - LO)
+    # both converge to the same minimum (FP64 models differ by < 1e-10 Ic)
+    same = dx.max(axis=1) < 1e-6
+    print("pixels at the oracle's minimum: %d / 10" % same.sum())
+    assert same.sum() >= 9
+    assert np.all(np.abs(gc[same] - ref["chi2"][same]) <= 1e-7 * np.maximum(ref["chi2"][same], 1e-6))
+    # never worse than the start
+    c0 = oracle.chi2(p0[:, None], obs, sig, olines)[:, 0]
+    assert np.all(gc <= c0 * (1 + 1e-9))
+    if not noise:
+        ok = gc < 1e-12
+        assert ok.sum() >= 8
+        err = np.abs(gp - truth) / (HI - LO)
+        angles = np.zeros_like(err, dtype=bool)
+        angles[:, 1:3] = truth[:, :1] < 100.0
+        assert np.all(err[ok][~angles[ok]] < 1e-6)
+
+
+def test_refine_edge_cases():
+    lines, grids, olines = _setup("tiny")
+    truth = si.draw_truth(4, 3)
+    obs = oracle.me_synth(truth, olines)
+    sig = si.sigma_for(truth)
+    obs[2, 1, 4] = np.inf
+    b = g.bounds(LO, HI)
+    p0 = truth.copy()
+    p0[0, 0] = 5000.0                        # outside the box: clamped
+    r = g.me_refine_f64(_t(obs), _t(sig), lines, grids, b, _t(p0), iterations=0)
+    gp = r["params"].cpu().numpy()
+    assert np.isnan(gp[2]).all() and np.isnan(r["chi2"][2].item())
+    assert abs(gp[0, 0] - HI[0]) < 1e-9
+    keep = [1, 3]
+    assert np.allclose(gp[keep], truth[keep], rtol=1e-12, atol=1e-12)
+    empty = g.me_refine_f64(_t(obs[:0]), _t(sig[:0]), lines, grids, b, _t(p0[:0]), 5)
+    assert empty["params"].shape == (0, 9)
+
+
+def test_ga_then_refine_pipeline_reaches_truth():
+    """The FP32 genetic search followed by the FP64 refinement on noise-free
+    synthetic truth of the slit-row line pair."""
+    lines, grids, olines = _setup("slit")
+    npix = 256
+    truth = si.draw_truth(npix, 0)
+    tt = torch.tensor(truth, dtype=torch.float32, device=DEV)
+    obs = g.me_synth(tt, lines, grids)
+    sig = torch.tensor(si.sigma_for(truth), dtype=torch.float32, device=DEV)
+    b = g.bounds(LO, HI)
+    ga = g.ga_invert(obs, sig, lines, grids, b, g.GAConfig(pop=128, generations=200, seed=0))
+    r = g.me_refine_f64(obs.double(), sig.double(), lines, grids, b, ga["params"].double(), 50)
+    dB_ga = np.abs(ga["params"][:, 0].double().cpu().numpy() - truth[:, 0])
+    dB = np.abs(r["params"][:, 0].cpu().numpy() - truth[:, 0])
+    print("p50/p90 |dB| GA %.2f / %.2f G, GA+refine %.3g / %.3g G"
+          % (np.median(dB_ga), np.percentile(dB_ga, 90), np.median(dB), np.percentile(dB, 90)))
+    assert np.median(dB) < np.median(dB_ga)
+    assert np.all(r["chi2"].cpu().numpy() <= ga["chi2"].double().cpu().numpy() * 1.001 + 1e-6)
