@@ -12,8 +12,10 @@
  *    Struct pointers (lines, grids, bounds, config) are HOST memory, read
  *    during the call only.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Calls are
- *    asynchronous on that stream; the library allocates nothing on the
- *    device and keeps no device state between calls.
+ *    asynchronous on that stream.  Apart from a serving session (gs_*),
+ *    which owns the resident populations of its requests, the library
+ *    allocates nothing on the device and keeps no device state between
+ *    calls.
  *  - Return value: 0 on success or a negative ME_E* code; the message of the
  *    last failure on the calling thread is returned by me_last_error().  No
  *    C++ exception crosses this boundary.  On error nothing is launched.
@@ -231,6 +233,36 @@ int me_refine_f64(const double *obs, const double *sigma, const double *mu, int6
                   const me_line *lines, const me_grid *grids, int32_t nlines,
                   const me_bounds *bounds, const double *params_in, int32_t iterations,
                   double *params_out, double *chi2_out, int32_t *iters_done, void *stream);
+
+/* ---- continuous-batching service -------------------------------------- */
+
+/* A session inverts a stream of requests (tiles of pixels), the near real-time
+ * use the paper aims at (Sec. 7).  gs_submit queues a request: the same
+ * arguments as ga_invert (device arrays owned by the caller, which must stay
+ * valid until the request is done; outputs are written when it finishes).
+ * Each gs_step admits queued requests in arrival order while their resident
+ * populations (npix x pop x (9 x 2 + 4) bytes, 256-byte aligned) fit in the
+ * session's budget, then advances every resident request by up to
+ * gens_per_step generations in one launch on `stream` (the first step of a
+ * request also creates and evaluates its generation 0); finished requests
+ * release their memory at once.  A request's result is bit-identical to
+ * ga_invert with the same arguments, whatever else is resident.
+ * gs_poll sets *done to 1 when the request's outputs are complete on the
+ * device, 0 while queued or running, -1 if cancelled.  gs_cancel drops a
+ * queued request at once and a resident one at the next step.  All calls
+ * on one session are serialised by a lock; calls of different sessions on
+ * one device may overlap.  gs_submit returns ME_ENOMEM for a request larger
+ * than the whole budget. */
+int gs_create(size_t hbm_budget_bytes, int32_t gens_per_step, void **session);
+int gs_submit(void *session, const float *obs, const float *sigma, const float *mu, int64_t npix,
+              const me_line *lines, const me_grid *grids, int32_t nlines,
+              const me_bounds *bounds, const ga_config *cfg, float *best_params,
+              float *best_chi2, int32_t *status, uint64_t *request_id);
+int gs_step(void *session, void *stream);
+int gs_poll(void *session, uint64_t request_id, int32_t *done);
+int gs_cancel(void *session, uint64_t request_id);
+int gs_stats(void *session, int64_t *queued, int64_t *resident, size_t *bytes_in_use);
+int gs_destroy(void *session);
 
 #ifdef __cplusplus
 }

@@ -111,6 +111,15 @@ _SIGS = {
                        _vp, C.c_size_t, _vp], C.c_int),
     "me_refine_f64": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _i32, _vp, _vp, _vp, _vp],
                       C.c_int),
+    "gs_create": ([C.c_size_t, _i32, C.POINTER(_vp)], C.c_int),
+    "gs_submit": ([_vp, _vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _cp, _vp, _vp, _vp,
+                   C.POINTER(C.c_uint64)], C.c_int),
+    "gs_step": ([_vp, _vp], C.c_int),
+    "gs_poll": ([_vp, C.c_uint64, C.POINTER(_i32)], C.c_int),
+    "gs_cancel": ([_vp, C.c_uint64], C.c_int),
+    "gs_stats": ([_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)],
+                 C.c_int),
+    "gs_destroy": ([_vp], C.c_int),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -362,3 +371,69 @@ def me_refine_f64(obs, sigma, lines, grids, bnds: MeBounds, params_in, iteration
                                _ptr(res["params"]), _ptr(res["chi2"]), _ptr(res["iters"]),
                                _stream(obs)))
     return res
+
+
+class ServingSession:
+    """Continuous-batching inversion service (gs_* in the C ABI).
+
+    submit() queues a tile and returns its id; step() admits what fits in the
+    memory budget and advances every resident tile by `gens_per_step`
+    generations; poll() tells when a tile's outputs are ready; result()
+    returns them.  Output tensors are allocated here and kept alive until the
+    session is closed."""
+
+    def __init__(self, budget_bytes: int, gens_per_step: int = 10, device="cuda"):
+        self._h = _vp()
+        self.device = torch.device(device)
+        _check(lib().gs_create(int(budget_bytes), int(gens_per_step), C.byref(self._h)))
+        self._req = {}
+
+    def submit(self, obs, sigma, lines, grids, bnds: MeBounds, cfg: GAConfig, mu=None):
+        npix = obs.shape[0]
+        L = total_samples(grids)
+        _dev(obs, torch.float32, "obs", (npix, 4, L))
+        _dev(sigma, torch.float32, "sigma", (npix, 4))
+        _dev(mu, torch.float32, "mu", (npix,))
+        out = dict(params=torch.empty((npix, NPAR), dtype=torch.float32, device=obs.device),
+                   chi2=torch.empty((npix,), dtype=torch.float32, device=obs.device),
+                   status=torch.empty((npix,), dtype=torch.int32, device=obs.device))
+        la, ga, nl = _lines(lines, grids)
+        c = cfg.c()
+        rid = C.c_uint64()
+        _check(lib().gs_submit(self._h, _ptr(obs), _ptr(sigma), _ptr(mu), npix, la, ga, nl,
+                               C.byref(bnds), C.byref(c), _ptr(out["params"]), _ptr(out["chi2"]),
+                               _ptr(out["status"]), C.byref(rid)))
+        # keep the inputs alive with the outputs until the session ends
+        self._req[rid.value] = dict(out=out, keep=(obs, sigma, mu))
+        return rid.value
+
+    def step(self):
+        _check(lib().gs_step(self._h, _vp(torch.cuda.current_stream(self.device).cuda_stream)))
+
+    def poll(self, rid) -> int:
+        d = _i32()
+        _check(lib().gs_poll(self._h, C.c_uint64(rid), C.byref(d)))
+        return int(d.value)
+
+    def cancel(self, rid):
+        _check(lib().gs_cancel(self._h, C.c_uint64(rid)))
+
+    def stats(self):
+        q, r, b = C.c_int64(), C.c_int64(), C.c_size_t()
+        _check(lib().gs_stats(self._h, C.byref(q), C.byref(r), C.byref(b)))
+        return dict(queued=q.value, resident=r.value, bytes_in_use=b.value)
+
+    def result(self, rid):
+        return self._req[rid]["out"]
+
+    def close(self):
+        if self._h:
+            lib().gs_destroy(self._h)
+            self._h = _vp()
+            self._req.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -12,9 +12,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libgenesis_hip.so")
-SRC = os.path.join(HERE, "csrc", "genesis.hip")
-DEPS = [SRC] + [os.path.join(HERE, "csrc", f) for f in
-                ("genesis_device.h", "voigt_rational.h", "weideman36.h")] + \
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("genesis.hip", "serving.hip")]
+DEPS = SRCS + [os.path.join(HERE, "csrc", f) for f in
+               ("genesis_device.h", "genesis_common.h", "voigt_rational.h", "weideman36.h")] + \
        [os.path.join(ROOT, "include", "genesis.h")]
 
 HIPCC_FLAGS = [
@@ -34,13 +34,13 @@ def hipcc():
 
 def build(verbose: bool = False) -> str:
     tmp = SO + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-o", tmp, SRC]
+    cmd = [hipcc()] + HIPCC_FLAGS + ["-o", tmp] + SRCS
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building %s" % SRC)
+        raise RuntimeError("hipcc failed building %s" % SO)
     os.replace(tmp, SO)
     return SO
 

@@ -19,13 +19,14 @@
 #include <string>
 #include <vector>
 
-#include "genesis_device.h"
+#include "genesis_common.h"
 
-using namespace genesis;
+namespace genesis {
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
 
 int fail(int code, const char *fmt, ...)
 {
@@ -43,107 +44,6 @@ int check_launch(const char *what)
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return fail(ME_EHIP, "%s: %s", what, hipGetErrorString(e));
-    return ME_OK;
-}
-
-hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
-
-constexpr int kMaxGrid = 1 << 30;
-constexpr size_t kMaxLds = 64 * 1024;
-
-int grid_for(int64_t n) { return (int)std::min<int64_t>(std::max<int64_t>(n, 1), kMaxGrid); }
-int block_for_pop(int pop) { return ((pop + 63) / 64) * 64; }
-
-// ---- line data ---------------------------------------------------------
-
-bool twice_int(double x, int *out)
-{
-    const double t = 2.0 * x, r = std::floor(t + 0.5);
-    if (!std::isfinite(x) || std::fabs(t - r) > 1e-9)
-        return false;
-    *out = (int)r;
-    return true;
-}
-
-// Relative strength of the component M_l -> M_u = M_l - q of a dipole
-// transition between the lower level J_l and the upper level J_u
-// (closed forms of Condon & Shortley for J_u = J_l + 1, J_l, J_l - 1;
-// normalised per q group by the caller).  Arguments are doubled integers.
-double cs_strength(int TJl, int TJu, int TM, int q)
-{
-    const double J = 0.5 * TJl, M = 0.5 * TM;
-    if (TJu == TJl + 2) {
-        if (q == 0)
-            return (J + 1) * (J + 1) - M * M;
-        if (q == -1)
-            return (J + M + 1) * (J + M + 2);
-        return (J - M + 1) * (J - M + 2);
-    }
-    if (TJu == TJl) {
-        if (q == 0)
-            return M * M;
-        if (q == -1)
-            return (J - M) * (J + M + 1);
-        return (J + M) * (J - M + 1);
-    }
-    // J_u = J_l - 1
-    if (q == 0)
-        return J * J - M * M;
-    if (q == -1)
-        return (J - M) * (J - M - 1);
-    return (J + M) * (J + M - 1);
-}
-
-template <typename Real>
-int pack_lines(const me_line *lines, const me_grid *grids, int nlines, DevLines<Real> &out)
-{
-    if (!lines || !grids)
-        return fail(ME_EINVAL, "lines and grids must not be NULL");
-    if (nlines < 1 || nlines > GENESIS_MAX_LINES)
-        return fail(ME_EINVAL, "nlines = %d outside [1, %d]", nlines, GENESIS_MAX_LINES);
-    std::memset(&out, 0, sizeof out);
-    out.nlines = nlines;
-    int off = 0;
-    for (int l = 0; l < nlines; ++l) {
-        const me_line &ln = lines[l];
-        const me_grid &gd = grids[l];
-        if (!(ln.lambda0_A > 0) || !std::isfinite(ln.lambda0_A))
-            return fail(ME_EINVAL, "line %d: lambda0 must be positive", l);
-        if (ln.ncomp < 1 || ln.ncomp > GENESIS_MAX_COMP)
-            return fail(ME_EINVAL, "line %d: ncomp = %d outside [1, %d]", l, ln.ncomp,
-                        GENESIS_MAX_COMP);
-        if (gd.n < 1 || !std::isfinite(gd.start_A) || !std::isfinite(gd.step_A))
-            return fail(ME_EINVAL, "line %d: invalid wavelength grid", l);
-        DevLine<Real> &d = out.l[l];
-        d.off0 = (Real)(gd.start_A - ln.lambda0_A);
-        d.step = (Real)gd.step_A;
-        d.dop_kms = (Real)(ln.lambda0_A / kCkms);
-        d.zee_G = (Real)(kZeeman * ln.lambda0_A * ln.lambda0_A);
-        d.nlam = gd.n;
-        d.off = off;
-        int n = 0;
-        int cnt[3] = {0, 0, 0};
-        for (int g = -1; g <= 1; ++g)
-            for (int c = 0; c < ln.ncomp; ++c) {
-                if (ln.q[c] < -1 || ln.q[c] > 1)
-                    return fail(ME_EINVAL, "line %d component %d: q must be -1, 0 or 1", l, c);
-                if (!std::isfinite(ln.shift[c]) || !std::isfinite(ln.strength[c]))
-                    return fail(ME_EINVAL, "line %d component %d: non-finite data", l, c);
-                if (ln.q[c] != g)
-                    continue;
-                d.s[n] = (Real)ln.shift[c];
-                d.w[n] = (Real)ln.strength[c];
-                ++n;
-                ++cnt[g + 1];
-            }
-        d.nb = cnt[0];
-        d.np = cnt[1];
-        d.nr = cnt[2];
-        off += gd.n;
-        if (off > (1 << 20))
-            return fail(ME_EINVAL, "too many wavelength samples");
-    }
-    out.L = off;
     return ME_OK;
 }
 
@@ -193,6 +93,53 @@ int pack_ga(const ga_config *cfg, GaConst &ga)
     return ME_OK;
 }
 
+
+}  // namespace genesis
+
+using namespace genesis;
+
+namespace {
+
+// ---- line data ---------------------------------------------------------
+
+bool twice_int(double x, int *out)
+{
+    const double t = 2.0 * x, r = std::floor(t + 0.5);
+    if (!std::isfinite(x) || std::fabs(t - r) > 1e-9)
+        return false;
+    *out = (int)r;
+    return true;
+}
+
+// Relative strength of the component M_l -> M_u = M_l - q of a dipole
+// transition between the lower level J_l and the upper level J_u
+// (closed forms of Condon & Shortley for J_u = J_l + 1, J_l, J_l - 1;
+// normalised per q group by the caller).  Arguments are doubled integers.
+double cs_strength(int TJl, int TJu, int TM, int q)
+{
+    const double J = 0.5 * TJl, M = 0.5 * TM;
+    if (TJu == TJl + 2) {
+        if (q == 0)
+            return (J + 1) * (J + 1) - M * M;
+        if (q == -1)
+            return (J + M + 1) * (J + M + 2);
+        return (J - M + 1) * (J - M + 2);
+    }
+    if (TJu == TJl) {
+        if (q == 0)
+            return M * M;
+        if (q == -1)
+            return (J - M) * (J + M + 1);
+        return (J + M) * (J - M + 1);
+    }
+    // J_u = J_l - 1
+    if (q == 0)
+        return J * J - M * M;
+    if (q == -1)
+        return (J - M) * (J - M - 1);
+    return (J + M) * (J + M - 1);
+}
+
 // ---- kernels -----------------------------------------------------------
 
 template <typename Real>
@@ -224,34 +171,6 @@ __global__ __launch_bounds__(256) void k_me_synth(const Real *__restrict__ param
     model_setup(p, mu ? (double)mu[i] : 1.0, m);
     StokesSink<Real> s{out + i * 4 * (int64_t)ls.L, ls.L};
     synthesize(m, ls, s);
-}
-
-// Stage one pixel's observation into LDS as [L] x (I, Q, U, V) and return
-// its status (0 ok, 1 non-finite observation, 2 bad sigma); w2 = 1/sigma^2.
-template <typename Real>
-__device__ __forceinline__ int stage_pixel(const Real *__restrict__ obs_p,
-                                           const Real *__restrict__ sig_p, int L,
-                                           Vec4<Real> *obs_s, Real (&w2)[4])
-{
-    int bad = 0;
-    for (int j = threadIdx.x; j < L; j += blockDim.x) {
-        Vec4<Real> o;
-        o.x = obs_p[j];
-        o.y = obs_p[L + j];
-        o.z = obs_p[2 * L + j];
-        o.w = obs_p[3 * L + j];
-        bad |= !(isfinite(o.x) && isfinite(o.y) && isfinite(o.z) && isfinite(o.w));
-        obs_s[j] = o;
-    }
-    bad = __syncthreads_or(bad);
-    int bad_sig = 0;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const Real sg = sig_p[s];
-        bad_sig |= !(sg > (Real)0 && isfinite(sg));
-        w2[s] = (Real)1 / (sg * sg);
-    }
-    return bad ? 1 : (bad_sig ? 2 : 0);
 }
 
 // Fitness of every individual of every pixel: from params (me_chi2) or from
@@ -337,56 +256,6 @@ __global__ void k_decode(const uint16_t *__restrict__ genes, int64_t n, Bounds b
         params[i * GENESIS_NPAR + j] = (Real)p[j];
 }
 
-// LDS of the GA kernels: observation [L] x 4, fitness [pop], argmin
-// scratch, and two gene buffers [9][pop] (parents, children).
-template <typename Real>
-struct GaLds {
-    Vec4<Real> *obs;
-    Real *fit, *red_f;
-    int *red_i;
-    uint16_t *genes;  // two buffers [9][pop] back to back
-};
-
-__host__ __device__ inline size_t align16(size_t o) { return (o + 15) & ~(size_t)15; }
-
-template <typename Real>
-__host__ __device__ inline size_t ga_lds_bytes(int L, int pop)
-{
-    size_t o = align16(sizeof(Vec4<Real>) * (size_t)L);
-    o = align16(o + sizeof(Real) * (size_t)pop);
-    o += (sizeof(Real) + sizeof(int)) * 16;
-    o = align16(o + 2 * sizeof(uint16_t) * GENESIS_NPAR * (size_t)pop);
-    return o;
-}
-
-template <typename Real>
-__device__ __forceinline__ GaLds<Real> ga_lds(unsigned char *base, int L, int pop)
-{
-    GaLds<Real> s;
-    size_t o = 0;
-    s.obs = reinterpret_cast<Vec4<Real> *>(base);
-    o = align16(sizeof(Vec4<Real>) * (size_t)L);
-    s.fit = reinterpret_cast<Real *>(base + o);
-    o = align16(o + sizeof(Real) * (size_t)pop);
-    s.red_f = reinterpret_cast<Real *>(base + o);
-    o += sizeof(Real) * 16;
-    s.red_i = reinterpret_cast<int *>(base + o);
-    o += sizeof(int) * 16;
-    s.genes = reinterpret_cast<uint16_t *>(base + o);
-    return s;
-}
-
-// Child sink writing into an LDS gene buffer [9][pop].
-struct LdsChild {
-    uint16_t *dst;
-    int pop, c;
-    __device__ __forceinline__ void meta(int, int, int) {}
-    __device__ __forceinline__ void gene(int j, uint32_t g, uint32_t)
-    {
-        dst[j * pop + c] = (uint16_t)g;
-    }
-};
-
 // Child sink writing the step outputs to global memory.
 struct GlobalChild {
     uint16_t *genes, *masks;  // row of this child [9]
@@ -469,23 +338,6 @@ struct InvertArgs {
     int32_t *status;
     uint16_t *final_genes;
 };
-
-template <typename Real>
-__device__ __forceinline__ Real evaluate_lds(const uint16_t *genes_s, int pop, int i,
-                                             const Bounds &b, double mu,
-                                             const DevLines<Real> &ls, const Vec4<Real> *obs_s,
-                                             const Real (&w2)[4], Real inv_nu)
-{
-    uint32_t g[GENESIS_NPAR];
-#pragma unroll
-    for (int j = 0; j < GENESIS_NPAR; ++j)
-        g[j] = genes_s[j * pop + i];
-    double par[GENESIS_NPAR];
-    decode(g, b, par);
-    Model<Real> m;
-    model_setup(par, mu, m);
-    return chi2_of(m, ls, obs_s, w2, inv_nu);
-}
 
 // The whole of Algorithm 1 for one pixel per workgroup: the population
 // lives in LDS (two buffers: parents and children), lane i owns

@@ -1,0 +1,433 @@
+// Continuous-batching inversion service (the streaming use the paper aims at
+// in Sec. 7: near real-time maps from a steady flow of observations).
+//
+// Requests (tiles of pixels, each with its own lines, bounds, genetic-
+// algorithm settings and seed) are admitted in arrival order while their
+// resident populations fit in a device-memory budget.  Every gs_step launch
+// advances all resident requests together by up to K generations: one
+// workgroup per pixel, the population resumed from HBM into LDS and stored
+// back.  A request leaves as soon as it reaches its own generation count and
+// its memory is returned, so later requests join the next launch.
+//
+// Every random number is a function of (request seed, request-local pixel id,
+// generation, individual) and each pixel's arithmetic does not depend on what
+// else is resident, so a request's result is bit-identical alone, in any mix,
+// and to a single ga_invert call with the same settings.
+#include <hip/hip_runtime.h>
+
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "genesis_common.h"
+
+namespace genesis {
+
+struct ReqDesc {
+    const float *obs, *sigma, *mu;
+    uint16_t *genes;  // [npix][pop][9], session-owned
+    float *fit;       // [npix][pop], session-owned
+    float *best_params, *best_chi2;
+    int32_t *status;
+    int64_t npix;
+    int32_t generations;  // G of the request
+    int32_t gen_done;     // generations completed before this launch, -1 = not started
+    int32_t gen_to;       // generation to reach in this launch
+    int32_t pad_;
+    DevLines<float> ls;
+    Bounds b;
+    GaConst ga;
+};
+
+}  // namespace genesis
+
+using namespace genesis;
+
+namespace {
+
+__global__ __launch_bounds__(1024) void k_ga_advance(const ReqDesc *__restrict__ reqs,
+                                                     const int64_t *__restrict__ first, int nreq)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    // request of this workgroup: the last r with first[r] <= blockIdx.x
+    const int64_t blk = blockIdx.x;
+    int lo = 0, hi = nreq - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= blk)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const ReqDesc &d = reqs[lo];
+    const int64_t p = blk - first[lo];
+    const int pop = d.ga.pop;
+    const int L = d.ls.L;
+    const GaLds<float> s = ga_lds<float>(smem, L, pop);
+    const int tid = threadIdx.x;
+    const bool active = tid < pop;
+    const float inv_nu = (float)(1.0 / (4.0 * L - GENESIS_NPAR));
+    const bool finish = d.gen_to == d.generations;
+
+    float w2[4];
+    const int st = stage_pixel(d.obs + p * 4 * (int64_t)L, d.sigma + p * 4, L, s.obs, w2);
+    if (st != 0) {
+        if (finish && tid == 0) {
+            for (int j = 0; j < GENESIS_NPAR; ++j)
+                d.best_params[p * GENESIS_NPAR + j] = NAN;
+            d.best_chi2[p] = NAN;
+            if (d.status)
+                d.status[p] = st;
+        }
+        return;
+    }
+    const double mu = d.mu ? (double)d.mu[p] : 1.0;
+    const uint32_t pix = d.ga.pixel_base + (uint32_t)p;
+    const int gstride = GENESIS_NPAR * pop;
+    int cur = 0;
+    float f = 0.0f;
+    int g = d.gen_done;
+    if (g < 0) {
+        if (active) {
+#pragma unroll
+            for (int blk4 = 0; blk4 < 3; ++blk4) {
+                const uint4 w = philox(pix, 0u, (uint32_t)tid, (kInit << 24) | (uint32_t)blk4,
+                                       d.ga.key);
+                const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (4 * blk4 + q < GENESIS_NPAR)
+                        s.genes[(4 * blk4 + q) * pop + tid] = (uint16_t)(ws[q] >> 16);
+            }
+            f = evaluate_lds(s.genes, pop, tid, d.b, mu, d.ls, s.obs, w2, inv_nu);
+            s.fit[tid] = f;
+        }
+        g = 0;
+    } else if (active) {
+        const int64_t row = p * pop + tid;
+#pragma unroll
+        for (int j = 0; j < GENESIS_NPAR; ++j)
+            s.genes[j * pop + tid] = d.genes[row * GENESIS_NPAR + j];
+        f = d.fit[row];
+        s.fit[tid] = f;
+    }
+    __syncthreads();
+    for (; g < d.gen_to; ++g) {
+        const int e = block_argmin(s.fit, pop, s.red_f, s.red_i);
+        if (active) {
+            LdsChild out{s.genes + (gstride - cur), pop, tid};
+            if (tid == 0) {
+                for (int j = 0; j < GENESIS_NPAR; ++j)
+                    out.gene(j, s.genes[cur + j * pop + e], 0u);
+            } else {
+                make_child(tid, pix, (uint32_t)(g + 1), s.fit, s.genes + cur, d.ga, out);
+            }
+        }
+        __syncthreads();
+        cur = gstride - cur;
+        if (active) {
+            f = evaluate_lds(s.genes + cur, pop, tid, d.b, mu, d.ls, s.obs, w2, inv_nu);
+            s.fit[tid] = f;
+        }
+        __syncthreads();
+    }
+    if (finish) {
+        const int e = block_argmin(s.fit, pop, s.red_f, s.red_i);
+        if (tid == 0) {
+            uint32_t gb[GENESIS_NPAR];
+            for (int j = 0; j < GENESIS_NPAR; ++j)
+                gb[j] = s.genes[cur + j * pop + e];
+            double par[GENESIS_NPAR];
+            decode(gb, d.b, par);
+            for (int j = 0; j < GENESIS_NPAR; ++j)
+                d.best_params[p * GENESIS_NPAR + j] = (float)par[j];
+            d.best_chi2[p] = s.fit[e];
+            if (d.status)
+                d.status[p] = 0;
+        }
+    } else if (active) {
+        const int64_t row = p * pop + tid;
+        for (int j = 0; j < GENESIS_NPAR; ++j)
+            d.genes[row * GENESIS_NPAR + j] = s.genes[cur + j * pop + tid];
+        d.fit[row] = f;
+    }
+}
+
+enum State { kQueued = 0, kResident = 1, kDone = 2, kCancelled = 3 };
+
+struct Request {
+    uint64_t id = 0;
+    ReqDesc desc{};
+    size_t bytes = 0;
+    int state = kQueued;
+    bool cancel = false;
+    hipEvent_t done_ev = nullptr;
+};
+
+struct Session {
+    size_t budget = 0, in_use = 0;
+    int gens_per_step = 1;
+    int device = 0;
+    uint64_t next_id = 1;
+    std::deque<std::shared_ptr<Request>> queue;
+    std::vector<std::shared_ptr<Request>> resident;
+    std::unordered_map<uint64_t, std::shared_ptr<Request>> all;
+    std::mutex mu;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t request_bytes(int64_t npix, int pop)
+{
+    return align256((size_t)npix * pop * GENESIS_NPAR * sizeof(uint16_t)) +
+           align256((size_t)npix * pop * sizeof(float));
+}
+
+void release(Request &r, hipStream_t st)
+{
+    if (r.desc.genes)
+        (void)hipFreeAsync(r.desc.genes, st);
+    if (r.desc.fit)
+        (void)hipFreeAsync(r.desc.fit, st);
+    r.desc.genes = nullptr;
+    r.desc.fit = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gs_create(size_t hbm_budget_bytes, int32_t gens_per_step, void **session)
+{
+    if (!session)
+        return fail(ME_EINVAL, "session must not be NULL");
+    if (gens_per_step < 1)
+        return fail(ME_EINVAL, "gens_per_step must be >= 1");
+    if (hbm_budget_bytes == 0)
+        return fail(ME_EINVAL, "the memory budget must be positive");
+    auto *s = new Session();
+    s->budget = hbm_budget_bytes;
+    s->gens_per_step = gens_per_step;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return fail(ME_EHIP, "hipGetDevice failed");
+    }
+    *session = s;
+    return ME_OK;
+}
+
+int gs_submit(void *session, const float *obs, const float *sigma, const float *mu, int64_t npix,
+              const me_line *lines, const me_grid *grids, int32_t nlines,
+              const me_bounds *bounds, const ga_config *cfg, float *best_params,
+              float *best_chi2, int32_t *status, uint64_t *request_id)
+{
+    auto *s = static_cast<Session *>(session);
+    if (!s || !request_id)
+        return fail(ME_EINVAL, "session and request_id must not be NULL");
+    auto r = std::make_shared<Request>();
+    ReqDesc &d = r->desc;
+    if (int rc = pack_lines(lines, grids, nlines, d.ls))
+        return rc;
+    if (int rc = pack_bounds(bounds, d.b))
+        return rc;
+    if (int rc = pack_ga(cfg, d.ga))
+        return rc;
+    if (npix < 1 || npix > kMaxGrid)
+        return fail(ME_EINVAL, "npix must lie in [1, 2^30]");
+    if (4 * d.ls.L <= GENESIS_NPAR)
+        return fail(ME_EINVAL, "need 4 L > 9 wavelength samples for nu > 0");
+    if (ga_lds_bytes<float>(d.ls.L, cfg->pop) > kMaxLds)
+        return fail(ME_ENOMEM, "L = %d, pop = %d exceed LDS", d.ls.L, cfg->pop);
+    if (!obs || !sigma || !best_params || !best_chi2)
+        return fail(ME_EINVAL, "NULL array argument");
+    d.obs = obs;
+    d.sigma = sigma;
+    d.mu = mu;
+    d.npix = npix;
+    d.generations = cfg->generations;
+    d.gen_done = -1;
+    d.best_params = best_params;
+    d.best_chi2 = best_chi2;
+    d.status = status;
+    r->bytes = request_bytes(npix, cfg->pop);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (r->bytes > s->budget)
+        return fail(ME_ENOMEM, "request needs %zu B, more than the whole budget %zu B", r->bytes,
+                    s->budget);
+    if (hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming) != hipSuccess)
+        return fail(ME_EHIP, "hipEventCreate failed");
+    r->id = s->next_id++;
+    s->queue.push_back(r);
+    s->all[r->id] = r;
+    *request_id = r->id;
+    return ME_OK;
+}
+
+int gs_step(void *session, void *stream)
+{
+    auto *s = static_cast<Session *>(session);
+    if (!s)
+        return fail(ME_EINVAL, "session must not be NULL");
+    hipStream_t st = as_stream(stream);
+    std::lock_guard<std::mutex> lk(s->mu);
+    // drop cancelled residents
+    for (auto it = s->resident.begin(); it != s->resident.end();) {
+        if ((*it)->cancel) {
+            release(**it, st);
+            s->in_use -= (*it)->bytes;
+            (*it)->state = kCancelled;
+            it = s->resident.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    // admission in arrival order while the budget allows
+    while (!s->queue.empty() && s->in_use + s->queue.front()->bytes <= s->budget) {
+        auto r = s->queue.front();
+        s->queue.pop_front();
+        const size_t gb = (size_t)r->desc.npix * r->desc.ga.pop * GENESIS_NPAR * sizeof(uint16_t);
+        const size_t fb = (size_t)r->desc.npix * r->desc.ga.pop * sizeof(float);
+        if (hipMallocAsync((void **)&r->desc.genes, gb, st) != hipSuccess ||
+            hipMallocAsync((void **)&r->desc.fit, fb, st) != hipSuccess) {
+            release(*r, st);
+            s->queue.push_front(r);
+            return fail(ME_ENOMEM, "device allocation of %zu B failed", r->bytes);
+        }
+        s->in_use += r->bytes;
+        r->state = kResident;
+        s->resident.push_back(r);
+    }
+    if (s->resident.empty())
+        return ME_OK;
+    // descriptors of this launch
+    const int nreq = (int)s->resident.size();
+    std::vector<ReqDesc> descs(nreq);
+    std::vector<int64_t> first(nreq + 1);
+    int max_pop = 2, max_L = 1;
+    size_t lds = 0;
+    first[0] = 0;
+    for (int i = 0; i < nreq; ++i) {
+        ReqDesc &d = s->resident[i]->desc;
+        const int from = d.gen_done < 0 ? 0 : d.gen_done;
+        d.gen_to = std::min(from + s->gens_per_step, d.generations);
+        descs[i] = d;
+        first[i + 1] = first[i] + d.npix;
+        max_pop = std::max(max_pop, d.ga.pop);
+        max_L = std::max(max_L, d.ls.L);
+        lds = std::max(lds, ga_lds_bytes<float>(d.ls.L, d.ga.pop));
+    }
+    if (first[nreq] > kMaxGrid)
+        return fail(ME_EINVAL, "more than 2^30 resident pixels");
+    void *dbuf = nullptr;
+    const size_t dbytes = align256(sizeof(ReqDesc) * nreq) + sizeof(int64_t) * (nreq + 1);
+    if (hipMallocAsync(&dbuf, dbytes, st) != hipSuccess)
+        return fail(ME_ENOMEM, "descriptor allocation failed");
+    ReqDesc *d_descs = (ReqDesc *)dbuf;
+    int64_t *d_first = (int64_t *)((char *)dbuf + align256(sizeof(ReqDesc) * nreq));
+    if (hipMemcpyAsync(d_descs, descs.data(), sizeof(ReqDesc) * nreq, hipMemcpyHostToDevice,
+                       st) != hipSuccess ||
+        hipMemcpyAsync(d_first, first.data(), sizeof(int64_t) * (nreq + 1), hipMemcpyHostToDevice,
+                       st) != hipSuccess) {
+        (void)hipFreeAsync(dbuf, st);
+        return fail(ME_EHIP, "descriptor upload failed");
+    }
+    hipLaunchKernelGGL(k_ga_advance, dim3((unsigned)first[nreq]), dim3(block_for_pop(max_pop)),
+                       lds, st, d_descs, d_first, nreq);
+    if (int rc = check_launch("gs_step"))
+        return rc;
+    (void)hipFreeAsync(dbuf, st);
+    // bookkeeping: finished requests leave and return their memory
+    for (auto it = s->resident.begin(); it != s->resident.end();) {
+        Request &r = **it;
+        r.desc.gen_done = r.desc.gen_to;
+        if (r.desc.gen_done == r.desc.generations) {
+            (void)hipEventRecord(r.done_ev, st);
+            release(r, st);
+            s->in_use -= r.bytes;
+            r.state = kDone;
+            it = s->resident.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    return ME_OK;
+}
+
+int gs_poll(void *session, uint64_t request_id, int32_t *done)
+{
+    auto *s = static_cast<Session *>(session);
+    if (!s || !done)
+        return fail(ME_EINVAL, "session and done must not be NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(request_id);
+    if (it == s->all.end())
+        return fail(ME_EINVAL, "unknown request %llu", (unsigned long long)request_id);
+    Request &r = *it->second;
+    *done = 0;
+    if (r.state == kDone)
+        *done = hipEventQuery(r.done_ev) == hipSuccess ? 1 : 0;
+    else if (r.state == kCancelled)
+        *done = -1;
+    return ME_OK;
+}
+
+int gs_cancel(void *session, uint64_t request_id)
+{
+    auto *s = static_cast<Session *>(session);
+    if (!s)
+        return fail(ME_EINVAL, "session must not be NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(request_id);
+    if (it == s->all.end())
+        return fail(ME_EINVAL, "unknown request %llu", (unsigned long long)request_id);
+    Request &r = *it->second;
+    if (r.state == kQueued) {
+        for (auto q = s->queue.begin(); q != s->queue.end(); ++q)
+            if ((*q)->id == request_id) {
+                s->queue.erase(q);
+                break;
+            }
+        r.state = kCancelled;
+    } else if (r.state == kResident) {
+        r.cancel = true;
+    }
+    return ME_OK;
+}
+
+int gs_stats(void *session, int64_t *queued, int64_t *resident, size_t *bytes_in_use)
+{
+    auto *s = static_cast<Session *>(session);
+    if (!s)
+        return fail(ME_EINVAL, "session must not be NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (queued)
+        *queued = (int64_t)s->queue.size();
+    if (resident)
+        *resident = (int64_t)s->resident.size();
+    if (bytes_in_use)
+        *bytes_in_use = s->in_use;
+    return ME_OK;
+}
+
+int gs_destroy(void *session)
+{
+    auto *s = static_cast<Session *>(session);
+    if (!s)
+        return ME_OK;
+    (void)hipDeviceSynchronize();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (auto &r : s->resident)
+            release(*r, nullptr);
+        for (auto &kv : s->all)
+            if (kv.second->done_ev)
+                (void)hipEventDestroy(kv.second->done_ev);
+    }
+    (void)hipDeviceSynchronize();
+    delete s;
+    return ME_OK;
+}
+
+}  // extern "C"

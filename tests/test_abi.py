@@ -26,7 +26,7 @@ def _declared():
 def test_library_exports_every_declared_symbol():
     L = g.lib()
     declared = _declared()
-    assert len(declared) >= 18
+    assert len(declared) >= 25
     for name in declared:
         assert hasattr(L, name), name
     assert sorted(g.EXPORTED) == declared

@@ -1,0 +1,126 @@
+"""Continuous-batching service: every request's result is bit-identical to a
+standalone ga_invert of the same request, alone or mixed with others arriving
+at different times; admission respects the memory budget; cancellation."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth_inputs as si
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a HIP device")]
+if gpu_available():
+    import paper_1208_0302_amd as g
+
+DEV = "cuda"
+
+
+def _request(kind, npix, seed, bad=False):
+    lines, grids, olines = [], [], []
+    for ln, n in si.line_set(kind):
+        st, sp = si.grid(ln, n)
+        lines.append(g.line_from_terms(ln["lambda0"], ln["Jl"], ln["gl"], ln["Ju"], ln["gu"]))
+        grids.append(g.grid(st, sp, n))
+        olines.append(oracle.make_line(ln["lambda0"], ln["Jl"], ln["gl"], ln["Ju"], ln["gu"],
+                                       st, sp, n))
+    truth = si.draw_truth(npix, seed)
+    obs = oracle.me_synth(truth, olines)
+    sig = si.sigma_for(truth)
+    obs = (obs + sig[:, :, None] * si.std_normal(obs.shape, seed)).astype(np.float32)
+    sig = sig.astype(np.float32)
+    if bad:
+        obs[npix // 2, 1, 3] = np.nan
+    return (lines, grids, torch.tensor(obs, device=DEV), torch.tensor(sig, device=DEV))
+
+
+def _alone(req, cfg):
+    lines, grids, obs, sig = req
+    return g.ga_invert(obs, sig, lines, grids, g.bounds(si.PRIOR_LO, si.PRIOR_HI), cfg)
+
+
+def _same(a, b):
+    return (torch.equal(a["params"].nan_to_num(-1), b["params"].nan_to_num(-1))
+            and torch.equal(a["chi2"].nan_to_num(-1), b["chi2"].nan_to_num(-1))
+            and torch.equal(a["status"], b["status"]))
+
+
+def _drain(sess, ids, max_steps=500):
+    for _ in range(max_steps):
+        if all(sess.poll(i) == 1 for i in ids):
+            return
+        sess.step()
+        torch.cuda.synchronize()
+    raise AssertionError("requests did not finish")
+
+
+def test_single_request_equals_ga_invert():
+    req = _request("slit", 100, 1, bad=True)
+    cfg = g.GAConfig(pop=128, generations=23, seed=5)
+    sess = g.ServingSession(budget_bytes=1 << 30, gens_per_step=7)
+    rid = sess.submit(req[2], req[3], req[0], req[1], g.bounds(si.PRIOR_LO, si.PRIOR_HI), cfg)
+    _drain(sess, [rid])
+    assert _same(sess.result(rid), _alone(req, cfg))
+    assert sess.stats() == dict(queued=0, resident=0, bytes_in_use=0)
+    sess.close()
+
+
+def test_mixed_requests_equal_their_standalone_runs():
+    b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
+    reqs = [(_request("tiny", 37, 2), g.GAConfig(pop=64, generations=15, seed=1)),
+            (_request("slit", 70, 3, bad=True), g.GAConfig(pop=128, generations=30, seed=2)),
+            (_request("slit1", 130, 4), g.GAConfig(pop=96, generations=9, seed=3, pixel_base=7)),
+            (_request("tiny", 5, 5), g.GAConfig(pop=2, generations=12, tournament_k=2, seed=4)),
+            (_request("slit", 64, 6), g.GAConfig(pop=128, generations=0, seed=6))]
+    sess = g.ServingSession(budget_bytes=1 << 30, gens_per_step=4)
+    ids = []
+    # staggered arrivals: two now, the rest after some steps
+    for r, c in reqs[:2]:
+        ids.append(sess.submit(r[2], r[3], r[0], r[1], b, c))
+    sess.step()
+    sess.step()
+    for r, c in reqs[2:]:
+        ids.append(sess.submit(r[2], r[3], r[0], r[1], b, c))
+        sess.step()
+    _drain(sess, ids)
+    for (r, c), rid in zip(reqs, ids):
+        assert _same(sess.result(rid), _alone(r, c)), rid
+    sess.close()
+
+
+def test_budget_admission_and_cancel():
+    b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
+    cfg = g.GAConfig(pop=128, generations=20, seed=9)
+    r1, r2, r3 = _request("tiny", 200, 11), _request("tiny", 150, 12), _request("tiny", 100, 13)
+    per_pixel = 128 * (9 * 2 + 4)
+    budget = 260 * per_pixel                  # room for one of the larger requests at a time
+    sess = g.ServingSession(budget_bytes=budget, gens_per_step=5)
+    i1 = sess.submit(r1[2], r1[3], r1[0], r1[1], b, cfg)
+    i2 = sess.submit(r2[2], r2[3], r2[0], r2[1], b, cfg)
+    i3 = sess.submit(r3[2], r3[3], r3[0], r3[1], b, cfg)
+    sess.step()
+    st = sess.stats()
+    assert st["resident"] == 1 and st["queued"] == 2 and st["bytes_in_use"] <= budget
+    sess.cancel(i3)                           # queued: dropped at once
+    assert sess.stats()["queued"] == 1 and sess.poll(i3) == -1
+    peak = 0
+    for _ in range(100):
+        sess.step()
+        torch.cuda.synchronize()
+        peak = max(peak, sess.stats()["bytes_in_use"])
+        if sess.poll(i1) == 1 and sess.poll(i2) == 1:
+            break
+    assert peak <= budget
+    assert _same(sess.result(i1), _alone(r1, cfg)) and _same(sess.result(i2), _alone(r2, cfg))
+    # a resident request can be cancelled too
+    i4 = sess.submit(r1[2], r1[3], r1[0], r1[1], b, cfg)
+    sess.step()
+    sess.cancel(i4)
+    sess.step()
+    assert sess.poll(i4) == -1 and sess.stats()["bytes_in_use"] == 0
+    # larger than the whole budget
+    big = _request("tiny", 400, 14)
+    with pytest.raises(g.GenesisError):
+        sess.submit(big[2], big[3], big[0], big[1], b, cfg)
+    sess.close()
