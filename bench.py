@@ -104,6 +104,85 @@ def cpu_baseline(w, truth, olines, budget_s=20.0):
                       % (npx, gs + 1, w["generations"] + 1, w["pop"], dt_ga, w["refine"], dt_lm)}
 
 
+def serving(args):
+    """Continuous-batching service under a Poisson stream of inversion
+    requests (tiles of lognormal size, 1-2 lines x 128 samples, 50-300
+    generations, population 128, 200 GB budget).  Latency = arrival to
+    outputs complete on the device, at launch granularity."""
+    import torch
+    import paper_1208_0302_amd as g
+    import synth_inputs as si
+
+    dev = torch.device("cuda:0")
+    sched = si.serving_schedule(args.rate, args.window, seed=0)
+    b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
+    linesets = {}
+    for name in ("slit", "slit1"):
+        ls, gs = [], []
+        for ln, n in si.line_set(name):
+            start, step = si.grid(ln, n)
+            ls.append(g.line_from_terms(ln["lambda0"], ln["Jl"], ln["gl"], ln["Ju"], ln["gu"]))
+            gs.append(g.grid(start, step, n))
+        linesets[name] = (ls, gs)
+    # observations of every request synthesised up front (resident before arrival)
+    reqs = []
+    for k, r in enumerate(sched):
+        ls, gs = linesets[r["lines"]]
+        truth = si.draw_truth(r["npix"], seed=r["seed"])
+        obs = g.me_synth(torch.tensor(truth, dtype=torch.float32, device=dev), ls, gs)
+        sig = torch.tensor(si.sigma_for(truth), dtype=torch.float32, device=dev)
+        reqs.append(dict(r, obs=obs, sig=sig, ls=ls, gs=gs))
+    torch.cuda.synchronize()
+    print("serving: %d requests, %d pixels synthesised" % (len(reqs), sum(r["npix"] for r in reqs)),
+          file=sys.stderr, flush=True)
+    sess = g.ServingSession(budget_bytes=200 * 10 ** 9, gens_per_step=args.gens_per_step)
+    pending, lat, done_px, launches = {}, [], 0, 0
+    nxt = 0
+    t0 = time.perf_counter()
+    last = t0
+    while nxt < len(reqs) or pending:
+        now = time.perf_counter() - t0
+        while nxt < len(reqs) and reqs[nxt]["t"] <= now:
+            r = reqs[nxt]
+            cfg = g.GAConfig(pop=128, generations=r["generations"], tournament_k=4,
+                             p_cross=0.85, p_mut=0.05, seed=r["seed"])
+            rid = sess.submit(r["obs"], r["sig"], r["ls"], r["gs"], b, cfg)
+            pending[rid] = r
+            nxt += 1
+        if not pending:
+            time.sleep(min(0.002, max(0.0, reqs[nxt]["t"] - now)))
+            continue
+        sess.step()
+        torch.cuda.synchronize()
+        launches += 1
+        tnow = time.perf_counter() - t0
+        for rid in [i for i in pending if sess.poll(i) == 1]:
+            r = pending.pop(rid)
+            lat.append(tnow - r["t"])
+            done_px += r["npix"]
+        if time.perf_counter() - last > 5.0:
+            last = time.perf_counter()
+            print("serving: t=%.1f s, done %d, pending %d, queued %d" %
+                  (tnow, len(lat), len(pending), sess.stats()["queued"]), file=sys.stderr,
+                  flush=True)
+    makespan = time.perf_counter() - t0
+    sess.close()
+    lat = np.array(lat)
+    out = {"metric": METRIC + " (serving)", "value": done_px / makespan, "unit": "pixels/s",
+           "n_gpus": 1, "steps": launches, "warmup": 0, "ms_per_step": makespan * 1e3 / launches,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (Poisson request stream, truth from the priors)",
+           "config": {"workload": "serving: Poisson %.2f req/s over %.0f s, tiles "
+                                  "clip(lognormal(ln 4096, 1.2), 256, 65536) px, 1-2 lines x 128, "
+                                  "G ~ U{50..300}, pop 128, %d generations per launch, 200 GB budget"
+                                  % (args.rate, args.window, args.gens_per_step),
+                      "requests": len(reqs)},
+           "latency_s_p50": float(np.percentile(lat, 50)),
+           "latency_s_p99": float(np.percentile(lat, 99)),
+           "makespan_s": makespan}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +191,9 @@ def main():
     ap.add_argument("--workload", default="slit")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--rate", type=float, default=2.0, help="serving: requests per second")
+    ap.add_argument("--window", type=float, default=20.0, help="serving: arrival window [s]")
+    ap.add_argument("--gens-per-step", type=int, default=10, help="serving: generations per launch")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times) so that "
                          "HBM byte counters can be scaled against a kernel of known traffic")
@@ -131,6 +213,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}), flush=True)
+        return
+    if args.workload == "serving":
+        serving(args)
         return
     import paper_1208_0302_amd as g
     import synth_inputs as si

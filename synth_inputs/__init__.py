@@ -121,3 +121,24 @@ def disc_mask(n: int = 2048, radius: float = 1024.0) -> np.ndarray:
     c = (n - 1) / 2.0
     y, x = np.mgrid[0:n, 0:n]
     return (x - c) ** 2 + (y - c) ** 2 <= radius ** 2
+
+
+def serving_schedule(rate_per_s: float, window_s: float, seed: int):
+    """Poisson arrivals at `rate_per_s` over `window_s` seconds.  Each request:
+    tile pixels clip(lognormal(ln 4096, 1.2), 256, 65536), one line (6302.5)
+    or both lines with probability 1/2 each, generations uniform in 50..300.
+    Returns a list of dicts (t, npix, lines, generations, seed)."""
+    rng = np.random.Generator(np.random.Philox(key=seed + 424242))
+    t = 0.0
+    out = []
+    i = 0
+    while True:
+        t += rng.exponential(1.0 / rate_per_s)
+        if t > window_s:
+            break
+        npix = int(np.clip(np.round(rng.lognormal(np.log(4096.0), 1.2)), 256, 65536))
+        lines = "slit" if rng.uniform() < 0.5 else "slit1"
+        gens = int(rng.integers(50, 301))
+        out.append(dict(t=t, npix=npix, lines=lines, generations=gens, seed=seed * 100003 + i))
+        i += 1
+    return out
