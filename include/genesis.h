@@ -89,23 +89,34 @@ typedef struct {
  *  pop          population size, 2 .. GENESIS_MAX_POP
  *  generations  G >= 0 iterations after the initial evaluation
  *  tournament_k contestants per tournament, 1 .. min(pop, GENESIS_MAX_K)
+ *  n_seeded     individuals 0 .. n_seeded-1 of generation 0 start from a
+ *               first guess per pixel instead of random genes (Sec. 5.5
+ *               seeds the population with first guesses): individual 0 is
+ *               seed_params[p] encoded exactly, individual i >= 1 adds to
+ *               each gene a uniform integer in [-seed_jitter, seed_jitter]
+ *               (stream purpose 5), clamped to [0, 65535]; 0 = no seeding
  *  p_cross      probability of single-point crossover of a pair
  *  p_mut        mean per-bit mutation probability r; bit k (0 = MSB) flips
  *               with probability 2 r (k + 1) / 17
  *  seed         key of the counter-based random stream
  *  pixel_base   pixel p of the call draws random numbers as pixel
  *               pixel_base + p, so a map split into calls reproduces the
- *               single-call result. */
+ *               single-call result
+ *  seed_jitter  see n_seeded, 0 .. 32767
+ *  seed_params  [npix][9] device array of first guesses (parameter units),
+ *               used when n_seeded > 0 */
 typedef struct {
     int32_t pop;
     int32_t generations;
     int32_t tournament_k;
-    int32_t reserved0;
+    int32_t n_seeded;
     float p_cross;
     float p_mut;
     uint64_t seed;
     uint32_t pixel_base;
-    int32_t reserved[7];
+    int32_t seed_jitter;
+    const float *seed_params;
+    int32_t reserved[4];
 } ga_config;
 
 /* Message of the last failure on this thread ("" if none). */
@@ -154,8 +165,11 @@ int me_chi2_f64(const double *params, int64_t npix, int32_t pop, const double *o
 
 /* Generation-0 population genes [npix][pop][9]: gene j of individual i of
  * pixel p = high 16 bits of word j of the random stream
- * (seed, pixel_base + p, generation 0, individual i, purpose 0). */
-int ga_init(int64_t npix, const ga_config *cfg, uint16_t *genes, void *stream);
+ * (seed, pixel_base + p, generation 0, individual i, purpose 0), or the
+ * seeded genes described at ga_config for i < n_seeded (bounds are needed
+ * then, to encode the first guesses; otherwise they may be NULL). */
+int ga_init(int64_t npix, const ga_config *cfg, const me_bounds *bounds, uint16_t *genes,
+            void *stream);
 
 /* Decoding operator E^-1 (Sec. 3 decode equation):
  * p_j = lo_j + (hi_j - lo_j) g_j / 65535, genes [n][9] -> params [n][9]. */
@@ -233,6 +247,62 @@ int me_refine_f64(const double *obs, const double *sigma, const double *mu, int6
                   const me_line *lines, const me_grid *grids, int32_t nlines,
                   const me_bounds *bounds, const double *params_in, int32_t iterations,
                   double *params_out, double *chi2_out, int32_t *iters_done, void *stream);
+
+/* ---- learned proposal (first guesses for seeding) ---------------------- */
+
+/* A multilayer perceptron maps a pixel's Stokes vector to a first guess of
+ * its parameters, which seeds part of generation 0 (ga_config.n_seeded); the
+ * paper seeds its population with heuristic first guesses (Sec. 5.5) and
+ * cites neural-network inversion (Sec. 1).  Fixed architecture: 1024 inputs
+ * (4 Stokes x 256 samples divided by the pixel's maximum of I) -> three GELU
+ * layers of 512 -> 9 outputs, the parameters scaled to [0, 1] by the search
+ * box (the azimuth periodic with period 1).  Parameters: one FP32 array of
+ * mlp_param_count() values, layer by layer W[out][in] then b[out].  Matrix
+ * products: BF16 operands with FP32 accumulation on the matrix cores
+ * (precision 0) or FP32 on the vector units (precision 1, for checks). */
+int64_t mlp_param_count(void);
+/* Device workspace for a batch (activations and a BF16 weight copy). */
+size_t mlp_workspace_bytes(int64_t batch);
+/* He-normal weights, zero biases, from the counter-based stream. */
+int mlp_init(float *master, uint64_t seed, void *stream);
+/* x [npix][1024] = obs [npix][4][L] / max_j I_j, L = 256 required. */
+int mlp_features(const float *obs, int64_t npix, const me_grid *grids, int32_t nlines,
+                 float *x, void *stream);
+/* y [n][9] = network(x [n][1024]). */
+int mlp_forward(const float *master, const float *x, int64_t n, int32_t precision, float *y,
+                void *workspace, size_t ws_bytes, void *stream);
+/* Gradient of loss = mean_b sum_j d_bj^2, d = y - target (azimuth d taken
+ * modulo 1), into grad [param_count]; *loss (device) receives the loss. */
+int mlp_grad(const float *master, const float *x, const float *target, int64_t batch,
+             int32_t precision, float *grad, float *loss, void *workspace, size_t ws_bytes,
+             void *stream);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8, bias-corrected; step >= 1). */
+int mlp_adam(float *master, float *m, float *v, const float *grad, int32_t step, float lr,
+             void *stream);
+/* Training examples n, counter-indexed from `first`: parameters [n][9]
+ * uniform in the box (v_los normal about the centre, sigma = width / 10,
+ * clipped) and their scaled targets [n][9]. */
+int mlp_draw_examples(uint64_t seed, int64_t first, int64_t n, const me_bounds *bounds,
+                      float *params, float *target, void *stream);
+/* stokes [n][4][L] += N(0, (sigma_rel (S0 + S1))^2), mu = 1. */
+int mlp_add_noise(uint64_t seed, int64_t first, const float *params, int64_t n,
+                  const me_grid *grids, int32_t nlines, float sigma_rel, float *stokes,
+                  void *stream);
+/* params [n][9] = box position of network outputs y [n][9] (clamped). */
+int mlp_unscale(const float *y, int64_t n, const me_bounds *bounds, float *params, void *stream);
+/* Device workspace of mlp_train for a batch. */
+size_t mlp_train_workspace_bytes(int64_t batch);
+/* `steps` Adam steps on fresh synthetic examples, all on `stream`: step
+ * t = first_step + s draws examples (t - 1) batch ... t batch - 1 of stream
+ * `seed` (mlp_draw_examples), synthesises them with me_synth (mu = 1), adds
+ * noise (mlp_add_noise), normalises (mlp_features), computes the gradient
+ * (mlp_grad) and applies mlp_adam with step number t.  losses [steps]
+ * (device) receives each step's loss.  m and v start at zero for
+ * first_step = 1 and carry over between calls. */
+int mlp_train(float *master, float *m, float *v, int32_t first_step, int32_t steps,
+              int64_t batch, float lr, uint64_t seed, const me_line *lines, const me_grid *grids,
+              int32_t nlines, const me_bounds *bounds, float sigma_rel, int32_t precision,
+              float *losses, void *workspace, size_t ws_bytes, void *stream);
 
 /* ---- continuous-batching service -------------------------------------- */
 

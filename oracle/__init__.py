@@ -35,7 +35,7 @@ def build(force: bool = True) -> str:
     if not force and os.path.exists(_SO):
         return _SO
     tmp = _SO + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-ffp-contract=off",
            "-D_GNU_SOURCE", "-o", tmp] + _SRC + ["-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _SO)
@@ -83,14 +83,16 @@ def lib():
             L.oracle_rng_word.argtypes = [C.c_uint64] + [C.c_uint32] * 5
             L.oracle_rng_word.restype = C.c_uint32
             L.oracle_decode.argtypes = [_u16p, _dp, _dp, _dp]
-            L.oracle_ga_init.argtypes = [C.c_uint64, C.c_uint32, C.c_int, _u16p]
+            L.oracle_ga_init.argtypes = [C.c_uint64, C.c_uint32, C.c_int, C.c_int, C.c_int, _dp,
+                                         _dp, _dp, _u16p]
             L.oracle_ga_step.argtypes = [_u16p, _dp, C.c_int, C.c_int, C.c_double, C.c_double,
                                          C.c_uint64, C.c_uint32, C.c_uint32,
                                          _u16p, _i32p, _i32p, _u16p, _i32p]
             L.oracle_ga_step.restype = C.c_int
             L.oracle_ga_invert.argtypes = [_dp, _dp, _dp, C.c_int64, _linep, C.c_int, _dp, _dp,
                                            C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
-                                           C.c_uint64, C.c_uint32, _dp, _dp, _i32p, _u16p, _dp]
+                                           C.c_uint64, C.c_uint32, C.c_int, C.c_int, _dp,
+                                           _dp, _dp, _i32p, _u16p, _dp]
             L.oracle_ga_invert.restype = C.c_int
             L.oracle_lm_refine.argtypes = [_dp, _dp, _dp, C.c_int64, _linep, C.c_int, _dp, _dp,
                                            _dp, C.c_int, _dp, _dp, _i32p]
@@ -222,9 +224,17 @@ def decode(genes, lo, hi):
     return out.reshape(np.shape(genes))
 
 
-def ga_init(seed, pixel, pop):
+def ga_init(seed, pixel, pop, n_seeded=0, jitter=0, seed_params=None, lo=None, hi=None):
+    """Generation 0 of one pixel; the first n_seeded individuals encode the
+    first guess seed_params [9] inside the box [lo, hi] (Sec. 5.5)."""
     g = np.empty((pop, NPAR), np.uint16)
-    lib().oracle_ga_init(int(seed), int(pixel), int(pop), _ptr(g, _u16p))
+    sp = lo_ = hi_ = None
+    if n_seeded > 0:
+        sp, lo_, hi_ = _f64(seed_params).reshape(NPAR), _f64(lo), _f64(hi)
+    lib().oracle_ga_init(int(seed), int(pixel), int(pop), int(n_seeded), int(jitter),
+                         None if sp is None else _ptr(sp, _dp),
+                         None if lo_ is None else _ptr(lo_, _dp),
+                         None if hi_ is None else _ptr(hi_, _dp), _ptr(g, _u16p))
     return g
 
 
@@ -248,7 +258,8 @@ def ga_step(genes_in, fitness, k, p_cross, p_mut, seed, pixel, gen):
 
 
 def ga_invert(obs, sigma, lines, lo, hi, pop, generations, k, p_cross, p_mut, seed,
-              mu=None, pixel_base=0, want_population=False):
+              mu=None, pixel_base=0, want_population=False, n_seeded=0, seed_jitter=0,
+              seed_params=None):
     o = _f64(obs)
     s = _f64(sigma)
     npix = o.shape[0]
@@ -261,10 +272,12 @@ def ga_invert(obs, sigma, lines, lo, hi, pop, generations, k, p_cross, p_mut, se
     ff = np.empty((npix, pop), np.float64) if want_population else None
     arr, lp = _lines_array(lines)
     m = None if mu is None else _f64(np.broadcast_to(mu, (npix,)))
+    sp = None if n_seeded == 0 else _f64(seed_params).reshape(npix, NPAR)
     rc = lib().oracle_ga_invert(
         _ptr(o, _dp), _ptr(s, _dp), None if m is None else _ptr(m, _dp), npix, lp, len(lines),
         _ptr(lo, _dp), _ptr(hi, _dp), int(pop), int(generations), int(k), float(p_cross),
-        float(p_mut), int(seed), int(pixel_base), _ptr(bp, _dp), _ptr(bc, _dp), _ptr(st, _i32p),
+        float(p_mut), int(seed), int(pixel_base), int(n_seeded), int(seed_jitter),
+        None if sp is None else _ptr(sp, _dp), _ptr(bp, _dp), _ptr(bc, _dp), _ptr(st, _i32p),
         None if fg is None else _ptr(fg, _u16p), None if ff is None else _ptr(ff, _dp))
     if rc != 0:
         raise ValueError("oracle_ga_invert rejected its arguments")

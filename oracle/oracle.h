@@ -81,8 +81,12 @@ uint32_t oracle_rng_word(uint64_t seed, uint32_t pixel, uint32_t gen, uint32_t i
 /* Decoding operator E^-1 (Sec. 3, decode equation) for 16-bit genes. */
 void oracle_decode(const uint16_t *genes, const double *lo, const double *hi, double *par);
 
-/* Generation-0 population: genes [pop][9]. */
-void oracle_ga_init(uint64_t seed, uint32_t pixel, int pop, uint16_t *genes);
+/* Generation-0 population: genes [pop][9].  Individuals below n_seeded encode
+ * the first guess seed_par [9] in the box [lo, hi] (exactly for individual 0,
+ * jittered by up to +-jitter codes per gene for the others); the rest are
+ * uniform random codes.  seed_par, lo and hi may be NULL when n_seeded = 0. */
+void oracle_ga_init(uint64_t seed, uint32_t pixel, int pop, int n_seeded, int jitter,
+                    const double *seed_par, const double *lo, const double *hi, uint16_t *genes);
 
 /* One generation of the operators S, R, M of the standard GA (Sec. 3,
  * Algorithm 1) with elitism.  Produces generation `gen` (>= 1) from the
@@ -99,11 +103,13 @@ int oracle_ga_step(const uint16_t *genes_in, const double *fit, int pop, int k,
  * initial evaluation).  Pixel p uses RNG pixel id pixel_base + p.
  * best_params [npix][9], best_chi2 [npix], status [npix] (0 ok, 1 non-finite
  * observation, 2 sigma <= 0 or non-finite); final_genes [npix][pop][9] and
- * final_fit [npix][pop] may be NULL.  Returns 0 or -1. */
+ * final_fit [npix][pop] may be NULL.  n_seeded > 0 seeds generation 0 of
+ * pixel p from seed_params [npix][9] as oracle_ga_init does.  Returns 0 or -1. */
 int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, int64_t npix,
                      const oracle_line *lines, int nlines, const double *lo, const double *hi,
                      int pop, int generations, int k, double p_cross, double p_mut,
-                     uint64_t seed, uint32_t pixel_base,
+                     uint64_t seed, uint32_t pixel_base, int n_seeded, int seed_jitter,
+                     const double *seed_params,
                      double *best_params, double *best_chi2, int32_t *status,
                      uint16_t *final_genes, double *final_fit);
 

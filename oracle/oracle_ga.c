@@ -24,6 +24,13 @@
  *    floor(p_k * 65536 + 0.5).
  *  - elitism: the best individual is copied unchanged into slot 0; slots
  *    1 .. pop-1 hold the children of pairs (2p+1, 2p+2).
+ *  - seeding (Sec. 5.5: first guesses placed in the initial population):
+ *    individuals 0 .. n_seeded-1 of generation 0 encode a first guess p of
+ *    the pixel, gene = floor(65535 clamp((p - u) / (v - u), 0, 1) + 0.5),
+ *    the inverse of the decoding equation rounded to the nearest code;
+ *    individual 0 keeps it exactly, individual i >= 1 adds to gene j the
+ *    integer d - J, d uniform in [0, 2J] from word j of stream purpose 5
+ *    (J = seed_jitter), clamped to [0, 65535].
  */
 #include "oracle.h"
 
@@ -97,12 +104,39 @@ void oracle_decode(const uint16_t *genes, const double *lo, const double *hi, do
         par[j] = lo[j] + (hi[j] - lo[j]) * (double)genes[j] / 65535.0;
 }
 
-void oracle_ga_init(uint64_t seed, uint32_t pixel, int pop, uint16_t *genes)
+/* Encoding: the gene whose decoded value lies nearest to p inside [u, v]. */
+static uint16_t encode(double p, double lo, double hi)
 {
-    for (int i = 0; i < pop; ++i)
+    const double span = hi - lo;
+    double u = (p - lo) / (span > 0.0 ? span : 1.0);
+    if (u < 0.0)
+        u = 0.0;
+    if (u > 1.0)
+        u = 1.0;
+    return (uint16_t)floor(u * 65535.0 + 0.5);
+}
+
+void oracle_ga_init(uint64_t seed, uint32_t pixel, int pop, int n_seeded, int jitter,
+                    const double *seed_par, const double *lo, const double *hi, uint16_t *genes)
+{
+    for (int i = 0; i < pop; ++i) {
+        uint16_t *g = genes + i * NGENE;
+        if (i < n_seeded && seed_par) {
+            for (int j = 0; j < NGENE; ++j) {
+                int v = encode(seed_par[j], lo[j], hi[j]);
+                if (i > 0) {
+                    const uint32_t w = oracle_rng_word(seed, pixel, 0u, (uint32_t)i, 5u,
+                                                       (uint32_t)j);
+                    v += (int)uniform_upto(w, 2u * (uint32_t)jitter) - jitter;
+                    v = v < 0 ? 0 : (v > 65535 ? 65535 : v);
+                }
+                g[j] = (uint16_t)v;
+            }
+            continue;
+        }
         for (int j = 0; j < NGENE; ++j)
-            genes[i * NGENE + j] = (uint16_t)(oracle_rng_word(seed, pixel, 0u, (uint32_t)i, 0u,
-                                                              (uint32_t)j) >> 16);
+            g[j] = (uint16_t)(oracle_rng_word(seed, pixel, 0u, (uint32_t)i, 0u, (uint32_t)j) >> 16);
+    }
 }
 
 /* fitness with NaN read as +infinity */
@@ -238,11 +272,14 @@ int oracle_ga_step(const uint16_t *genes_in, const double *fit, int pop, int k,
 int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, int64_t npix,
                      const oracle_line *lines, int nlines, const double *lo, const double *hi,
                      int pop, int generations, int k, double p_cross, double p_mut,
-                     uint64_t seed, uint32_t pixel_base,
+                     uint64_t seed, uint32_t pixel_base, int n_seeded, int seed_jitter,
+                     const double *seed_params,
                      double *best_params, double *best_chi2, int32_t *status,
                      uint16_t *final_genes, double *final_fit)
 {
     if (pop < 2 || k < 1 || k > pop || k > 64 || generations < 0)
+        return -1;
+    if (n_seeded < 0 || n_seeded > pop || seed_jitter < 0 || (n_seeded > 0 && !seed_params))
         return -1;
     const int L = oracle__total_samples(lines, nlines);
     int err = 0;
@@ -282,7 +319,8 @@ int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, i
             const uint32_t pix = pixel_base + (uint32_t)p;
             const double m = mu ? mu[p] : 1.0;
             double par[NGENE];
-            oracle_ga_init(seed, pix, pop, g0);
+            oracle_ga_init(seed, pix, pop, n_seeded, seed_jitter,
+                           seed_params ? seed_params + p * NGENE : NULL, lo, hi, g0);
             for (int i = 0; i < pop; ++i) {
                 oracle_decode(g0 + i * NGENE, lo, hi, par);
                 fit[i] = oracle__chi2_single(par, m, lines, nlines, o, s, scratch);

@@ -50,8 +50,9 @@ class MeBounds(C.Structure):
 
 class GaConfigC(C.Structure):
     _fields_ = [("pop", C.c_int32), ("generations", C.c_int32), ("tournament_k", C.c_int32),
-                ("reserved0", C.c_int32), ("p_cross", C.c_float), ("p_mut", C.c_float),
-                ("seed", C.c_uint64), ("pixel_base", C.c_uint32), ("reserved", C.c_int32 * 7)]
+                ("n_seeded", C.c_int32), ("p_cross", C.c_float), ("p_mut", C.c_float),
+                ("seed", C.c_uint64), ("pixel_base", C.c_uint32), ("seed_jitter", C.c_int32),
+                ("seed_params", C.c_void_p), ("reserved", C.c_int32 * 4)]
 
 
 @dataclasses.dataclass
@@ -64,6 +65,9 @@ class GAConfig:
     p_mut: float = 0.05
     seed: int = 0
     pixel_base: int = 0
+    n_seeded: int = 0
+    seed_jitter: int = 0
+    seed_params: Optional[torch.Tensor] = None   # [npix, 9] float32 device tensor
 
     def c(self) -> GaConfigC:
         cfg = GaConfigC()
@@ -74,6 +78,11 @@ class GAConfig:
         cfg.p_mut = self.p_mut
         cfg.seed = self.seed
         cfg.pixel_base = self.pixel_base
+        cfg.n_seeded = self.n_seeded
+        cfg.seed_jitter = self.seed_jitter
+        if self.seed_params is not None:
+            _dev(self.seed_params, torch.float32, "seed_params")
+            cfg.seed_params = self.seed_params.data_ptr()
         return cfg
 
 
@@ -97,7 +106,7 @@ _SIGS = {
     "me_synth_f64": ([_vp, _i64, _lp, _gp, _i32, _vp, _vp, _vp], C.c_int),
     "me_chi2": ([_vp, _i64, _i32, _vp, _vp, _vp, _lp, _gp, _i32, _vp, _vp], C.c_int),
     "me_chi2_f64": ([_vp, _i64, _i32, _vp, _vp, _vp, _lp, _gp, _i32, _vp, _vp], C.c_int),
-    "ga_init": ([_i64, _cp, _vp, _vp], C.c_int),
+    "ga_init": ([_i64, _cp, _bp, _vp, _vp], C.c_int),
     "ga_decode": ([_vp, _i64, _bp, _vp, _vp], C.c_int),
     "ga_evaluate": ([_vp, _i64, _i32, _bp, _vp, _vp, _vp, _lp, _gp, _i32, _vp, _vp], C.c_int),
     "ga_evaluate_f64": ([_vp, _i64, _i32, _bp, _vp, _vp, _vp, _lp, _gp, _i32, _vp, _vp],
@@ -111,6 +120,19 @@ _SIGS = {
                        _vp, C.c_size_t, _vp], C.c_int),
     "me_refine_f64": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _i32, _vp, _vp, _vp, _vp],
                       C.c_int),
+    "mlp_param_count": ([], C.c_int64),
+    "mlp_workspace_bytes": ([_i64], C.c_size_t),
+    "mlp_init": ([_vp, C.c_uint64, _vp], C.c_int),
+    "mlp_features": ([_vp, _i64, _gp, _i32, _vp, _vp], C.c_int),
+    "mlp_forward": ([_vp, _vp, _i64, _i32, _vp, _vp, C.c_size_t, _vp], C.c_int),
+    "mlp_grad": ([_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int),
+    "mlp_adam": ([_vp, _vp, _vp, _vp, _i32, C.c_float, _vp], C.c_int),
+    "mlp_draw_examples": ([C.c_uint64, _i64, _i64, _bp, _vp, _vp, _vp], C.c_int),
+    "mlp_add_noise": ([C.c_uint64, _i64, _vp, _i64, _gp, _i32, C.c_float, _vp, _vp], C.c_int),
+    "mlp_unscale": ([_vp, _i64, _bp, _vp, _vp], C.c_int),
+    "mlp_train_workspace_bytes": ([_i64], C.c_size_t),
+    "mlp_train": ([_vp, _vp, _vp, _i32, _i32, _i64, C.c_float, C.c_uint64, _lp, _gp, _i32, _bp,
+                   C.c_float, _i32, _vp, _vp, C.c_size_t, _vp], C.c_int),
     "gs_create": ([C.c_size_t, _i32, C.POINTER(_vp)], C.c_int),
     "gs_submit": ([_vp, _vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _cp, _vp, _vp, _vp,
                    C.POINTER(C.c_uint64)], C.c_int),
@@ -264,10 +286,11 @@ def me_chi2(params, obs, sigma, lines, grids, mu=None, out=None):
 # --------------------------------------------------------------------------- #
 # genetic operators
 
-def ga_init(npix: int, cfg: GAConfig, device="cuda"):
+def ga_init(npix: int, cfg: GAConfig, bnds: Optional[MeBounds] = None, device="cuda"):
     genes = torch.empty((npix, cfg.pop, NPAR), dtype=torch.uint16, device=device)
     c = cfg.c()
-    _check(lib().ga_init(npix, C.byref(c), _ptr(genes), _stream(genes)))
+    _check(lib().ga_init(npix, C.byref(c), None if bnds is None else C.byref(bnds), _ptr(genes),
+                         _stream(genes)))
     return genes
 
 
@@ -404,7 +427,7 @@ class ServingSession:
                                C.byref(bnds), C.byref(c), _ptr(out["params"]), _ptr(out["chi2"]),
                                _ptr(out["status"]), C.byref(rid)))
         # keep the inputs alive with the outputs until the session ends
-        self._req[rid.value] = dict(out=out, keep=(obs, sigma, mu))
+        self._req[rid.value] = dict(out=out, keep=(obs, sigma, mu, cfg.seed_params))
         return rid.value
 
     def step(self):
@@ -437,3 +460,98 @@ class ServingSession:
             self.close()
         except Exception:
             pass
+
+
+class MLP:
+    """The learned proposal network (mlp_* in the C ABI): FP32 master weights,
+    Adam moments and a workspace on the device; every step runs in the
+    library's kernels (MFMA BF16 products by default, precision=1 for FP32)."""
+
+    def __init__(self, seed=0, device="cuda", precision=0):
+        self.device = torch.device(device)
+        self.precision = precision
+        self.n = int(lib().mlp_param_count())
+        self.master = torch.empty(self.n, dtype=torch.float32, device=self.device)
+        self.m = torch.zeros_like(self.master)
+        self.v = torch.zeros_like(self.master)
+        self.grad = torch.zeros_like(self.master)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        self.step_no = 0
+        self._ws = None
+        self._ws_batch = 0
+        _check(lib().mlp_init(_ptr(self.master), int(seed), _stream(self.master)))
+
+    def _workspace(self, batch):
+        if self._ws is None or self._ws_batch < batch:
+            nb = int(lib().mlp_workspace_bytes(int(batch)))
+            self._ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+            self._ws_batch = batch
+        return self._ws, int(lib().mlp_workspace_bytes(int(self._ws_batch)))
+
+    def features(self, obs, grids):
+        npix = obs.shape[0]
+        _dev(obs, torch.float32, "obs")
+        x = torch.empty((npix, 1024), dtype=torch.float32, device=obs.device)
+        ga = (MeGrid * len(grids))(*grids)
+        _check(lib().mlp_features(_ptr(obs), npix, ga, len(grids), _ptr(x), _stream(obs)))
+        return x
+
+    def forward(self, x, precision=None):
+        n = x.shape[0]
+        _dev(x, torch.float32, "x", (n, 1024))
+        y = torch.empty((n, NPAR), dtype=torch.float32, device=x.device)
+        ws, nb = self._workspace(n)
+        _check(lib().mlp_forward(_ptr(self.master), _ptr(x), n,
+                                 self.precision if precision is None else precision, _ptr(y),
+                                 _ptr(ws), nb, _stream(x)))
+        return y
+
+    def compute_grad(self, x, target, precision=None):
+        b = x.shape[0]
+        _dev(x, torch.float32, "x", (b, 1024))
+        _dev(target, torch.float32, "target", (b, NPAR))
+        ws, nb = self._workspace(b)
+        _check(lib().mlp_grad(_ptr(self.master), _ptr(x), _ptr(target), b,
+                              self.precision if precision is None else precision,
+                              _ptr(self.grad), _ptr(self.loss), _ptr(ws), nb, _stream(x)))
+        return self.grad, self.loss
+
+    def adam(self, lr):
+        self.step_no += 1
+        _check(lib().mlp_adam(_ptr(self.master), _ptr(self.m), _ptr(self.v), _ptr(self.grad),
+                              self.step_no, float(lr), _stream(self.master)))
+
+    def examples(self, seed, first, n, lines, grids, bnds, sigma_rel=1e-3):
+        """n noisy synthetic training pairs (features, scaled targets), drawn,
+        synthesised and normalised on the device."""
+        params = torch.empty((n, NPAR), dtype=torch.float32, device=self.device)
+        target = torch.empty_like(params)
+        _check(lib().mlp_draw_examples(int(seed), int(first), n, C.byref(bnds), _ptr(params),
+                                       _ptr(target), _stream(params)))
+        stokes = me_synth(params, lines, grids)
+        ga = (MeGrid * len(grids))(*grids)
+        _check(lib().mlp_add_noise(int(seed), int(first), _ptr(params), n, ga, len(grids),
+                                   float(sigma_rel), _ptr(stokes), _stream(params)))
+        return self.features(stokes, grids), target
+
+    def train(self, lines, grids, bnds, steps, batch=512, lr=1e-3, seed=1, sigma_rel=1e-3):
+        """`steps` Adam steps on fresh synthetic examples (one library call);
+        returns the per-step losses as a device tensor."""
+        nb = int(lib().mlp_train_workspace_bytes(int(batch)))
+        if getattr(self, "_tws", None) is None or self._tws.numel() < nb:
+            self._tws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        losses = torch.empty(max(int(steps), 1), dtype=torch.float32, device=self.device)
+        la, ga, nl = _lines(lines, grids)
+        _check(lib().mlp_train(_ptr(self.master), _ptr(self.m), _ptr(self.v), self.step_no + 1,
+                               int(steps), int(batch), float(lr), int(seed), la, ga, nl,
+                               C.byref(bnds), float(sigma_rel), self.precision, _ptr(losses),
+                               _ptr(self._tws), self._tws.numel(), _stream(self.master)))
+        self.step_no += int(steps)
+        return losses[:steps]
+
+    def predict(self, obs, grids, bnds):
+        """First-guess parameters [npix, 9] for observations [npix, 4, L]."""
+        y = self.forward(self.features(obs, grids))
+        params = torch.empty_like(y)
+        _check(lib().mlp_unscale(_ptr(y), y.shape[0], C.byref(bnds), _ptr(params), _stream(y)))
+        return params

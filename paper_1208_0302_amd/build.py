@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libgenesis_hip.so")
-SRCS = [os.path.join(HERE, "csrc", f) for f in ("genesis.hip", "serving.hip")]
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("genesis.hip", "serving.hip", "mlp.hip")]
 DEPS = SRCS + [os.path.join(HERE, "csrc", f) for f in
                ("genesis_device.h", "genesis_common.h", "voigt_rational.h", "weideman36.h")] + \
        [os.path.join(ROOT, "include", "genesis.h")]

@@ -90,6 +90,15 @@ int pack_ga(const ga_config *cfg, GaConst &ga)
     ga.key.k0 = (uint32_t)(cfg->seed & 0xFFFFFFFFu);
     ga.key.k1 = (uint32_t)(cfg->seed >> 32);
     ga.pixel_base = cfg->pixel_base;
+    if (cfg->n_seeded < 0 || cfg->n_seeded > cfg->pop)
+        return fail(ME_EINVAL, "n_seeded = %d outside [0, pop]", cfg->n_seeded);
+    if (cfg->seed_jitter < 0 || cfg->seed_jitter > 32767)
+        return fail(ME_EINVAL, "seed_jitter = %d outside [0, 32767]", cfg->seed_jitter);
+    if (cfg->n_seeded > 0 && !cfg->seed_params)
+        return fail(ME_EINVAL, "n_seeded > 0 needs seed_params");
+    ga.n_seeded = cfg->n_seeded;
+    ga.seed_jitter = cfg->seed_jitter;
+    ga.seed_params = cfg->n_seeded > 0 ? cfg->seed_params : nullptr;
     return ME_OK;
 }
 
@@ -218,24 +227,19 @@ __global__ __launch_bounds__(1024) void k_fitness(const Real *__restrict__ param
     }
 }
 
-__global__ void k_ga_init(int64_t npix, int pop, Key key, uint32_t pixel_base,
-                          uint16_t *__restrict__ genes)
+__global__ void k_ga_init(int64_t npix, GaConst ga, Bounds b, uint16_t *__restrict__ genes)
 {
+    const int pop = ga.pop;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= npix * pop)
         return;
     const int64_t p = t / pop;
     const int i = (int)(t - p * pop);
-    const uint32_t pix = pixel_base + (uint32_t)p;
+    uint32_t g[GENESIS_NPAR];
+    initial_genes(ga.pixel_base + (uint32_t)p, p, i, ga, b, g);
 #pragma unroll
-    for (int blk = 0; blk < 3; ++blk) {
-        const uint4 w = philox(pix, 0u, (uint32_t)i, (kInit << 24) | (uint32_t)blk, key);
-        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (4 * blk + q < GENESIS_NPAR)
-                genes[t * GENESIS_NPAR + 4 * blk + q] = (uint16_t)(ws[q] >> 16);
-    }
+    for (int j = 0; j < GENESIS_NPAR; ++j)
+        genes[t * GENESIS_NPAR + j] = (uint16_t)g[j];
 }
 
 template <typename Real>
@@ -378,16 +382,11 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real> a)
         const int gstride = GENESIS_NPAR * pop;
         int cur = 0;  // offset of the current generation's gene buffer
         if (active) {
+            uint32_t g0[GENESIS_NPAR];
+            initial_genes(pix, p, tid, a.ga, a.b, g0);
 #pragma unroll
-            for (int blk = 0; blk < 3; ++blk) {
-                const uint4 w = philox(pix, 0u, (uint32_t)tid, (kInit << 24) | (uint32_t)blk,
-                                       a.ga.key);
-                const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (4 * blk + q < GENESIS_NPAR)
-                        s.genes[(4 * blk + q) * pop + tid] = (uint16_t)(ws[q] >> 16);
-            }
+            for (int j = 0; j < GENESIS_NPAR; ++j)
+                s.genes[j * pop + tid] = (uint16_t)g0[j];
         }
         Real f = (Real)0;
         for (int t = 0;; ++t) {
@@ -988,11 +987,16 @@ int me_chi2_f64(const double *params, int64_t npix, int32_t pop, const double *o
                                        grids, nlines, chi2, stream);
 }
 
-int ga_init(int64_t npix, const ga_config *cfg, uint16_t *genes, void *stream)
+int ga_init(int64_t npix, const ga_config *cfg, const me_bounds *bounds, uint16_t *genes,
+            void *stream)
 {
     GaConst ga;
     if (int rc = pack_ga(cfg, ga))
         return rc;
+    Bounds b{};
+    if (ga.n_seeded > 0)
+        if (int rc = pack_bounds(bounds, b))
+            return rc;
     if (npix < 0)
         return fail(ME_EINVAL, "npix must be >= 0");
     if (npix == 0)
@@ -1005,7 +1009,7 @@ int ga_init(int64_t npix, const ga_config *cfg, uint16_t *genes, void *stream)
     if (blocks > kMaxGrid)
         return fail(ME_EINVAL, "npix * pop too large");
     hipLaunchKernelGGL(k_ga_init, dim3((unsigned)blocks), dim3(bs), 0, as_stream(stream), npix,
-                       cfg->pop, ga.key, ga.pixel_base, genes);
+                       ga, b, genes);
     return check_launch("ga_init");
 }
 

@@ -91,16 +91,11 @@ __global__ __launch_bounds__(1024) void k_ga_advance(const ReqDesc *__restrict__
     int g = d.gen_done;
     if (g < 0) {
         if (active) {
+            uint32_t g0[GENESIS_NPAR];
+            initial_genes(pix, p, tid, d.ga, d.b, g0);
 #pragma unroll
-            for (int blk4 = 0; blk4 < 3; ++blk4) {
-                const uint4 w = philox(pix, 0u, (uint32_t)tid, (kInit << 24) | (uint32_t)blk4,
-                                       d.ga.key);
-                const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (4 * blk4 + q < GENESIS_NPAR)
-                        s.genes[(4 * blk4 + q) * pop + tid] = (uint16_t)(ws[q] >> 16);
-            }
+            for (int j = 0; j < GENESIS_NPAR; ++j)
+                s.genes[j * pop + tid] = (uint16_t)g0[j];
             f = evaluate_lds(s.genes, pop, tid, d.b, mu, d.ls, s.obs, w2, inv_nu);
             s.fit[tid] = f;
         }

@@ -26,7 +26,7 @@ def _declared():
 def test_library_exports_every_declared_symbol():
     L = g.lib()
     declared = _declared()
-    assert len(declared) >= 25
+    assert len(declared) >= 35
     for name in declared:
         assert hasattr(L, name), name
     assert sorted(g.EXPORTED) == declared
@@ -81,7 +81,17 @@ def test_invalid_arguments_fail_before_device_work():
     for kw in (dict(pop=1), dict(pop=2000), dict(tournament_k=9), dict(tournament_k=0),
                dict(p_cross=1.5), dict(p_mut=-0.1), dict(generations=-1)):
         cfg = g.GAConfig(**{**dict(pop=16, tournament_k=4), **kw}).c()
-        assert L.ga_init(4, C.byref(cfg), None, None) == g.ME_EINVAL
+        assert L.ga_init(4, C.byref(cfg), None, None, None) == g.ME_EINVAL
+    # bad seeding: more seeded slots than the population, jitter out of range,
+    # seeded slots without first guesses or without a search box
+    for kw in (dict(n_seeded=17), dict(n_seeded=-1), dict(seed_jitter=40000)):
+        cfg = g.GAConfig(**{**dict(pop=16), **kw}).c()
+        assert L.ga_init(4, C.byref(cfg), None, None, None) == g.ME_EINVAL
+    cfg = g.GAConfig(pop=16, n_seeded=4).c()
+    assert L.ga_init(4, C.byref(cfg), None, None, None) == g.ME_EINVAL
+    assert b"seed_params" in L.me_last_error()
+    cfg.seed_params = 256          # never dereferenced: the missing box fails first
+    assert L.ga_init(4, C.byref(cfg), None, None, None) == g.ME_EINVAL
     cfg = g.GAConfig(pop=16).c()
     assert L.ga_step(None, None, 2, C.byref(cfg), 0, None, None, None, None, None,
                      None) == g.ME_EINVAL      # generation 0 is not a step

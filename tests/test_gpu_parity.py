@@ -215,7 +215,7 @@ def _problem(kind, npix, seed, noise=True, dtype=np.float32):
 
 
 def _stepwise(obs_t, sig_t, lines, grids, b, cfg):
-    genes = g.ga_init(obs_t.shape[0], cfg)
+    genes = g.ga_init(obs_t.shape[0], cfg, b)
     fit = g.ga_evaluate(genes, b, obs_t, sig_t, lines, grids)
     for t in range(1, cfg.generations + 1):
         genes = g.ga_step(genes, fit, cfg, t, diagnostics=False)["genes"]

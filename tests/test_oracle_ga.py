@@ -211,3 +211,69 @@ def test_loop_converges_on_noise_free_truth():
                          p_cross=PC, p_mut=PM, seed=0)
     ratio = r["chi2"] / r0["chi2"]
     assert np.all(ratio < 0.5) and np.median(ratio) < 0.02
+
+
+# ---- seeding of generation 0 with first guesses (Sec. 5.5) -------------------
+
+def test_seeded_init_encodes_and_jitters():
+    lo, hi = si.PRIOR_LO, si.PRIOR_HI
+    guess = si.draw_uniform_box(1, 5)[0]
+    pop, ns, jit = 64, 40, 3
+    g = oracle.ga_init(7, 11, pop, n_seeded=ns, jitter=jit, seed_params=guess, lo=lo, hi=hi)
+    # individual 0 decodes to the nearest code of the guess: within half a step
+    dec = oracle.decode(g[0], lo, hi)
+    assert np.all(np.abs(dec - guess) <= 0.5 * (hi - lo) / 65535 * (1 + 1e-12))
+    # the jittered copies stay within +-jit codes and use every offset
+    d = g[1:ns].astype(int) - g[0].astype(int)
+    assert np.abs(d).max() <= jit
+    assert set(np.unique(d)) == set(range(-jit, jit + 1))
+    # offsets are near-uniform over 2 jit + 1 values (39 x 9 draws)
+    counts = np.array([(d == v).sum() for v in range(-jit, jit + 1)])
+    assert stats.chisquare(counts).pvalue > 1e-4
+    # the unseeded tail is the plain random population, unchanged by seeding
+    assert np.array_equal(g[ns:], oracle.ga_init(7, 11, pop)[ns:])
+    # no seeds: the plain population
+    assert np.array_equal(oracle.ga_init(7, 11, pop, n_seeded=0, jitter=jit),
+                          oracle.ga_init(7, 11, pop))
+
+
+def test_seeded_init_clamps_to_box():
+    lo, hi = si.PRIOR_LO, si.PRIOR_HI
+    guess = np.where(np.arange(9) % 2 == 0, lo - 5.0, hi + 5.0)
+    g = oracle.ga_init(1, 0, 8, n_seeded=8, jitter=100, seed_params=guess, lo=lo, hi=hi)
+    want = np.where(np.arange(9) % 2 == 0, 0, 65535)
+    assert np.array_equal(g[0], want)
+    # jitter never leaves [0, 65535]
+    assert g.min() >= 0 and g.max() <= 65535
+    assert np.all(np.abs(g[1:].astype(int) - want) <= 100)
+    # exact box corners encode exactly
+    g = oracle.ga_init(1, 0, 2, n_seeded=1, seed_params=hi, lo=lo, hi=hi)
+    assert np.all(g[0] == 65535)
+    g = oracle.ga_init(1, 0, 2, n_seeded=1, seed_params=lo, lo=lo, hi=hi)
+    assert np.all(g[0] == 0)
+
+
+def test_seeded_inversion_starts_at_the_guess():
+    # a perfect first guess makes generation 0 already near-optimal: with no
+    # generations the best chi-square is that of the truth's nearest code,
+    # far below the random population's best
+    lines = [oracle.make_line(l["lambda0"], l["Jl"], l["gl"], l["Ju"], l["gu"], *si.grid(l, n), n)
+             for l, n in si.line_set("tiny")]
+    truth = si.draw_truth(4, 21)
+    obs = oracle.me_synth(truth, lines)
+    sig = si.sigma_for(truth)
+    obs = obs + sig[:, :, None] * si.std_normal(obs.shape, 21)
+    kw = dict(pop=32, generations=0, k=4, p_cross=0.85, p_mut=0.05, seed=3)
+    r0 = oracle.ga_invert(obs, sig, lines, si.PRIOR_LO, si.PRIOR_HI, **kw)
+    r1 = oracle.ga_invert(obs, sig, lines, si.PRIOR_LO, si.PRIOR_HI, n_seeded=8, seed_jitter=50,
+                          seed_params=truth, **kw)
+    nu = 4 * 100 - 9
+    assert np.all(r1["chi2"] < 2.0)            # reduced chi-square ~ 1 at the truth
+    assert np.all(r0["chi2"] > 10.0 * r1["chi2"])
+    # the elite of generation 0 is the exactly encoded guess or a jittered copy
+    codes = np.array([oracle.ga_init(3, p, 32, 8, 50, truth[p], si.PRIOR_LO, si.PRIOR_HI)
+                      for p in range(4)])
+    direct = oracle.chi2(oracle.decode(codes[:, :1], si.PRIOR_LO, si.PRIOR_HI), obs, sig,
+                         lines)[:, 0]
+    assert np.all(r1["chi2"] <= direct * (1 + 1e-12))
+    assert nu > 0
