@@ -315,6 +315,104 @@ def proposal(args):
     print(json.dumps(out), flush=True)
 
 
+def disc(args):
+    """Precision study on the full-disc configuration: on-disc pixels of a
+    2048 x 2048 map (every `disc_stride`-th), parameters from smooth random
+    fields plus strong-field patches, mu from the disc position, 2 lines x
+    128 samples, noise 1e-3 Ic; population 128, 150 generations.  The GA runs
+    with FP32 synthesis and with packed-FP16 profile synthesis (FP32
+    chi-square); each is followed by 50 FP64 Levenberg-Marquardt iterations.
+    One step = GA + refinement of every pixel of the sample, FP16 synthesis."""
+    import torch
+    import paper_1208_0302_amd as g
+    import synth_inputs as si
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    truth, mu_np, _ = si.full_disc(2048, seed=0, stride=args.disc_stride)
+    npix = truth.shape[0]
+    print("disc: %d on-disc pixels sampled (%.1f s)" % (npix, time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+    lines, grids = [], []
+    for ln, n in si.line_set("slit"):
+        start, step = si.grid(ln, n)
+        lines.append(g.line_from_terms(ln["lambda0"], ln["Jl"], ln["gl"], ln["Ju"], ln["gu"]))
+        grids.append(g.grid(start, step, n))
+    mu = torch.tensor(mu_np, dtype=torch.float32, device=dev)
+    obs = g.me_synth(torch.tensor(truth, dtype=torch.float32, device=dev), lines, grids, mu=mu)
+    sig_np = si.sigma_for(truth, mu=mu_np)
+    sig = torch.tensor(sig_np, dtype=torch.float32, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(20480)
+    obs += sig[:, :, None] * torch.randn(obs.shape, generator=gen, device=dev)
+    obs64, sig64, mu64 = obs.double(), sig.double(), mu.double()
+    b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+
+    def errors(params):
+        d = np.abs(params - truth)
+        d[:, 2] = np.minimum(d[:, 2], 180.0 - d[:, 2])
+        strong = truth[:, 0] >= 500.0
+        out = {}
+        for j, name in enumerate(si.PARAM_NAMES):
+            sel = strong if name in ("incl", "azim") else slice(None)
+            out[name] = {"p50": float(np.percentile(d[sel, j], 50)),
+                         "p90": float(np.percentile(d[sel, j], 90))}
+        return out
+
+    rows, times = {}, {}
+    for name, sp in (("fp32", g.SYNTH_NATIVE), ("fp16", g.SYNTH_FP16)):
+        cfg = g.GAConfig(pop=128, generations=150, tournament_k=4, p_cross=0.85, p_mut=0.05,
+                         seed=0, synth_precision=sp)
+        g.ga_invert(obs[:256], sig[:256], lines, grids, b, cfg, mu=mu[:256])   # warm-up
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        w0 = time.perf_counter()
+        ev[0].record(stream)
+        r = g.ga_invert(obs, sig, lines, grids, b, cfg, mu=mu)
+        ev[1].record(stream)
+        ref = g.me_refine_f64(obs64, sig64, lines, grids, b, r["params"].double().contiguous(),
+                              REFINE_ITERS, mu=mu64)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        times[name] = {"ga_ms": ev[0].elapsed_time(ev[1]), "refine_ms": ev[1].elapsed_time(ev[2]),
+                       "wall_s": wall}
+        rows[name + "_ga"] = errors(r["params"].double().cpu().numpy())
+        rows[name + "_ga_refine"] = errors(ref["params"].cpu().numpy())
+        rows[name + "_ga"]["median_chi2"] = float(r["chi2"].median().item())
+        rows[name + "_ga_refine"]["median_chi2"] = float(ref["chi2"].median().item())
+        print("disc: %s GA %.1f ms, refine %.1f ms" % (name, times[name]["ga_ms"],
+                                                      times[name]["refine_ms"]),
+              file=sys.stderr, flush=True)
+    lines_grids = list(zip(lines, grids))
+    evals = npix * 128 * 151
+    fpe = flops_per_eval(lines_grids)
+    ga_s = times["fp16"]["ga_ms"] / 1e3
+    out = {"metric": "pixel inversions/s, full-disc precision study (FP16 synthesis + FP64 refine)",
+           "value": npix / times["fp16"]["wall_s"], "unit": "pixels/s", "n_gpus": 1, "steps": 1,
+           "warmup": 1, "ms_per_step": times["fp16"]["wall_s"] * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f16",
+           "data": "synthetic (smooth random parameter fields + strong-field patches on a "
+                   "2048^2 disc, mu from the disc position, noise 1e-3 Ic)",
+           "config": {"workload": "full disc 2048^2 (every %d-th of the on-disc pixels), "
+                                  "2 lines x 128, pop 128, G 150, FP32 vs FP16 synthesis, "
+                                  "FP32 chi-square, 50 FP64 L-M iterations" % args.disc_stride,
+                      "npix": npix},
+           "fp32_pixels_per_s": npix / times["fp32"]["wall_s"],
+           "times_ms": times,
+           "error_table": rows,
+           "roofline": {"bound": "alu", "achieved": evals * fpe / ga_s / 1e12,
+                        "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                        "frac": evals * fpe / ga_s / PEAK_FP32_VALU, "traffic": None,
+                        "kernel": "k_ga_invert<float, FP16 synthesis>",
+                        "flop_per_eval": fpe, "evals_per_launch": evals,
+                        "peak_note": "packed FP16 FMA issues at the published 157.3 TFLOP/s "
+                                     "vector rate"}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -326,6 +424,8 @@ def main():
     ap.add_argument("--rate", type=float, default=2.0, help="serving: requests per second")
     ap.add_argument("--window", type=float, default=20.0, help="serving: arrival window [s]")
     ap.add_argument("--gens-per-step", type=int, default=10, help="serving: generations per launch")
+    ap.add_argument("--disc-stride", type=int, default=16,
+                    help="disc: keep every n-th on-disc pixel of the 2048^2 map")
     ap.add_argument("--batch", type=int, default=1024, help="proposal: training batch")
     ap.add_argument("--heldout", type=int, default=16384, help="proposal: held-out pixels")
     ap.add_argument("--chi2-target", type=float, default=2.0,
@@ -355,6 +455,9 @@ def main():
         return
     if args.workload == "proposal":
         proposal(args)
+        return
+    if args.workload == "disc":
+        disc(args)
         return
     import paper_1208_0302_amd as g
     import synth_inputs as si

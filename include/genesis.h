@@ -104,7 +104,13 @@ typedef struct {
  *               single-call result
  *  seed_jitter  see n_seeded, 0 .. 32767
  *  seed_params  [npix][9] device array of first guesses (parameter units),
- *               used when n_seeded > 0 */
+ *               used when n_seeded > 0
+ *  synth_precision  arithmetic of the profile synthesis inside ga_invert:
+ *               GENESIS_SYNTH_NATIVE (that of the entry point) or
+ *               GENESIS_SYNTH_FP16 (FP32 entry point only: Voigt and
+ *               Faraday-Voigt profiles in packed FP16, two wavelengths per
+ *               instruction, Unno-Rachkovsky and chi-square in FP32; needs a
+ *               damping upper bound <= 1) */
 typedef struct {
     int32_t pop;
     int32_t generations;
@@ -116,8 +122,12 @@ typedef struct {
     uint32_t pixel_base;
     int32_t seed_jitter;
     const float *seed_params;
-    int32_t reserved[4];
+    int32_t synth_precision;
+    int32_t reserved[3];
 } ga_config;
+
+#define GENESIS_SYNTH_NATIVE 0
+#define GENESIS_SYNTH_FP16 1
 
 /* Message of the last failure on this thread ("" if none). */
 const char *me_last_error(void);
@@ -144,6 +154,11 @@ int me_line_triplet(double lambda0_A, double geff, me_line *out);
  * with n < 1, or an invalid line. */
 int me_synth(const float *params, int64_t n, const me_line *lines, const me_grid *grids,
              int32_t nlines, const float *mu, float *stokes, void *stream);
+/* FP32 parameters and Stokes vectors, profiles of the Zeeman components in
+ * packed FP16 as in ga_config.synth_precision = GENESIS_SYNTH_FP16 (the same
+ * device code); damping of every model must lie in [0, 1]. */
+int me_synth_f16(const float *params, int64_t n, const me_line *lines, const me_grid *grids,
+                 int32_t nlines, const float *mu, float *stokes, void *stream);
 /* FP64 arithmetic with the Weideman N = 36 Faddeeva approximation. */
 int me_synth_f64(const double *params, int64_t n, const me_line *lines, const me_grid *grids,
                  int32_t nlines, const double *mu, double *stokes, void *stream);

@@ -48,11 +48,16 @@ class MeBounds(C.Structure):
     _fields_ = [("lo", C.c_double * NPAR), ("hi", C.c_double * NPAR)]
 
 
+SYNTH_NATIVE = 0
+SYNTH_FP16 = 1
+
+
 class GaConfigC(C.Structure):
     _fields_ = [("pop", C.c_int32), ("generations", C.c_int32), ("tournament_k", C.c_int32),
                 ("n_seeded", C.c_int32), ("p_cross", C.c_float), ("p_mut", C.c_float),
                 ("seed", C.c_uint64), ("pixel_base", C.c_uint32), ("seed_jitter", C.c_int32),
-                ("seed_params", C.c_void_p), ("reserved", C.c_int32 * 4)]
+                ("seed_params", C.c_void_p), ("synth_precision", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 @dataclasses.dataclass
@@ -68,6 +73,7 @@ class GAConfig:
     n_seeded: int = 0
     seed_jitter: int = 0
     seed_params: Optional[torch.Tensor] = None   # [npix, 9] float32 device tensor
+    synth_precision: int = 0                     # SYNTH_NATIVE or SYNTH_FP16
 
     def c(self) -> GaConfigC:
         cfg = GaConfigC()
@@ -80,6 +86,7 @@ class GAConfig:
         cfg.pixel_base = self.pixel_base
         cfg.n_seeded = self.n_seeded
         cfg.seed_jitter = self.seed_jitter
+        cfg.synth_precision = self.synth_precision
         if self.seed_params is not None:
             _dev(self.seed_params, torch.float32, "seed_params")
             cfg.seed_params = self.seed_params.data_ptr()
@@ -104,6 +111,7 @@ _SIGS = {
     "me_line_triplet": ([C.c_double, C.c_double, _lp], C.c_int),
     "me_synth": ([_vp, _i64, _lp, _gp, _i32, _vp, _vp, _vp], C.c_int),
     "me_synth_f64": ([_vp, _i64, _lp, _gp, _i32, _vp, _vp, _vp], C.c_int),
+    "me_synth_f16": ([_vp, _i64, _lp, _gp, _i32, _vp, _vp, _vp], C.c_int),
     "me_chi2": ([_vp, _i64, _i32, _vp, _vp, _vp, _lp, _gp, _i32, _vp, _vp], C.c_int),
     "me_chi2_f64": ([_vp, _i64, _i32, _vp, _vp, _vp, _lp, _gp, _i32, _vp, _vp], C.c_int),
     "ga_init": ([_i64, _cp, _bp, _vp, _vp], C.c_int),
@@ -248,8 +256,9 @@ def _real(t: torch.Tensor):
 # --------------------------------------------------------------------------- #
 # forward model
 
-def me_synth(params: torch.Tensor, lines, grids, mu=None, out=None):
-    """Stokes [n, 4, L] from params [n, 9] (Sec. 5 analytic solution)."""
+def me_synth(params: torch.Tensor, lines, grids, mu=None, out=None, fp16=False):
+    """Stokes [n, 4, L] from params [n, 9] (Sec. 5 analytic solution).
+    fp16=True (float32 tensors only): profiles in packed FP16 (me_synth_f16)."""
     dt = _real(params)
     n = params.shape[0]
     L = total_samples(grids)
@@ -259,7 +268,12 @@ def me_synth(params: torch.Tensor, lines, grids, mu=None, out=None):
         out = torch.empty((n, 4, L), dtype=dt, device=params.device)
     _dev(out, dt, "out", (n, 4, L))
     la, ga, nl = _lines(lines, grids)
-    f = lib().me_synth if dt == torch.float32 else lib().me_synth_f64
+    if fp16:
+        if dt != torch.float32:
+            raise ValueError("fp16 synthesis takes float32 parameters")
+        f = lib().me_synth_f16
+    else:
+        f = lib().me_synth if dt == torch.float32 else lib().me_synth_f64
     _check(f(_ptr(params), n, la, ga, nl, _ptr(mu), _ptr(out), _stream(params)))
     return out
 

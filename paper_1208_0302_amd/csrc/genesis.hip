@@ -11,6 +11,8 @@
 // in LDS, random numbers from a counter-based stream.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
@@ -96,6 +98,9 @@ int pack_ga(const ga_config *cfg, GaConst &ga)
         return fail(ME_EINVAL, "seed_jitter = %d outside [0, 32767]", cfg->seed_jitter);
     if (cfg->n_seeded > 0 && !cfg->seed_params)
         return fail(ME_EINVAL, "n_seeded > 0 needs seed_params");
+    if (cfg->synth_precision != GENESIS_SYNTH_NATIVE && cfg->synth_precision != GENESIS_SYNTH_FP16)
+        return fail(ME_EINVAL, "synth_precision = %d is not a GENESIS_SYNTH_* value",
+                    cfg->synth_precision);
     ga.n_seeded = cfg->n_seeded;
     ga.seed_jitter = cfg->seed_jitter;
     ga.seed_params = cfg->n_seeded > 0 ? cfg->seed_params : nullptr;
@@ -180,6 +185,26 @@ __global__ __launch_bounds__(256) void k_me_synth(const Real *__restrict__ param
     model_setup(p, mu ? (double)mu[i] : 1.0, m);
     StokesSink<Real> s{out + i * 4 * (int64_t)ls.L, ls.L};
     synthesize(m, ls, s);
+}
+
+// Stokes vectors with the FP16 profile synthesis of ga_invert's
+// GENESIS_SYNTH_FP16 mode (one thread per model).
+__global__ __launch_bounds__(256) void k_me_synth_h(const float *__restrict__ params, int64_t n,
+                                                    DevLines<float> ls, DevLinesH lh,
+                                                    const float *__restrict__ mu,
+                                                    float *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    double p[GENESIS_NPAR];
+#pragma unroll
+    for (int j = 0; j < GENESIS_NPAR; ++j)
+        p[j] = (double)params[i * GENESIS_NPAR + j];
+    ModelH m;
+    model_setup(p, mu ? (double)mu[i] : 1.0, m);
+    StokesSink<float> s{out + i * 4 * (int64_t)ls.L, ls.L};
+    synthesize_h(m, ls, lh, s);
 }
 
 // Fitness of every individual of every pixel: from params (me_chi2) or from
@@ -330,8 +355,15 @@ __global__ __launch_bounds__(1024) void k_ga_step(StepArgs<Real> a)
     }
 }
 
-template <typename Real>
-struct InvertArgs {
+template <int SYN>
+struct SynLines {};
+template <>
+struct SynLines<GENESIS_SYNTH_FP16> {
+    DevLinesH lh;
+};
+
+template <typename Real, int SYN = GENESIS_SYNTH_NATIVE>
+struct InvertArgs : SynLines<SYN> {
     const Real *obs, *sigma, *mu;
     int64_t npix;
     int32_t generations;
@@ -346,8 +378,8 @@ struct InvertArgs {
 // The whole of Algorithm 1 for one pixel per workgroup: the population
 // lives in LDS (two buffers: parents and children), lane i owns
 // individual i.
-template <typename Real>
-__global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real> a)
+template <typename Real, int SYN>
+__global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN> a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int pop = a.ga.pop;
@@ -392,7 +424,11 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real> a)
         for (int t = 0;; ++t) {
             // evaluate generation t (each lane reads only its own genes)
             if (active) {
-                f = evaluate_lds(s.genes + cur, pop, tid, a.b, mu, a.ls, s.obs, w2, inv_nu);
+                if constexpr (SYN == GENESIS_SYNTH_FP16)
+                    f = evaluate_lds_h(s.genes + cur, pop, tid, a.b, mu, a.ls, a.lh, s.obs, w2,
+                                       inv_nu);
+                else
+                    f = evaluate_lds(s.genes + cur, pop, tid, a.b, mu, a.ls, s.obs, w2, inv_nu);
                 s.fit[tid] = f;
             }
             __syncthreads();
@@ -805,19 +841,22 @@ int step_impl(const uint16_t *genes_in, const Real *fitness, int64_t npix, const
     return check_launch("ga_step");
 }
 
-template <typename Real>
+template <typename Real, int SYN>
 int invert_impl(const Real *obs, const Real *sigma, const Real *mu, int64_t npix,
                 const me_line *lines, const me_grid *grids, int nlines, const me_bounds *bounds,
                 const ga_config *cfg, Real *best_params, Real *best_chi2, int32_t *status,
                 uint16_t *final_genes, Real *final_fitness, void *stream)
 {
-    InvertArgs<Real> a{};
+    InvertArgs<Real, SYN> a{};
     if (int rc = pack_lines(lines, grids, nlines, a.ls))
         return rc;
     if (int rc = pack_bounds(bounds, a.b))
         return rc;
     if (int rc = pack_ga(cfg, a.ga))
         return rc;
+    if (SYN == GENESIS_SYNTH_FP16 && !(bounds->lo[5] >= 0.0 && bounds->hi[5] <= kHalfMaxDamping))
+        return fail(ME_EINVAL, "FP16 synthesis needs damping bounds within [0, %g]",
+                    kHalfMaxDamping);
     if (npix < 0)
         return fail(ME_EINVAL, "npix must be >= 0");
     if (4 * a.ls.L <= GENESIS_NPAR)
@@ -840,9 +879,35 @@ int invert_impl(const Real *obs, const Real *sigma, const Real *mu, int64_t npix
     a.status = status;
     a.final_genes = final_genes;
     a.final_fitness = final_fitness;
-    hipLaunchKernelGGL(k_ga_invert<Real>, dim3(grid_for(npix)), dim3(block_for_pop(cfg->pop)),
-                       lds, as_stream(stream), a);
+    if constexpr (SYN == GENESIS_SYNTH_FP16)
+        pack_lines_h(a.ls, a.lh);
+    hipLaunchKernelGGL((k_ga_invert<Real, SYN>), dim3(grid_for(npix)),
+                       dim3(block_for_pop(cfg->pop)), lds, as_stream(stream), a);
     return check_launch("ga_invert");
+}
+
+template <typename Real>
+int invert_dispatch(const Real *obs, const Real *sigma, const Real *mu, int64_t npix,
+                    const me_line *lines, const me_grid *grids, int nlines,
+                    const me_bounds *bounds, const ga_config *cfg, Real *best_params,
+                    Real *best_chi2, int32_t *status, uint16_t *final_genes, Real *final_fitness,
+                    void *stream)
+{
+    if (!cfg)
+        return fail(ME_EINVAL, "config must not be NULL");
+    if (cfg->synth_precision == GENESIS_SYNTH_NATIVE)
+        return invert_impl<Real, GENESIS_SYNTH_NATIVE>(obs, sigma, mu, npix, lines, grids, nlines,
+                                                       bounds, cfg, best_params, best_chi2,
+                                                       status, final_genes, final_fitness, stream);
+    if constexpr (std::is_same<Real, float>::value) {
+        if (cfg->synth_precision == GENESIS_SYNTH_FP16)
+            return invert_impl<float, GENESIS_SYNTH_FP16>(obs, sigma, mu, npix, lines, grids,
+                                                          nlines, bounds, cfg, best_params,
+                                                          best_chi2, status, final_genes,
+                                                          final_fitness, stream);
+    }
+    return fail(ME_EINVAL, "synth_precision = %d not available for this entry point",
+                cfg->synth_precision);
 }
 
 
@@ -965,6 +1030,29 @@ int me_synth(const float *params, int64_t n, const me_line *lines, const me_grid
     return synth_impl<float>(params, n, lines, grids, nlines, mu, stokes, stream);
 }
 
+int me_synth_f16(const float *params, int64_t n, const me_line *lines, const me_grid *grids,
+                 int32_t nlines, const float *mu, float *stokes, void *stream)
+{
+    DevLines<float> ls;
+    if (int rc = pack_lines(lines, grids, nlines, ls))
+        return rc;
+    if (n < 0)
+        return fail(ME_EINVAL, "n must be >= 0");
+    if (n == 0)
+        return ME_OK;
+    if (!params || !stokes)
+        return fail(ME_EINVAL, "params and stokes must not be NULL");
+    const int bs = 256;
+    const int64_t blocks = (n + bs - 1) / bs;
+    if (blocks > kMaxGrid)
+        return fail(ME_EINVAL, "n too large");
+    DevLinesH lh;
+    pack_lines_h(ls, lh);
+    hipLaunchKernelGGL(k_me_synth_h, dim3((unsigned)blocks), dim3(bs), 0, as_stream(stream),
+                       params, n, ls, lh, mu, stokes);
+    return check_launch("me_synth_f16");
+}
+
 int me_synth_f64(const double *params, int64_t n, const me_line *lines, const me_grid *grids,
                  int32_t nlines, const double *mu, double *stokes, void *stream)
 {
@@ -1082,7 +1170,7 @@ int ga_invert(const float *obs, const float *sigma, const float *mu, int64_t npi
 {
     (void)workspace;
     (void)ws_bytes;
-    return invert_impl<float>(obs, sigma, mu, npix, lines, grids, nlines, bounds, cfg,
+    return invert_dispatch<float>(obs, sigma, mu, npix, lines, grids, nlines, bounds, cfg,
                               best_params, best_chi2, status, final_genes, final_fitness, stream);
 }
 
@@ -1094,7 +1182,7 @@ int ga_invert_f64(const double *obs, const double *sigma, const double *mu, int6
 {
     (void)workspace;
     (void)ws_bytes;
-    return invert_impl<double>(obs, sigma, mu, npix, lines, grids, nlines, bounds, cfg,
+    return invert_dispatch<double>(obs, sigma, mu, npix, lines, grids, nlines, bounds, cfg,
                                best_params, best_chi2, status, final_genes, final_fitness,
                                stream);
 }

@@ -11,6 +11,7 @@
 #include <string>
 
 #include "genesis_device.h"
+#include "genesis_half.h"
 
 namespace genesis {
 
@@ -180,6 +181,33 @@ __device__ __forceinline__ Real evaluate_lds(const uint16_t *genes_s, int pop, i
     Model<Real> m;
     model_setup(par, mu, m);
     return chi2_of(m, ls, obs_s, w2, inv_nu);
+}
+
+// FP16-synthesis variant of evaluate_lds (FP32 decode set-up and chi-square).
+__device__ __forceinline__ float evaluate_lds_h(const uint16_t *genes_s, int pop, int i,
+                                                const Bounds &b, double mu,
+                                                const DevLines<float> &ls, const DevLinesH &lh,
+                                                const Vec4<float> *obs_s, const float (&w2)[4],
+                                                float inv_nu)
+{
+    uint32_t g[GENESIS_NPAR];
+#pragma unroll
+    for (int j = 0; j < GENESIS_NPAR; ++j)
+        g[j] = genes_s[j * pop + i];
+    double par[GENESIS_NPAR];
+    decode(g, b, par);
+    ModelH m;
+    model_setup(par, mu, m);
+    return chi2_of_h(m, ls, lh, obs_s, w2, inv_nu);
+}
+
+// FP16 strength table of packed lines (after pack_lines).
+inline void pack_lines_h(const DevLines<float> &ls, DevLinesH &out)
+{
+    std::memset(&out, 0, sizeof out);
+    for (int l = 0; l < ls.nlines; ++l)
+        for (int c = 0; c < GENESIS_MAX_COMP; ++c)
+            out.w[l][c] = (half_t)ls.l[l].w[c];
 }
 
 }  // namespace genesis

@@ -336,8 +336,8 @@ __device__ __forceinline__ void group(const Model<Real> &m, const DevLine<Real> 
 //   Pi = c2 h_t l_t + eta_V rho_V,
 //   Q = -mu S1 (cQ A + cU k X) / Delta, U = -mu S1 (cU A - cQ k X) / Delta,
 //   V = -mu S1 (k^2 eta_V + rho_V Pi) / Delta.
-template <typename Real>
-__device__ __forceinline__ void unno_rachkovsky(const Model<Real> &m, Real hb, Real lb, Real hp,
+template <typename Real, typename M>
+__device__ __forceinline__ void unno_rachkovsky(const M &m, Real hb, Real lb, Real hp,
                                                 Real lp, Real hr, Real lr, Real &I, Real &Q,
                                                 Real &U, Real &V)
 {

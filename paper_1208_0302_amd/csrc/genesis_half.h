@@ -1,0 +1,262 @@
+// Reduced-precision synthesis: the Voigt and Faraday-Voigt profiles of every
+// Zeeman component (Sec. 5) evaluated in packed FP16, two wavelengths per
+// lane per instruction (v_pk_fma_f16), with the reduced wavelength formed in
+// FP32, the Unno-Rachkovsky solution and the chi-square in FP32.
+//
+// The FP32 rational w = P(Z)/Q(Z) of the library (degree 7/8 in Z = a - i v)
+// gives, per individual, H = NH(u)/D(u) and L = v NL(u)/D(u) with u = v^2,
+// NH and NL of degree 7 and D of degree 8.  Their values span many orders of
+// magnitude over the line window, beyond FP16's range, so each is mapped to
+// the compact variable t = 1/(1 + u/s) in (0, 1]:
+//   X~(t) = t^8 X(s (1 - t)/t) = sum_k x_k s^k (1 - t)^k t^(8 - k),
+// a degree-8 polynomial in t whose ratio NH~/D~ is still H.  Numerators and
+// denominator are scaled by the same factor 1/sqrt(D~(0) D~(1)), which keeps
+// every coefficient and value of the three polynomials within about 10^(+-3)
+// for damping a <= 1 (largest coefficient 115 at a = 0.5, 232 at a = 1).
+// Per component and pair of wavelengths: 2 FP32 FMAs and conversions for v,
+// 1 multiply and 1 FMA for t's denominator, 2 reciprocals, 24 Horner FMAs,
+// 2 reciprocals for 1/D~, and 4 operations to accumulate the strength-weighted
+// H and L.  Measured worst error of the FP16 evaluation over a in [0, 1],
+// |v| <= 300: 4e-3 in H, 3.2e-3 in L (1 = H(0, 0)).
+#pragma once
+
+#include "genesis_device.h"
+
+namespace genesis {
+
+typedef _Float16 half_t;
+typedef half_t h2 __attribute__((ext_vector_type(2)));
+
+constexpr double kHalfS = 2.0;        // u scale of the compact variable
+constexpr double kHalfMaxDamping = 1.0;
+
+// T[m][k]: coefficient of t^m contributed by u^k, s^k C(k, i) (-1)^i with
+// i = m - 8 + k, for k >= 8 - m.
+struct TTable {
+    double t[9][9];
+};
+
+constexpr TTable make_ttable()
+{
+    TTable T{};
+    for (int m = 0; m <= 8; ++m)
+        for (int k = 8 - m; k <= 8; ++k) {
+            const int i = m - 8 + k;
+            double binom = 1.0;
+            for (int r = 0; r < i; ++r)
+                binom = binom * (double)(k - r) / (double)(r + 1);
+            double sk = 1.0;
+            for (int r = 0; r < k; ++r)
+                sk *= kHalfS;
+            T.t[m][k] = sk * binom * ((i & 1) ? -1.0 : 1.0);
+        }
+    return T;
+}
+
+constexpr TTable kTT = make_ttable();
+
+// Packed coefficients: nh~[0..8], nl~[0..8], d~[0..8] at index q of c[q / 2][q % 2].
+struct VoigtH {
+    h2 c[14];
+};
+
+__device__ __forceinline__ void to_t(const float (&x)[9], float (&y)[9])
+{
+#pragma unroll
+    for (int m = 0; m <= 8; ++m) {
+        float s = 0.0f;
+#pragma unroll
+        for (int k = 8 - m; k <= 8; ++k)
+            s = fmaf((float)kTT.t[m][k], x[k], s);
+        y[m] = s;
+    }
+}
+
+__device__ __forceinline__ VoigtH voigt_setup_h(double a)
+{
+    const VoigtF32 f = voigt_setup_f32(a);
+    float nh[9] = {}, nl[9] = {}, d[9] = {};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            nh[i + j] = fmaf(f.ep[i], f.eq[j], nh[i + j]);
+            nl[i + j] = fmaf(-f.op[i], f.eq[j], nl[i + j]);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            nh[i + j + 1] = fmaf(f.op[i], f.oq[j], nh[i + j + 1]);
+            nl[i + j] = fmaf(f.ep[i], f.oq[j], nl[i + j]);
+            d[i + j + 1] = fmaf(f.oq[i], f.oq[j], d[i + j + 1]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+            d[i + j] = fmaf(f.eq[i], f.eq[j], d[i + j]);
+    float th[9], tl[9], td[9];
+    to_t(nh, th);
+    to_t(nl, tl);
+    to_t(d, td);
+    float d1 = 0.0f;
+#pragma unroll
+    for (int m = 0; m <= 8; ++m)
+        d1 += td[m];
+    const float k = rsqrtf(td[0] * d1);
+    half_t q[27];
+#pragma unroll
+    for (int m = 0; m <= 8; ++m) {
+        q[m] = (half_t)(th[m] * k);
+        q[9 + m] = (half_t)(tl[m] * k);
+        q[18 + m] = (half_t)(td[m] * k);
+    }
+    VoigtH c;
+#pragma unroll
+    for (int i = 0; i < 13; ++i)
+        c.c[i] = h2{q[2 * i], q[2 * i + 1]};
+    c.c[13] = h2{q[26], (half_t)0};
+    return c;
+}
+
+__device__ __forceinline__ h2 hcoef(const VoigtH &c, int q)
+{
+    const half_t x = c.c[q >> 1][q & 1];
+    return h2{x, x};
+}
+
+__device__ __forceinline__ h2 hfma(h2 a, h2 b, h2 c) { return __builtin_elementwise_fma(a, b, c); }
+
+__device__ __forceinline__ h2 hrcp(h2 x)
+{
+    return h2{(half_t)__builtin_amdgcn_rcph(x.x), (half_t)__builtin_amdgcn_rcph(x.y)};
+}
+
+// h += w H(v), l += w L(v) for the two wavelengths of the pair.
+__device__ __forceinline__ void voigt_acc_h(const VoigtH &c, h2 v, h2 w, h2 &h, h2 &l)
+{
+    const h2 u = v * v;
+    const h2 t = hrcp(hfma(u, h2{(half_t)(1.0 / kHalfS), (half_t)(1.0 / kHalfS)},
+                           h2{(half_t)1, (half_t)1}));
+    h2 ph = hcoef(c, 8), pl = hcoef(c, 17), pd = hcoef(c, 26);
+#pragma unroll
+    for (int m = 7; m >= 0; --m) {
+        ph = hfma(ph, t, hcoef(c, m));
+        pl = hfma(pl, t, hcoef(c, 9 + m));
+        pd = hfma(pd, t, hcoef(c, 18 + m));
+    }
+    const h2 wr = hrcp(pd) * w;
+    h = hfma(ph, wr, h);
+    l = hfma(pl * v, wr, l);
+}
+
+// FP32 model constants of one individual with FP16 profile coefficients.
+struct ModelH {
+    float B, inv_dop, vlos;
+    float cI1, cI2, cQ, cU, cV, c2;
+    float S0, muS1;
+    VoigtH vh;
+};
+
+__device__ __forceinline__ void model_setup(const double (&p)[GENESIS_NPAR], double mu,
+                                            ModelH &m)
+{
+    float sg, cg, s2x, c2x;
+    sincosf((float)(p[1] * (kPi / 180.0)), &sg, &cg);
+    sincosf((float)(p[2] * (kPi / 90.0)), &s2x, &c2x);
+    const float h = 0.5f * (float)p[6];
+    const float sg2 = sg * sg;
+    m.B = (float)p[0];
+    m.inv_dop = (float)(1.0 / p[4]);
+    m.vlos = (float)p[3];
+    m.cI1 = h * sg2;
+    m.cI2 = 0.5f * h * fmaf(cg, cg, 1.0f);
+    m.cQ = h * sg2 * c2x;
+    m.cU = h * sg2 * s2x;
+    m.cV = h * cg;
+    m.c2 = (h * sg2) * (h * sg2);
+    m.S0 = (float)p[7];
+    m.muS1 = (float)(mu * p[8]);
+    m.vh = voigt_setup_h(p[5]);
+}
+
+// Component strengths of every line in FP16 (kernel argument; the shifts
+// stay FP32 because the reduced wavelength is formed in FP32).
+struct DevLinesH {
+    half_t w[GENESIS_MAX_LINES][GENESIS_MAX_COMP];
+};
+
+template <int N>
+__device__ __forceinline__ void group_h(const ModelH &m, const DevLine<float> &ln,
+                                        const half_t *wh, int c0, int n, float xa, float xb,
+                                        float zb, h2 &h, h2 &l)
+{
+    auto one = [&](int c) {
+        const float s = ln.s[c];
+        const h2 v = h2{(half_t)fmaf(-s, zb, xa), (half_t)fmaf(-s, zb, xb)};
+        voigt_acc_h(m.vh, v, h2{wh[c], wh[c]}, h, l);
+    };
+    if constexpr (N >= 0) {
+#pragma unroll
+        for (int c = 0; c < N; ++c)
+            one(c0 + c);
+    } else {
+        for (int c = c0; c < c0 + n; ++c)
+            one(c);
+    }
+}
+
+// One line, two wavelengths per iteration (the last one alone when nlam is odd).
+template <int NB, int NP, int NR, typename Sink>
+__device__ __forceinline__ void synth_line_h(const ModelH &m, const DevLine<float> &ln,
+                                             const half_t *wh, Sink &sink)
+{
+    const float xb = (ln.off0 - m.vlos * ln.dop_kms) * m.inv_dop;
+    const float xs = ln.step * m.inv_dop;
+    const float zb = ln.zee_G * m.B * m.inv_dop;
+    const int nb = NB >= 0 ? NB : ln.nb, np = NP >= 0 ? NP : ln.np;
+    const int nr = NR >= 0 ? NR : ln.nr;
+    for (int j = 0; j < ln.nlam; j += 2) {
+        const float x0 = fmaf((float)j, xs, xb), x1 = fmaf((float)(j + 1), xs, xb);
+        const h2 z = h2{(half_t)0, (half_t)0};
+        h2 hb = z, lb = z, hp = z, lp = z, hr = z, lr = z;
+        group_h<NB>(m, ln, wh, 0, nb, x0, x1, zb, hb, lb);
+        group_h<NP>(m, ln, wh, nb, np, x0, x1, zb, hp, lp);
+        group_h<NR>(m, ln, wh, nb + np, nr, x0, x1, zb, hr, lr);
+        float I, Q, U, V;
+        unno_rachkovsky<float>(m, (float)hb.x, (float)lb.x, (float)hp.x, (float)lp.x,
+                               (float)hr.x, (float)lr.x, I, Q, U, V);
+        sink(ln.off + j, I, Q, U, V);
+        if (j + 1 < ln.nlam) {
+            unno_rachkovsky<float>(m, (float)hb.y, (float)lb.y, (float)hp.y, (float)lp.y,
+                                   (float)hr.y, (float)lr.y, I, Q, U, V);
+            sink(ln.off + j + 1, I, Q, U, V);
+        }
+    }
+}
+
+template <typename Sink>
+__device__ __forceinline__ void synthesize_h(const ModelH &m, const DevLines<float> &ls,
+                                             const DevLinesH &lh, Sink &sink)
+{
+    for (int l = 0; l < ls.nlines; ++l) {
+        const DevLine<float> &ln = ls.l[l];
+        if (ln.nb == 1 && ln.np == 1 && ln.nr == 1)
+            synth_line_h<1, 1, 1>(m, ln, lh.w[l], sink);
+        else if (ln.nb == 4 && ln.np == 4 && ln.nr == 4)
+            synth_line_h<4, 4, 4>(m, ln, lh.w[l], sink);
+        else
+            synth_line_h<-1, -1, -1>(m, ln, lh.w[l], sink);
+    }
+}
+
+__device__ __forceinline__ float chi2_of_h(const ModelH &m, const DevLines<float> &ls,
+                                           const DevLinesH &lh, const Vec4<float> *obs_lds,
+                                           const float (&w2)[4], float inv_nu)
+{
+    Chi2Sink<float> s{obs_lds, 0, 0, 0, 0};
+    synthesize_h(m, ls, lh, s);
+    return fmaf(w2[0], s.sI, fmaf(w2[1], s.sQ, fmaf(w2[2], s.sU, w2[3] * s.sV))) * inv_nu;
+}
+
+}  // namespace genesis

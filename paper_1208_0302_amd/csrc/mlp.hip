@@ -100,55 +100,89 @@ __device__ __forceinline__ void epilogue(const GemmArgs &a, int m, int n, float 
     }
 }
 
+// One 64 x 64 bf16 tile of a matrix operand, element (r, c) = global
+// (row0 + r, k0 + c), moved global -> registers -> LDS T[r][c] (k contiguous
+// in LDS).  The matrix is stored either with k contiguous ([rows][ld],
+// KC = true) or with rows contiguous ([K][ld], KC = false).  Each of the 256
+// threads owns two chunks of 8 elements that are contiguous in memory: one
+// 16-byte load where the chunk is aligned and inside the matrix, element
+// loads with zero fill elsewhere.
+constexpr int kTile = 64, kTileK = 64, kLdsPitch = kTileK + 8;
+
+template <bool KC>
+struct TileLoader {
+    bf16x8 v[2];
+
+    __device__ __forceinline__ void load(const uint16_t *__restrict__ X, int ld, int rows, int K,
+                                         int row0, int k0, int tid)
+    {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int q = tid + 256 * j;
+            // KC: chunk = 8 consecutive k of one row; else 8 consecutive rows of one k
+            const int r = KC ? q >> 3 : (q & 7) * 8;
+            const int c = KC ? (q & 7) * 8 : q >> 3;
+            const int gr = row0 + r, gc = k0 + c;
+            const int64_t base = KC ? (int64_t)gr * ld + gc : (int64_t)gc * ld + gr;
+            const bool inside = KC ? (gr < rows && gc + 8 <= K) : (gc < K && gr + 8 <= rows);
+            if (inside && (ld & 7) == 0 && ((uintptr_t)(X + base) & 15) == 0) {
+                v[j] = *(const bf16x8 *)(X + base);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int er = KC ? gr : gr + e, ec = KC ? gc + e : gc;
+                    v[j][e] = (er < rows && ec < K) ? (short)X[KC ? (int64_t)er * ld + ec
+                                                                  : (int64_t)ec * ld + er]
+                                                    : (short)0;
+                }
+            }
+        }
+    }
+
+    __device__ __forceinline__ void store(uint16_t (*T)[kLdsPitch], int tid) const
+    {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int q = tid + 256 * j;
+            if (KC) {
+                *(bf16x8 *)&T[q >> 3][(q & 7) * 8] = v[j];
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    T[(q & 7) * 8 + e][q >> 3] = (uint16_t)v[j][e];
+            }
+        }
+    }
+};
+
 // C[M][N] = op(A)[M][K] op(B)[K][N].  TA: A stored [K][M]; TB: B stored [N][K].
-// Block 256 threads, 64 x 64 output tile, K step 32 through LDS (both tiles
-// K-contiguous so that every MFMA operand is one 16-byte LDS read).
+// Block 256 threads (4 waves in 2 x 2, each a 32 x 32 MFMA tile), 64 x 64
+// output tile, k step 64 staged through LDS with the next step's operands
+// loaded into registers while the current step's 4 MFMAs run.
 template <bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs a)
 {
-    constexpr int BM = 64, BN = 64, BK = 32;
-    __shared__ __align__(16) uint16_t As[BM][BK + 8];
-    __shared__ __align__(16) uint16_t Bs[BN][BK + 8];
+    __shared__ __align__(16) uint16_t As[kTile][kLdsPitch];
+    __shared__ __align__(16) uint16_t Bs[kTile][kLdsPitch];
     const uint16_t *A = (const uint16_t *)a.A, *B = (const uint16_t *)a.B;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    TileLoader<!TA> la;
+    TileLoader<TB> lb;
+    la.load(A, a.lda, a.M, a.K, m0, 0, tid);
+    lb.load(B, a.ldb, a.N, a.K, n0, 0, tid);
     f32x16 acc = {0};
-    for (int k0 = 0; k0 < a.K; k0 += BK) {
-        // 64 x 32 elements per tile, 8 per thread
-        for (int e = tid; e < BM * BK; e += 256) {
-            int r, c;  // r: m or n index inside the tile, c: k index inside the tile
-            if (TA) {
-                c = e / BM;
-                r = e % BM;
-            } else {
-                r = e / BK;
-                c = e % BK;
-            }
-            const int gm = m0 + r, gk = k0 + c;
-            uint16_t v = 0;
-            if (gm < a.M && gk < a.K)
-                v = TA ? A[(int64_t)gk * a.lda + gm] : A[(int64_t)gm * a.lda + gk];
-            As[r][c] = v;
-        }
-        for (int e = tid; e < BN * BK; e += 256) {
-            int r, c;
-            if (TB) {
-                r = e / BK;
-                c = e % BK;
-            } else {
-                c = e / BN;
-                r = e % BN;
-            }
-            const int gn = n0 + r, gk = k0 + c;
-            uint16_t v = 0;
-            if (gn < a.N && gk < a.K)
-                v = TB ? B[(int64_t)gn * a.ldb + gk] : B[(int64_t)gk * a.ldb + gn];
-            Bs[r][c] = v;
-        }
+    for (int k0 = 0; k0 < a.K; k0 += kTileK) {
+        la.store(As, tid);
+        lb.store(Bs, tid);
         __syncthreads();
+        if (k0 + kTileK < a.K) {
+            la.load(A, a.lda, a.M, a.K, m0, k0 + kTileK, tid);
+            lb.load(B, a.ldb, a.N, a.K, n0, k0 + kTileK, tid);
+        }
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 16) {
+        for (int kk = 0; kk < kTileK; kk += 16) {
             const int kr = kk + 8 * (lane >> 5);
             const bf16x8 av = *(const bf16x8 *)&As[wm + (lane & 31)][kr];
             const bf16x8 bv = *(const bf16x8 *)&Bs[wn + (lane & 31)][kr];
@@ -204,16 +238,26 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs a)
             epilogue<float, EPI>(a, m0 + tm + i, n0 + tn + j, acc[i][j]);
 }
 
-// column sums: out[n] = sum_m in[m][n] (fixed order)
-__global__ void k_colsum(const float *in, int M, int N, float *out)
+// column sums: out[n] = sum_m in[m][n].  Block (64 columns) x (16 row
+// phases); thread (c, r) sums rows r, r + 16, ... in order, then the 16
+// partials are added in order: a fixed summation order for every launch.
+__global__ __launch_bounds__(1024) void k_colsum(const float *in, int M, int N, float *out)
 {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N)
-        return;
+    __shared__ float part[16][64];
+    const int c = threadIdx.x & 63, r = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + c;
     float s = 0.0f;
-    for (int m = 0; m < M; ++m)
-        s += in[(int64_t)m * N + n];
-    out[n] = s;
+    if (n < N)
+        for (int m = r; m < M; m += 16)
+            s += in[(int64_t)m * N + n];
+    part[r][c] = s;
+    __syncthreads();
+    if (r == 0 && n < N) {
+        float t = 0.0f;
+        for (int i = 0; i < 16; ++i)
+            t += part[i][c];
+        out[n] = t;
+    }
 }
 
 template <typename T>
@@ -247,14 +291,22 @@ __global__ void k_loss(const float *out, const float *target, int B, float *dout
     per_sample[b] = s;
 }
 
-__global__ void k_sum(const float *in, int n, float scale, float *out)
+// out = scale * sum in[0..n): 256 strided partial sums, then a fixed tree.
+__global__ __launch_bounds__(256) void k_sum(const float *in, int n, float scale, float *out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0)
-        return;
+    __shared__ float red[256];
     float s = 0.0f;
-    for (int i = 0; i < n; ++i)
+    for (int i = threadIdx.x; i < n; i += 256)
         s += in[i];
-    *out = s * scale;
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        *out = red[0] * scale;
 }
 
 __global__ void k_adam(float *p, float *m, float *v, const float *g, int64_t n, float lr,
@@ -523,7 +575,7 @@ int backward(bool bf16, const float *master, const Ws &w, int64_t B, float *grad
         g.outf = grad + w_off(l);
         if (int rc = gemm<kGradW, true, false>(bf16, g, st))
             return rc;
-        hipLaunchKernelGGL(k_colsum, dim3(blocks(nout, 256)), dim3(256), 0, st, dcur_f, (int)B,
+        hipLaunchKernelGGL(k_colsum, dim3(blocks(nout, 64)), dim3(1024), 0, st, dcur_f, (int)B,
                            nout, grad + b_off(l));
         if (l == 0)
             break;
@@ -620,7 +672,7 @@ int grad_pass(bool bf16, const float *master, const Ws &w, const float *target, 
     else
         hipLaunchKernelGGL(k_loss<float>, dim3(blocks(batch, 256)), dim3(256), 0, st, w.out,
                            target, (int)batch, w.dout_f, (float *)w.dout_t, w.per_sample);
-    hipLaunchKernelGGL(k_sum, dim3(1), dim3(64), 0, st, w.per_sample, (int)batch,
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, st, w.per_sample, (int)batch,
                        1.0f / (float)batch, loss);
     return backward(bf16, master, w, batch, grad, st);
 }

@@ -229,6 +229,8 @@ int gs_submit(void *session, const float *obs, const float *sigma, const float *
         return rc;
     if (int rc = pack_ga(cfg, d.ga))
         return rc;
+    if (cfg->synth_precision != GENESIS_SYNTH_NATIVE)
+        return fail(ME_EINVAL, "the service synthesises in FP32 (synth_precision must be 0)");
     if (npix < 1 || npix > kMaxGrid)
         return fail(ME_EINVAL, "npix must lie in [1, 2^30]");
     if (4 * d.ls.L <= GENESIS_NPAR)

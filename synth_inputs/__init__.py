@@ -142,3 +142,48 @@ def serving_schedule(rate_per_s: float, window_s: float, seed: int):
         out.append(dict(t=t, npix=npix, lines=lines, generations=gens, seed=seed * 100003 + i))
         i += 1
     return out
+
+
+def full_disc(n: int = 2048, seed: int = 0, corr_px: float = 20.0, strong_frac: float = 0.01,
+              stride: int = 1):
+    """Full-disc parameter maps: every parameter is a smooth random field
+    (white noise filtered by a Gaussian of `corr_px` pixels, rescaled to unit
+    variance, then mapped through the prior: uniform priors by the normal CDF,
+    v_los as 1.5 z clipped to +-7.5), plus strong-field patches of B in
+    U(1500, 3000) G covering about `strong_frac` of the disc.  Returns
+    (params [m, 9], mu [m], (y, x) [m, 2]) for the on-disc pixels of an n x n
+    grid (disc radius n/2), keeping every `stride`-th on-disc pixel.
+    mu = cos(heliocentric angle) = sqrt(1 - r^2)."""
+    from scipy.ndimage import gaussian_filter
+    from scipy.special import ndtr
+    rng = np.random.Generator(np.random.Philox(key=seed + 8191))
+    c = (n - 1) / 2.0
+    yy, xx = np.mgrid[0:n, 0:n]
+    r = np.hypot(xx - c, yy - c) / (n / 2.0)
+    on = r < 1.0
+    fields = np.empty((NPAR, n, n), np.float32)
+    for j in range(NPAR):
+        z = gaussian_filter(rng.standard_normal((n, n)).astype(np.float32), corr_px,
+                            mode="wrap")
+        z /= z.std()
+        fields[j] = z
+    p = np.empty((NPAR, n, n), np.float64)
+    for j in range(NPAR):
+        if j == 3:
+            p[j] = np.clip(1.5 * fields[j], -7.5, 7.5)
+        else:
+            p[j] = PRIOR_LO[j] + (PRIOR_HI[j] - PRIOR_LO[j]) * ndtr(fields[j])
+    # strong-field patches: discs of radius 8..24 px until strong_frac is covered
+    strong = np.zeros((n, n), bool)
+    target = strong_frac * on.sum()
+    while (strong & on).sum() < target:
+        cy, cx = rng.uniform(0, n, 2)
+        rad = rng.uniform(8, 24)
+        m = (yy - cy) ** 2 + (xx - cx) ** 2 <= rad * rad
+        p[0][m] = rng.uniform(1500.0, 3000.0)
+        strong |= m
+    iy, ix = np.nonzero(on)
+    iy, ix = iy[::stride], ix[::stride]
+    params = p[:, iy, ix].T.copy()
+    mu = np.sqrt(np.clip(1.0 - r[iy, ix] ** 2, 0.0, 1.0))
+    return params, mu, np.stack([iy, ix], 1)

@@ -92,6 +92,18 @@ def test_invalid_arguments_fail_before_device_work():
     assert b"seed_params" in L.me_last_error()
     cfg.seed_params = 256          # never dereferenced: the missing box fails first
     assert L.ga_init(4, C.byref(cfg), None, None, None) == g.ME_EINVAL
+    # synthesis precision: unknown value; FP16 only for the FP32 entry point and
+    # damping bounds within [0, 1]
+    b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
+    cfg = g.GAConfig(pop=16, synth_precision=2).c()
+    assert L.ga_init(4, C.byref(cfg), None, None, None) == g.ME_EINVAL
+    cfg = g.GAConfig(pop=16, synth_precision=g.SYNTH_FP16).c()
+    assert L.ga_invert_f64(None, None, None, 3, la, ga, 1, C.byref(b), C.byref(cfg), None, None,
+                           None, None, None, None, 0, None) == g.ME_EINVAL
+    wide = g.bounds(si.PRIOR_LO, np.where(np.arange(9) == 5, 1.5, si.PRIOR_HI))
+    assert L.ga_invert(None, None, None, 3, la, ga, 1, C.byref(wide), C.byref(cfg), None, None,
+                       None, None, None, None, 0, None) == g.ME_EINVAL
+    assert b"FP16" in L.me_last_error()
     cfg = g.GAConfig(pop=16).c()
     assert L.ga_step(None, None, 2, C.byref(cfg), 0, None, None, None, None, None,
                      None) == g.ME_EINVAL      # generation 0 is not a step
