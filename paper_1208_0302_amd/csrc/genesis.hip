@@ -381,6 +381,9 @@ struct InvertArgs : SynLines<SYN> {
 template <typename Real, int SYN>
 __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN> a)
 {
+    code_shift<SYN == GENESIS_SYNTH_FP16 ? GENESIS_PAD_INVERT_F16
+                                         : (sizeof(Real) == 8 ? GENESIS_PAD_INVERT_F64
+                                                              : GENESIS_PAD_INVERT_F32)>();
     extern __shared__ __align__(16) unsigned char smem[];
     const int pop = a.ga.pop;
     const int L = a.ls.L;
@@ -594,6 +597,7 @@ __device__ bool cholesky9(double (&M)[GENESIS_NPAR][GENESIS_NPAR], const double 
 
 __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
 {
+    code_shift<GENESIS_PAD_REFINE>();
     extern __shared__ __align__(16) unsigned char smem[];
     const int L = a.ls.L;
     Vec4<double> *obs_s = reinterpret_cast<Vec4<double> *>(smem);

@@ -50,6 +50,7 @@ namespace {
 __global__ __launch_bounds__(1024) void k_ga_advance(const ReqDesc *__restrict__ reqs,
                                                      const int64_t *__restrict__ first, int nreq)
 {
+    code_shift<GENESIS_PAD_ADVANCE>();
     extern __shared__ __align__(16) unsigned char smem[];
     // request of this workgroup: the last r with first[r] <= blockIdx.x
     const int64_t blk = blockIdx.x;
