@@ -41,6 +41,25 @@ PEAK_FP64_VALU = 78.6e12
 
 REFINE_ITERS = 50
 
+# HBM bytes per launch of k_ga_invert<float> on the slit workload, from the
+# FETCH_SIZE and WRITE_SIZE counters scaled by a device copy of known size
+# (profiles/k_ga_invert_slit_counters.md).  Valid only for the sources they
+# were measured on: reported when the kernel's sources hash to this value.
+TRAFFIC_SLIT_BYTES = 43.70e6
+TRAFFIC_SOURCES = ("csrc/genesis.hip", "csrc/genesis_device.h", "csrc/genesis_common.h",
+                   "csrc/genesis_half.h", "csrc/voigt_rational.h", "csrc/weideman36.h",
+                   "build.py")
+TRAFFIC_SOURCES_SHA256 = "83fc126329c79e1e10870e966c3b6576ee9e76ec74a744c34afd9c5907882e53"
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1208_0302_amd", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
 
 def workload(name):
     if name == "slit":
@@ -554,7 +573,9 @@ def main():
         "refine_ms": float((step_ms - ga_ms).mean()),
         "accuracy": acc,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": (TRAFFIC_SLIT_BYTES if w["name"] == "slit" and dt == torch.float32
+                                 and kernel_sources_sha256() == TRAFFIC_SOURCES_SHA256 else None),
                      "kernel": "k_ga_invert<%s>" % ("float" if dt == torch.float32 else "double"),
                      "flop_per_eval": fpe, "evals_per_launch": evals,
                      "peak_unpacked_fp32": unpacked / 1e12,

@@ -477,7 +477,10 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN> a)
 
 // ---- FP64 Levenberg-Marquardt refinement --------------------------------
 //
-// One workgroup of kRefineThreads per pixel, one wavelength per thread.  In
+// One workgroup of kRefineThreads per pixel; thread t takes samples t,
+// t + kRefineThreads, ... of every line, so with the 128-sample lines of the
+// slit workload every thread holds one sample of each line (the 12- and the
+// 3-component one) and no wavefront idles at the reductions.  In
 // normalised coordinates x_j = (p_j - lo_j)/(hi_j - lo_j) in [0, 1]: forward
 // differences with step h = 1e-7 (backwards at the upper edge) give the
 // Jacobian; A = J^T J and g = J^T r are reduced over the workgroup; thread 0
@@ -486,7 +489,7 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN> a)
 // 1e-12), else lambda *= 10 (cap 1e12), at most 10 trials per iteration;
 // lambda starts at 1e-3; the loop stops after an iteration without an
 // accepted trial.
-constexpr int kRefineThreads = 256;
+constexpr int kRefineThreads = 128;
 constexpr int kNA = GENESIS_NPAR * (GENESIS_NPAR + 1) / 2;  // packed upper triangle of A
 
 struct RefineArgs {
