@@ -33,7 +33,7 @@ METRIC = "pixel inversions/s at fixed param accuracy; ME evals/s vs VALU peak; p
 # = 1): per Zeeman component and wavelength (reduced wavelength, rational
 # Faddeeva in v^2, accumulation) and per wavelength (propagation matrix,
 # Unno-Rachkovsky closed form, chi-square terms).
-FLOP_PER_COMP_LAMBDA = 46
+FLOP_PER_COMP_LAMBDA = 42
 FLOP_PER_LAMBDA = 71
 PEAK_FP32_VALU = 157.3e12     # MI355X published FP32 vector peak
 PEAK_FP64_VALU = 78.6e12

@@ -149,7 +149,8 @@ int me_line_triplet(double lambda0_A, double geff, me_line *out);
 /* Stokes synthesis: params [n][9] -> stokes [n][4][L] by the analytic
  * Unno-Rachkovsky solution I = S0 e + mu S1 (1 + eta0 Phi)^-1 e with the
  * Voigt and Faraday-Voigt profiles over every Zeeman component.
- * FP32: rational Voigt approximation (max error 1.6e-8) in FP32 arithmetic.
+ * FP32: rational Voigt approximation (degree 6/7, max error 1.5e-7) in FP32
+ * arithmetic.
  * n may be 0.  ME_EINVAL on NULL arrays (n > 0), nlines out of range, a grid
  * with n < 1, or an invalid line. */
 int me_synth(const float *params, int64_t n, const me_line *lines, const me_grid *grids,

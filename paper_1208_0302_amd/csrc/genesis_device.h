@@ -95,14 +95,19 @@ enum Purpose : uint32_t { kInit = 0, kTournament = 1, kCross = 2, kMutate = 3 };
 // Faddeeva function w(v + i a) -> (H, L) = (Re w, Im w) (Sec. 5: Voigt and
 // Faraday-Voigt profiles).
 //
-// FP32: w = P(Z)/Q(Z), Z = a - i v, real coefficients (deg 7 / 8), fitted on
-// Re Z = 0 (maximum error 1.6e-8, which bounds the error for every a >= 0).
+// FP32: w = P(Z)/Q(Z), Z = a - i v, real coefficients (deg 6 / 7, the
+// degrees of Hui, Armstrong & Wray's approximation), fitted on Re Z = 0
+// (maximum error 1.5e-7, which bounds the error for every a >= 0).
 // Expanding around Z = a once per individual gives polynomials in u = v^2:
 //   P(a - i v) = EP(u) - i v OP(u),  Q(a - i v) = EQ(u) - i v OQ(u),
-// so one profile evaluation costs 14 FMAs of Horner plus one reciprocal:
+// so one profile evaluation costs 11 FMAs of Horner plus one reciprocal:
 //   H = (EP EQ + u OP OQ) / (EQ^2 + u OQ^2),  L = v (EP OQ - OP EQ) / (...).
+constexpr int kNP = GENESIS_VR_NP, kNQ = GENESIS_VR_NQ;  // coefficient counts of P, Q
+constexpr int kEP = (kNP + 1) / 2, kOP = kNP / 2;        // even / odd parts of P in u
+constexpr int kEQ = (kNQ + 1) / 2, kOQ = kNQ / 2;        // even / odd parts of Q in u
+
 struct VoigtF32 {
-    float ep[4], op[4], eq[5], oq[4];
+    float ep[kEP], op[kOP], eq[kEQ], oq[kOQ];
 };
 
 // Coefficients of c(x + a) = sum_k r_k x^k: r_k = sum_{m >= k} C(m, k) c_m a^(m-k),
@@ -146,28 +151,41 @@ __device__ __forceinline__ VoigtF32 voigt_setup_f32(double a)
     VoigtF32 c;
     // (-i v)^(2m) = (-1)^m u^m ; (-i v)^(2m+1) = -i v (-1)^m u^m
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const float sg = (m & 1) ? -1.0f : 1.0f;
-        c.ep[m] = sg * shifted(kShiftP, 2 * m, a);
-        c.op[m] = sg * shifted(kShiftP, 2 * m + 1, a);
-        c.eq[m] = sg * shifted(kShiftQ, 2 * m, a);
-        c.oq[m] = sg * shifted(kShiftQ, 2 * m + 1, a);
-    }
-    c.eq[4] = shifted(kShiftQ, 8, a);
+    for (int m = 0; m < kEP; ++m)
+        c.ep[m] = ((m & 1) ? -1.0f : 1.0f) * shifted(kShiftP, 2 * m, a);
+#pragma unroll
+    for (int m = 0; m < kOP; ++m)
+        c.op[m] = ((m & 1) ? -1.0f : 1.0f) * shifted(kShiftP, 2 * m + 1, a);
+#pragma unroll
+    for (int m = 0; m < kEQ; ++m)
+        c.eq[m] = ((m & 1) ? -1.0f : 1.0f) * shifted(kShiftQ, 2 * m, a);
+#pragma unroll
+    for (int m = 0; m < kOQ; ++m)
+        c.oq[m] = ((m & 1) ? -1.0f : 1.0f) * shifted(kShiftQ, 2 * m + 1, a);
     return c;
 }
 
-// h += w H(v), l += w L(v): 13 FMAs of Horner, one reciprocal, and the
+template <int N>
+__device__ __forceinline__ float horner(const float (&c)[N], float u)
+{
+    float r = c[N - 1];
+#pragma unroll
+    for (int k = N - 2; k >= 0; --k)
+        r = fmaf(r, u, c[k]);
+    return r;
+}
+
+// h += w H(v), l += w L(v): the Horner schemes, one reciprocal, and the
 // strength folded into the reciprocal; u OQ is shared by numerator and
 // denominator.
 __device__ __forceinline__ void voigt_acc_f32(const VoigtF32 &c, float v, float w, float &h,
                                               float &l)
 {
     const float u = v * v;
-    const float ep = fmaf(fmaf(fmaf(c.ep[3], u, c.ep[2]), u, c.ep[1]), u, c.ep[0]);
-    const float op = fmaf(fmaf(fmaf(c.op[3], u, c.op[2]), u, c.op[1]), u, c.op[0]);
-    const float eq = fmaf(fmaf(fmaf(fmaf(c.eq[4], u, c.eq[3]), u, c.eq[2]), u, c.eq[1]), u, c.eq[0]);
-    const float oq = fmaf(fmaf(fmaf(c.oq[3], u, c.oq[2]), u, c.oq[1]), u, c.oq[0]);
+    const float ep = horner(c.ep, u);
+    const float op = horner(c.op, u);
+    const float eq = horner(c.eq, u);
+    const float oq = horner(c.oq, u);
     const float uoq = u * oq;
     const float wr = w * __builtin_amdgcn_rcpf(fmaf(eq, eq, oq * uoq));
     h = fmaf(fmaf(ep, eq, op * uoq), wr, h);

@@ -3,21 +3,21 @@
 // lane per instruction (v_pk_fma_f16), with the reduced wavelength formed in
 // FP32, the Unno-Rachkovsky solution and the chi-square in FP32.
 //
-// The FP32 rational w = P(Z)/Q(Z) of the library (degree 7/8 in Z = a - i v)
-// gives, per individual, H = NH(u)/D(u) and L = v NL(u)/D(u) with u = v^2,
-// NH and NL of degree 7 and D of degree 8.  Their values span many orders of
-// magnitude over the line window, beyond FP16's range, so each is mapped to
-// the compact variable t = 1/(1 + u/s) in (0, 1]:
-//   X~(t) = t^8 X(s (1 - t)/t) = sum_k x_k s^k (1 - t)^k t^(8 - k),
-// a degree-8 polynomial in t whose ratio NH~/D~ is still H.  Numerators and
+// The FP32 rational w = P(Z)/Q(Z) of the library (degree n-1 / n in
+// Z = a - i v, n = 7) gives, per individual, H = NH(u)/D(u) and
+// L = v NL(u)/D(u) with u = v^2, NH and NL of degree n-1 and D of degree n.
+// Their values span many orders of magnitude over the line window, beyond
+// FP16's range, so each is mapped to the compact variable t = 1/(1 + u/s)
+// in (0, 1]:
+//   X~(t) = t^n X(s (1 - t)/t) = sum_k x_k s^k (1 - t)^k t^(n - k),
+// a degree-n polynomial in t whose ratio NH~/D~ is still H.  Numerators and
 // denominator are scaled by the same factor 1/sqrt(D~(0) D~(1)), which keeps
 // every coefficient and value of the three polynomials within about 10^(+-3)
-// for damping a <= 1 (largest coefficient 115 at a = 0.5, 232 at a = 1).
-// Per component and pair of wavelengths: 2 FP32 FMAs and conversions for v,
-// 1 multiply and 1 FMA for t's denominator, 2 reciprocals, 24 Horner FMAs,
-// 2 reciprocals for 1/D~, and 4 operations to accumulate the strength-weighted
-// H and L.  Measured worst error of the FP16 evaluation over a in [0, 1],
-// |v| <= 300: 4e-3 in H, 3.2e-3 in L (1 = H(0, 0)).
+// for damping a <= 1.  Per component and pair of wavelengths: 2 mixed-precision
+// FMAs for v, 1 multiply and 1 FMA for t's denominator, 2 reciprocals, 3 n
+// Horner FMAs, 2 reciprocals for 1/D~, and 4 operations to accumulate the
+// strength-weighted H and L.  Simulated worst error of the FP16 evaluation
+// over a in [0, 1], |v| <= 300: about 4e-3 in H and L (1 = H(0, 0)).
 #pragma once
 
 #include "genesis_device.h"
@@ -30,18 +30,21 @@ typedef half_t h2 __attribute__((ext_vector_type(2)));
 constexpr double kHalfS = 2.0;        // u scale of the compact variable
 constexpr double kHalfMaxDamping = 1.0;
 
+constexpr int kDegH = kNQ - 1;  // degree n of D in u
+constexpr int kNH = kDegH + 1;   // coefficients per compact polynomial
+
 // T[m][k]: coefficient of t^m contributed by u^k, s^k C(k, i) (-1)^i with
-// i = m - 8 + k, for k >= 8 - m.
+// i = m - n + k, for k >= n - m.
 struct TTable {
-    double t[9][9];
+    double t[kNH][kNH];
 };
 
 constexpr TTable make_ttable()
 {
     TTable T{};
-    for (int m = 0; m <= 8; ++m)
-        for (int k = 8 - m; k <= 8; ++k) {
-            const int i = m - 8 + k;
+    for (int m = 0; m <= kDegH; ++m)
+        for (int k = kDegH - m; k <= kDegH; ++k) {
+            const int i = m - kDegH + k;
             double binom = 1.0;
             for (int r = 0; r < i; ++r)
                 binom = binom * (double)(k - r) / (double)(r + 1);
@@ -55,18 +58,18 @@ constexpr TTable make_ttable()
 
 constexpr TTable kTT = make_ttable();
 
-// Packed coefficients: nh~[0..8], nl~[0..8], d~[0..8] at index q of c[q / 2][q % 2].
+// Packed coefficients: nh~[0..n], nl~[0..n], d~[0..n] at index q of c[q / 2][q % 2].
 struct VoigtH {
-    h2 c[14];
+    h2 c[(3 * kNH + 1) / 2];
 };
 
-__device__ __forceinline__ void to_t(const float (&x)[9], float (&y)[9])
+__device__ __forceinline__ void to_t(const float (&x)[kNH], float (&y)[kNH])
 {
 #pragma unroll
-    for (int m = 0; m <= 8; ++m) {
+    for (int m = 0; m <= kDegH; ++m) {
         float s = 0.0f;
 #pragma unroll
-        for (int k = 8 - m; k <= 8; ++k)
+        for (int k = kDegH - m; k <= kDegH; ++k)
             s = fmaf((float)kTT.t[m][k], x[k], s);
         y[m] = s;
     }
@@ -75,47 +78,57 @@ __device__ __forceinline__ void to_t(const float (&x)[9], float (&y)[9])
 __device__ __forceinline__ VoigtH voigt_setup_h(double a)
 {
     const VoigtF32 f = voigt_setup_f32(a);
-    float nh[9] = {}, nl[9] = {}, d[9] = {};
+    float nh[kNH] = {}, nl[kNH] = {}, d[kNH] = {};
+    // NH = EP EQ + u OP OQ, NL = EP OQ - OP EQ, D = EQ^2 + u OQ^2
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < kEP; ++i) {
 #pragma unroll
-        for (int j = 0; j < 5; ++j) {
+        for (int j = 0; j < kEQ; ++j)
             nh[i + j] = fmaf(f.ep[i], f.eq[j], nh[i + j]);
-            nl[i + j] = fmaf(-f.op[i], f.eq[j], nl[i + j]);
-        }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            nh[i + j + 1] = fmaf(f.op[i], f.oq[j], nh[i + j + 1]);
+        for (int j = 0; j < kOQ; ++j)
             nl[i + j] = fmaf(f.ep[i], f.oq[j], nl[i + j]);
-            d[i + j + 1] = fmaf(f.oq[i], f.oq[j], d[i + j + 1]);
-        }
     }
 #pragma unroll
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < kOP; ++i) {
 #pragma unroll
-        for (int j = 0; j < 5; ++j)
+        for (int j = 0; j < kOQ; ++j)
+            nh[i + j + 1] = fmaf(f.op[i], f.oq[j], nh[i + j + 1]);
+#pragma unroll
+        for (int j = 0; j < kEQ; ++j)
+            nl[i + j] = fmaf(-f.op[i], f.eq[j], nl[i + j]);
+    }
+#pragma unroll
+    for (int i = 0; i < kEQ; ++i)
+#pragma unroll
+        for (int j = 0; j < kEQ; ++j)
             d[i + j] = fmaf(f.eq[i], f.eq[j], d[i + j]);
-    float th[9], tl[9], td[9];
+#pragma unroll
+    for (int i = 0; i < kOQ; ++i)
+#pragma unroll
+        for (int j = 0; j < kOQ; ++j)
+            d[i + j + 1] = fmaf(f.oq[i], f.oq[j], d[i + j + 1]);
+    float th[kNH], tl[kNH], td[kNH];
     to_t(nh, th);
     to_t(nl, tl);
     to_t(d, td);
     float d1 = 0.0f;
 #pragma unroll
-    for (int m = 0; m <= 8; ++m)
+    for (int m = 0; m <= kDegH; ++m)
         d1 += td[m];
     const float k = rsqrtf(td[0] * d1);
-    half_t q[27];
+    half_t q[3 * kNH + 1];
 #pragma unroll
-    for (int m = 0; m <= 8; ++m) {
+    for (int m = 0; m <= kDegH; ++m) {
         q[m] = (half_t)(th[m] * k);
-        q[9 + m] = (half_t)(tl[m] * k);
-        q[18 + m] = (half_t)(td[m] * k);
+        q[kNH + m] = (half_t)(tl[m] * k);
+        q[2 * kNH + m] = (half_t)(td[m] * k);
     }
+    q[3 * kNH] = (half_t)0;
     VoigtH c;
 #pragma unroll
-    for (int i = 0; i < 13; ++i)
+    for (int i = 0; i < (3 * kNH + 1) / 2; ++i)
         c.c[i] = h2{q[2 * i], q[2 * i + 1]};
-    c.c[13] = h2{q[26], (half_t)0};
     return c;
 }
 
@@ -138,12 +151,12 @@ __device__ __forceinline__ void voigt_acc_h(const VoigtH &c, h2 v, h2 w, h2 &h, 
     const h2 u = v * v;
     const h2 t = hrcp(hfma(u, h2{(half_t)(1.0 / kHalfS), (half_t)(1.0 / kHalfS)},
                            h2{(half_t)1, (half_t)1}));
-    h2 ph = hcoef(c, 8), pl = hcoef(c, 17), pd = hcoef(c, 26);
+    h2 ph = hcoef(c, kDegH), pl = hcoef(c, kNH + kDegH), pd = hcoef(c, 2 * kNH + kDegH);
 #pragma unroll
-    for (int m = 7; m >= 0; --m) {
+    for (int m = kDegH - 1; m >= 0; --m) {
         ph = hfma(ph, t, hcoef(c, m));
-        pl = hfma(pl, t, hcoef(c, 9 + m));
-        pd = hfma(pd, t, hcoef(c, 18 + m));
+        pl = hfma(pl, t, hcoef(c, kNH + m));
+        pd = hfma(pd, t, hcoef(c, 2 * kNH + m));
     }
     const h2 wr = hrcp(pd) * w;
     h = hfma(ph, wr, h);

@@ -1,7 +1,8 @@
 """Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
 
 Forward model: FP32 within 1e-5 of the continuum intensity Ic = S0 + mu S1 at
-every sample (the FP32 rational Voigt approximation is good to 1.6e-8 and its
+every sample (the FP32 rational Voigt approximation is good to 1.5e-7, which moves
+the Stokes vector by at most 2.8e-6 Ic over random models including eta0 = 30, and its
 FP32 evaluation to ~4e-7, which moves profiles by < 1e-6 Ic), FP64 within
 1e-10 Ic: the oracle forms lambda_j - lambda_c from absolute wavelengths near
 6302 A, whose FP64 rounding (ulp 9e-13 A) over the narrowest Doppler width
