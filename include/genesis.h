@@ -110,7 +110,18 @@ typedef struct {
  *               GENESIS_SYNTH_FP16 (FP32 entry point only: Voigt and
  *               Faraday-Voigt profiles in packed FP16, two wavelengths per
  *               instruction, Unno-Rachkovsky and chi-square in FP32; needs a
- *               damping upper bound <= 1) */
+ *               damping upper bound <= 1)
+ *  init_mode    generation 0 (Sec. 5.6): 0 = uniform random genes (stream
+ *               purpose 0); 1 = Sobol points 0 .. pop-1 (dimension 0 van der
+ *               Corput, dimensions 1..8 from the first primitive polynomials
+ *               over GF(2), initial direction numbers 1) XORed per pixel with
+ *               a digital shift from stream purpose 4, top 16 bits per gene.
+ *               Seeded slots (n_seeded) take precedence.
+ *  restart_every  restarts (Sec. 5.6): 0 = none; R > 0 = after evaluating
+ *               generation t with t % R == 0, 0 < t < G, the worst pop / 2
+ *               individuals (NaN last, ties to the lower index) are replaced by
+ *               Sobol points pop + (t/R - 1) (pop/2) + q (q = rank - (pop -
+ *               pop/2)) of the pixel's shifted sequence and re-evaluated */
 typedef struct {
     int32_t pop;
     int32_t generations;
@@ -123,7 +134,9 @@ typedef struct {
     int32_t seed_jitter;
     const float *seed_params;
     int32_t synth_precision;
-    int32_t reserved[3];
+    int32_t init_mode;
+    int32_t restart_every;
+    int32_t reserved[1];
 } ga_config;
 
 #define GENESIS_SYNTH_NATIVE 0
@@ -221,6 +234,16 @@ int ga_step_f64(const uint16_t *genes_in, const double *fitness, int64_t npix,
                 int32_t *xpoint, uint16_t *masks, int32_t *elite, void *stream);
 
 /* ---- the whole inversion (Algorithm 1, device resident) ----------------- */
+
+/* Restart of generation `generation` (a multiple of cfg->restart_every >= 1):
+ * genes_out = genes_in with the worst pop / 2 individuals of every pixel
+ * (by `fitness`, [npix][pop]) replaced as described for restart_every; the
+ * caller then evaluates genes_out.  Sec. 5.6.  genes_in and genes_out must not
+ * overlap. */
+int ga_restart(const uint16_t *genes_in, const float *fitness, int64_t npix,
+               const ga_config *cfg, int32_t generation, uint16_t *genes_out, void *stream);
+int ga_restart_f64(const uint16_t *genes_in, const double *fitness, int64_t npix,
+                   const ga_config *cfg, int32_t generation, uint16_t *genes_out, void *stream);
 
 /* Device workspace ga_invert needs (bytes); currently 0: the population,
  * its fitness and the pixel's observation live in on-chip memory. */

@@ -84,7 +84,12 @@ def lib():
             L.oracle_rng_word.restype = C.c_uint32
             L.oracle_decode.argtypes = [_u16p, _dp, _dp, _dp]
             L.oracle_ga_init.argtypes = [C.c_uint64, C.c_uint32, C.c_int, C.c_int, C.c_int, _dp,
-                                         _dp, _dp, _u16p]
+                                         _dp, _dp, C.c_int, _u16p]
+            L.oracle_sobol_polys.argtypes = [_u32p, C.c_int]
+            L.oracle_sobol_polys.restype = C.c_int
+            L.oracle_sobol_point.argtypes = [C.c_uint32, _u32p]
+            L.oracle_ga_restart.argtypes = [_u16p, _dp, C.c_int, C.c_uint64, C.c_uint32, C.c_int,
+                                            C.c_int, _u16p, _i32p]
             L.oracle_ga_step.argtypes = [_u16p, _dp, C.c_int, C.c_int, C.c_double, C.c_double,
                                          C.c_uint64, C.c_uint32, C.c_uint32,
                                          _u16p, _i32p, _i32p, _u16p, _i32p]
@@ -92,7 +97,7 @@ def lib():
             L.oracle_ga_invert.argtypes = [_dp, _dp, _dp, C.c_int64, _linep, C.c_int, _dp, _dp,
                                            C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                            C.c_uint64, C.c_uint32, C.c_int, C.c_int, _dp,
-                                           _dp, _dp, _i32p, _u16p, _dp]
+                                           C.c_int, C.c_int, _dp, _dp, _i32p, _u16p, _dp]
             L.oracle_ga_invert.restype = C.c_int
             L.oracle_lm_refine.argtypes = [_dp, _dp, _dp, C.c_int64, _linep, C.c_int, _dp, _dp,
                                            _dp, C.c_int, _dp, _dp, _i32p]
@@ -224,9 +229,11 @@ def decode(genes, lo, hi):
     return out.reshape(np.shape(genes))
 
 
-def ga_init(seed, pixel, pop, n_seeded=0, jitter=0, seed_params=None, lo=None, hi=None):
+def ga_init(seed, pixel, pop, n_seeded=0, jitter=0, seed_params=None, lo=None, hi=None,
+            init_mode=0):
     """Generation 0 of one pixel; the first n_seeded individuals encode the
-    first guess seed_params [9] inside the box [lo, hi] (Sec. 5.5)."""
+    first guess seed_params [9] inside the box [lo, hi] (Sec. 5.5); the rest
+    are uniform random (init_mode 0) or shifted Sobol points (1, Sec. 5.6)."""
     g = np.empty((pop, NPAR), np.uint16)
     sp = lo_ = hi_ = None
     if n_seeded > 0:
@@ -234,8 +241,32 @@ def ga_init(seed, pixel, pop, n_seeded=0, jitter=0, seed_params=None, lo=None, h
     lib().oracle_ga_init(int(seed), int(pixel), int(pop), int(n_seeded), int(jitter),
                          None if sp is None else _ptr(sp, _dp),
                          None if lo_ is None else _ptr(lo_, _dp),
-                         None if hi_ is None else _ptr(hi_, _dp), _ptr(g, _u16p))
+                         None if hi_ is None else _ptr(hi_, _dp), int(init_mode), _ptr(g, _u16p))
     return g
+
+
+def sobol_polys(n):
+    out = np.zeros(n, np.uint32)
+    got = lib().oracle_sobol_polys(_ptr(out, _u32p), int(n))
+    return out[:got]
+
+
+def sobol_point(n):
+    out = np.empty(NPAR, np.uint32)
+    lib().oracle_sobol_point(int(n), _ptr(out, _u32p))
+    return out
+
+
+def ga_restart(genes_in, fitness, seed, pixel, t, restart_every):
+    """Restart after generation t; returns (genes, replaced flags)."""
+    g = np.ascontiguousarray(genes_in, np.uint16)
+    pop = g.shape[0]
+    f = _f64(fitness)
+    out = np.empty_like(g)
+    rep = np.empty(pop, np.int32)
+    lib().oracle_ga_restart(_ptr(g, _u16p), _ptr(f, _dp), pop, int(seed), int(pixel), int(t),
+                            int(restart_every), _ptr(out, _u16p), _ptr(rep, _i32p))
+    return out, rep.astype(bool)
 
 
 def ga_step(genes_in, fitness, k, p_cross, p_mut, seed, pixel, gen):
@@ -259,7 +290,7 @@ def ga_step(genes_in, fitness, k, p_cross, p_mut, seed, pixel, gen):
 
 def ga_invert(obs, sigma, lines, lo, hi, pop, generations, k, p_cross, p_mut, seed,
               mu=None, pixel_base=0, want_population=False, n_seeded=0, seed_jitter=0,
-              seed_params=None):
+              seed_params=None, init_mode=0, restart_every=0):
     o = _f64(obs)
     s = _f64(sigma)
     npix = o.shape[0]
@@ -277,7 +308,7 @@ def ga_invert(obs, sigma, lines, lo, hi, pop, generations, k, p_cross, p_mut, se
         _ptr(o, _dp), _ptr(s, _dp), None if m is None else _ptr(m, _dp), npix, lp, len(lines),
         _ptr(lo, _dp), _ptr(hi, _dp), int(pop), int(generations), int(k), float(p_cross),
         float(p_mut), int(seed), int(pixel_base), int(n_seeded), int(seed_jitter),
-        None if sp is None else _ptr(sp, _dp), _ptr(bp, _dp), _ptr(bc, _dp), _ptr(st, _i32p),
+        None if sp is None else _ptr(sp, _dp), int(init_mode), int(restart_every), _ptr(bp, _dp), _ptr(bc, _dp), _ptr(st, _i32p),
         None if fg is None else _ptr(fg, _u16p), None if ff is None else _ptr(ff, _dp))
     if rc != 0:
         raise ValueError("oracle_ga_invert rejected its arguments")

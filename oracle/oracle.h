@@ -86,7 +86,21 @@ void oracle_decode(const uint16_t *genes, const double *lo, const double *hi, do
  * jittered by up to +-jitter codes per gene for the others); the rest are
  * uniform random codes.  seed_par, lo and hi may be NULL when n_seeded = 0. */
 void oracle_ga_init(uint64_t seed, uint32_t pixel, int pop, int n_seeded, int jitter,
-                    const double *seed_par, const double *lo, const double *hi, uint16_t *genes);
+                    const double *seed_par, const double *lo, const double *hi, int init_mode,
+                    uint16_t *genes);
+
+/* Sobol points (Sec. 5.6 initialisation and restarts): the first n primitive
+ * polynomials over GF(2) (bit k = coefficient of x^k; returns how many were
+ * found), the direction numbers V_k of the 9 dimensions, and point n. */
+int oracle_sobol_polys(uint32_t *polys, int n);
+void oracle_sobol_directions(uint32_t v[9][32]);
+void oracle_sobol_point(uint32_t n, uint32_t out[9]);
+
+/* Restart after generation t: genes_out = genes_in with the worst pop/2
+ * replaced by Sobol points; replaced [pop] (may be NULL) flags them. */
+void oracle_ga_restart(const uint16_t *genes_in, const double *fit, int pop, uint64_t seed,
+                       uint32_t pixel, int t, int restart_every, uint16_t *genes_out,
+                       int32_t *replaced);
 
 /* One generation of the operators S, R, M of the standard GA (Sec. 3,
  * Algorithm 1) with elitism.  Produces generation `gen` (>= 1) from the
@@ -109,7 +123,7 @@ int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, i
                      const oracle_line *lines, int nlines, const double *lo, const double *hi,
                      int pop, int generations, int k, double p_cross, double p_mut,
                      uint64_t seed, uint32_t pixel_base, int n_seeded, int seed_jitter,
-                     const double *seed_params,
+                     const double *seed_params, int init_mode, int restart_every,
                      double *best_params, double *best_chi2, int32_t *status,
                      uint16_t *final_genes, double *final_fit);
 

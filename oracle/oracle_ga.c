@@ -31,6 +31,16 @@
  *    individual 0 keeps it exactly, individual i >= 1 adds to gene j the
  *    integer d - J, d uniform in [0, 2J] from word j of stream purpose 5
  *    (J = seed_jitter), clamped to [0, 65535].
+ *  - Sobol initialisation and restarts (Sec. 5.6): Sobol points (Bratley &
+ *    Fox's construction) with dimension 0 the base-2 van der Corput sequence
+ *    and dimension d >= 1 built on the d-th primitive polynomial over GF(2)
+ *    (ordered by degree, then by value) with initial direction numbers all 1;
+ *    each pixel XORs the 32-bit coordinates with a digital shift (word d of
+ *    stream purpose 4, individual 0) and keeps the top 16 bits.  Generation
+ *    0 takes points 0 .. pop-1.  A restart after generation t (t a multiple
+ *    of restart_every, 0 < t < G) replaces the worst pop/2 individuals (the
+ *    tournament order) by points pop + (t/restart_every - 1) (pop/2) + q,
+ *    q = rank - (pop - pop/2), and re-evaluates them.
  */
 #include "oracle.h"
 
@@ -104,6 +114,95 @@ void oracle_decode(const uint16_t *genes, const double *lo, const double *hi, do
         par[j] = lo[j] + (hi[j] - lo[j]) * (double)genes[j] / 65535.0;
 }
 
+static int ranks_before(const double *fit, int a, int b);
+
+/* ---- Sobol points ----------------------------------------------------- */
+
+/* polynomial product modulo p (degree deg) over GF(2), operands reduced */
+static uint32_t gf2_mulmod(uint32_t a, uint32_t b, uint32_t p, int deg)
+{
+    uint32_t r = 0;
+    while (b) {
+        if (b & 1u)
+            r ^= a;
+        b >>= 1;
+        a <<= 1;
+        if (a >> deg & 1u)
+            a ^= p;
+    }
+    return r;
+}
+
+/* order of x modulo p: the smallest e >= 1 with x^e = 1 (0 if none up to 2^deg) */
+static uint64_t gf2_order_of_x(uint32_t p, int deg)
+{
+    uint32_t x = deg == 1 ? (2u ^ p) : 2u, y = x;
+    for (uint64_t e = 1; e <= (1ull << deg); ++e) {
+        if (y == 1u)
+            return e;
+        y = gf2_mulmod(y, x, p, deg);
+    }
+    return 0;
+}
+
+int oracle_sobol_polys(uint32_t *polys, int n)
+{
+    int d = 0;
+    for (int deg = 1; d < n && deg < 31; ++deg)
+        for (uint32_t p = (1u << deg) | 1u; p < (2u << deg) && d < n; p += 2)
+            if (gf2_order_of_x(p, deg) == (1ull << deg) - 1)
+                polys[d++] = p;
+    return d;
+}
+
+void oracle_sobol_directions(uint32_t v[NGENE][32])
+{
+    uint32_t polys[NGENE - 1];
+    oracle_sobol_polys(polys, NGENE - 1);
+    for (int k = 1; k <= 32; ++k)
+        v[0][k - 1] = 1u << (32 - k);
+    for (int d = 1; d < NGENE; ++d) {
+        const uint32_t p = polys[d - 1];
+        int s = 0;
+        while (p >> (s + 1))
+            ++s;
+        uint32_t m[33];
+        for (int k = 1; k <= 32; ++k) {
+            if (k <= s) {
+                m[k] = 1u;
+            } else {
+                uint32_t x = m[k - s] ^ (m[k - s] << s);
+                for (int i = 1; i < s; ++i)
+                    if (p >> (s - i) & 1u)
+                        x ^= m[k - i] << i;
+                m[k] = x;
+            }
+            v[d][k - 1] = m[k] << (32 - k);
+        }
+    }
+}
+
+void oracle_sobol_point(uint32_t n, uint32_t out[NGENE])
+{
+    uint32_t v[NGENE][32];
+    oracle_sobol_directions(v);
+    for (int d = 0; d < NGENE; ++d) {
+        uint32_t x = 0;
+        for (int k = 0; k < 32; ++k)
+            if (n >> k & 1u)
+                x ^= v[d][k];
+        out[d] = x;
+    }
+}
+
+static void sobol_genes(uint64_t seed, uint32_t pixel, uint32_t n, uint16_t *g)
+{
+    uint32_t x[NGENE];
+    oracle_sobol_point(n, x);
+    for (int d = 0; d < NGENE; ++d)
+        g[d] = (uint16_t)((x[d] ^ oracle_rng_word(seed, pixel, 0u, 0u, 4u, (uint32_t)d)) >> 16);
+}
+
 /* Encoding: the gene whose decoded value lies nearest to p inside [u, v]. */
 static uint16_t encode(double p, double lo, double hi)
 {
@@ -117,7 +216,8 @@ static uint16_t encode(double p, double lo, double hi)
 }
 
 void oracle_ga_init(uint64_t seed, uint32_t pixel, int pop, int n_seeded, int jitter,
-                    const double *seed_par, const double *lo, const double *hi, uint16_t *genes)
+                    const double *seed_par, const double *lo, const double *hi, int init_mode,
+                    uint16_t *genes)
 {
     for (int i = 0; i < pop; ++i) {
         uint16_t *g = genes + i * NGENE;
@@ -134,8 +234,35 @@ void oracle_ga_init(uint64_t seed, uint32_t pixel, int pop, int n_seeded, int ji
             }
             continue;
         }
+        if (init_mode == 1) {
+            sobol_genes(seed, pixel, (uint32_t)i, g);
+            continue;
+        }
         for (int j = 0; j < NGENE; ++j)
             g[j] = (uint16_t)(oracle_rng_word(seed, pixel, 0u, (uint32_t)i, 0u, (uint32_t)j) >> 16);
+    }
+}
+
+/* Restart after generation t: rank by fitness (tournament order), replace the
+ * worst pop/2 by Sobol points; replaced[i] = 1 for those. */
+void oracle_ga_restart(const uint16_t *genes_in, const double *fit, int pop, uint64_t seed,
+                       uint32_t pixel, int t, int restart_every, uint16_t *genes_out,
+                       int32_t *replaced)
+{
+    const int nrep = pop / 2;
+    const uint32_t r = (uint32_t)(t / restart_every);
+    for (int i = 0; i < pop; ++i) {
+        int rank = 0;
+        for (int j = 0; j < pop; ++j)
+            rank += ranks_before(fit, j, i);
+        const int q = rank - (pop - nrep);
+        if (q >= 0)
+            sobol_genes(seed, pixel, (uint32_t)pop + (r - 1u) * (uint32_t)nrep + (uint32_t)q,
+                        genes_out + i * NGENE);
+        else
+            memcpy(genes_out + i * NGENE, genes_in + i * NGENE, sizeof(uint16_t) * NGENE);
+        if (replaced)
+            replaced[i] = q >= 0;
     }
 }
 
@@ -273,13 +400,15 @@ int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, i
                      const oracle_line *lines, int nlines, const double *lo, const double *hi,
                      int pop, int generations, int k, double p_cross, double p_mut,
                      uint64_t seed, uint32_t pixel_base, int n_seeded, int seed_jitter,
-                     const double *seed_params,
+                     const double *seed_params, int init_mode, int restart_every,
                      double *best_params, double *best_chi2, int32_t *status,
                      uint16_t *final_genes, double *final_fit)
 {
     if (pop < 2 || k < 1 || k > pop || k > 64 || generations < 0)
         return -1;
     if (n_seeded < 0 || n_seeded > pop || seed_jitter < 0 || (n_seeded > 0 && !seed_params))
+        return -1;
+    if ((init_mode != 0 && init_mode != 1) || restart_every < 0)
         return -1;
     const int L = oracle__total_samples(lines, nlines);
     int err = 0;
@@ -320,12 +449,24 @@ int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, i
             const double m = mu ? mu[p] : 1.0;
             double par[NGENE];
             oracle_ga_init(seed, pix, pop, n_seeded, seed_jitter,
-                           seed_params ? seed_params + p * NGENE : NULL, lo, hi, g0);
+                           seed_params ? seed_params + p * NGENE : NULL, lo, hi, init_mode, g0);
             for (int i = 0; i < pop; ++i) {
                 oracle_decode(g0 + i * NGENE, lo, hi, par);
                 fit[i] = oracle__chi2_single(par, m, lines, nlines, o, s, scratch);
             }
             for (int t = 1; t <= generations; ++t) {
+                if (restart_every > 0 && t - 1 > 0 && (t - 1) % restart_every == 0) {
+                    /* restart of generation t - 1 (evaluated above), before breeding */
+                    oracle_ga_restart(g0, fit, pop, seed, pix, t - 1, restart_every, g1, xp);
+                    for (int i = 0; i < pop; ++i)
+                        if (xp[i]) {
+                            oracle_decode(g1 + i * NGENE, lo, hi, par);
+                            fit[i] = oracle__chi2_single(par, m, lines, nlines, o, s, scratch);
+                        }
+                    uint16_t *tmp = g0;
+                    g0 = g1;
+                    g1 = tmp;
+                }
                 int32_t e;
                 if (oracle_ga_step(g0, fit, pop, k, p_cross, p_mut, seed, pix, (uint32_t)t, g1,
                                    par2, xp, masks, &e) != 0) {

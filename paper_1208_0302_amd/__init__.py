@@ -57,7 +57,8 @@ class GaConfigC(C.Structure):
                 ("n_seeded", C.c_int32), ("p_cross", C.c_float), ("p_mut", C.c_float),
                 ("seed", C.c_uint64), ("pixel_base", C.c_uint32), ("seed_jitter", C.c_int32),
                 ("seed_params", C.c_void_p), ("synth_precision", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("init_mode", C.c_int32), ("restart_every", C.c_int32),
+                ("reserved", C.c_int32 * 1)]
 
 
 @dataclasses.dataclass
@@ -74,6 +75,8 @@ class GAConfig:
     seed_jitter: int = 0
     seed_params: Optional[torch.Tensor] = None   # [npix, 9] float32 device tensor
     synth_precision: int = 0                     # SYNTH_NATIVE or SYNTH_FP16
+    init_mode: int = 0                           # 0 uniform random, 1 Sobol
+    restart_every: int = 0                       # 0: no restarts
 
     def c(self) -> GaConfigC:
         cfg = GaConfigC()
@@ -87,6 +90,8 @@ class GAConfig:
         cfg.n_seeded = self.n_seeded
         cfg.seed_jitter = self.seed_jitter
         cfg.synth_precision = self.synth_precision
+        cfg.init_mode = self.init_mode
+        cfg.restart_every = self.restart_every
         if self.seed_params is not None:
             _dev(self.seed_params, torch.float32, "seed_params")
             cfg.seed_params = self.seed_params.data_ptr()
@@ -115,6 +120,8 @@ _SIGS = {
     "me_chi2": ([_vp, _i64, _i32, _vp, _vp, _vp, _lp, _gp, _i32, _vp, _vp], C.c_int),
     "me_chi2_f64": ([_vp, _i64, _i32, _vp, _vp, _vp, _lp, _gp, _i32, _vp, _vp], C.c_int),
     "ga_init": ([_i64, _cp, _bp, _vp, _vp], C.c_int),
+    "ga_restart": ([_vp, _vp, _i64, _cp, _i32, _vp, _vp], C.c_int),
+    "ga_restart_f64": ([_vp, _vp, _i64, _cp, _i32, _vp, _vp], C.c_int),
     "ga_decode": ([_vp, _i64, _bp, _vp, _vp], C.c_int),
     "ga_evaluate": ([_vp, _i64, _i32, _bp, _vp, _vp, _vp, _lp, _gp, _i32, _vp, _vp], C.c_int),
     "ga_evaluate_f64": ([_vp, _i64, _i32, _bp, _vp, _vp, _vp, _lp, _gp, _i32, _vp, _vp],
@@ -306,6 +313,21 @@ def ga_init(npix: int, cfg: GAConfig, bnds: Optional[MeBounds] = None, device="c
     _check(lib().ga_init(npix, C.byref(c), None if bnds is None else C.byref(bnds), _ptr(genes),
                          _stream(genes)))
     return genes
+
+
+def ga_restart(genes, fitness, cfg: GAConfig, generation: int):
+    """Restart of generation `generation` (Sec. 5.6): the worst half replaced by
+    Sobol points; returns the new genes (the caller evaluates them)."""
+    npix = genes.shape[0]
+    dt = _real(fitness)
+    _dev(genes, torch.uint16, "genes", (npix, cfg.pop, NPAR))
+    _dev(fitness, dt, "fitness", (npix, cfg.pop))
+    out = torch.empty_like(genes)
+    c = cfg.c()
+    f = lib().ga_restart if dt == torch.float32 else lib().ga_restart_f64
+    _check(f(_ptr(genes), _ptr(fitness), npix, C.byref(c), int(generation), _ptr(out),
+             _stream(genes)))
+    return out
 
 
 def ga_decode(genes: torch.Tensor, bnds: MeBounds):

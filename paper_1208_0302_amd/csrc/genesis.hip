@@ -101,6 +101,12 @@ int pack_ga(const ga_config *cfg, GaConst &ga)
     if (cfg->synth_precision != GENESIS_SYNTH_NATIVE && cfg->synth_precision != GENESIS_SYNTH_FP16)
         return fail(ME_EINVAL, "synth_precision = %d is not a GENESIS_SYNTH_* value",
                     cfg->synth_precision);
+    if (cfg->init_mode != 0 && cfg->init_mode != 1)
+        return fail(ME_EINVAL, "init_mode = %d must be 0 (Philox) or 1 (Sobol)", cfg->init_mode);
+    if (cfg->restart_every < 0)
+        return fail(ME_EINVAL, "restart_every must be >= 0");
+    ga.init_mode = cfg->init_mode;
+    ga.restart_every = cfg->restart_every;
     ga.n_seeded = cfg->n_seeded;
     ga.seed_jitter = cfg->seed_jitter;
     ga.seed_params = cfg->n_seeded > 0 ? cfg->seed_params : nullptr;
@@ -267,6 +273,36 @@ __global__ void k_ga_init(int64_t npix, GaConst ga, Bounds b, uint16_t *__restri
         genes[t * GENESIS_NPAR + j] = (uint16_t)g[j];
 }
 
+// Restart of generation t (workgroup per pixel): ranks by fitness, the worst
+// half replaced by Sobol points, the rest copied.
+template <typename Real>
+__global__ __launch_bounds__(1024) void k_ga_restart(const uint16_t *__restrict__ genes_in,
+                                                     const Real *__restrict__ fitness,
+                                                     int64_t npix, GaConst ga, int t,
+                                                     uint16_t *__restrict__ genes_out)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    Real *fit_s = reinterpret_cast<Real *>(smem);
+    const int pop = ga.pop;
+    const int tid = threadIdx.x;
+    for (int64_t p = blockIdx.x; p < npix; p += gridDim.x) {
+        for (int i = tid; i < pop; i += blockDim.x)
+            fit_s[i] = fitness[p * pop + i];
+        __syncthreads();
+        const uint32_t pix = ga.pixel_base + (uint32_t)p;
+        for (int i = tid; i < pop; i += blockDim.x) {
+            const int64_t row = (p * pop + i) * GENESIS_NPAR;
+            uint32_t g[GENESIS_NPAR];
+            if (!restart_genes(ga, pix, t, fitness_rank(fit_s, pop, i), g))
+                for (int j = 0; j < GENESIS_NPAR; ++j)
+                    g[j] = genes_in[row + j];
+            for (int j = 0; j < GENESIS_NPAR; ++j)
+                genes_out[row + j] = (uint16_t)g[j];
+        }
+        __syncthreads();
+    }
+}
+
 template <typename Real>
 __global__ void k_decode(const uint16_t *__restrict__ genes, int64_t n, Bounds b,
                          Real *__restrict__ params)
@@ -424,9 +460,12 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN> a)
                 s.genes[j * pop + tid] = (uint16_t)g0[j];
         }
         Real f = (Real)0;
-        for (int t = 0;; ++t) {
+        // one evaluation site: after a restart the loop comes back here with
+        // only the replaced lanes to evaluate
+        bool eval = active, restarted = false;
+        for (int t = 0;;) {
             // evaluate generation t (each lane reads only its own genes)
-            if (active) {
+            if (eval) {
                 if constexpr (SYN == GENESIS_SYNTH_FP16)
                     f = evaluate_lds_h(s.genes + cur, pop, tid, a.b, mu, a.ls, a.lh, s.obs, w2,
                                        inv_nu);
@@ -435,6 +474,18 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN> a)
                 s.fit[tid] = f;
             }
             __syncthreads();
+            if (!restarted && restart_due(a.ga, t, a.generations)) {
+                const int rank = active ? fitness_rank(s.fit, pop, tid) : 0;
+                __syncthreads();
+                uint32_t gr[GENESIS_NPAR];
+                eval = active && restart_genes(a.ga, pix, t, rank, gr);
+                if (eval)
+#pragma unroll
+                    for (int j = 0; j < GENESIS_NPAR; ++j)
+                        s.genes[cur + j * pop + tid] = (uint16_t)gr[j];
+                restarted = true;
+                continue;
+            }
             if (t == a.generations)
                 break;
             const int e = block_argmin(s.fit, pop, s.red_f, s.red_i);
@@ -449,6 +500,9 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN> a)
             }
             __syncthreads();
             cur = gstride - cur;
+            ++t;
+            eval = active;
+            restarted = false;
         }
         const int e = block_argmin(s.fit, pop, s.red_f, s.red_i);
         if (tid == 0) {
@@ -965,6 +1019,33 @@ int refine_impl(const double *obs, const double *sigma, const double *mu, int64_
 
 // ---- C ABI -------------------------------------------------------------
 
+template <typename Real>
+int restart_impl(const uint16_t *genes_in, const Real *fitness, int64_t npix,
+                 const ga_config *cfg, int32_t generation, uint16_t *genes_out, void *stream)
+{
+    GaConst ga;
+    if (int rc = pack_ga(cfg, ga))
+        return rc;
+    if (ga.restart_every < 1 || generation < 1 || generation % ga.restart_every != 0)
+        return fail(ME_EINVAL, "generation %d is not a restart generation (restart_every %d)",
+                    generation, ga.restart_every);
+    if (npix < 0)
+        return fail(ME_EINVAL, "npix must be >= 0");
+    if (npix == 0)
+        return ME_OK;
+    if (!genes_in || !fitness || !genes_out)
+        return fail(ME_EINVAL, "NULL array argument");
+    const size_t bytes = (size_t)npix * cfg->pop * GENESIS_NPAR * sizeof(uint16_t);
+    const char *gi = (const char *)genes_in, *go = (const char *)genes_out;
+    if (gi < go + bytes && go < gi + bytes)
+        return fail(ME_EINVAL, "genes_in and genes_out overlap");
+    hipLaunchKernelGGL(k_ga_restart<Real>, dim3(grid_for(npix)), dim3(block_for_pop(cfg->pop)),
+                       sizeof(Real) * cfg->pop, as_stream(stream), genes_in, fitness, npix, ga,
+                       (int)generation, genes_out);
+    return check_launch("ga_restart");
+}
+
+
 extern "C" {
 
 const char *me_last_error(void) { return g_err.c_str(); }
@@ -1106,6 +1187,18 @@ int ga_init(int64_t npix, const ga_config *cfg, const me_bounds *bounds, uint16_
     hipLaunchKernelGGL(k_ga_init, dim3((unsigned)blocks), dim3(bs), 0, as_stream(stream), npix,
                        ga, b, genes);
     return check_launch("ga_init");
+}
+
+int ga_restart(const uint16_t *genes_in, const float *fitness, int64_t npix,
+               const ga_config *cfg, int32_t generation, uint16_t *genes_out, void *stream)
+{
+    return restart_impl<float>(genes_in, fitness, npix, cfg, generation, genes_out, stream);
+}
+
+int ga_restart_f64(const uint16_t *genes_in, const double *fitness, int64_t npix,
+                   const ga_config *cfg, int32_t generation, uint16_t *genes_out, void *stream)
+{
+    return restart_impl<double>(genes_in, fitness, npix, cfg, generation, genes_out, stream);
 }
 
 int ga_decode(const uint16_t *genes, int64_t n, const me_bounds *bounds, float *params,

@@ -486,13 +486,141 @@ struct GaConst {
     uint32_t pixel_base;
     int32_t n_seeded, seed_jitter;
     const float *seed_params;    // [npix][9] first guesses, or nullptr
+    int32_t init_mode;           // 0 Philox-uniform genes, 1 Sobol points
+    int32_t restart_every;       // 0: no restarts
 };
 
-enum : uint32_t { kSeedJitter = 5 };
+enum : uint32_t { kSobolShift = 4, kSeedJitter = 5 };
+
+// ------------------------------------------------------------------------
+// Sobol' points (Sobol' 1967; the construction of Bratley & Fox 1988) for
+// the initial population and the restarts of Sec. 5.6.  Dimension 0 is the
+// base-2 van der Corput sequence; dimension d >= 1 uses the d-th primitive
+// polynomial over GF(2) in order of degree and then of value, with initial
+// direction numbers m_1 = ... = m_s = 1 (odd and below 2^k, as required),
+// and m_k = m_{k-s} ^ (m_{k-s} << s) ^ sum_{i=1}^{s-1} a_i (m_{k-i} << i)
+// for p(x) = x^s + a_1 x^(s-1) + ... + a_(s-1) x + 1.  Point n, coordinate d:
+// the XOR of V_k = m_k << (32 - k) over the set bits k - 1 of n.  The tables
+// are built at compile time from these definitions.
+struct SobolTable {
+    uint32_t poly[GENESIS_NPAR];         // polynomial bits (x^s ... 1); dimension 0 unused
+    uint32_t v[GENESIS_NPAR][32];        // V_k, k = 1 .. 32
+};
+
+constexpr uint32_t gf2_mulmod(uint32_t a, uint32_t b, uint32_t p, int deg)
+{
+    uint32_t r = 0;
+    for (int i = 0; i < deg; ++i) {
+        if (b & 1u)
+            r ^= a;
+        b >>= 1;
+        a <<= 1;
+        if (a & (1u << deg))
+            a ^= p;
+    }
+    return r;
+}
+
+constexpr uint32_t gf2_xpow(uint64_t e, uint32_t p, int deg)
+{
+    uint32_t r = 1, b = deg > 1 ? 2u : (2u ^ p);  // x mod p
+    while (e) {
+        if (e & 1u)
+            r = gf2_mulmod(r, b, p, deg);
+        b = gf2_mulmod(b, b, p, deg);
+        e >>= 1;
+    }
+    return r;
+}
+
+// p of degree deg with p(0) = 1 is primitive iff x has order 2^deg - 1 mod p.
+constexpr bool gf2_primitive(uint32_t p, int deg)
+{
+    const uint64_t n = (1ull << deg) - 1;
+    if (gf2_xpow(n, p, deg) != 1u)
+        return false;
+    uint64_t m = n;
+    for (uint64_t q = 2; q * q <= m; ++q) {
+        if (m % q)
+            continue;
+        if (gf2_xpow(n / q, p, deg) == 1u)
+            return false;
+        while (m % q == 0)
+            m /= q;
+    }
+    if (m > 1 && m != n && gf2_xpow(n / m, p, deg) == 1u)
+        return false;
+    if (m == n && n > 1 && gf2_xpow(1, p, deg) == 1u)
+        return false;
+    return true;
+}
+
+constexpr SobolTable make_sobol()
+{
+    SobolTable t{};
+    for (int k = 1; k <= 32; ++k)
+        t.v[0][k - 1] = 1u << (32 - k);
+    int d = 1;
+    for (int deg = 1; d < GENESIS_NPAR; ++deg)
+        for (uint32_t p = (1u << deg) | 1u; p < (2u << deg) && d < GENESIS_NPAR; p += 2)
+            if (gf2_primitive(p, deg))
+                t.poly[d++] = p;
+    for (d = 1; d < GENESIS_NPAR; ++d) {
+        const uint32_t p = t.poly[d];
+        int s = 0;
+        while ((p >> (s + 1)) != 0)
+            ++s;
+        uint32_t m[33] = {};
+        for (int k = 1; k <= 32; ++k) {
+            if (k <= s) {
+                m[k] = 1u;
+            } else {
+                uint32_t x = m[k - s] ^ (m[k - s] << s);
+                for (int i = 1; i < s; ++i)
+                    if ((p >> (s - i)) & 1u)
+                        x ^= m[k - i] << i;
+                m[k] = x;
+            }
+            t.v[d][k - 1] = m[k] << (32 - k);
+        }
+    }
+    return t;
+}
+
+constexpr SobolTable kSobol = make_sobol();
+
+__device__ __forceinline__ uint32_t sobol_coord(int d, uint32_t n)
+{
+    uint32_t x = 0;
+#pragma unroll
+    for (int k = 0; k < 32; ++k)
+        if ((n >> k) & 1u)
+            x ^= kSobol.v[d][k];
+    return x;
+}
+
+// Genes of Sobol point n for pixel pix: the point's coordinates XORed with a
+// per-pixel digital shift (stream purpose 4, individual 0), top 16 bits.
+__device__ __forceinline__ void sobol_genes(uint32_t pix, uint32_t n, const Key &key,
+                                            uint32_t (&g)[GENESIS_NPAR])
+{
+#pragma unroll
+    for (int blk = 0; blk < 3; ++blk) {
+        const uint4 w = philox(pix, 0u, 0u, (kSobolShift << 24) | (uint32_t)blk, key);
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = 4 * blk + q;
+            if (j < GENESIS_NPAR)
+                g[j] = (sobol_coord(j, n) ^ ws[q]) >> 16;
+        }
+    }
+}
 
 // The nine genes of individual i of pixel p (call-local index) in generation
-// 0: random (stream purpose 0), or, for i < n_seeded, the encoded first guess
-// (exact for i = 0, integer-jittered for i >= 1, stream purpose 5).
+// 0: random (stream purpose 0) or Sobol point i (init_mode 1), or, for
+// i < n_seeded, the encoded first guess (exact for i = 0, integer-jittered
+// for i >= 1, stream purpose 5).
 __device__ __forceinline__ void initial_genes(uint32_t pix, int64_t p, int i, const GaConst &ga,
                                               const Bounds &b, uint32_t (&g)[GENESIS_NPAR])
 {
@@ -522,6 +650,10 @@ __device__ __forceinline__ void initial_genes(uint32_t pix, int64_t p, int i, co
                 }
             }
         }
+        return;
+    }
+    if (ga.init_mode == 1) {
+        sobol_genes(pix, (uint32_t)i, ga.key, g);
         return;
     }
 #pragma unroll
@@ -671,6 +803,41 @@ __device__ __forceinline__ int block_argmin(const Real *fit_s, int pop, Real *re
             idx = red_i[w];
         }
     return idx;
+}
+
+// Restarts (Sec. 5.6): after the evaluation of generation t, when
+// restart_every > 0, t > 0, t < G and t is a multiple of restart_every, the
+// worst nrep = pop / 2 individuals (fitness order of the tournaments: NaN
+// last, ties to the lower index) are replaced by fresh Sobol points: the
+// individual of rank pop - nrep + q takes point pop + (r - 1) nrep + q of
+// the pixel's shifted sequence, r = t / restart_every.
+__device__ __forceinline__ bool restart_due(const GaConst &ga, int t, int generations)
+{
+    return ga.restart_every > 0 && t > 0 && t < generations && t % ga.restart_every == 0;
+}
+
+template <typename Real>
+__device__ __forceinline__ int fitness_rank(const Real *fit_s, int pop, int i)
+{
+    const Real fi = fit_key(fit_s[i]);
+    int r = 0;
+    for (int j = 0; j < pop; ++j)
+        r += before(fit_key(fit_s[j]), j, fi, i) ? 1 : 0;
+    return r;
+}
+
+// Genes of the restart replacement for an individual of rank `rank` at
+// generation t; false if the individual is kept.
+__device__ __forceinline__ bool restart_genes(const GaConst &ga, uint32_t pix, int t, int rank,
+                                              uint32_t (&g)[GENESIS_NPAR])
+{
+    const int nrep = ga.pop / 2;
+    const int q = rank - (ga.pop - nrep);
+    if (q < 0)
+        return false;
+    const uint32_t r = (uint32_t)(t / ga.restart_every);
+    sobol_genes(pix, (uint32_t)ga.pop + (r - 1u) * (uint32_t)nrep + (uint32_t)q, ga.key, g);
+    return true;
 }
 
 }  // namespace genesis

@@ -89,7 +89,12 @@ __global__ __launch_bounds__(1024) void k_ga_advance(const ReqDesc *__restrict__
     const int gstride = GENESIS_NPAR * pop;
     int cur = 0;
     float f = 0.0f;
+    // one evaluation site, as in k_ga_invert: generation g is evaluated, then
+    // restarted if due (the replaced lanes come back to be evaluated), then
+    // bred into generation g + 1 until gen_to is reached.  A resumed
+    // generation was saved after its restart.
     int g = d.gen_done;
+    bool eval, restarted;
     if (g < 0) {
         if (active) {
             uint32_t g0[GENESIS_NPAR];
@@ -97,20 +102,42 @@ __global__ __launch_bounds__(1024) void k_ga_advance(const ReqDesc *__restrict__
 #pragma unroll
             for (int j = 0; j < GENESIS_NPAR; ++j)
                 s.genes[j * pop + tid] = (uint16_t)g0[j];
-            f = evaluate_lds(s.genes, pop, tid, d.b, mu, d.ls, s.obs, w2, inv_nu);
-            s.fit[tid] = f;
         }
         g = 0;
-    } else if (active) {
-        const int64_t row = p * pop + tid;
+        eval = active;
+        restarted = false;
+    } else {
+        if (active) {
+            const int64_t row = p * pop + tid;
 #pragma unroll
-        for (int j = 0; j < GENESIS_NPAR; ++j)
-            s.genes[j * pop + tid] = d.genes[row * GENESIS_NPAR + j];
-        f = d.fit[row];
-        s.fit[tid] = f;
+            for (int j = 0; j < GENESIS_NPAR; ++j)
+                s.genes[j * pop + tid] = d.genes[row * GENESIS_NPAR + j];
+            f = d.fit[row];
+            s.fit[tid] = f;
+        }
+        eval = false;
+        restarted = true;
     }
-    __syncthreads();
-    for (; g < d.gen_to; ++g) {
+    for (;;) {
+        if (eval) {
+            f = evaluate_lds(s.genes + cur, pop, tid, d.b, mu, d.ls, s.obs, w2, inv_nu);
+            s.fit[tid] = f;
+        }
+        __syncthreads();
+        if (!restarted && restart_due(d.ga, g, d.generations)) {
+            const int rank = active ? fitness_rank(s.fit, pop, tid) : 0;
+            __syncthreads();
+            uint32_t gr[GENESIS_NPAR];
+            eval = active && restart_genes(d.ga, pix, g, rank, gr);
+            if (eval)
+#pragma unroll
+                for (int j = 0; j < GENESIS_NPAR; ++j)
+                    s.genes[cur + j * pop + tid] = (uint16_t)gr[j];
+            restarted = true;
+            continue;
+        }
+        if (g == d.gen_to)
+            break;
         const int e = block_argmin(s.fit, pop, s.red_f, s.red_i);
         if (active) {
             LdsChild out{s.genes + (gstride - cur), pop, tid};
@@ -123,11 +150,9 @@ __global__ __launch_bounds__(1024) void k_ga_advance(const ReqDesc *__restrict__
         }
         __syncthreads();
         cur = gstride - cur;
-        if (active) {
-            f = evaluate_lds(s.genes + cur, pop, tid, d.b, mu, d.ls, s.obs, w2, inv_nu);
-            s.fit[tid] = f;
-        }
-        __syncthreads();
+        ++g;
+        eval = active;
+        restarted = false;
     }
     if (finish) {
         const int e = block_argmin(s.fit, pop, s.red_f, s.red_i);
