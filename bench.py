@@ -214,11 +214,13 @@ PEAK_BF16_MFMA = 2.5e15       # MI355X published dense BF16 matrix peak
 def proposal(args):
     """Learned proposal: BF16 training of the network on examples synthesised
     on the fly (one step = one mlp_train step of `batch` examples: draw,
-    me_synth, noise, features, forward, backward, Adam), then the seeding
-    comparison on held-out noisy pixels: median chi-square and the fraction of
-    pixels at or below the chi-square target after G generations, random
-    initial population versus 32 of 128 individuals seeded from the network
-    (1 exact + 31 jittered)."""
+    me_synth, noise, features, forward, backward, Adam), then the comparison
+    of initial populations on held-out noisy pixels: median chi-square and the
+    fraction of pixels at or below the reduced chi-square target after G
+    generations (and after G = 200 plus the FP64 refinement), for a random
+    population, 32 of 128 individuals seeded from the network (1 exact + 31
+    jittered), Sobol points, and Sobol points with restarts every 50
+    generations (G/4 of the 200-generation run, Sec. 5.6)."""
     import torch
     import paper_1208_0302_amd as g
     import synth_inputs as si
@@ -283,17 +285,26 @@ def proposal(args):
     torch.cuda.synchronize()
     infer_ms = ei[0].elapsed_time(ei[1])
     target = args.chi2_target
+    strategies = (("random", {}),
+                  ("seeded", dict(n_seeded=32, seed_jitter=512, seed_params=guess)),
+                  ("sobol", dict(init_mode=1)),
+                  ("sobol_restart", dict(init_mode=1, restart_every=50)))
     table = []
     for gens in (0, 10, 25, 50, 100, 150, 200):
         row = {"generations": gens}
-        for name, extra in (("random", {}),
-                            ("seeded", dict(n_seeded=32, seed_jitter=512, seed_params=guess))):
+        for name, extra in strategies:
             cfg = g.GAConfig(pop=128, generations=gens, tournament_k=4, p_cross=0.85,
                              p_mut=0.05, seed=7, **extra)
             r = g.ga_invert(obs, sig, lines, grids, b, cfg)
             c = r["chi2"].cpu().numpy()
             row[name + "_median_chi2"] = float(np.median(c))
             row[name + "_frac_at_target"] = float((c <= target).mean())
+            if gens == 200:
+                ref = g.me_refine_f64(obs.double(), sig.double(), lines, grids, b,
+                                      r["params"].double().contiguous(), REFINE_ITERS)
+                cr = ref["chi2"].cpu().numpy()
+                row[name + "_refined_median_chi2"] = float(np.median(cr))
+                row[name + "_refined_frac_at_target"] = float((cr <= target).mean())
         table.append(row)
         print("proposal: G=%d %s" % (gens, row), file=sys.stderr, flush=True)
 
@@ -322,8 +333,7 @@ def proposal(args):
            "proposal_median_abs_err": dict(zip(si.PARAM_NAMES,
                                                np.median(err, axis=0).round(4).tolist())),
            "chi2_target": target,
-           "generations_to_median_target": {"random": first_reaching("random"),
-                                            "seeded": first_reaching("seeded")},
+           "generations_to_median_target": {n: first_reaching(n) for n, _ in strategies},
            "seeding_table": table,
            "roofline": {"bound": "mfma", "achieved": pass_flop / pass_s / 1e12,
                         "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
@@ -447,7 +457,7 @@ def main():
                     help="disc: keep every n-th on-disc pixel of the 2048^2 map")
     ap.add_argument("--batch", type=int, default=1024, help="proposal: training batch")
     ap.add_argument("--heldout", type=int, default=16384, help="proposal: held-out pixels")
-    ap.add_argument("--chi2-target", type=float, default=2.0,
+    ap.add_argument("--chi2-target", type=float, default=1.2,
                     help="proposal: reduced chi-square target")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times) so that "

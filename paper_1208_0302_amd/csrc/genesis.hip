@@ -175,14 +175,31 @@ struct StokesSink {
     }
 };
 
+// Stokes vectors of n models: one thread per model and chunk of
+// kSynthChunk consecutive samples of one line, so that a batch of a thousand
+// models still fills the chip (the model set-up is repeated per chunk).
+constexpr int kSynthChunk = 8;
+
+template <typename Real>
+__host__ __device__ inline int synth_chunks(const DevLines<Real> &ls)
+{
+    int n = 0;
+    for (int l = 0; l < ls.nlines; ++l)
+        n += (ls.l[l].nlam + kSynthChunk - 1) / kSynthChunk;
+    return n;
+}
+
 template <typename Real>
 __global__ __launch_bounds__(256) void k_me_synth(const Real *__restrict__ params, int64_t n,
-                                                  DevLines<Real> ls, const Real *__restrict__ mu,
+                                                  DevLines<Real> ls, int nch,
+                                                  const Real *__restrict__ mu,
                                                   Real *__restrict__ out)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n)
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nch)
         return;
+    const int64_t i = t / nch;
+    int c = (int)(t - i * nch);
     double p[GENESIS_NPAR];
 #pragma unroll
     for (int j = 0; j < GENESIS_NPAR; ++j)
@@ -190,7 +207,19 @@ __global__ __launch_bounds__(256) void k_me_synth(const Real *__restrict__ param
     Model<Real> m;
     model_setup(p, mu ? (double)mu[i] : 1.0, m);
     StokesSink<Real> s{out + i * 4 * (int64_t)ls.L, ls.L};
-    synthesize(m, ls, s);
+#pragma unroll
+    for (int l = 0; l < GENESIS_MAX_LINES; ++l) {
+        if (l >= ls.nlines)
+            return;
+        const DevLine<Real> &ln = ls.l[l];
+        const int cl = (ln.nlam + kSynthChunk - 1) / kSynthChunk;
+        if (c < cl) {
+            const int j0 = c * kSynthChunk;
+            synth_line_range(m, ln, s, j0, min(j0 + kSynthChunk, ln.nlam));
+            return;
+        }
+        c -= cl;
+    }
 }
 
 // Stokes vectors with the FP16 profile synthesis of ga_invert's
@@ -829,12 +858,13 @@ int synth_impl(const Real *params, int64_t n, const me_line *lines, const me_gri
         return ME_OK;
     if (!params || !stokes)
         return fail(ME_EINVAL, "params and stokes must not be NULL");
+    const int nch = synth_chunks(ls);
     const int bs = 256;
-    const int64_t blocks = (n + bs - 1) / bs;
-    if (blocks > kMaxGrid)
+    const int64_t blocks = (n * nch + bs - 1) / bs;
+    if (n > ((int64_t)1 << 40) / nch || blocks > kMaxGrid)
         return fail(ME_EINVAL, "n too large");
     hipLaunchKernelGGL(k_me_synth<Real>, dim3((unsigned)blocks), dim3(bs), 0, as_stream(stream),
-                       params, n, ls, mu, stokes);
+                       params, n, ls, nch, mu, stokes);
     return check_launch("me_synth");
 }
 

@@ -379,17 +379,17 @@ __device__ __forceinline__ void unno_rachkovsky(const M &m, Real hb, Real lb, Re
     V = fma(k2, eV, rV * Pi) * nrD;
 }
 
-// One line: every wavelength, handing (j, I, Q, U, V) to `sink`.
+// Samples j0 .. j1-1 of one line, handing (j, I, Q, U, V) to `sink`.
 template <int NB, int NP, int NR, typename Real, typename Sink>
 __device__ __forceinline__ void synth_line(const Model<Real> &m, const DevLine<Real> &ln,
-                                           Sink &sink)
+                                           Sink &sink, int j0, int j1)
 {
     const Real xb = (ln.off0 - m.vlos * ln.dop_kms) * m.inv_dop;
     const Real xs = ln.step * m.inv_dop;
     const Real zb = ln.zee_G * m.B * m.inv_dop;
     const int nb = NB >= 0 ? NB : ln.nb, np = NP >= 0 ? NP : ln.np;
     const int nr = NR >= 0 ? NR : ln.nr;
-    for (int j = 0; j < ln.nlam; ++j) {
+    for (int j = j0; j < j1; ++j) {
         const Real x0 = fma((Real)j, xs, xb);
         Real hb = 0, lb = 0, hp = 0, lp = 0, hr = 0, lr = 0;
         group<NB>(m, ln, 0, nb, x0, zb, hb, lb);
@@ -401,20 +401,28 @@ __device__ __forceinline__ void synth_line(const Model<Real> &m, const DevLine<R
     }
 }
 
-// Every line; the two Zeeman patterns of the Fe I 6302 pair (a triplet and
-// the 4 + 4 + 4 pattern of 6301.5) get compile-time component counts.
+// The two Zeeman patterns of the Fe I 6302 pair (a triplet and the 4 + 4 + 4
+// pattern of 6301.5) get compile-time component counts.
+template <typename Real, typename Sink>
+__device__ __forceinline__ void synth_line_range(const Model<Real> &m, const DevLine<Real> &ln,
+                                                 Sink &sink, int j0, int j1)
+{
+    if (ln.nb == 1 && ln.np == 1 && ln.nr == 1)
+        synth_line<1, 1, 1>(m, ln, sink, j0, j1);
+    else if (ln.nb == 4 && ln.np == 4 && ln.nr == 4)
+        synth_line<4, 4, 4>(m, ln, sink, j0, j1);
+    else
+        synth_line<-1, -1, -1>(m, ln, sink, j0, j1);
+}
+
+// Every line.
 template <typename Real, typename Sink>
 __device__ __forceinline__ void synthesize(const Model<Real> &m, const DevLines<Real> &ls,
                                            Sink &sink)
 {
     for (int l = 0; l < ls.nlines; ++l) {
         const DevLine<Real> &ln = ls.l[l];
-        if (ln.nb == 1 && ln.np == 1 && ln.nr == 1)
-            synth_line<1, 1, 1>(m, ln, sink);
-        else if (ln.nb == 4 && ln.np == 4 && ln.nr == 4)
-            synth_line<4, 4, 4>(m, ln, sink);
-        else
-            synth_line<-1, -1, -1>(m, ln, sink);
+        synth_line_range(m, ln, sink, 0, ln.nlam);
     }
 }
 
