@@ -281,11 +281,16 @@ int ga_invert_f64(const double *obs, const double *sigma, const double *mu, int6
  * outputs params_out [npix][9], chi2_out [npix] (FP64 model, same merit
  * function), iters_done [npix] (may be NULL).  Bounds need hi > lo for all
  * nine parameters.  Pixels with non-finite observations or sigma <= 0 give
- * NaN. */
+ * NaN.  sigma_params [npix][9] (may be NULL): the uncertainties of Sec. 6,
+ * sigma_j^2 = [H^-1]_jj chi2 / M (M = 9) with H the Hessian of the reduced
+ * chi-square at the result in Gauss-Newton form (2/nu) J^T J (same forward
+ * differences, one more Jacobian at the final model); +infinity for a
+ * parameter the model does not depend on, NaN when J^T J is singular. */
 int me_refine_f64(const double *obs, const double *sigma, const double *mu, int64_t npix,
                   const me_line *lines, const me_grid *grids, int32_t nlines,
                   const me_bounds *bounds, const double *params_in, int32_t iterations,
-                  double *params_out, double *chi2_out, int32_t *iters_done, void *stream);
+                  double *params_out, double *chi2_out, int32_t *iters_done,
+                  double *sigma_params, void *stream);
 
 /* ---- learned proposal (first guesses for seeding) ---------------------- */
 

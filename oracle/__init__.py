@@ -100,7 +100,7 @@ def lib():
                                            C.c_int, C.c_int, _dp, _dp, _i32p, _u16p, _dp]
             L.oracle_ga_invert.restype = C.c_int
             L.oracle_lm_refine.argtypes = [_dp, _dp, _dp, C.c_int64, _linep, C.c_int, _dp, _dp,
-                                           _dp, C.c_int, _dp, _dp, _i32p]
+                                           _dp, C.c_int, _dp, _dp, _i32p, _dp]
             L.oracle_lm_refine.restype = C.c_int
             L.oracle_num_threads.restype = C.c_int
             _LIB = L
@@ -319,7 +319,8 @@ def ga_invert(obs, sigma, lines, lo, hi, pop, generations, k, p_cross, p_mut, se
 
 
 def lm_refine(obs, sigma, lines, lo, hi, params_in, iterations, mu=None):
-    """FP64 Levenberg-Marquardt refinement; returns dict(params, chi2, iters)."""
+    """FP64 Levenberg-Marquardt refinement; returns dict(params, chi2, iters,
+    sigma): sigma [npix, 9] are the Sec. 6 uncertainties at the result."""
     o = _f64(obs)
     s = _f64(sigma)
     npix = o.shape[0]
@@ -329,15 +330,16 @@ def lm_refine(obs, sigma, lines, lo, hi, params_in, iterations, mu=None):
     po = np.empty((npix, NPAR), np.float64)
     co = np.empty(npix, np.float64)
     it = np.empty(npix, np.int32)
+    sg = np.empty((npix, NPAR), np.float64)
     arr, lp = _lines_array(lines)
     m = None if mu is None else _f64(np.broadcast_to(mu, (npix,)))
     rc = lib().oracle_lm_refine(_ptr(o, _dp), _ptr(s, _dp), None if m is None else _ptr(m, _dp),
                                 npix, lp, len(lines), _ptr(lo, _dp), _ptr(hi, _dp),
                                 _ptr(p0, _dp), int(iterations), _ptr(po, _dp), _ptr(co, _dp),
-                                _ptr(it, _i32p))
+                                _ptr(it, _i32p), _ptr(sg, _dp))
     if rc != 0:
         raise ValueError("oracle_lm_refine rejected its arguments")
-    return dict(params=po, chi2=co, iters=it)
+    return dict(params=po, chi2=co, iters=it, sigma=sg)
 
 
 def num_threads():

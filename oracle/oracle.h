@@ -134,7 +134,7 @@ int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, i
 int oracle_lm_refine(const double *obs, const double *sigma, const double *mu, int64_t npix,
                      const oracle_line *lines, int nlines, const double *lo, const double *hi,
                      const double *params_in, int iterations, double *params_out,
-                     double *chi2_out, int32_t *iters_done);
+                     double *chi2_out, int32_t *iters_done, double *sigma_params);
 
 /* Threads the OpenMP loops would use. */
 int oracle_num_threads(void);

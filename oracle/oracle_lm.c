@@ -17,6 +17,15 @@
  *   chi2(x') < chi2(x) (lambda /= 10, not below 1e-12), else lambda *= 10
  *   (not above 1e12) and retry, at most 10 trials per iteration; stop when a
  *   whole iteration fails.  lambda starts at 1e-3.
+ *
+ * Uncertainties (Sec. 6): sigma_j^2 = [H^-1]_jj chi2(p_opt) / M with H the
+ * Hessian of the reduced chi-square at the refined optimum in its
+ * Gauss-Newton form, H = (2/nu) J_p^T J_p (J_p the Jacobian of the weighted
+ * residuals in parameter units, from the same forward differences), so
+ * [H^-1]_jj = (nu/2) (hi_j - lo_j)^2 [A^-1]_jj with A the normalised-
+ * coordinate J^T J.  A parameter the model does not depend on (A_jj = 0)
+ * gets +infinity and is left out of the inverse of the others; a matrix
+ * that is not positive definite gives NaN for every parameter.
  */
 #include "oracle.h"
 
@@ -52,6 +61,39 @@ static double chi2_at(const double *x, const double *lo, const double *hi, doubl
     double p[NP];
     to_params(x, lo, hi, p);
     return oracle__chi2_single(p, mu, lines, nlines, obs, sigma, scratch);
+}
+
+/* J (R x 9, normalised coordinates, weighted), A = J^T J and g = J^T r at x */
+static void normal_equations(const double *x, const double *lo, const double *hi, double mu,
+                             const oracle_line *lines, int nlines, const double *o,
+                             const double *s, int L, double *m0, double *m1, double *J,
+                             double *A, double *g)
+{
+    const int R = 4 * L;
+    const double h = 1e-7;
+    model_at(x, lo, hi, mu, lines, nlines, m0);
+    for (int j = 0; j < NP; ++j) {
+        double xs[NP];
+        memcpy(xs, x, sizeof xs);
+        const double hj = (x[j] + h <= 1.0) ? h : -h;
+        xs[j] += hj;
+        model_at(xs, lo, hi, mu, lines, nlines, m1);
+        for (int i = 0; i < R; ++i)
+            J[i * NP + j] = (m1[i] - m0[i]) / (hj * s[i / L]);
+    }
+    for (int a = 0; a < NP; ++a) {
+        g[a] = 0.0;
+        for (int b = 0; b < NP; ++b)
+            A[a * NP + b] = 0.0;
+    }
+    for (int i = 0; i < R; ++i) {
+        const double r = (o[i] - m0[i]) / s[i / L];
+        for (int a = 0; a < NP; ++a) {
+            g[a] += J[i * NP + a] * r;
+            for (int b = 0; b < NP; ++b)
+                A[a * NP + b] += J[i * NP + a] * J[i * NP + b];
+        }
+    }
 }
 
 /* Cholesky solve of the SPD system M d = g (9 x 9, row-major, overwritten) */
@@ -92,7 +134,7 @@ static int cholesky_solve(double *M, const double *g, double *d)
 int oracle_lm_refine(const double *obs, const double *sigma, const double *mu, int64_t npix,
                      const oracle_line *lines, int nlines, const double *lo, const double *hi,
                      const double *params_in, int iterations, double *params_out,
-                     double *chi2_out, int32_t *iters_done)
+                     double *chi2_out, int32_t *iters_done, double *sigma_params)
 {
     if (iterations < 0)
         return -1;
@@ -136,32 +178,8 @@ int oracle_lm_refine(const double *obs, const double *sigma, const double *mu, i
             double lam = 1e-3;
             int it = 0;
             for (; it < iterations; ++it) {
-                /* Jacobian by forward differences */
-                const double h = 1e-7;
-                model_at(x, lo, hi, m, lines, nlines, m0);
-                for (int j = 0; j < NP; ++j) {
-                    double xs[NP];
-                    memcpy(xs, x, sizeof xs);
-                    const double hj = (x[j] + h <= 1.0) ? h : -h;
-                    xs[j] += hj;
-                    model_at(xs, lo, hi, m, lines, nlines, m1);
-                    for (int i = 0; i < R; ++i)
-                        J[i * NP + j] = (m1[i] - m0[i]) / (hj * s[i / L]);
-                }
                 double A[NP * NP], g[NP];
-                for (int a = 0; a < NP; ++a) {
-                    g[a] = 0.0;
-                    for (int b = 0; b < NP; ++b)
-                        A[a * NP + b] = 0.0;
-                }
-                for (int i = 0; i < R; ++i) {
-                    const double r = (o[i] - m0[i]) / s[i / L];
-                    for (int a = 0; a < NP; ++a) {
-                        g[a] += J[i * NP + a] * r;
-                        for (int b = 0; b < NP; ++b)
-                            A[a * NP + b] += J[i * NP + a] * J[i * NP + b];
-                    }
-                }
+                normal_equations(x, lo, hi, m, lines, nlines, o, s, L, m0, m1, J, A, g);
                 int accepted = 0;
                 for (int trial = 0; trial < 10 && !accepted; ++trial) {
                     double M[NP * NP], gg[NP], d[NP];
@@ -204,6 +222,38 @@ int oracle_lm_refine(const double *obs, const double *sigma, const double *mu, i
             chi2_out[p] = c;
             if (iters_done)
                 iters_done[p] = it;
+            if (sigma_params) {
+                double A[NP * NP], g[NP];
+                normal_equations(x, lo, hi, m, lines, nlines, o, s, L, m0, m1, J, A, g);
+                double *sg = sigma_params + p * NP;
+                int keep[NP];
+                for (int a = 0; a < NP; ++a)
+                    keep[a] = A[a * NP + a] != 0.0;
+                int ok = 1;
+                for (int k = 0; k < NP && ok; ++k) {
+                    if (!keep[k]) {
+                        sg[k] = INFINITY;
+                        continue;
+                    }
+                    double M[NP * NP], e[NP], y[NP];
+                    for (int a = 0; a < NP; ++a) {
+                        for (int b = 0; b < NP; ++b)
+                            M[a * NP + b] = (keep[a] && keep[b]) ? A[a * NP + b]
+                                                                  : (a == b ? 1.0 : 0.0);
+                        e[a] = a == k ? 1.0 : 0.0;
+                    }
+                    if (cholesky_solve(M, e, y) != 0) {
+                        ok = 0;
+                        break;
+                    }
+                    const double span = hi[k] - lo[k];
+                    const double nu = (double)(R - NP);
+                    sg[k] = sqrt(0.5 * nu * span * span * y[k] * c / (double)NP);
+                }
+                if (!ok)
+                    for (int k = 0; k < NP; ++k)
+                        sg[k] = NAN;
+            }
         }
         free(m0);
         free(m1);

@@ -133,7 +133,7 @@ _SIGS = {
                    C.c_size_t, _vp], C.c_int),
     "ga_invert_f64": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _cp, _vp, _vp, _vp, _vp, _vp,
                        _vp, C.c_size_t, _vp], C.c_int),
-    "me_refine_f64": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _i32, _vp, _vp, _vp, _vp],
+    "me_refine_f64": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _i32, _vp, _vp, _vp, _vp, _vp],
                       C.c_int),
     "mlp_param_count": ([], C.c_int64),
     "mlp_workspace_bytes": ([_i64], C.c_size_t),
@@ -411,9 +411,11 @@ def ga_invert(obs, sigma, lines, grids, bnds: MeBounds, cfg: GAConfig, mu=None,
     return res
 
 
-def me_refine_f64(obs, sigma, lines, grids, bnds: MeBounds, params_in, iterations=50, mu=None):
+def me_refine_f64(obs, sigma, lines, grids, bnds: MeBounds, params_in, iterations=50, mu=None,
+                  want_sigma=False):
     """FP64 Levenberg-Marquardt refinement of params_in [npix, 9]; returns a
-    dict(params, chi2, iters).  obs, sigma, mu and params_in are float64."""
+    dict(params, chi2, iters[, sigma]).  obs, sigma, mu and params_in are
+    float64; want_sigma adds the Sec. 6 uncertainties [npix, 9]."""
     npix = obs.shape[0]
     L = total_samples(grids)
     _dev(obs, torch.float64, "obs", (npix, 4, L))
@@ -424,11 +426,13 @@ def me_refine_f64(obs, sigma, lines, grids, bnds: MeBounds, params_in, iteration
     res = dict(params=torch.empty((npix, NPAR), dtype=torch.float64, device=dev),
                chi2=torch.empty((npix,), dtype=torch.float64, device=dev),
                iters=torch.empty((npix,), dtype=torch.int32, device=dev))
+    if want_sigma:
+        res["sigma"] = torch.empty((npix, NPAR), dtype=torch.float64, device=dev)
     la, ga, nl = _lines(lines, grids)
     _check(lib().me_refine_f64(_ptr(obs), _ptr(sigma), _ptr(mu), npix, la, ga, nl,
                                C.byref(bnds), _ptr(params_in), int(iterations),
                                _ptr(res["params"]), _ptr(res["chi2"]), _ptr(res["iters"]),
-                               _stream(obs)))
+                               _ptr(res.get("sigma")), _stream(obs)))
     return res
 
 

@@ -583,12 +583,14 @@ struct RefineArgs {
     double lo[GENESIS_NPAR], span[GENESIS_NPAR];
     double *params_out, *chi2_out;
     int32_t *iters_done;
+    double *sigma_out;  // [npix][9] uncertainties, or nullptr
 };
 
 struct RefineShared {
     double x[GENESIS_NPAR], xt[GENESIS_NPAR];
     double red[kRefineThreads / 64][kNA + GENESIS_NPAR + 1];
     double tot[kNA + GENESIS_NPAR + 1];
+    double nrm[kNA + GENESIS_NPAR];  // J^T J (packed) and J^T r at x
     double lam, chi2;
     int flag;
 };
@@ -681,6 +683,44 @@ __device__ bool cholesky9(double (&M)[GENESIS_NPAR][GENESIS_NPAR], const double 
     return true;
 }
 
+// Uncertainties (Sec. 6): sigma_j^2 = [H^-1]_jj chi2 / M, H the Hessian of the
+// reduced chi-square at the refined optimum in Gauss-Newton form,
+// (2/nu) J_p^T J_p, so [H^-1]_jj = (nu/2) span_j^2 [A^-1]_jj for the
+// normalised-coordinate A = J^T J in sh.nrm.  A_jj = 0 gives +infinity and
+// leaves j out; a matrix that is not positive definite gives NaN.
+__device__ void refine_sigma(const RefineArgs &a, const RefineShared &sh, double inv_nu,
+                             double *out)
+{
+    double A[GENESIS_NPAR][GENESIS_NPAR];
+    int q = 0;
+    for (int i = 0; i < GENESIS_NPAR; ++i)
+        for (int j = i; j < GENESIS_NPAR; ++j, ++q)
+            A[i][j] = A[j][i] = sh.nrm[q];
+    bool keep[GENESIS_NPAR];
+    for (int i = 0; i < GENESIS_NPAR; ++i)
+        keep[i] = A[i][i] != 0.0;
+    for (int i = 0; i < GENESIS_NPAR; ++i)
+        for (int j = 0; j < GENESIS_NPAR; ++j)
+            if (!(keep[i] && keep[j]))
+                A[i][j] = i == j ? 1.0 : 0.0;
+    const double chi2_nu = sh.chi2 * inv_nu;
+    for (int k = 0; k < GENESIS_NPAR; ++k) {
+        if (!keep[k]) {
+            out[k] = INFINITY;
+            continue;
+        }
+        double e[GENESIS_NPAR], y[GENESIS_NPAR];
+        for (int i = 0; i < GENESIS_NPAR; ++i)
+            e[i] = i == k ? 1.0 : 0.0;
+        if (!cholesky9(A, e, y)) {
+            for (int i = 0; i < GENESIS_NPAR; ++i)
+                out[i] = NAN;
+            return;
+        }
+        out[k] = sqrt(0.5 / inv_nu * a.span[k] * a.span[k] * y[k] * chi2_nu / GENESIS_NPAR);
+    }
+}
+
 __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
 {
     code_shift<GENESIS_PAD_REFINE>();
@@ -723,7 +763,13 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
             __syncthreads();
         }
         int it = 0;
-        for (; it < a.iterations; ++it) {
+        // one Jacobian per iteration; after the last one (iteration limit, or
+        // an iteration without an accepted trial) the normal matrix at the
+        // final x gives the uncertainties
+        for (;; ++it) {
+            const bool last = it >= a.iterations;
+            if (last && !a.sigma_out)
+                break;
             // ---- Jacobian and normal equations
             double acc[kNA + GENESIS_NPAR];
 #pragma unroll
@@ -774,17 +820,20 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
                 }
             }
             block_sum(acc, sh);
+            if (tid < kNA + GENESIS_NPAR)
+                sh.nrm[tid] = sh.tot[tid];
+            __syncthreads();
             // ---- damped trials
             bool accepted = false;
-            for (int trial = 0; trial < 10; ++trial) {
+            for (int trial = 0; trial < 10 && !last; ++trial) {
                 if (tid == 0) {
                     double Mx[GENESIS_NPAR][GENESIS_NPAR], g[GENESIS_NPAR], d[GENESIS_NPAR];
                     int q = 0;
                     for (int i = 0; i < GENESIS_NPAR; ++i)
                         for (int j = i; j < GENESIS_NPAR; ++j, ++q)
-                            Mx[i][j] = Mx[j][i] = sh.tot[q];
+                            Mx[i][j] = Mx[j][i] = sh.nrm[q];
                     for (int i = 0; i < GENESIS_NPAR; ++i)
-                        g[i] = sh.tot[kNA + i];
+                        g[i] = sh.nrm[kNA + i];
                     for (int i = 0; i < GENESIS_NPAR; ++i) {
                         const double aii = Mx[i][i];
                         if (aii == 0.0) {
@@ -829,8 +878,11 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
                 if (accepted)
                     break;
             }
-            if (!accepted)
-                break;
+            if (accepted)
+                continue;
+            if (a.sigma_out && tid == 0)
+                refine_sigma(a, sh, inv_nu, a.sigma_out + p * GENESIS_NPAR);
+            break;
         }
         if (tid < GENESIS_NPAR)
             a.params_out[p * GENESIS_NPAR + tid] = a.lo[tid] + a.span[tid] * sh.x[tid];
@@ -1005,7 +1057,7 @@ int invert_dispatch(const Real *obs, const Real *sigma, const Real *mu, int64_t 
 int refine_impl(const double *obs, const double *sigma, const double *mu, int64_t npix,
                 const me_line *lines, const me_grid *grids, int nlines, const me_bounds *bounds,
                 const double *params_in, int iterations, double *params_out, double *chi2_out,
-                int32_t *iters_done, void *stream)
+                int32_t *iters_done, double *sigma_params, void *stream)
 {
     RefineArgs a{};
     if (int rc = pack_lines(lines, grids, nlines, a.ls))
@@ -1041,6 +1093,7 @@ int refine_impl(const double *obs, const double *sigma, const double *mu, int64_
     a.params_out = params_out;
     a.chi2_out = chi2_out;
     a.iters_done = iters_done;
+    a.sigma_out = sigma_params;
     hipLaunchKernelGGL(k_refine_f64, dim3(grid_for(npix)), dim3(kRefineThreads), lds,
                        as_stream(stream), a);
     return check_launch("me_refine_f64");
@@ -1320,10 +1373,11 @@ int ga_invert_f64(const double *obs, const double *sigma, const double *mu, int6
 int me_refine_f64(const double *obs, const double *sigma, const double *mu, int64_t npix,
                   const me_line *lines, const me_grid *grids, int32_t nlines,
                   const me_bounds *bounds, const double *params_in, int32_t iterations,
-                  double *params_out, double *chi2_out, int32_t *iters_done, void *stream)
+                  double *params_out, double *chi2_out, int32_t *iters_done,
+                  double *sigma_params, void *stream)
 {
     return refine_impl(obs, sigma, mu, npix, lines, grids, nlines, bounds, params_in, iterations,
-                       params_out, chi2_out, iters_done, stream);
+                       params_out, chi2_out, iters_done, sigma_params, stream);
 }
 
 }  // extern "C"

@@ -106,3 +106,30 @@ def test_ga_then_refine_pipeline_reaches_truth():
           % (np.median(dB_ga), np.percentile(dB_ga, 90), np.median(dB), np.percentile(dB, 90)))
     assert np.median(dB) < np.median(dB_ga)
     assert np.all(r["chi2"].cpu().numpy() <= ga["chi2"].double().cpu().numpy() * 1.001 + 1e-6)
+
+
+def test_uncertainties_match_oracle():
+    """Sec. 6 uncertainties at the refined optimum: both sides evaluate the
+    same Gauss-Newton formula from forward differences of FP64 models that
+    differ by < 1e-10 Ic; a difference of 3e-11 over the step 1e-7 moves a
+    derivative by 3e-4 (normalised units), a relative 1e-3 of the typical
+    derivative, so sigma agrees to 1 % where both runs end at the same x."""
+    lines, grids, olines = _setup("slit")
+    truth = si.draw_truth(12, 14)
+    truth[:, 0] = np.linspace(600.0, 2800.0, 12)
+    obs = oracle.me_synth(truth, olines)
+    sig = si.sigma_for(truth)
+    obs = obs + sig[:, :, None] * si.std_normal(obs.shape, 14)
+    b = g.bounds(LO, HI)
+    r = g.me_refine_f64(_t(obs), _t(sig), lines, grids, b, _t(truth), iterations=40,
+                        want_sigma=True)
+    ref = oracle.lm_refine(obs, sig, olines, LO, HI, truth, 40)
+    gp = r["params"].cpu().numpy()
+    same = (np.abs(gp - ref["params"]) / (HI - LO)).max(axis=1) < 1e-6
+    assert same.sum() >= 10
+    gs = r["sigma"].cpu().numpy()
+    assert np.all(np.isfinite(gs[same])) and np.all(gs[same] > 0)
+    assert np.all(np.abs(gs[same] - ref["sigma"][same]) <= 1e-2 * ref["sigma"][same])
+    # the uncertainties do not change the refinement itself
+    r0 = g.me_refine_f64(_t(obs), _t(sig), lines, grids, b, _t(truth), iterations=40)
+    assert torch.equal(r0["params"], r["params"]) and torch.equal(r0["iters"], r["iters"])
