@@ -219,8 +219,9 @@ def proposal(args):
     fraction of pixels at or below the reduced chi-square target after G
     generations (and after G = 200 plus the FP64 refinement), for a random
     population, 32 of 128 individuals seeded from the network (1 exact + 31
-    jittered), Sobol points, and Sobol points with restarts every 50
-    generations (G/4 of the 200-generation run, Sec. 5.6)."""
+    jittered), 32 seeded from the physics first guesses (me_first_guess: B,
+    inclination and v_los), Sobol points, and Sobol points with restarts every
+    50 generations (G/4 of the 200-generation run, Sec. 5.6)."""
     import torch
     import paper_1208_0302_amd as g
     import synth_inputs as si
@@ -285,8 +286,13 @@ def proposal(args):
     torch.cuda.synchronize()
     infer_ms = ei[0].elapsed_time(ei[1])
     target = args.chi2_target
+    # physics first guesses (weak-field, centre-of-gravity) for B, inclination
+    # and v_los, the parameters those approximations estimate; NaN elsewhere
+    phys = g.me_first_guess(obs.double().contiguous(), lines, grids, b)
+    phys[:, [2, 4, 5, 6, 7, 8]] = float("nan")
     strategies = (("random", {}),
                   ("seeded", dict(n_seeded=32, seed_jitter=512, seed_params=guess)),
+                  ("physics", dict(n_seeded=32, seed_jitter=512, seed_params=phys)),
                   ("sobol", dict(init_mode=1)),
                   ("sobol_restart", dict(init_mode=1, restart_every=50)))
     table = []

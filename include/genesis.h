@@ -104,7 +104,8 @@ typedef struct {
  *               single-call result
  *  seed_jitter  see n_seeded, 0 .. 32767
  *  seed_params  [npix][9] device array of first guesses (parameter units),
- *               used when n_seeded > 0
+ *               used when n_seeded > 0; a NaN entry leaves that parameter's
+ *               gene as drawn for an unseeded individual
  *  synth_precision  arithmetic of the profile synthesis inside ga_invert:
  *               GENESIS_SYNTH_NATIVE (that of the entry point) or
  *               GENESIS_SYNTH_FP16 (FP32 entry point only: Voigt and
@@ -268,6 +269,24 @@ int ga_invert_f64(const double *obs, const double *sigma, const double *mu, int6
                   double *final_fitness, void *workspace, size_t ws_bytes, void *stream);
 
 /* ---- FP64 refinement of a solution (non-linear least squares) ----------- */
+
+/* Heuristic first guesses [npix][9] (float) from the observed Stokes vectors
+ * obs [npix][4][L] (FP64), for ga_config.seed_params: the paper seeds its
+ * population with weak-field, centre-of-gravity and integral estimates
+ * (Sec. 5.5).  Per line: v_los from the centre of gravity of the absorption
+ * I_c - I; the longitudinal field from the centres of gravity of I + V and
+ * I - V (their separation is 2 C gbar B cos(incl), C = 4.6686e-13 lambda0^2,
+ * gbar the first moment of the red sigma group); the transverse field and
+ * azimuth from the weak-field second-order relation of Q and U to the second
+ * derivative of I (least squares); the Doppler width from the half-depth
+ * width corrected for saturation; eta0 from the core depth with the source
+ * function split mu S1 = 3/4 I_c, S0 = I_c / 4; damping the middle of its
+ * range.  Lines combined by equivalent width; every value clamped into the
+ * box.  mu [npix] may be NULL (mu = 1).  Every line needs >= 3 samples and a
+ * red sigma group. */
+int me_first_guess(const double *obs, const double *mu, int64_t npix, const me_line *lines,
+                   const me_grid *grids, int32_t nlines, const me_bounds *bounds, float *params,
+                   void *stream);
 
 /* Levenberg-Marquardt refinement in FP64 of one model per pixel, the local
  * least-squares polish of the genetic algorithm's best individual (the

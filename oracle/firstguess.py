@@ -1,0 +1,125 @@
+"""FP64 oracle of the heuristic first guesses (Sec. 5.5 seeds the initial
+population with field estimates from the weak-field approximation, the
+centre-of-gravity method and the observed profile's shape; the formulas below
+are this package's readings, written from those approximations).
+
+TEST INFRASTRUCTURE ONLY, like the rest of this package: plain numpy in
+float64, one pixel at a time.
+
+Per line, with x_j the sample offsets from the rest wavelength lambda0,
+I_c the largest I sample of the pixel (all lines), d_j = I_c - I_j,
+d+-_j = I_c - (I_j +- V_j), I' and I'' central differences (one-sided first
+differences and I'' = 0 at the window ends), C = 4.6686e-13 lambda0^2 and
+gbar the first moment of the line's red sigma group:
+  centre of gravity  x_cog = sum x d / sum d  ->  v_los = c x_cog / lambda0;
+  longitudinal field (centre of gravity of I + V and I - V)
+                     B_par = (x_cog(d+) - x_cog(d-)) / (2 C gbar);
+  transverse field (weak-field second-order Q, U = -(1/4) C^2 gbar^2 B_perp^2
+                     (cos 2chi, sin 2chi) I'', least squares over the samples)
+                     q = -4 sum Q I'' / (C^2 gbar^2 sum I''^2), u likewise;
+  half-depth width   hw = step #{j : d_j >= max d / 2} / 2 (half the width
+                     of the samples at or above half depth);
+  core depth         D = 1 - min I / I_c.
+Lines are combined with their equivalent widths W = step sum d as weights
+(times gbar for B_par, gbar^2 for q and u).  Then B_perp = sqrt(hypot(q, u)),
+azimuth = atan2(u, q)/2, B = hypot(B_par, B_perp), inclination =
+atan2(B_perp, B_par); with the source function split S1 mu = 3/4 I_c,
+S0 = I_c / 4, eta0 = D'/(1 - D') for D' = min(D / 0.75, 0.97); the Doppler
+width from the W-weighted half-depth width: for S0 = 0 the depth 1 - 1/(1 +
+eta0 H) falls to half its centre value where H = 1/(eta0 + 2), at
+x = dlambda_D sqrt(ln(eta0 + 2)) for a Gaussian core, so dlambda_D =
+hw / sqrt(ln(eta0 + 2)); damping the middle of its range; a non-finite
+estimate becomes the middle of its range; every value clamped into the
+search box (the azimuth wrapped into [0, 180)).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+C_KMS = 299792.458
+ZEEMAN = 4.6686e-13
+
+
+def gbar_of(line):
+    """First moment of the red sigma group of a line's Zeeman pattern."""
+    q = np.asarray(line.q[:line.ncomp])
+    s = np.asarray(line.shift[:line.ncomp])
+    w = np.asarray(line.strength[:line.ncomp])
+    r = q == 1
+    return float((w[r] * s[r]).sum())
+
+
+def _derivs(I, step):
+    n = len(I)
+    d1 = np.empty(n)
+    d1[1:-1] = (I[2:] - I[:-2]) / (2 * step)
+    d1[0] = (I[1] - I[0]) / step
+    d1[-1] = (I[-1] - I[-2]) / step
+    d2 = np.zeros(n)
+    d2[1:-1] = (I[2:] - 2 * I[1:-1] + I[:-2]) / step ** 2
+    return d1, d2
+
+
+def first_guess(obs, lines, lo, hi, mu=None):
+    """obs [npix, 4, L] (the lines' samples concatenated), oracle lines (with
+    their grids) -> first guesses [npix, 9]."""
+    obs = np.asarray(obs, np.float64)
+    npix = obs.shape[0]
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    mus = np.ones(npix) if mu is None else np.broadcast_to(np.asarray(mu, np.float64), (npix,))
+    out = np.empty((npix, 9))
+    for p in range(npix):
+        I_all = obs[p, 0]
+        Ic = I_all.max()
+        off = 0
+        acc = dict(W=0.0, Wv=0.0, Wg=0.0, WgB=0.0, Wg2=0.0, Wq=0.0, Wu=0.0, Wdop=0.0)
+        depth = 0.0
+        for ln in lines:
+            n = ln.nlam
+            I, Q, U, V = (obs[p, s, off:off + n] for s in range(4))
+            off += n
+            x = (ln.start - ln.lambda0) + ln.step * np.arange(n)
+            d = Ic - I
+            dp = Ic - (I + V)
+            dm = Ic - (I - V)
+            d1, d2 = _derivs(I, ln.step)
+            C = ZEEMAN * ln.lambda0 ** 2
+            g = gbar_of(ln)
+            s0 = d.sum()
+            xc = (x * d).sum() / s0
+            v = C_KMS * xc / ln.lambda0
+            bpar = ((x * dp).sum() / dp.sum() - (x * dm).sum() / dm.sum()) / (2 * C * g)
+            s2 = (d2 * d2).sum()
+            q = -4 * (Q * d2).sum() / (C * C * g * g * s2)
+            u = -4 * (U * d2).sum() / (C * C * g * g * s2)
+            hw = 0.5 * ln.step * np.count_nonzero(d >= 0.5 * d.max())
+            W = ln.step * s0
+            acc["W"] += W
+            acc["Wv"] += W * v
+            acc["Wg"] += W * g
+            acc["WgB"] += W * g * bpar
+            acc["Wg2"] += W * g * g
+            acc["Wq"] += W * g * g * q
+            acc["Wu"] += W * g * g * u
+            acc["Wdop"] += W * hw
+            depth = max(depth, 1.0 - I.min() / Ic)
+        vlos = acc["Wv"] / acc["W"]
+        bpar = acc["WgB"] / acc["Wg"]
+        q = acc["Wq"] / acc["Wg2"]
+        u = acc["Wu"] / acc["Wg2"]
+        bperp = np.sqrt(np.hypot(q, u))
+        azim = np.degrees(0.5 * np.arctan2(u, q)) % 180.0
+        B = np.hypot(bpar, bperp)
+        incl = np.degrees(np.arctan2(bperp, bpar))
+        Dp = min(depth / 0.75, 0.97)
+        eta0 = Dp / (1.0 - Dp)
+        dop = acc["Wdop"] / acc["W"] / np.sqrt(np.log(eta0 + 2.0))
+        S1 = 0.75 * Ic / mus[p]
+        S0 = 0.25 * Ic
+        damp = 0.5 * (lo[5] + hi[5])
+        g9 = np.array([B, incl, azim, vlos, dop, damp, eta0, S0, S1])
+        g9 = np.where(np.isfinite(g9), g9, 0.5 * (lo + hi))
+        g9 = np.minimum(np.maximum(g9, lo), hi)
+        out[p] = g9
+    return out

@@ -30,7 +30,8 @@
  *    the inverse of the decoding equation rounded to the nearest code;
  *    individual 0 keeps it exactly, individual i >= 1 adds to gene j the
  *    integer d - J, d uniform in [0, 2J] from word j of stream purpose 5
- *    (J = seed_jitter), clamped to [0, 65535].
+ *    (J = seed_jitter), clamped to [0, 65535]; a NaN first guess leaves that
+ *    parameter's gene as drawn for an unseeded individual.
  *  - Sobol initialisation and restarts (Sec. 5.6): Sobol points (Bratley &
  *    Fox's construction) with dimension 0 the base-2 van der Corput sequence
  *    and dimension d >= 1 built on the d-th primitive polynomial over GF(2)
@@ -221,25 +222,25 @@ void oracle_ga_init(uint64_t seed, uint32_t pixel, int pop, int n_seeded, int ji
 {
     for (int i = 0; i < pop; ++i) {
         uint16_t *g = genes + i * NGENE;
-        if (i < n_seeded && seed_par) {
-            for (int j = 0; j < NGENE; ++j) {
-                int v = encode(seed_par[j], lo[j], hi[j]);
-                if (i > 0) {
-                    const uint32_t w = oracle_rng_word(seed, pixel, 0u, (uint32_t)i, 5u,
-                                                       (uint32_t)j);
-                    v += (int)uniform_upto(w, 2u * (uint32_t)jitter) - jitter;
-                    v = v < 0 ? 0 : (v > 65535 ? 65535 : v);
-                }
-                g[j] = (uint16_t)v;
-            }
-            continue;
-        }
-        if (init_mode == 1) {
+        if (init_mode == 1)
             sobol_genes(seed, pixel, (uint32_t)i, g);
+        else
+            for (int j = 0; j < NGENE; ++j)
+                g[j] = (uint16_t)(oracle_rng_word(seed, pixel, 0u, (uint32_t)i, 0u, (uint32_t)j) >>
+                                  16);
+        if (!(i < n_seeded && seed_par))
             continue;
+        for (int j = 0; j < NGENE; ++j) {
+            if (isnan(seed_par[j]))
+                continue;              /* no first guess for this parameter */
+            int v = encode(seed_par[j], lo[j], hi[j]);
+            if (i > 0) {
+                const uint32_t w = oracle_rng_word(seed, pixel, 0u, (uint32_t)i, 5u, (uint32_t)j);
+                v += (int)uniform_upto(w, 2u * (uint32_t)jitter) - jitter;
+                v = v < 0 ? 0 : (v > 65535 ? 65535 : v);
+            }
+            g[j] = (uint16_t)v;
         }
-        for (int j = 0; j < NGENE; ++j)
-            g[j] = (uint16_t)(oracle_rng_word(seed, pixel, 0u, (uint32_t)i, 0u, (uint32_t)j) >> 16);
     }
 }
 

@@ -135,6 +135,7 @@ _SIGS = {
                        _vp, C.c_size_t, _vp], C.c_int),
     "me_refine_f64": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _i32, _vp, _vp, _vp, _vp, _vp],
                       C.c_int),
+    "me_first_guess": ([_vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _vp], C.c_int),
     "mlp_param_count": ([], C.c_int64),
     "mlp_workspace_bytes": ([_i64], C.c_size_t),
     "mlp_init": ([_vp, C.c_uint64, _vp], C.c_int),
@@ -409,6 +410,21 @@ def ga_invert(obs, sigma, lines, grids, bnds: MeBounds, cfg: GAConfig, mu=None,
              _ptr(res["params"]), _ptr(res["chi2"]), _ptr(res.get("status")),
              _ptr(res.get("genes")), _ptr(res.get("fitness")), None, 0, _stream(obs)))
     return res
+
+
+def me_first_guess(obs, lines, grids, bnds: MeBounds, mu=None):
+    """Heuristic first guesses [npix, 9] (float32) from float64 observations
+    [npix, 4, L] (weak-field, centre-of-gravity and profile-shape estimates,
+    Sec. 5.5), for GAConfig.seed_params."""
+    npix = obs.shape[0]
+    L = total_samples(grids)
+    _dev(obs, torch.float64, "obs", (npix, 4, L))
+    _dev(mu, torch.float64, "mu", (npix,))
+    out = torch.empty((npix, NPAR), dtype=torch.float32, device=obs.device)
+    la, ga, nl = _lines(lines, grids)
+    _check(lib().me_first_guess(_ptr(obs), _ptr(mu), npix, la, ga, nl, C.byref(bnds), _ptr(out),
+                                _stream(obs)))
+    return out
 
 
 def me_refine_f64(obs, sigma, lines, grids, bnds: MeBounds, params_in, iterations=50, mu=None,

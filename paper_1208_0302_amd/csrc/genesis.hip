@@ -558,6 +558,137 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN> a)
 }
 
 
+// ---- heuristic first guesses (Sec. 5.5 seeds) ---------------------------
+//
+// One workgroup of 256 per pixel, FP64.  Per line (x the offset of a sample
+// from the rest wavelength, I_c the largest I of the pixel, d = I_c - I,
+// d+- = I_c - (I +- V), I'' the central second difference, 0 at the ends,
+// C = 4.6686e-13 lambda0^2, gbar the first moment of the red sigma group):
+// v = c (sum x d / sum d) / lambda0; B_par from the centres of gravity of d+
+// and d-, (x+ - x-) / (2 C gbar); weak-field (q, u) = -4 (sum Q I'', sum U I'')
+// / (C^2 gbar^2 sum I''^2); half-depth width hw = step #{d >= max d / 2} / 2;
+// core depth 1 - min I / I_c.  Lines are combined with weights W = step sum d
+// (times gbar for B_par, gbar^2 for q, u); B_perp = sqrt(hypot(q, u)),
+// azimuth = atan2(u, q) / 2, B = hypot(B_par, B_perp), inclination =
+// atan2(B_perp, B_par); mu S1 = 3/4 I_c, S0 = I_c / 4, eta0 = D'/(1 - D') for
+// D' = min(D / 0.75, 0.97), Doppler width hw / sqrt(ln(eta0 + 2)), damping
+// the middle of its range; a non-finite estimate becomes the middle of its
+// range; all clamped into the box.
+constexpr int kGuessThreads = 256;
+constexpr int kGuessSums = 10;  // per line: s0 s1 sp0 sp1 sm0 sm1 sQ sU s2 cnt
+
+struct GuessArgs {
+    const double *obs, *mu;
+    int64_t npix;
+    DevLines<double> ls;
+    double gbar[GENESIS_MAX_LINES];
+    double lo[GENESIS_NPAR], hi[GENESIS_NPAR];
+    float *params;
+};
+
+__device__ double guess_reduce(double v, bool take_max, double *red)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double o = __shfl_xor(v, off);
+        v = take_max ? fmax(v, o) : v + o;
+    }
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        red[w] = v;
+    __syncthreads();
+    double t = red[0];
+    for (int k = 1; k < kGuessThreads / 64; ++k)
+        t = take_max ? fmax(t, red[k]) : t + red[k];
+    return t;
+}
+
+__global__ __launch_bounds__(kGuessThreads) void k_first_guess(GuessArgs a)
+{
+    __shared__ double red[kGuessThreads / 64];
+    const int L = a.ls.L;
+    for (int64_t p = blockIdx.x; p < a.npix; p += gridDim.x) {
+        const double *I = a.obs + p * 4 * (int64_t)L, *Q = I + L, *U = I + 2 * L, *V = I + 3 * L;
+        double m = -INFINITY;
+        for (int j = threadIdx.x; j < L; j += kGuessThreads)
+            m = fmax(m, I[j]);
+        const double Ic = guess_reduce(m, true, red);
+        double W = 0, Wv = 0, Wg = 0, WgB = 0, Wg2 = 0, Wq = 0, Wu = 0, Whw = 0, depth = 0;
+        for (int l = 0; l < a.ls.nlines; ++l) {
+            const DevLine<double> &ln = a.ls.l[l];
+            const double *Il = I + ln.off;
+            double mx = -INFINITY;
+            for (int j = threadIdx.x; j < ln.nlam; j += kGuessThreads)
+                mx = fmax(mx, Ic - Il[j]);
+            const double dmax = guess_reduce(mx, true, red);
+            double acc[kGuessSums] = {};
+            for (int j = threadIdx.x; j < ln.nlam; j += kGuessThreads) {
+                const double x = ln.off0 + ln.step * j;
+                const double i0 = Il[j], v = V[ln.off + j];
+                const double d = Ic - i0, dp = Ic - (i0 + v), dm = Ic - (i0 - v);
+                const double d2 = (j > 0 && j + 1 < ln.nlam)
+                                      ? (Il[j + 1] - 2.0 * i0 + Il[j - 1]) / (ln.step * ln.step)
+                                      : 0.0;
+                acc[0] += d;
+                acc[1] += x * d;
+                acc[2] += dp;
+                acc[3] += x * dp;
+                acc[4] += dm;
+                acc[5] += x * dm;
+                acc[6] += Q[ln.off + j] * d2;
+                acc[7] += U[ln.off + j] * d2;
+                acc[8] += d2 * d2;
+                acc[9] += d >= 0.5 * dmax ? 1.0 : 0.0;
+            }
+            double tot[kGuessSums];
+#pragma unroll
+            for (int k = 0; k < kGuessSums; ++k)
+                tot[k] = guess_reduce(acc[k], false, red);
+            const double lam0 = ln.dop_kms * kCkms;
+            const double C = kZeeman * lam0 * lam0, g = a.gbar[l];
+            const double xc = tot[1] / tot[0];
+            const double bpar = (tot[3] / tot[2] - tot[5] / tot[4]) / (2.0 * C * g);
+            const double qq = -4.0 * tot[6] / (C * C * g * g * tot[8]);
+            const double uu = -4.0 * tot[7] / (C * C * g * g * tot[8]);
+            const double hw = 0.5 * ln.step * tot[9];
+            const double Wl = ln.step * tot[0];
+            W += Wl;
+            Wv += Wl * kCkms * xc / lam0;
+            Wg += Wl * g;
+            WgB += Wl * g * bpar;
+            Wg2 += Wl * g * g;
+            Wq += Wl * g * g * qq;
+            Wu += Wl * g * g * uu;
+            Whw += Wl * hw;
+            depth = fmax(depth, dmax / Ic);
+        }
+        if (threadIdx.x == 0) {
+            const double bpar = WgB / Wg, q = Wq / Wg2, u = Wu / Wg2;
+            const double bperp = sqrt(hypot(q, u));
+            double azim = 0.5 * atan2(u, q) * (180.0 / kPi);
+            azim = fmod(azim + 180.0, 180.0);
+            const double Dp = fmin(depth / 0.75, 0.97);
+            const double eta0 = Dp / (1.0 - Dp);
+            const double mu = a.mu ? a.mu[p] : 1.0;
+            const double g9[GENESIS_NPAR] = {hypot(bpar, bperp),
+                                             atan2(bperp, bpar) * (180.0 / kPi),
+                                             azim,
+                                             Wv / W,
+                                             Whw / W / sqrt(log(eta0 + 2.0)),
+                                             0.5 * (a.lo[5] + a.hi[5]),
+                                             eta0,
+                                             0.25 * Ic,
+                                             0.75 * Ic / mu};
+            for (int j = 0; j < GENESIS_NPAR; ++j) {
+                const double v = isfinite(g9[j]) ? g9[j] : 0.5 * (a.lo[j] + a.hi[j]);
+                a.params[p * GENESIS_NPAR + j] = (float)fmin(fmax(v, a.lo[j]), a.hi[j]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ---- FP64 Levenberg-Marquardt refinement --------------------------------
 //
 // One workgroup of kRefineThreads per pixel; thread t takes samples t,
@@ -1368,6 +1499,47 @@ int ga_invert_f64(const double *obs, const double *sigma, const double *mu, int6
     return invert_dispatch<double>(obs, sigma, mu, npix, lines, grids, nlines, bounds, cfg,
                                best_params, best_chi2, status, final_genes, final_fitness,
                                stream);
+}
+
+int me_first_guess(const double *obs, const double *mu, int64_t npix, const me_line *lines,
+                   const me_grid *grids, int32_t nlines, const me_bounds *bounds, float *params,
+                   void *stream)
+{
+    GuessArgs a{};
+    if (int rc = pack_lines(lines, grids, nlines, a.ls))
+        return rc;
+    Bounds b;
+    if (int rc = pack_bounds(bounds, b))
+        return rc;
+    for (int l = 0; l < nlines; ++l) {
+        double g = 0.0;
+        for (int c = 0; c < lines[l].ncomp; ++c)
+            if (lines[l].q[c] == 1)
+                g += (double)lines[l].strength[c] * (double)lines[l].shift[c];
+        if (!(g > 0.0))
+            return fail(ME_EINVAL, "line %d has no Zeeman splitting (first moment of the red "
+                                   "sigma group %g)", l, g);
+        a.gbar[l] = g;
+        if (grids[l].n < 3)
+            return fail(ME_EINVAL, "line %d: need at least 3 samples", l);
+    }
+    for (int j = 0; j < GENESIS_NPAR; ++j) {
+        a.lo[j] = bounds->lo[j];
+        a.hi[j] = bounds->hi[j];
+    }
+    if (npix < 0)
+        return fail(ME_EINVAL, "npix must be >= 0");
+    if (npix == 0)
+        return ME_OK;
+    if (!obs || !params)
+        return fail(ME_EINVAL, "NULL array argument");
+    a.obs = obs;
+    a.mu = mu;
+    a.npix = npix;
+    a.params = params;
+    hipLaunchKernelGGL(k_first_guess, dim3(grid_for(npix)), dim3(kGuessThreads), 0,
+                       as_stream(stream), a);
+    return check_launch("me_first_guess");
 }
 
 int me_refine_f64(const double *obs, const double *sigma, const double *mu, int64_t npix,

@@ -626,52 +626,51 @@ __device__ __forceinline__ void sobol_genes(uint32_t pix, uint32_t n, const Key 
 }
 
 // The nine genes of individual i of pixel p (call-local index) in generation
-// 0: random (stream purpose 0) or Sobol point i (init_mode 1), or, for
-// i < n_seeded, the encoded first guess (exact for i = 0, integer-jittered
-// for i >= 1, stream purpose 5).
+// 0: random (stream purpose 0) or Sobol point i (init_mode 1); for
+// i < n_seeded, every parameter whose first guess is not NaN instead takes
+// the encoded guess (exact for i = 0, integer-jittered for i >= 1, stream
+// purpose 5).
 __device__ __forceinline__ void initial_genes(uint32_t pix, int64_t p, int i, const GaConst &ga,
                                               const Bounds &b, uint32_t (&g)[GENESIS_NPAR])
 {
-    if (i < ga.n_seeded && ga.seed_params) {
-#pragma unroll
-        for (int j = 0; j < GENESIS_NPAR; ++j) {
-            double u = ((double)ga.seed_params[p * GENESIS_NPAR + j] - b.lo[j]) /
-                       (b.span[j] > 0.0 ? b.span[j] : 1.0);
-            u = u < 0.0 ? 0.0 : (u > 1.0 ? 1.0 : u);
-            g[j] = (uint32_t)floor(u * 65535.0 + 0.5);
-        }
-        if (i > 0) {
-#pragma unroll
-            for (int blk = 0; blk < 3; ++blk) {
-                const uint4 w = philox(pix, 0u, (uint32_t)i, (kSeedJitter << 24) | (uint32_t)blk,
-                                       ga.key);
-                const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int j = 4 * blk + q;
-                    if (j < GENESIS_NPAR) {
-                        const int d = (int)uniform_upto(ws[q], 2u * (uint32_t)ga.seed_jitter) -
-                                      ga.seed_jitter;
-                        const int v = (int)g[j] + d;
-                        g[j] = (uint32_t)(v < 0 ? 0 : (v > 65535 ? 65535 : v));
-                    }
-                }
-            }
-        }
-        return;
-    }
+    // the unseeded genes of individual i first
     if (ga.init_mode == 1) {
         sobol_genes(pix, (uint32_t)i, ga.key, g);
-        return;
+    } else {
+#pragma unroll
+        for (int blk = 0; blk < 3; ++blk) {
+            const uint4 w = philox(pix, 0u, (uint32_t)i, (kInit << 24) | (uint32_t)blk, ga.key);
+            const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (4 * blk + q < GENESIS_NPAR)
+                    g[4 * blk + q] = ws[q] >> 16;
+        }
     }
+    if (!(i < ga.n_seeded && ga.seed_params))
+        return;
+    // seeded slot: every parameter with a finite first guess takes its code
 #pragma unroll
     for (int blk = 0; blk < 3; ++blk) {
-        const uint4 w = philox(pix, 0u, (uint32_t)i, (kInit << 24) | (uint32_t)blk, ga.key);
+        const uint4 w = philox(pix, 0u, (uint32_t)i, (kSeedJitter << 24) | (uint32_t)blk, ga.key);
         const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (4 * blk + q < GENESIS_NPAR)
-                g[4 * blk + q] = ws[q] >> 16;
+        for (int q = 0; q < 4; ++q) {
+            const int j = 4 * blk + q;
+            if (j >= GENESIS_NPAR)
+                continue;
+            const float sp = ga.seed_params[p * GENESIS_NPAR + j];
+            if (isnan(sp))
+                continue;
+            double u = ((double)sp - b.lo[j]) / (b.span[j] > 0.0 ? b.span[j] : 1.0);
+            u = u < 0.0 ? 0.0 : (u > 1.0 ? 1.0 : u);
+            int v = (int)floor(u * 65535.0 + 0.5);
+            if (i > 0) {
+                v += (int)uniform_upto(ws[q], 2u * (uint32_t)ga.seed_jitter) - ga.seed_jitter;
+                v = v < 0 ? 0 : (v > 65535 ? 65535 : v);
+            }
+            g[j] = (uint32_t)v;
+        }
     }
 }
 

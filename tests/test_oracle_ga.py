@@ -277,3 +277,19 @@ def test_seeded_inversion_starts_at_the_guess():
                          lines)[:, 0]
     assert np.all(r1["chi2"] <= direct * (1 + 1e-12))
     assert nu > 0
+
+
+def test_seeded_init_nan_leaves_a_parameter_unseeded():
+    lo, hi = si.PRIOR_LO, si.PRIOR_HI
+    guess = si.draw_uniform_box(1, 6)[0]
+    guess[[4, 5, 6]] = np.nan
+    for mode in (0, 1):
+        g = oracle.ga_init(2, 9, 32, n_seeded=10, jitter=20, seed_params=guess, lo=lo, hi=hi,
+                           init_mode=mode)
+        plain = oracle.ga_init(2, 9, 32, init_mode=mode)
+        assert np.array_equal(g[:, [4, 5, 6]], plain[:, [4, 5, 6]])
+        assert np.array_equal(g[10:], plain[10:])
+        full = oracle.ga_init(2, 9, 32, n_seeded=10, jitter=20,
+                              seed_params=np.nan_to_num(guess), lo=lo, hi=hi, init_mode=mode)
+        keep = [0, 1, 2, 3, 7, 8]
+        assert np.array_equal(g[:, keep], full[:, keep])
