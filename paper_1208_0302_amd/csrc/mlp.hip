@@ -11,6 +11,7 @@
 // (VALU FMA tiles) exists for gradient checks.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -76,6 +77,13 @@ struct GemmArgs {
     const float *pre_in;  // [M][N]       (backward: pre-activation)
     float *outf;        // [M][N] f32 result (pre-activation / output / gradient)
     void *outt;         // [M][N] T result (activation or gradient operand)
+    // split-K weight gradients (bf16 path): block z covers k in [z kper, (z + 1) kper)
+    // and writes its partial product to outf + z M N; block (x, y, z) also sums
+    // bsrc[k][m] (f32 [K][M]) over the x-th of gridDim.x equal slices of that k
+    // range into bpart[z gridDim.x + x][m] (the bias-gradient partials)
+    int kper;
+    const float *bsrc;
+    float *bpart;
 };
 
 // Epilogue of one accumulated element (m, n).
@@ -102,16 +110,47 @@ __device__ __forceinline__ void epilogue(const GemmArgs &a, int m, int n, float 
 
 // One 64 x 64 bf16 tile of a matrix operand, element (r, c) = global
 // (row0 + r, k0 + c), moved global -> registers -> LDS T[r][c] (k contiguous
-// in LDS).  The matrix is stored either with k contiguous ([rows][ld],
-// KC = true) or with rows contiguous ([K][ld], KC = false).  Each of the 256
-// threads owns two chunks of 8 elements that are contiguous in memory: one
-// 16-byte load where the chunk is aligned and inside the matrix, element
-// loads with zero fill elsewhere.
+// in LDS), in chunks of 8 elements contiguous in memory.  EDGE = false: the
+// chunks are 16-byte aligned and each lies wholly inside or wholly outside the
+// matrix (leading dimension, base and the chunked extent multiples of 8), so a
+// chunk is one unconditional 16-byte load (from the base when outside, then
+// zeroed): no branches, which lets loads of later k-steps stay in flight.
+// EDGE = true: element loads with zero fill where a chunk is not whole.
 constexpr int kTile = 64, kTileK = 64, kLdsPitch = kTileK + 8;
 
-template <bool KC>
-struct TileLoader {
+// EDGE = false returns the raw load; the caller zeroes it (keep) when it is
+// consumed, so that the load is not waited for here.
+template <bool EDGE>
+__device__ __forceinline__ bf16x8 load8(const uint16_t *__restrict__ X, int64_t base, bool whole,
+                                        int nvalid)
+{
+    if (!EDGE)
+        return *(const bf16x8 *)(X + (whole ? base : 0));
+    if (whole && ((uintptr_t)(X + base) & 15) == 0)
+        return *(const bf16x8 *)(X + base);
+    bf16x8 v;
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        v[e] = e < nvalid ? (short)X[base + e] : (short)0;
+    return v;
+}
+
+template <bool KC, bool EDGE>
+struct TileLoader;
+
+__device__ __forceinline__ bf16x8 keep(bf16x8 v, bool whole)
+{
+    const bf16x8 z = {0};
+    return whole ? v : z;
+}
+
+// Stored with k contiguous ([rows][ld]): each of the 256 threads owns two
+// chunks of 8 consecutive k of one row, written to LDS as 16 bytes (8 lanes
+// fill one 128-byte LDS row segment: conflict-free).
+template <bool EDGE>
+struct TileLoader<true, EDGE> {
     bf16x8 v[2];
+    bool whole[2];
 
     __device__ __forceinline__ void load(const uint16_t *__restrict__ X, int ld, int rows, int K,
                                          int row0, int k0, int tid)
@@ -119,23 +158,10 @@ struct TileLoader {
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int q = tid + 256 * j;
-            // KC: chunk = 8 consecutive k of one row; else 8 consecutive rows of one k
-            const int r = KC ? q >> 3 : (q & 7) * 8;
-            const int c = KC ? (q & 7) * 8 : q >> 3;
-            const int gr = row0 + r, gc = k0 + c;
-            const int64_t base = KC ? (int64_t)gr * ld + gc : (int64_t)gc * ld + gr;
-            const bool inside = KC ? (gr < rows && gc + 8 <= K) : (gc < K && gr + 8 <= rows);
-            if (inside && (ld & 7) == 0 && ((uintptr_t)(X + base) & 15) == 0) {
-                v[j] = *(const bf16x8 *)(X + base);
-            } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int er = KC ? gr : gr + e, ec = KC ? gc + e : gc;
-                    v[j][e] = (er < rows && ec < K) ? (short)X[KC ? (int64_t)er * ld + ec
-                                                                  : (int64_t)ec * ld + er]
-                                                    : (short)0;
-                }
-            }
+            const int gr = row0 + (q >> 3), gc = k0 + (q & 7) * 8;
+            const bool in_row = gr < rows;
+            whole[j] = in_row && gc + 8 <= K && (EDGE ? (ld & 7) == 0 : true);
+            v[j] = load8<EDGE>(X, (int64_t)gr * ld + gc, whole[j], in_row ? min(8, K - gc) : 0);
         }
     }
 
@@ -144,58 +170,178 @@ struct TileLoader {
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int q = tid + 256 * j;
-            if (KC) {
-                *(bf16x8 *)&T[q >> 3][(q & 7) * 8] = v[j];
-            } else {
-#pragma unroll
-                for (int e = 0; e < 8; ++e)
-                    T[(q & 7) * 8 + e][q >> 3] = (uint16_t)v[j][e];
-            }
+            *(bf16x8 *)&T[q >> 3][(q & 7) * 8] = EDGE ? v[j] : keep(v[j], whole[j]);
         }
     }
 };
 
+// Stored with rows contiguous ([K][ld]): thread t loads rows 8 (t / 32) ..
+// + 7 of the two k-columns 2 (t % 32) and 2 (t % 32) + 1 (two 16-byte loads),
+// pairs the two k of each row into one dword and writes 8 dwords; the 32
+// lanes of a half-wave write 128 consecutive bytes of one LDS row, so the
+// transposing store is conflict-free.
+template <bool EDGE>
+struct TileLoader<false, EDGE> {
+    bf16x8 v[2];
+    bool whole[2];
+
+    __device__ __forceinline__ void load(const uint16_t *__restrict__ X, int ld, int rows, int K,
+                                         int row0, int k0, int tid)
+    {
+        const int gr = row0 + 8 * (tid >> 5);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int gc = k0 + 2 * (tid & 31) + j;
+            const bool in_k = gc < K;
+            whole[j] = in_k && gr + 8 <= rows && (EDGE ? (ld & 7) == 0 : true);
+            v[j] = load8<EDGE>(X, (int64_t)gc * ld + gr, whole[j], in_k ? min(8, rows - gr) : 0);
+        }
+    }
+
+    __device__ __forceinline__ void store(uint16_t (*T)[kLdsPitch], int tid) const
+    {
+        const int r = 8 * (tid >> 5), c = 2 * (tid & 31);
+        const bf16x8 v0 = EDGE ? v[0] : keep(v[0], whole[0]);
+        const bf16x8 v1 = EDGE ? v[1] : keep(v[1], whole[1]);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const uint32_t w = (uint32_t)(uint16_t)v0[e] | ((uint32_t)(uint16_t)v1[e] << 16);
+            *(uint32_t *)&T[r + e][c] = w;
+        }
+    }
+};
+
+// One k-step of a tile product: registers -> LDS buffer, one barrier, the
+// loads of the step two ahead into the same registers, then the four MFMAs of
+// each wave.  The two LDS buffers alternate with the two register stages, so
+// the store of the next step never overwrites a buffer still being read and
+// one barrier per step suffices.
+template <bool TA, bool TB, bool EDGE>
+__device__ __forceinline__ void gemm_step(TileLoader<!TA, EDGE> &la, TileLoader<TB, EDGE> &lb,
+                                          uint16_t (*As)[kLdsPitch], uint16_t (*Bs)[kLdsPitch],
+                                          const GemmArgs &a, int ke, int m0, int n0, int knext,
+                                          int tid, int lane, int wm, int wn, f32x16 &acc)
+{
+    la.store(As, tid);
+    lb.store(Bs, tid);
+    __syncthreads();
+    // whole-chunk loaders load unconditionally (past ke every chunk reads the
+    // operand base and is zeroed), so the number of loads in flight is the
+    // same on every path and each store waits only for its own step's loads
+    if (!EDGE || knext < ke) {
+        la.load((const uint16_t *)a.A, a.lda, a.M, ke, m0, knext, tid);
+        lb.load((const uint16_t *)a.B, a.ldb, a.N, ke, n0, knext, tid);
+    }
+#pragma unroll
+    for (int kk = 0; kk < kTileK; kk += 16) {
+        const int kr = kk + 8 * (lane >> 5);
+        const bf16x8 av = *(const bf16x8 *)&As[wm + (lane & 31)][kr];
+        const bf16x8 bv = *(const bf16x8 *)&Bs[wn + (lane & 31)][kr];
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+    }
+}
+
 // C[M][N] = op(A)[M][K] op(B)[K][N].  TA: A stored [K][M]; TB: B stored [N][K].
 // Block 256 threads (4 waves in 2 x 2, each a 32 x 32 MFMA tile), 64 x 64
-// output tile, k step 64 staged through LDS with the next step's operands
-// loaded into registers while the current step's 4 MFMAs run.
-template <bool TA, bool TB, int EPI>
+// output tile, k step 64 staged through two LDS buffers, with the operands of
+// the next two steps in flight in registers.
+template <bool TA, bool TB, int EPI, bool EDGE>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs a)
 {
-    __shared__ __align__(16) uint16_t As[kTile][kLdsPitch];
-    __shared__ __align__(16) uint16_t Bs[kTile][kLdsPitch];
+    __shared__ __align__(16) uint16_t As[2][kTile][kLdsPitch];
+    __shared__ __align__(16) uint16_t Bs[2][kTile][kLdsPitch];
     const uint16_t *A = (const uint16_t *)a.A, *B = (const uint16_t *)a.B;
     const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    TileLoader<!TA> la;
-    TileLoader<TB> lb;
-    la.load(A, a.lda, a.M, a.K, m0, 0, tid);
-    lb.load(B, a.ldb, a.N, a.K, n0, 0, tid);
+    const bool split = EPI == kGradW;
+    const int kb = split ? blockIdx.z * a.kper : 0;
+    const int ke = split ? min(a.K, kb + a.kper) : a.K;
+    TileLoader<!TA, EDGE> la0, la1;
+    TileLoader<TB, EDGE> lb0, lb1;
+    la0.load(A, a.lda, a.M, ke, m0, kb, tid);
+    lb0.load(B, a.ldb, a.N, ke, n0, kb, tid);
+    la1.load(A, a.lda, a.M, ke, m0, kb + kTileK, tid);
+    lb1.load(B, a.ldb, a.N, ke, n0, kb + kTileK, tid);
     f32x16 acc = {0};
-    for (int k0 = 0; k0 < a.K; k0 += kTileK) {
-        la.store(As, tid);
-        lb.store(Bs, tid);
-        __syncthreads();
-        if (k0 + kTileK < a.K) {
-            la.load(A, a.lda, a.M, a.K, m0, k0 + kTileK, tid);
-            lb.load(B, a.ldb, a.N, a.K, n0, k0 + kTileK, tid);
-        }
-#pragma unroll
-        for (int kk = 0; kk < kTileK; kk += 16) {
-            const int kr = kk + 8 * (lane >> 5);
-            const bf16x8 av = *(const bf16x8 *)&As[wm + (lane & 31)][kr];
-            const bf16x8 bv = *(const bf16x8 *)&Bs[wn + (lane & 31)][kr];
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
-        }
-        __syncthreads();
+    const int nsteps = ke > kb ? (ke - kb + kTileK - 1) / kTileK : 0;
+    int st = 0;
+    for (; st + 2 <= nsteps; st += 2) {
+        const int k0 = kb + st * kTileK;
+        gemm_step<TA, TB, EDGE>(la0, lb0, As[0], Bs[0], a, ke, m0, n0, k0 + 2 * kTileK, tid, lane,
+                                wm, wn, acc);
+        gemm_step<TA, TB, EDGE>(la1, lb1, As[1], Bs[1], a, ke, m0, n0, k0 + 3 * kTileK, tid, lane,
+                                wm, wn, acc);
     }
+    if (st < nsteps)
+        gemm_step<TA, TB, EDGE>(la0, lb0, As[0], Bs[0], a, ke, m0, n0, ke, tid, lane, wm, wn, acc);
     // D layout: column n = lane % 32, row m = 8 (r / 4) + 4 (lane / 32) + r % 4
+    GemmArgs e = a;
+    if (split)
+        e.outf = a.outf + (int64_t)blockIdx.z * a.M * a.N;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int m = m0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         const int n = n0 + wn + (lane & 31);
-        epilogue<uint16_t, EPI>(a, m, n, acc[r]);
+        epilogue<uint16_t, EPI>(e, m, n, acc[r]);
+    }
+    if (split) {
+        // bias-gradient partial of rows m0 .. m0 + 63 over this block's slice
+        // of the k range: thread (c, r) sums k = k1 + r, k1 + r + 4, ... in
+        // order, then the four phases are added in order
+        const int sub = (ke - kb + gridDim.x - 1) / gridDim.x;
+        const int k1 = kb + blockIdx.x * sub, k2 = min(ke, k1 + sub);
+        __syncthreads();  // the last step's MFMA operands may still be read
+        float(*part)[64] = (float(*)[64])&As[0][0][0];
+        const int c = tid & 63, ph = tid >> 6, m = m0 + c;
+        float s = 0.0f;
+        if (m < a.M) {
+#pragma unroll 4
+            for (int k = k1 + ph; k < k2; k += 4)
+                s += a.bsrc[(int64_t)k * a.M + m];
+        }
+        part[ph][c] = s;
+        __syncthreads();
+        if (ph == 0 && m < a.M)
+            a.bpart[((int64_t)blockIdx.z * gridDim.x + blockIdx.x) * a.M + m] =
+                ((part[0][c] + part[1][c]) + part[2][c]) + part[3][c];
+    }
+}
+
+// Sum of the split-K partials in block order: out[i] = sum_z part[z][i] for the
+// weight gradient (n elements) and bout[m] = sum_q bpart[q][m] over the P bias
+// partials (nb elements).
+__global__ __launch_bounds__(256) void k_split_sum(const float *__restrict__ part, int S, int64_t n,
+                                                   float *__restrict__ out,
+                                                   const float *__restrict__ bpart, int P, int nb,
+                                                   float *__restrict__ bout)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if ((n & 3) == 0 && 4 * i + 3 < n) {
+        float4 s = ((const float4 *)part)[i];
+        for (int z = 1; z < S; ++z) {
+            const float4 t = ((const float4 *)(part + z * n))[i];
+            s.x += t.x;
+            s.y += t.y;
+            s.z += t.z;
+            s.w += t.w;
+        }
+        ((float4 *)out)[i] = s;
+    } else if ((n & 3) != 0) {
+        for (int64_t j = 4 * i; j < min(4 * i + 4, n); ++j) {
+            float s = part[j];
+            for (int z = 1; z < S; ++z)
+                s += part[z * n + j];
+            out[j] = s;
+        }
+    }
+    if (i < nb) {
+        // in order; the unrolled loads are all in flight before the adds
+        float s = bpart[i];
+#pragma unroll 16
+        for (int q = 1; q < P; ++q)
+            s += bpart[q * nb + i];
+        bout[i] = s;
     }
 }
 
@@ -438,7 +584,19 @@ struct Ws {
     float *dh_f;               // [B][512]
     void *dh_t[2];             // [B][512] (T)
     float *per_sample;         // [B]
+    float *split;              // split-K weight-gradient partials [kSplitMax][512 * 1024]
+    float *bsplit;             // bias-gradient partials [kSplitMax * 16][512]
 };
+
+// Split-K factor of a weight-gradient product with `tiles` output tiles and
+// K = batch: enough splits for about 512 workgroups, at least 128 k per split.
+constexpr int kSplitMax = 8;
+int split_of(int tiles, int64_t K)
+{
+    int s = (512 + tiles - 1) / tiles;
+    s = (int)std::min<int64_t>(s, std::max<int64_t>(1, K / 128));
+    return std::max(1, std::min(s, kSplitMax));
+}
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -451,6 +609,7 @@ size_t ws_bytes(int64_t B)
     s += al(B * kOut * 4) * 2 + al(B * kOut * 4);
     s += al(B * kHid * 4) + 2 * al(B * kHid * 4);
     s += al(B * 4);
+    s += al((size_t)kSplitMax * kHid * kIn * 4) + al((size_t)kSplitMax * (kIn / 64) * kHid * 4);
     return s;
 }
 
@@ -477,6 +636,8 @@ Ws ws_layout(void *base, int64_t B)
     w.dh_t[0] = take(B * kHid * 4);
     w.dh_t[1] = take(B * kHid * 4);
     w.per_sample = (float *)take(B * 4);
+    w.split = (float *)take((size_t)kSplitMax * kHid * kIn * 4);
+    w.bsplit = (float *)take((size_t)kSplitMax * (kIn / 64) * kHid * 4);
     return w;
 }
 
@@ -505,12 +666,33 @@ TrainWs train_layout(void *base, int64_t B, int L)
     return t;
 }
 
+// Whether every 8-element chunk the bf16 tile loaders read is 16-byte aligned
+// and wholly inside or wholly outside its operand (the branch-free loaders).
+bool whole_chunks(const GemmArgs &a, bool TA, bool TB)
+{
+    auto al16 = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
+    // A: k-contiguous rows (chunks along K) unless TA (chunks along M)
+    const bool okA = (a.lda & 7) == 0 && ((TA ? a.M : a.K) & 7) == 0 && al16(a.A);
+    // B: k-contiguous rows when TB (chunks along K), else chunks along N
+    const bool okB = (a.ldb & 7) == 0 && ((TB ? a.K : a.N) & 7) == 0 && al16(a.B);
+    return okA && okB;
+}
+
+template <bool TA, bool TB, int EPI>
+void launch_bf16(dim3 grid, const GemmArgs &a, hipStream_t st)
+{
+    if (whole_chunks(a, TA, TB))
+        hipLaunchKernelGGL((k_gemm_bf16<TA, TB, EPI, false>), grid, dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_gemm_bf16<TA, TB, EPI, true>), grid, dim3(256), 0, st, a);
+}
+
 template <int EPI, bool TA, bool TB>
 int gemm(bool bf16, GemmArgs a, hipStream_t st)
 {
     const dim3 grid((a.N + 63) / 64, (a.M + 63) / 64);
     if (bf16)
-        hipLaunchKernelGGL((k_gemm_bf16<TA, TB, EPI>), grid, dim3(256), 0, st, a);
+        launch_bf16<TA, TB, EPI>(grid, a, st);
     else
         hipLaunchKernelGGL((k_gemm_f32<TA, TB, EPI>), grid, dim3(256), 0, st, a);
     return check_launch("mlp gemm");
@@ -572,11 +754,31 @@ int backward(bool bf16, const float *master, const Ws &w, int64_t B, float *grad
         g.K = (int)B;
         g.lda = nout;
         g.ldb = nin;
-        g.outf = grad + w_off(l);
-        if (int rc = gemm<kGradW, true, false>(bf16, g, st))
-            return rc;
-        hipLaunchKernelGGL(k_colsum, dim3(blocks(nout, 64)), dim3(1024), 0, st, dcur_f, (int)B,
-                           nout, grad + b_off(l));
+        if (bf16) {
+            // split K = batch over blockIdx.z, partials summed in block order
+            const int tiles = ((nout + 63) / 64) * ((nin + 63) / 64);
+            const int S = split_of(tiles, B);
+            g.kper = (int)((((B + S - 1) / S) + kTileK - 1) / kTileK * kTileK);
+            const int S_used = (int)((B + g.kper - 1) / g.kper);
+            g.outf = w.split;
+            g.bsrc = dcur_f;
+            g.bpart = w.bsplit;
+            const int nx = (nin + 63) / 64;  // <= kIn / 64
+            launch_bf16<true, false, kGradW>(dim3(nx, (nout + 63) / 64, S_used), g, st);
+            const int64_t n = (int64_t)nout * nin;
+            hipLaunchKernelGGL(k_split_sum, dim3(blocks(std::max<int64_t>((n + 3) / 4, nout), 256)),
+                               dim3(256), 0, st, (const float *)w.split, S_used, n,
+                               grad + w_off(l), (const float *)w.bsplit, S_used * nx, nout,
+                               grad + b_off(l));
+            if (int rc = check_launch("mlp weight gradient"))
+                return rc;
+        } else {
+            g.outf = grad + w_off(l);
+            if (int rc = gemm<kGradW, true, false>(bf16, g, st))
+                return rc;
+            hipLaunchKernelGGL(k_colsum, dim3(blocks(nout, 64)), dim3(1024), 0, st, dcur_f,
+                               (int)B, nout, grad + b_off(l));
+        }
         if (l == 0)
             break;
         GemmArgs d{};

@@ -111,7 +111,8 @@ def test_gradient_fp32_matches_oracle(batch):
     assert np.all(_layer_errors(grad.cpu().numpy().astype(np.float64), gref) <= 1e-4)
 
 
-@pytest.mark.parametrize("batch", [9, 256])
+# 1000: the weight gradients split the batch into four k ranges, the last ragged
+@pytest.mark.parametrize("batch", [9, 256, 1000])
 def test_gradient_bf16_matches_oracle(batch):
     net, p = _net(6)
     x = _x(batch, 3 * batch)
