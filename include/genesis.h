@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define GENESIS_ABI_VERSION 1
+#define GENESIS_ABI_VERSION 2
 #define GENESIS_NPAR 9
 #define GENESIS_MAX_COMP 32   /* Zeeman components per line */
 #define GENESIS_MAX_LINES 4
@@ -122,7 +122,17 @@ typedef struct {
  *               generation t with t % R == 0, 0 < t < G, the worst pop / 2
  *               individuals (NaN last, ties to the lower index) are replaced by
  *               Sobol points pop + (t/R - 1) (pop/2) + q (q = rank - (pop -
- *               pop/2)) of the pixel's shifted sequence and re-evaluated */
+ *               pop/2)) of the pixel's shifted sequence and re-evaluated
+ *  pixel_bounds [npix][2][9] device array (row 0 lo, row 1 hi, parameter
+ *               units) or NULL: each pixel's own search box (Sec. 5.3 bounds
+ *               the thermodynamic parameters per pixel from a pre-fit, Sec.
+ *               5.5 restricts the inclination to one polarity), used by
+ *               ga_init, ga_invert, ga_invert_f64 and the service for seeding,
+ *               decoding and the result in place of the `bounds` argument
+ *               (which must still be valid).  A pixel whose box is not finite
+ *               with hi >= lo (or, for GENESIS_SYNTH_FP16, has damping
+ *               outside [0, 1]) gets status 3 and NaN outputs.  ga_decode and
+ *               ga_evaluate take the common box only.  See me_search_box. */
 typedef struct {
     int32_t pop;
     int32_t generations;
@@ -138,6 +148,7 @@ typedef struct {
     int32_t init_mode;
     int32_t restart_every;
     int32_t reserved[1];
+    const float *pixel_bounds;
 } ga_config;
 
 #define GENESIS_SYNTH_NATIVE 0
@@ -146,6 +157,10 @@ typedef struct {
 /* Message of the last failure on this thread ("" if none). */
 const char *me_last_error(void);
 int genesis_abi_version(void);
+/* sizeof of the argument structs as compiled into the library, for bindings
+ * to check their own layouts against: which = 0 me_line, 1 me_grid,
+ * 2 me_bounds, 3 ga_config; 0 for any other value. */
+size_t genesis_struct_size(int32_t which);
 
 /* ---- line data (host only, no device work) ------------------------------ */
 
@@ -254,8 +269,8 @@ size_t ga_workspace_bytes(int64_t npix, const ga_config *cfg);
  * mutate, decode and evaluate; one workgroup per pixel, one individual per
  * lane, a single launch.  Outputs best_params [npix][9] (decoded best
  * genotype of the last generation), best_chi2 [npix], status [npix]
- * (0 ok, 1 non-finite observation, 2 sigma <= 0 or non-finite; outputs NaN
- * for status != 0) -- status may be NULL; final_genes [npix][pop][9] and
+ * (0 ok, 1 non-finite observation, 2 sigma <= 0 or non-finite, 3 invalid
+ * pixel box (ga_config.pixel_bounds); outputs NaN for status != 0) -- status may be NULL; final_genes [npix][pop][9] and
  * final_fitness [npix][pop] may be NULL.  workspace/ws_bytes may be NULL/0. */
 int ga_invert(const float *obs, const float *sigma, const float *mu, int64_t npix,
               const me_line *lines, const me_grid *grids, int32_t nlines,
@@ -310,6 +325,44 @@ int me_refine_f64(const double *obs, const double *sigma, const double *mu, int6
                   const me_bounds *bounds, const double *params_in, int32_t iterations,
                   double *params_out, double *chi2_out, int32_t *iters_done,
                   double *sigma_params, void *stream);
+
+/* Non-magnetic pre-fit (Sec. 5.3): before the genetic search the paper fits
+ * a non-magnetic model to the observed Stokes I by Levenberg-Marquardt and
+ * uses the thermodynamic values only to confine the search.  This is the
+ * me_refine_f64 iteration (same coordinates, steps and stopping rule) with B
+ * held at 0, so neither field angle enters the model and Q = U = V = 0,
+ * adjusting v_los, the Doppler width, damping, eta0, S0 and S1 from
+ * params_in [npix][9] (its B is ignored; e.g. me_first_guess output).  The
+ * box must contain B = 0 (ME_EINVAL otherwise).  Outputs params_out [npix][9]
+ * (B = 0), chi2_out [npix] (the full four-Stokes merit function, whose Q, U,
+ * V terms do not depend on the fitted parameters), iters_done [npix] (may be
+ * NULL); NaN for pixels with non-finite observations or sigma <= 0. */
+int me_prefit_f64(const double *obs, const double *sigma, const double *mu, int64_t npix,
+                  const me_line *lines, const me_grid *grids, int32_t nlines,
+                  const me_bounds *bounds, const double *params_in, int32_t iterations,
+                  double *params_out, double *chi2_out, int32_t *iters_done, void *stream);
+
+/* Per-pixel search boxes box [npix][2][9] (float; row 0 lo, row 1 hi) for
+ * ga_config.pixel_bounds, starting from `bounds`:
+ *  - with prefit [npix][9] (me_prefit_f64 output; may be NULL), the ranges of
+ *    Sec. 5.3: a non-magnetic fit absorbs Zeeman broadening, so the Doppler
+ *    width is bounded above by 1.1 x its pre-fit value and the damping by
+ *    1.5 x its pre-fit value + 0.1 (hi - lo); eta0 is confined to [f/8, 8 f]
+ *    and S1 (the paper's beta0) to [f/1.5, 1.5 f] about the pre-fit value f
+ *    (all clipped to `bounds`; a non-finite or non-positive f leaves the
+ *    range as it was);
+ *  - with polarity_nsigma > 0, the polarity restriction of Sec. 5.5: with
+ *    x_j the sample offsets from each line's centre of gravity of I_c - I
+ *    (I_c the pixel's largest I), the first moment s = sum_lines sum_j x_j
+ *    V_j is negative for inclinations below 90 degrees; when |s| exceeds
+ *    polarity_nsigma x sigma_V x sqrt(sum x_j^2) the inclination range
+ *    becomes its intersection with [0, 90] (s < 0) or [90, 180] (s > 0),
+ *    unless that intersection is empty.  polarity_nsigma <= 0 skips it (obs
+ *    and sigma may then be NULL).
+ * obs [npix][4][L] and sigma [npix][4] FP64, as for me_first_guess. */
+int me_search_box(const double *obs, const double *sigma, int64_t npix, const me_line *lines,
+                  const me_grid *grids, int32_t nlines, const me_bounds *bounds,
+                  const double *prefit, double polarity_nsigma, float *box, void *stream);
 
 /* ---- learned proposal (first guesses for seeding) ---------------------- */
 

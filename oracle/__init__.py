@@ -95,13 +95,16 @@ def lib():
                                          _u16p, _i32p, _i32p, _u16p, _i32p]
             L.oracle_ga_step.restype = C.c_int
             L.oracle_ga_invert.argtypes = [_dp, _dp, _dp, C.c_int64, _linep, C.c_int, _dp, _dp,
-                                           C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                           _dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                            C.c_uint64, C.c_uint32, C.c_int, C.c_int, _dp,
                                            C.c_int, C.c_int, _dp, _dp, _i32p, _u16p, _dp]
             L.oracle_ga_invert.restype = C.c_int
             L.oracle_lm_refine.argtypes = [_dp, _dp, _dp, C.c_int64, _linep, C.c_int, _dp, _dp,
                                            _dp, C.c_int, _dp, _dp, _i32p, _dp]
             L.oracle_lm_refine.restype = C.c_int
+            L.oracle_lm_fit.argtypes = [_dp, _dp, _dp, C.c_int64, _linep, C.c_int, _dp, _dp,
+                                        _dp, C.c_int, C.c_uint32, _dp, _dp, _i32p, _dp]
+            L.oracle_lm_fit.restype = C.c_int
             L.oracle_num_threads.restype = C.c_int
             _LIB = L
     return _LIB
@@ -290,12 +293,15 @@ def ga_step(genes_in, fitness, k, p_cross, p_mut, seed, pixel, gen):
 
 def ga_invert(obs, sigma, lines, lo, hi, pop, generations, k, p_cross, p_mut, seed,
               mu=None, pixel_base=0, want_population=False, n_seeded=0, seed_jitter=0,
-              seed_params=None, init_mode=0, restart_every=0):
+              seed_params=None, init_mode=0, restart_every=0, pixel_box=None):
+    """Algorithm 1 for npix pixels; pixel_box [npix, 2, 9] (lo row, hi row)
+    gives each pixel its own search box (status 3 where it is invalid)."""
     o = _f64(obs)
     s = _f64(sigma)
     npix = o.shape[0]
     lo = _f64(lo)
     hi = _f64(hi)
+    pb = None if pixel_box is None else _f64(pixel_box).reshape(npix, 2, NPAR)
     bp = np.empty((npix, NPAR), np.float64)
     bc = np.empty(npix, np.float64)
     st = np.empty(npix, np.int32)
@@ -306,7 +312,8 @@ def ga_invert(obs, sigma, lines, lo, hi, pop, generations, k, p_cross, p_mut, se
     sp = None if n_seeded == 0 else _f64(seed_params).reshape(npix, NPAR)
     rc = lib().oracle_ga_invert(
         _ptr(o, _dp), _ptr(s, _dp), None if m is None else _ptr(m, _dp), npix, lp, len(lines),
-        _ptr(lo, _dp), _ptr(hi, _dp), int(pop), int(generations), int(k), float(p_cross),
+        _ptr(lo, _dp), _ptr(hi, _dp), None if pb is None else _ptr(pb, _dp), int(pop),
+        int(generations), int(k), float(p_cross),
         float(p_mut), int(seed), int(pixel_base), int(n_seeded), int(seed_jitter),
         None if sp is None else _ptr(sp, _dp), int(init_mode), int(restart_every), _ptr(bp, _dp), _ptr(bc, _dp), _ptr(st, _i32p),
         None if fg is None else _ptr(fg, _u16p), None if ff is None else _ptr(ff, _dp))
@@ -318,9 +325,10 @@ def ga_invert(obs, sigma, lines, lo, hi, pop, generations, k, p_cross, p_mut, se
     return res
 
 
-def lm_refine(obs, sigma, lines, lo, hi, params_in, iterations, mu=None):
+def lm_refine(obs, sigma, lines, lo, hi, params_in, iterations, mu=None, free_mask=0x1FF):
     """FP64 Levenberg-Marquardt refinement; returns dict(params, chi2, iters,
-    sigma): sigma [npix, 9] are the Sec. 6 uncertainties at the result."""
+    sigma): sigma [npix, 9] are the Sec. 6 uncertainties at the result.  Only
+    the parameters in free_mask (bit j = parameter j) are adjusted."""
     o = _f64(obs)
     s = _f64(sigma)
     npix = o.shape[0]
@@ -333,13 +341,30 @@ def lm_refine(obs, sigma, lines, lo, hi, params_in, iterations, mu=None):
     sg = np.empty((npix, NPAR), np.float64)
     arr, lp = _lines_array(lines)
     m = None if mu is None else _f64(np.broadcast_to(mu, (npix,)))
-    rc = lib().oracle_lm_refine(_ptr(o, _dp), _ptr(s, _dp), None if m is None else _ptr(m, _dp),
-                                npix, lp, len(lines), _ptr(lo, _dp), _ptr(hi, _dp),
-                                _ptr(p0, _dp), int(iterations), _ptr(po, _dp), _ptr(co, _dp),
-                                _ptr(it, _i32p), _ptr(sg, _dp))
+    rc = lib().oracle_lm_fit(_ptr(o, _dp), _ptr(s, _dp), None if m is None else _ptr(m, _dp),
+                             npix, lp, len(lines), _ptr(lo, _dp), _ptr(hi, _dp),
+                             _ptr(p0, _dp), int(iterations), int(free_mask), _ptr(po, _dp),
+                             _ptr(co, _dp), _ptr(it, _i32p), _ptr(sg, _dp))
     if rc != 0:
-        raise ValueError("oracle_lm_refine rejected its arguments")
+        raise ValueError("oracle_lm_fit rejected its arguments")
     return dict(params=po, chi2=co, iters=it, sigma=sg)
+
+
+PREFIT_FREE = 0x1F8   # v_los, Doppler width, damping, eta0, S0, S1
+
+
+def prefit(obs, sigma, lines, lo, hi, params_in, iterations, mu=None):
+    """Non-magnetic pre-fit (Sec. 5.3): the Levenberg-Marquardt fit of the
+    model with B held at 0 (so neither field angle matters and Q = U = V =
+    0), adjusting v_los, the Doppler width, damping, eta0, S0 and S1 from
+    params_in; the box must contain B = 0."""
+    lo = _f64(lo)
+    hi = _f64(hi)
+    if not lo[0] <= 0.0 <= hi[0]:
+        raise ValueError("the box must contain B = 0")
+    p0 = _f64(params_in).reshape(-1, NPAR).copy()
+    p0[:, 0] = 0.0
+    return lm_refine(obs, sigma, lines, lo, hi, p0, iterations, mu=mu, free_mask=PREFIT_FREE)
 
 
 def num_threads():

@@ -116,12 +116,15 @@ int oracle_ga_step(const uint16_t *genes_in, const double *fit, int pop, int k,
 /* Full inversion of npix pixels (Algorithm 1 run for G generations after the
  * initial evaluation).  Pixel p uses RNG pixel id pixel_base + p.
  * best_params [npix][9], best_chi2 [npix], status [npix] (0 ok, 1 non-finite
- * observation, 2 sigma <= 0 or non-finite); final_genes [npix][pop][9] and
- * final_fit [npix][pop] may be NULL.  n_seeded > 0 seeds generation 0 of
- * pixel p from seed_params [npix][9] as oracle_ga_init does.  Returns 0 or -1. */
+ * observation, 2 sigma <= 0 or non-finite, 3 invalid pixel box);
+ * final_genes [npix][pop][9] and final_fit [npix][pop] may be NULL.
+ * n_seeded > 0 seeds generation 0 of pixel p from seed_params [npix][9] as
+ * oracle_ga_init does.  pixel_box [npix][2][9] (lo row, then hi row; may be
+ * NULL) replaces [lo, hi] for each pixel: decoding, seeding and the result
+ * use the pixel's box.  Returns 0 or -1. */
 int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, int64_t npix,
                      const oracle_line *lines, int nlines, const double *lo, const double *hi,
-                     int pop, int generations, int k, double p_cross, double p_mut,
+                     const double *pixel_box, int pop, int generations, int k, double p_cross, double p_mut,
                      uint64_t seed, uint32_t pixel_base, int n_seeded, int seed_jitter,
                      const double *seed_params, int init_mode, int restart_every,
                      double *best_params, double *best_chi2, int32_t *status,
@@ -135,6 +138,14 @@ int oracle_lm_refine(const double *obs, const double *sigma, const double *mu, i
                      const oracle_line *lines, int nlines, const double *lo, const double *hi,
                      const double *params_in, int iterations, double *params_out,
                      double *chi2_out, int32_t *iters_done, double *sigma_params);
+
+/* The same fit with only the parameters in free_mask (bit j = parameter j)
+ * adjusted; the others keep their (clamped) starting values. */
+int oracle_lm_fit(const double *obs, const double *sigma, const double *mu, int64_t npix,
+                  const oracle_line *lines, int nlines, const double *lo, const double *hi,
+                  const double *params_in, int iterations, uint32_t free_mask,
+                  double *params_out, double *chi2_out, int32_t *iters_done,
+                  double *sigma_params);
 
 /* Threads the OpenMP loops would use. */
 int oracle_num_threads(void);

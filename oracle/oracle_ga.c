@@ -398,8 +398,8 @@ int oracle_ga_step(const uint16_t *genes_in, const double *fit, int pop, int k,
 /* Full inversion: Algorithm 1 with the evaluation operator F = chi-square of
  * the decoded model against the pixel's observation. */
 int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, int64_t npix,
-                     const oracle_line *lines, int nlines, const double *lo, const double *hi,
-                     int pop, int generations, int k, double p_cross, double p_mut,
+                     const oracle_line *lines, int nlines, const double *lo_all,
+                     const double *hi_all, const double *pixel_box, int pop, int generations, int k, double p_cross, double p_mut,
                      uint64_t seed, uint32_t pixel_base, int n_seeded, int seed_jitter,
                      const double *seed_params, int init_mode, int restart_every,
                      double *best_params, double *best_chi2, int32_t *status,
@@ -433,6 +433,14 @@ int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, i
             for (int i = 0; i < 4; ++i)
                 if (!(isfinite(s[i]) && s[i] > 0.0))
                     st = st ? st : 2;
+            /* the pixel's own search box when given (Sec. 5.3 and 5.5 narrow
+               it per pixel), else the common one */
+            const double *lo = pixel_box ? pixel_box + p * 2 * NGENE : lo_all;
+            const double *hi = pixel_box ? pixel_box + p * 2 * NGENE + NGENE : hi_all;
+            if (pixel_box)
+                for (int j = 0; j < NGENE; ++j)
+                    if (!(isfinite(lo[j]) && isfinite(hi[j]) && hi[j] >= lo[j]))
+                        st = st ? st : 3;
             status[p] = st;
             if (st) {
                 for (int j = 0; j < NGENE; ++j)

@@ -18,6 +18,12 @@
  *   (not above 1e12) and retry, at most 10 trials per iteration; stop when a
  *   whole iteration fails.  lambda starts at 1e-3.
  *
+ * A parameter outside free_mask (bit j = parameter j) is held: its Jacobian
+ * column is zero, so it is treated like A_jj = 0 (d_j = 0, uncertainty
+ * +infinity).  The non-magnetic pre-fit of Sec. 5.3 is this fit with B held
+ * at 0 (the model then does not depend on the two field angles) and v_los,
+ * the Doppler width, damping, eta0, S0 and S1 free.
+ *
  * Uncertainties (Sec. 6): sigma_j^2 = [H^-1]_jj chi2(p_opt) / M with H the
  * Hessian of the reduced chi-square at the refined optimum in its
  * Gauss-Newton form, H = (2/nu) J_p^T J_p (J_p the Jacobian of the weighted
@@ -66,13 +72,18 @@ static double chi2_at(const double *x, const double *lo, const double *hi, doubl
 /* J (R x 9, normalised coordinates, weighted), A = J^T J and g = J^T r at x */
 static void normal_equations(const double *x, const double *lo, const double *hi, double mu,
                              const oracle_line *lines, int nlines, const double *o,
-                             const double *s, int L, double *m0, double *m1, double *J,
-                             double *A, double *g)
+                             const double *s, int L, uint32_t free_mask, double *m0,
+                             double *m1, double *J, double *A, double *g)
 {
     const int R = 4 * L;
     const double h = 1e-7;
     model_at(x, lo, hi, mu, lines, nlines, m0);
     for (int j = 0; j < NP; ++j) {
+        if (!((free_mask >> j) & 1u)) {
+            for (int i = 0; i < R; ++i)
+                J[i * NP + j] = 0.0;
+            continue;
+        }
         double xs[NP];
         memcpy(xs, x, sizeof xs);
         const double hj = (x[j] + h <= 1.0) ? h : -h;
@@ -136,6 +147,16 @@ int oracle_lm_refine(const double *obs, const double *sigma, const double *mu, i
                      const double *params_in, int iterations, double *params_out,
                      double *chi2_out, int32_t *iters_done, double *sigma_params)
 {
+    return oracle_lm_fit(obs, sigma, mu, npix, lines, nlines, lo, hi, params_in, iterations,
+                         0x1ffu, params_out, chi2_out, iters_done, sigma_params);
+}
+
+int oracle_lm_fit(const double *obs, const double *sigma, const double *mu, int64_t npix,
+                  const oracle_line *lines, int nlines, const double *lo, const double *hi,
+                  const double *params_in, int iterations, uint32_t free_mask,
+                  double *params_out, double *chi2_out, int32_t *iters_done,
+                  double *sigma_params)
+{
     if (iterations < 0)
         return -1;
     for (int j = 0; j < NP; ++j)
@@ -179,7 +200,7 @@ int oracle_lm_refine(const double *obs, const double *sigma, const double *mu, i
             int it = 0;
             for (; it < iterations; ++it) {
                 double A[NP * NP], g[NP];
-                normal_equations(x, lo, hi, m, lines, nlines, o, s, L, m0, m1, J, A, g);
+                normal_equations(x, lo, hi, m, lines, nlines, o, s, L, free_mask, m0, m1, J, A, g);
                 int accepted = 0;
                 for (int trial = 0; trial < 10 && !accepted; ++trial) {
                     double M[NP * NP], gg[NP], d[NP];
@@ -224,7 +245,7 @@ int oracle_lm_refine(const double *obs, const double *sigma, const double *mu, i
                 iters_done[p] = it;
             if (sigma_params) {
                 double A[NP * NP], g[NP];
-                normal_equations(x, lo, hi, m, lines, nlines, o, s, L, m0, m1, J, A, g);
+                normal_equations(x, lo, hi, m, lines, nlines, o, s, L, free_mask, m0, m1, J, A, g);
                 double *sg = sigma_params + p * NP;
                 int keep[NP];
                 for (int a = 0; a < NP; ++a)

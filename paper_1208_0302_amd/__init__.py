@@ -58,7 +58,7 @@ class GaConfigC(C.Structure):
                 ("seed", C.c_uint64), ("pixel_base", C.c_uint32), ("seed_jitter", C.c_int32),
                 ("seed_params", C.c_void_p), ("synth_precision", C.c_int32),
                 ("init_mode", C.c_int32), ("restart_every", C.c_int32),
-                ("reserved", C.c_int32 * 1)]
+                ("reserved", C.c_int32 * 1), ("pixel_bounds", C.c_void_p)]
 
 
 @dataclasses.dataclass
@@ -77,8 +77,10 @@ class GAConfig:
     synth_precision: int = 0                     # SYNTH_NATIVE or SYNTH_FP16
     init_mode: int = 0                           # 0 uniform random, 1 Sobol
     restart_every: int = 0                       # 0: no restarts
+    pixel_bounds: Optional[torch.Tensor] = None  # [npix, 2, 9] float32 per-pixel boxes
 
-    def c(self) -> GaConfigC:
+    def c(self, npix: Optional[int] = None) -> GaConfigC:
+        """The C struct; with npix, the per-pixel arrays' shapes are checked."""
         cfg = GaConfigC()
         cfg.pop = self.pop
         cfg.generations = self.generations
@@ -93,8 +95,13 @@ class GAConfig:
         cfg.init_mode = self.init_mode
         cfg.restart_every = self.restart_every
         if self.seed_params is not None:
-            _dev(self.seed_params, torch.float32, "seed_params")
+            _dev(self.seed_params, torch.float32, "seed_params",
+                 None if npix is None else (npix, NPAR))
             cfg.seed_params = self.seed_params.data_ptr()
+        if self.pixel_bounds is not None:
+            _dev(self.pixel_bounds, torch.float32, "pixel_bounds",
+                 None if npix is None else (npix, 2, NPAR))
+            cfg.pixel_bounds = self.pixel_bounds.data_ptr()
         return cfg
 
 
@@ -112,6 +119,7 @@ _cp = C.POINTER(GaConfigC)
 _SIGS = {
     "me_last_error": ([], C.c_char_p),
     "genesis_abi_version": ([], C.c_int),
+    "genesis_struct_size": ([_i32], C.c_size_t),
     "me_line_from_terms": ([C.c_double] * 5 + [_lp], C.c_int),
     "me_line_triplet": ([C.c_double, C.c_double, _lp], C.c_int),
     "me_synth": ([_vp, _i64, _lp, _gp, _i32, _vp, _vp, _vp], C.c_int),
@@ -136,6 +144,10 @@ _SIGS = {
     "me_refine_f64": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _i32, _vp, _vp, _vp, _vp, _vp],
                       C.c_int),
     "me_first_guess": ([_vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _vp], C.c_int),
+    "me_prefit_f64": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _i32, _vp, _vp, _vp, _vp],
+                      C.c_int),
+    "me_search_box": ([_vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, C.c_double, _vp, _vp],
+                      C.c_int),
     "mlp_param_count": ([], C.c_int64),
     "mlp_workspace_bytes": ([_i64], C.c_size_t),
     "mlp_init": ([_vp, C.c_uint64, _vp], C.c_int),
@@ -161,6 +173,8 @@ _SIGS = {
 }
 
 EXPORTED = tuple(_SIGS)
+STRUCTS = (("me_line", MeLine), ("me_grid", MeGrid), ("me_bounds", MeBounds),
+           ("ga_config", GaConfigC))
 
 
 def lib_path() -> str:
@@ -181,6 +195,14 @@ def lib():
                 f = getattr(L, name)
                 f.argtypes = args
                 f.restype = res
+            # a struct laid out differently here than in the library would
+            # hand the device garbage pointers: refuse to run instead
+            for which, (sname, struct) in enumerate(STRUCTS):
+                if L.genesis_struct_size(which) != C.sizeof(struct):
+                    raise RuntimeError(
+                        "%s is %d bytes in libgenesis_hip.so but %d in this binding; rebuild "
+                        "the library from these sources" % (sname, L.genesis_struct_size(which),
+                                                             C.sizeof(struct)))
             _LIB = L
     return _LIB
 
@@ -310,7 +332,7 @@ def me_chi2(params, obs, sigma, lines, grids, mu=None, out=None):
 
 def ga_init(npix: int, cfg: GAConfig, bnds: Optional[MeBounds] = None, device="cuda"):
     genes = torch.empty((npix, cfg.pop, NPAR), dtype=torch.uint16, device=device)
-    c = cfg.c()
+    c = cfg.c(npix)
     _check(lib().ga_init(npix, C.byref(c), None if bnds is None else C.byref(bnds), _ptr(genes),
                          _stream(genes)))
     return genes
@@ -324,7 +346,7 @@ def ga_restart(genes, fitness, cfg: GAConfig, generation: int):
     _dev(genes, torch.uint16, "genes", (npix, cfg.pop, NPAR))
     _dev(fitness, dt, "fitness", (npix, cfg.pop))
     out = torch.empty_like(genes)
-    c = cfg.c()
+    c = cfg.c(npix)
     f = lib().ga_restart if dt == torch.float32 else lib().ga_restart_f64
     _check(f(_ptr(genes), _ptr(fitness), npix, C.byref(c), int(generation), _ptr(out),
              _stream(genes)))
@@ -373,7 +395,7 @@ def ga_step(genes_in, fitness, cfg: GAConfig, generation: int, diagnostics=True)
                    xpoint=torch.empty((npix, pop), dtype=torch.int32, device=dev),
                    masks=torch.empty_like(genes_in),
                    elite=torch.empty((npix,), dtype=torch.int32, device=dev))
-    c = cfg.c()
+    c = cfg.c(npix)
     f = lib().ga_step if dt == torch.float32 else lib().ga_step_f64
     _check(f(_ptr(genes_in), _ptr(fitness), npix, C.byref(c), int(generation), _ptr(out),
              _ptr(res.get("parents")), _ptr(res.get("xpoint")), _ptr(res.get("masks")),
@@ -382,7 +404,7 @@ def ga_step(genes_in, fitness, cfg: GAConfig, generation: int, diagnostics=True)
 
 
 def ga_workspace_bytes(npix: int, cfg: GAConfig) -> int:
-    c = cfg.c()
+    c = cfg.c(npix)
     return int(lib().ga_workspace_bytes(npix, C.byref(c)))
 
 
@@ -404,7 +426,7 @@ def ga_invert(obs, sigma, lines, grids, bnds: MeBounds, cfg: GAConfig, mu=None,
         res["genes"] = torch.empty((npix, cfg.pop, NPAR), dtype=torch.uint16, device=dev)
         res["fitness"] = torch.empty((npix, cfg.pop), dtype=dt, device=dev)
     la, ga, nl = _lines(lines, grids)
-    c = cfg.c()
+    c = cfg.c(npix)
     f = lib().ga_invert if dt == torch.float32 else lib().ga_invert_f64
     _check(f(_ptr(obs), _ptr(sigma), _ptr(mu), npix, la, ga, nl, C.byref(bnds), C.byref(c),
              _ptr(res["params"]), _ptr(res["chi2"]), _ptr(res.get("status")),
@@ -452,6 +474,45 @@ def me_refine_f64(obs, sigma, lines, grids, bnds: MeBounds, params_in, iteration
     return res
 
 
+def me_prefit_f64(obs, sigma, lines, grids, bnds: MeBounds, params_in, iterations=30, mu=None):
+    """Non-magnetic pre-fit (Sec. 5.3): Levenberg-Marquardt with B held at 0,
+    adjusting v_los, Doppler width, damping, eta0, S0 and S1 from params_in
+    [npix, 9] (float64); returns dict(params, chi2, iters)."""
+    npix = obs.shape[0]
+    L = total_samples(grids)
+    _dev(obs, torch.float64, "obs", (npix, 4, L))
+    _dev(sigma, torch.float64, "sigma", (npix, 4))
+    _dev(mu, torch.float64, "mu", (npix,))
+    _dev(params_in, torch.float64, "params_in", (npix, NPAR))
+    dev = obs.device
+    res = dict(params=torch.empty((npix, NPAR), dtype=torch.float64, device=dev),
+               chi2=torch.empty((npix,), dtype=torch.float64, device=dev),
+               iters=torch.empty((npix,), dtype=torch.int32, device=dev))
+    la, ga, nl = _lines(lines, grids)
+    _check(lib().me_prefit_f64(_ptr(obs), _ptr(sigma), _ptr(mu), npix, la, ga, nl,
+                               C.byref(bnds), _ptr(params_in), int(iterations),
+                               _ptr(res["params"]), _ptr(res["chi2"]), _ptr(res["iters"]),
+                               _stream(obs)))
+    return res
+
+
+def me_search_box(obs, sigma, lines, grids, bnds: MeBounds, prefit=None, polarity_nsigma=3.0):
+    """Per-pixel search boxes [npix, 2, 9] (float32) for GAConfig.pixel_bounds:
+    pre-fit ranges (Sec. 5.3) from prefit [npix, 9] (float64, may be None) and
+    the polarity restriction (Sec. 5.5) where Stokes V's first moment exceeds
+    polarity_nsigma noise deviations (<= 0: none)."""
+    npix = obs.shape[0]
+    L = total_samples(grids)
+    _dev(obs, torch.float64, "obs", (npix, 4, L))
+    _dev(sigma, torch.float64, "sigma", (npix, 4))
+    _dev(prefit, torch.float64, "prefit", (npix, NPAR))
+    out = torch.empty((npix, 2, NPAR), dtype=torch.float32, device=obs.device)
+    la, ga, nl = _lines(lines, grids)
+    _check(lib().me_search_box(_ptr(obs), _ptr(sigma), npix, la, ga, nl, C.byref(bnds),
+                               _ptr(prefit), float(polarity_nsigma), _ptr(out), _stream(obs)))
+    return out
+
+
 class ServingSession:
     """Continuous-batching inversion service (gs_* in the C ABI).
 
@@ -477,13 +538,14 @@ class ServingSession:
                    chi2=torch.empty((npix,), dtype=torch.float32, device=obs.device),
                    status=torch.empty((npix,), dtype=torch.int32, device=obs.device))
         la, ga, nl = _lines(lines, grids)
-        c = cfg.c()
+        c = cfg.c(npix)
         rid = C.c_uint64()
         _check(lib().gs_submit(self._h, _ptr(obs), _ptr(sigma), _ptr(mu), npix, la, ga, nl,
                                C.byref(bnds), C.byref(c), _ptr(out["params"]), _ptr(out["chi2"]),
                                _ptr(out["status"]), C.byref(rid)))
         # keep the inputs alive with the outputs until the session ends
-        self._req[rid.value] = dict(out=out, keep=(obs, sigma, mu, cfg.seed_params))
+        self._req[rid.value] = dict(out=out, keep=(obs, sigma, mu, cfg.seed_params,
+                                                    cfg.pixel_bounds))
         return rid.value
 
     def step(self):

@@ -110,6 +110,7 @@ int pack_ga(const ga_config *cfg, GaConst &ga)
     ga.n_seeded = cfg->n_seeded;
     ga.seed_jitter = cfg->seed_jitter;
     ga.seed_params = cfg->n_seeded > 0 ? cfg->seed_params : nullptr;
+    ga.pixel_bounds = cfg->pixel_bounds;
     return ME_OK;
 }
 
@@ -296,7 +297,9 @@ __global__ void k_ga_init(int64_t npix, GaConst ga, Bounds b, uint16_t *__restri
     const int64_t p = t / pop;
     const int i = (int)(t - p * pop);
     uint32_t g[GENESIS_NPAR];
-    initial_genes(ga.pixel_base + (uint32_t)p, p, i, ga, b, g);
+    Bounds box;
+    stage_box(b, ga.pixel_bounds, p, box);
+    initial_genes(ga.pixel_base + (uint32_t)p, p, i, ga, box, g);
 #pragma unroll
     for (int j = 0; j < GENESIS_NPAR; ++j)
         genes[t * GENESIS_NPAR + j] = (uint16_t)g[j];
@@ -457,8 +460,12 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN> a)
     const bool active = tid < pop;
     const Real inv_nu = (Real)(1.0 / (4.0 * L - GENESIS_NPAR));
     for (int64_t p = blockIdx.x; p < a.npix; p += gridDim.x) {
+        if (tid == 0)
+            stage_box(a.b, a.ga.pixel_bounds, p, *s.box);
         Real w2[4];
-        const int st = stage_pixel(a.obs + p * 4 * (int64_t)L, a.sigma + p * 4, L, s.obs, w2);
+        int st = stage_pixel(a.obs + p * 4 * (int64_t)L, a.sigma + p * 4, L, s.obs, w2);
+        if (st == 0 && a.ga.pixel_bounds)
+            st = box_status(*s.box, SYN == GENESIS_SYNTH_FP16);
         if (st != 0) {
             if (tid == 0) {
                 for (int j = 0; j < GENESIS_NPAR; ++j)
@@ -483,7 +490,7 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN> a)
         int cur = 0;  // offset of the current generation's gene buffer
         if (active) {
             uint32_t g0[GENESIS_NPAR];
-            initial_genes(pix, p, tid, a.ga, a.b, g0);
+            initial_genes(pix, p, tid, a.ga, *s.box, g0);
 #pragma unroll
             for (int j = 0; j < GENESIS_NPAR; ++j)
                 s.genes[j * pop + tid] = (uint16_t)g0[j];
@@ -496,10 +503,11 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN> a)
             // evaluate generation t (each lane reads only its own genes)
             if (eval) {
                 if constexpr (SYN == GENESIS_SYNTH_FP16)
-                    f = evaluate_lds_h(s.genes + cur, pop, tid, a.b, mu, a.ls, a.lh, s.obs, w2,
-                                       inv_nu);
+                    f = evaluate_lds_h(s.genes + cur, pop, tid, *s.box, mu, a.ls, a.lh, s.obs,
+                                       w2, inv_nu);
                 else
-                    f = evaluate_lds(s.genes + cur, pop, tid, a.b, mu, a.ls, s.obs, w2, inv_nu);
+                    f = evaluate_lds(s.genes + cur, pop, tid, *s.box, mu, a.ls, s.obs, w2,
+                                     inv_nu);
                 s.fit[tid] = f;
             }
             __syncthreads();
@@ -539,7 +547,7 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN> a)
             for (int j = 0; j < GENESIS_NPAR; ++j)
                 gb[j] = s.genes[cur + j * pop + e];
             double par[GENESIS_NPAR];
-            decode(gb, a.b, par);
+            decode(gb, *s.box, par);
             for (int j = 0; j < GENESIS_NPAR; ++j)
                 a.best_params[p * GENESIS_NPAR + j] = (Real)par[j];
             a.best_chi2[p] = s.fit[e];
@@ -602,6 +610,99 @@ __device__ double guess_reduce(double v, bool take_max, double *red)
     for (int k = 1; k < kGuessThreads / 64; ++k)
         t = take_max ? fmax(t, red[k]) : t + red[k];
     return t;
+}
+
+// ---- per-pixel search boxes (Sec. 5.3 pre-fit ranges, Sec. 5.5 polarity)
+
+struct BoxArgs {
+    const double *obs, *sigma, *prefit;
+    int64_t npix;
+    DevLines<double> ls;
+    double lo[GENESIS_NPAR], hi[GENESIS_NPAR];
+    double nsigma;
+    float *box;
+};
+
+__device__ __forceinline__ double clampd(double v, double lo, double hi)
+{
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// One workgroup per pixel: the first moment of V about each line's centre of
+// gravity (of I_c - I) decides the polarity; thread 0 applies the pre-fit
+// ranges and writes the box.
+__global__ __launch_bounds__(kGuessThreads) void k_search_box(BoxArgs a)
+{
+    __shared__ double red[kGuessThreads / 64];
+    const int L = a.ls.L;
+    for (int64_t p = blockIdx.x; p < a.npix; p += gridDim.x) {
+        const double *I = a.obs + p * 4 * (int64_t)L, *V = I + 3 * L;
+        double lo[GENESIS_NPAR], hi[GENESIS_NPAR];
+#pragma unroll
+        for (int j = 0; j < GENESIS_NPAR; ++j) {
+            lo[j] = a.lo[j];
+            hi[j] = a.hi[j];
+        }
+        if (a.nsigma > 0.0) {
+            double m = -INFINITY;
+            for (int j = threadIdx.x; j < L; j += kGuessThreads)
+                m = fmax(m, I[j]);
+            const double Ic = guess_reduce(m, true, red);
+            double sV = 0.0, sxx = 0.0;
+            for (int l = 0; l < a.ls.nlines; ++l) {
+                const DevLine<double> &ln = a.ls.l[l];
+                double d0 = 0.0, d1 = 0.0;
+                for (int j = threadIdx.x; j < ln.nlam; j += kGuessThreads) {
+                    const double d = Ic - I[ln.off + j];
+                    d0 += d;
+                    d1 += (ln.off0 + ln.step * j) * d;
+                }
+                const double xc = guess_reduce(d1, false, red) / guess_reduce(d0, false, red);
+                double m1 = 0.0, m2 = 0.0;
+                for (int j = threadIdx.x; j < ln.nlam; j += kGuessThreads) {
+                    const double x = ln.off0 + ln.step * j - xc;
+                    m1 += x * V[ln.off + j];
+                    m2 += x * x;
+                }
+                sV += guess_reduce(m1, false, red);
+                sxx += guess_reduce(m2, false, red);
+            }
+            const double noise = a.sigma[p * 4 + 3] * sqrt(sxx);
+            // V's first moment is negative for inclinations below 90 degrees
+            if (fabs(sV) > a.nsigma * noise) {
+                if (sV > 0.0 && a.hi[1] >= 90.0)
+                    lo[1] = fmax(a.lo[1], 90.0);
+                else if (sV < 0.0 && a.lo[1] <= 90.0)
+                    hi[1] = fmin(a.hi[1], 90.0);
+            }
+        }
+        if (threadIdx.x == 0) {
+            if (a.prefit) {
+                const double *f = a.prefit + p * GENESIS_NPAR;
+                // a non-magnetic fit absorbs Zeeman broadening into the
+                // Doppler width and the damping: upper bounds
+                if (isfinite(f[4]))
+                    hi[4] = clampd(1.1 * f[4], a.lo[4], a.hi[4]);
+                if (isfinite(f[5]))
+                    hi[5] = clampd(1.5 * f[5] + 0.1 * (a.hi[5] - a.lo[5]), a.lo[5], a.hi[5]);
+                // eta0 and S1 (beta0): multiplicative windows
+                if (isfinite(f[6]) && f[6] > 0.0) {
+                    lo[6] = clampd(f[6] / 8.0, a.lo[6], a.hi[6]);
+                    hi[6] = clampd(f[6] * 8.0, a.lo[6], a.hi[6]);
+                }
+                if (isfinite(f[8]) && f[8] > 0.0) {
+                    lo[8] = clampd(f[8] / 1.5, a.lo[8], a.hi[8]);
+                    hi[8] = clampd(f[8] * 1.5, a.lo[8], a.hi[8]);
+                }
+            }
+            float *out = a.box + p * 2 * GENESIS_NPAR;
+            for (int j = 0; j < GENESIS_NPAR; ++j) {
+                out[j] = (float)lo[j];
+                out[GENESIS_NPAR + j] = (float)hi[j];
+            }
+        }
+        __syncthreads();
+    }
 }
 
 __global__ __launch_bounds__(kGuessThreads) void k_first_guess(GuessArgs a)
@@ -715,6 +816,8 @@ struct RefineArgs {
     double *params_out, *chi2_out;
     int32_t *iters_done;
     double *sigma_out;  // [npix][9] uncertainties, or nullptr
+    uint32_t free_mask;  // bit j: parameter j is adjusted (held otherwise)
+    int32_t zero_field;  // start (and, with bit 0 clear, hold) B at 0
 };
 
 struct RefineShared {
@@ -880,7 +983,8 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
         const double sig[4] = {a.sigma[p * 4], a.sigma[p * 4 + 1], a.sigma[p * 4 + 2],
                                a.sigma[p * 4 + 3]};
         if (tid < GENESIS_NPAR) {
-            const double v = (a.params_in[p * GENESIS_NPAR + tid] - a.lo[tid]) / a.span[tid];
+            const double pin = (a.zero_field && tid == 0) ? 0.0 : a.params_in[p * GENESIS_NPAR + tid];
+            const double v = (pin - a.lo[tid]) / a.span[tid];
             sh.x[tid] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
         }
         if (tid == 0)
@@ -920,6 +1024,13 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
                         stokes_at(m, ln, jj, M0[0], M0[1], M0[2], M0[3]);
                     }
                     for (int k = 0; k < GENESIS_NPAR; ++k) {
+                        if (!((a.free_mask >> k) & 1u)) {
+                            // a held parameter: zero column, so A_kk = 0 and d_k = 0
+#pragma unroll
+                            for (int s4 = 0; s4 < 4; ++s4)
+                                Jm[k][s4] = 0.0;
+                            continue;
+                        }
                         double xk[GENESIS_NPAR];
 #pragma unroll
                         for (int j = 0; j < GENESIS_NPAR; ++j)
@@ -1188,7 +1299,8 @@ int invert_dispatch(const Real *obs, const Real *sigma, const Real *mu, int64_t 
 int refine_impl(const double *obs, const double *sigma, const double *mu, int64_t npix,
                 const me_line *lines, const me_grid *grids, int nlines, const me_bounds *bounds,
                 const double *params_in, int iterations, double *params_out, double *chi2_out,
-                int32_t *iters_done, double *sigma_params, void *stream)
+                int32_t *iters_done, double *sigma_params, void *stream,
+                uint32_t free_mask = 0x1ffu, bool zero_field = false)
 {
     RefineArgs a{};
     if (int rc = pack_lines(lines, grids, nlines, a.ls))
@@ -1225,6 +1337,8 @@ int refine_impl(const double *obs, const double *sigma, const double *mu, int64_
     a.chi2_out = chi2_out;
     a.iters_done = iters_done;
     a.sigma_out = sigma_params;
+    a.free_mask = free_mask;
+    a.zero_field = zero_field ? 1 : 0;
     hipLaunchKernelGGL(k_refine_f64, dim3(grid_for(npix)), dim3(kRefineThreads), lds,
                        as_stream(stream), a);
     return check_launch("me_refine_f64");
@@ -1265,6 +1379,17 @@ extern "C" {
 const char *me_last_error(void) { return g_err.c_str(); }
 
 int genesis_abi_version(void) { return GENESIS_ABI_VERSION; }
+
+size_t genesis_struct_size(int32_t which)
+{
+    switch (which) {
+    case 0: return sizeof(me_line);
+    case 1: return sizeof(me_grid);
+    case 2: return sizeof(me_bounds);
+    case 3: return sizeof(ga_config);
+    default: return 0;
+    }
+}
 
 int me_line_from_terms(double lambda0_A, double Jl, double gl, double Ju, double gu,
                        me_line *out)
@@ -1501,6 +1626,39 @@ int ga_invert_f64(const double *obs, const double *sigma, const double *mu, int6
                                stream);
 }
 
+int me_search_box(const double *obs, const double *sigma, int64_t npix, const me_line *lines,
+                  const me_grid *grids, int32_t nlines, const me_bounds *bounds,
+                  const double *prefit, double polarity_nsigma, float *box, void *stream)
+{
+    BoxArgs a{};
+    if (int rc = pack_lines(lines, grids, nlines, a.ls))
+        return rc;
+    Bounds b;
+    if (int rc = pack_bounds(bounds, b))
+        return rc;
+    for (int j = 0; j < GENESIS_NPAR; ++j) {
+        a.lo[j] = bounds->lo[j];
+        a.hi[j] = bounds->hi[j];
+    }
+    if (!std::isfinite(polarity_nsigma))
+        return fail(ME_EINVAL, "polarity_nsigma must be finite");
+    if (npix < 0)
+        return fail(ME_EINVAL, "npix must be >= 0");
+    if (npix == 0)
+        return ME_OK;
+    if (!box || (polarity_nsigma > 0.0 && (!obs || !sigma)))
+        return fail(ME_EINVAL, "NULL array argument");
+    a.obs = obs;
+    a.sigma = sigma;
+    a.prefit = prefit;
+    a.npix = npix;
+    a.nsigma = polarity_nsigma;
+    a.box = box;
+    hipLaunchKernelGGL(k_search_box, dim3(grid_for(npix)), dim3(kGuessThreads), 0,
+                       as_stream(stream), a);
+    return check_launch("me_search_box");
+}
+
 int me_first_guess(const double *obs, const double *mu, int64_t npix, const me_line *lines,
                    const me_grid *grids, int32_t nlines, const me_bounds *bounds, float *params,
                    void *stream)
@@ -1550,6 +1708,19 @@ int me_refine_f64(const double *obs, const double *sigma, const double *mu, int6
 {
     return refine_impl(obs, sigma, mu, npix, lines, grids, nlines, bounds, params_in, iterations,
                        params_out, chi2_out, iters_done, sigma_params, stream);
+}
+
+int me_prefit_f64(const double *obs, const double *sigma, const double *mu, int64_t npix,
+                  const me_line *lines, const me_grid *grids, int32_t nlines,
+                  const me_bounds *bounds, const double *params_in, int32_t iterations,
+                  double *params_out, double *chi2_out, int32_t *iters_done, void *stream)
+{
+    if (bounds && !(bounds->lo[0] <= 0.0 && bounds->hi[0] >= 0.0))
+        return fail(ME_EINVAL, "the non-magnetic pre-fit needs a box containing B = 0");
+    // v_los, Doppler width, damping, eta0, S0, S1 free; B held at 0 (the angles
+    // then do not enter the model)
+    return refine_impl(obs, sigma, mu, npix, lines, grids, nlines, bounds, params_in, iterations,
+                       params_out, chi2_out, iters_done, nullptr, stream, 0x1f8u, true);
 }
 
 }  // extern "C"

@@ -148,14 +148,50 @@ __device__ __forceinline__ int stage_pixel(const Real *__restrict__ obs_p,
 }
 
 // LDS of the GA kernels: observation [L] x 4, fitness [pop], argmin
-// scratch, and two gene buffers [9][pop] (parents, children).
+// scratch, two gene buffers [9][pop] (parents, children) and the pixel's
+// search box.
 template <typename Real>
 struct GaLds {
     Vec4<Real> *obs;
     Real *fit, *red_f;
     int *red_i;
     uint16_t *genes;  // two buffers [9][pop] back to back
+    Bounds *box;
 };
+
+// The search box of pixel p, written by one thread: its row of
+// pixel_bounds [npix][2][9] (lo, hi) when given, else the common box.
+__device__ __forceinline__ void stage_box(const Bounds &common, const float *pixel_bounds,
+                                          int64_t p, Bounds &box)
+{
+    if (!pixel_bounds) {
+#pragma unroll
+        for (int j = 0; j < GENESIS_NPAR; ++j) {
+            box.lo[j] = common.lo[j];
+            box.span[j] = common.span[j];
+        }
+        return;
+    }
+    const float *row = pixel_bounds + p * 2 * GENESIS_NPAR;
+#pragma unroll
+    for (int j = 0; j < GENESIS_NPAR; ++j) {
+        const double lo = (double)row[j], hi = (double)row[GENESIS_NPAR + j];
+        box.lo[j] = lo;
+        box.span[j] = hi - lo;  // exact for two floats
+    }
+}
+
+// 0, or 3 for a box that is not finite with hi >= lo or, for the FP16
+// synthesis, has damping outside [0, 1].
+__device__ __forceinline__ int box_status(const Bounds &box, bool fp16)
+{
+    for (int j = 0; j < GENESIS_NPAR; ++j)
+        if (!(isfinite(box.lo[j]) && isfinite(box.span[j]) && box.span[j] >= 0.0))
+            return 3;
+    if (fp16 && !(box.lo[5] >= 0.0 && box.lo[5] + box.span[5] <= 1.0))
+        return 3;
+    return 0;
+}
 
 __host__ __device__ inline size_t align16(size_t o) { return (o + 15) & ~(size_t)15; }
 
@@ -166,6 +202,7 @@ __host__ __device__ inline size_t ga_lds_bytes(int L, int pop)
     o = align16(o + sizeof(Real) * (size_t)pop);
     o += (sizeof(Real) + sizeof(int)) * 16;
     o = align16(o + 2 * sizeof(uint16_t) * GENESIS_NPAR * (size_t)pop);
+    o = align16(o + sizeof(Bounds));
     return o;
 }
 
@@ -183,6 +220,8 @@ __device__ __forceinline__ GaLds<Real> ga_lds(unsigned char *base, int L, int po
     s.red_i = reinterpret_cast<int *>(base + o);
     o += sizeof(int) * 16;
     s.genes = reinterpret_cast<uint16_t *>(base + o);
+    o = align16(o + 2 * sizeof(uint16_t) * GENESIS_NPAR * (size_t)pop);
+    s.box = reinterpret_cast<Bounds *>(base + o);
     return s;
 }
 

@@ -496,6 +496,7 @@ struct GaConst {
     const float *seed_params;    // [npix][9] first guesses, or nullptr
     int32_t init_mode;           // 0 Philox-uniform genes, 1 Sobol points
     int32_t restart_every;       // 0: no restarts
+    const float *pixel_bounds;   // [npix][2][9] per-pixel boxes (lo, hi), or nullptr
 };
 
 enum : uint32_t { kSobolShift = 4, kSeedJitter = 5 };

@@ -72,8 +72,12 @@ __global__ __launch_bounds__(1024) void k_ga_advance(const ReqDesc *__restrict__
     const float inv_nu = (float)(1.0 / (4.0 * L - GENESIS_NPAR));
     const bool finish = d.gen_to == d.generations;
 
+    if (tid == 0)
+        stage_box(d.b, d.ga.pixel_bounds, p, *s.box);
     float w2[4];
-    const int st = stage_pixel(d.obs + p * 4 * (int64_t)L, d.sigma + p * 4, L, s.obs, w2);
+    int st = stage_pixel(d.obs + p * 4 * (int64_t)L, d.sigma + p * 4, L, s.obs, w2);
+    if (st == 0 && d.ga.pixel_bounds)
+        st = box_status(*s.box, false);
     if (st != 0) {
         if (finish && tid == 0) {
             for (int j = 0; j < GENESIS_NPAR; ++j)
@@ -98,7 +102,7 @@ __global__ __launch_bounds__(1024) void k_ga_advance(const ReqDesc *__restrict__
     if (g < 0) {
         if (active) {
             uint32_t g0[GENESIS_NPAR];
-            initial_genes(pix, p, tid, d.ga, d.b, g0);
+            initial_genes(pix, p, tid, d.ga, *s.box, g0);
 #pragma unroll
             for (int j = 0; j < GENESIS_NPAR; ++j)
                 s.genes[j * pop + tid] = (uint16_t)g0[j];
@@ -120,7 +124,7 @@ __global__ __launch_bounds__(1024) void k_ga_advance(const ReqDesc *__restrict__
     }
     for (;;) {
         if (eval) {
-            f = evaluate_lds(s.genes + cur, pop, tid, d.b, mu, d.ls, s.obs, w2, inv_nu);
+            f = evaluate_lds(s.genes + cur, pop, tid, *s.box, mu, d.ls, s.obs, w2, inv_nu);
             s.fit[tid] = f;
         }
         __syncthreads();
@@ -161,7 +165,7 @@ __global__ __launch_bounds__(1024) void k_ga_advance(const ReqDesc *__restrict__
             for (int j = 0; j < GENESIS_NPAR; ++j)
                 gb[j] = s.genes[cur + j * pop + e];
             double par[GENESIS_NPAR];
-            decode(gb, d.b, par);
+            decode(gb, *s.box, par);
             for (int j = 0; j < GENESIS_NPAR; ++j)
                 d.best_params[p * GENESIS_NPAR + j] = (float)par[j];
             d.best_chi2[p] = s.fit[e];

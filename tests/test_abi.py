@@ -30,7 +30,17 @@ def test_library_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(L, name), name
     assert sorted(g.EXPORTED) == declared
-    assert L.genesis_abi_version() == 1
+    assert L.genesis_abi_version() == 2
+
+
+def test_binding_structs_match_the_library():
+    # the binding refuses to load when a layout differs (a stale field list
+    # would hand the device garbage pointers); check the sizes directly too
+    L = g.lib()
+    for which, (name, struct) in enumerate(g.STRUCTS):
+        assert L.genesis_struct_size(which) == C.sizeof(struct), name
+    assert L.genesis_struct_size(len(g.STRUCTS)) == 0
+    assert g.GaConfigC.pixel_bounds.offset == 64 and C.sizeof(g.GaConfigC) == 72
 
 
 def _sorted_components(q, s, st):
