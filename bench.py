@@ -223,8 +223,11 @@ def proposal(args):
     generations (and after G = 200 plus the FP64 refinement), for a random
     population, 32 of 128 individuals seeded from the network (1 exact + 31
     jittered), 32 seeded from the physics first guesses (me_first_guess: B,
-    inclination and v_los), Sobol points, and Sobol points with restarts every
-    50 generations (G/4 of the 200-generation run, Sec. 5.6)."""
+    inclination and v_los), Sobol points, Sobol points with restarts every
+    50 generations (G/4 of the 200-generation run, Sec. 5.6), and random
+    populations searched in per-pixel boxes (me_search_box): the V-lobe
+    polarity alone, with the ranges of the non-magnetic pre-fit
+    (me_prefit_f64), and those boxes with the physics seeds inside them."""
     import torch
     import paper_1208_0302_amd as g
     import synth_inputs as si
@@ -291,11 +294,40 @@ def proposal(args):
     target = args.chi2_target
     # physics first guesses (weak-field, centre-of-gravity) for B, inclination
     # and v_los, the parameters those approximations estimate; NaN elsewhere
-    phys = g.me_first_guess(obs.double().contiguous(), lines, grids, b)
+    obs64 = obs.double().contiguous()
+    sig64 = sig.double().contiguous()
+    guess9 = g.me_first_guess(obs64, lines, grids, b)
+    phys = guess9.clone()
     phys[:, [2, 4, 5, 6, 7, 8]] = float("nan")
+    # per-pixel search boxes: the V-lobe polarity alone, and with the ranges
+    # of the non-magnetic pre-fit (Sec. 5.3, 5.5)
+    eb = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    eb[0].record(stream)
+    pre = g.me_prefit_f64(obs64, sig64, lines, grids, b, guess9.double().contiguous(), 20)
+    eb[1].record(stream)
+    box_pf = g.me_search_box(obs64, sig64, lines, grids, b, prefit=pre["params"],
+                             polarity_nsigma=3.0)
+    eb[2].record(stream)
+    box_pol = g.me_search_box(obs64, sig64, lines, grids, b, polarity_nsigma=3.0)
+    torch.cuda.synchronize()
+    prefit_ms, box_ms = eb[0].elapsed_time(eb[1]), eb[1].elapsed_time(eb[2])
+    bp = box_pf.cpu().numpy()
+    inside = (truth >= bp[:, 0]) & (truth <= bp[:, 1])
+    box_stats = {"prefit_ms": prefit_ms, "search_box_ms": box_ms,
+                 "polarity_restricted_frac": float(((bp[:, 1, 1] - bp[:, 0, 1]) <= 90.0).mean()),
+                 "truth_inside_frac": {si.PARAM_NAMES[j]: float(inside[:, j].mean())
+                                       for j in (1, 4, 5, 6, 8)},
+                 "median_width_frac": {si.PARAM_NAMES[j]: float(np.median(
+                     (bp[:, 1, j] - bp[:, 0, j]) / (si.PRIOR_HI[j] - si.PRIOR_LO[j])))
+                     for j in (1, 4, 5, 6, 8)}}
+    print("proposal: search boxes %s" % box_stats, file=sys.stderr, flush=True)
     strategies = (("random", {}),
                   ("seeded", dict(n_seeded=32, seed_jitter=512, seed_params=guess)),
                   ("physics", dict(n_seeded=32, seed_jitter=512, seed_params=phys)),
+                  ("polarity_box", dict(pixel_bounds=box_pol)),
+                  ("prefit_box", dict(pixel_bounds=box_pf)),
+                  ("physics_in_box", dict(n_seeded=32, seed_jitter=512, seed_params=phys,
+                                          pixel_bounds=box_pf)),
                   ("sobol", dict(init_mode=1)),
                   ("sobol_restart", dict(init_mode=1, restart_every=50)))
     table = []
@@ -343,6 +375,7 @@ def proposal(args):
                                                np.median(err, axis=0).round(4).tolist())),
            "chi2_target": target,
            "generations_to_median_target": {n: first_reaching(n) for n, _ in strategies},
+           "search_boxes": box_stats,
            "seeding_table": table,
            "roofline": {"bound": "mfma", "achieved": pass_flop / pass_s / 1e12,
                         "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
