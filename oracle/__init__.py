@@ -22,7 +22,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = [os.path.join(_HERE, f) for f in ("oracle_me.c", "oracle_ga.c", "oracle_lm.c")]
+_SRC = [os.path.join(_HERE, f) for f in ("oracle_me.c", "oracle_ga.c", "oracle_lm.c",
+                                          "oracle_fill.c")]
 _LOCK = threading.Lock()
 _LIB = None
 
@@ -53,6 +54,32 @@ class Line(C.Structure):
         ("step", C.c_double),
         ("nlam", C.c_int32),
     ]
+
+
+MAXLINES = 8
+
+
+class FillLine(C.Structure):
+    _fields_ = [("depth", C.c_double * 4), ("width", C.c_double * 4), ("damp", C.c_double * 4)]
+
+
+class Fill(C.Structure):
+    """Fill fraction (Sec. 5.2): alpha range and, per line, the cubic-in-mu
+    coefficients of the field-free profile's depth, width [A] and damping."""
+    _fields_ = [("alpha_lo", C.c_double), ("alpha_hi", C.c_double),
+                ("line", FillLine * MAXLINES)]
+
+
+def make_fill(alpha_lo, alpha_hi, depth, width, damp) -> Fill:
+    """depth, width, damp: [nlines, 4] cubic coefficients (mu^0 .. mu^3)."""
+    f = Fill()
+    f.alpha_lo, f.alpha_hi = float(alpha_lo), float(alpha_hi)
+    for l in range(len(depth)):
+        for k in range(4):
+            f.line[l].depth[k] = float(depth[l][k])
+            f.line[l].width[k] = float(width[l][k])
+            f.line[l].damp[k] = float(damp[l][k])
+    return f
 
 
 _dp = C.POINTER(C.c_double)
@@ -95,7 +122,7 @@ def lib():
                                          _u16p, _i32p, _i32p, _u16p, _i32p]
             L.oracle_ga_step.restype = C.c_int
             L.oracle_ga_invert.argtypes = [_dp, _dp, _dp, C.c_int64, _linep, C.c_int, _dp, _dp,
-                                           _dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                           _dp, C.POINTER(Fill), _dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                            C.c_uint64, C.c_uint32, C.c_int, C.c_int, _dp,
                                            C.c_int, C.c_int, _dp, _dp, _i32p, _u16p, _dp]
             L.oracle_ga_invert.restype = C.c_int
@@ -105,6 +132,15 @@ def lib():
             L.oracle_lm_fit.argtypes = [_dp, _dp, _dp, C.c_int64, _linep, C.c_int, _dp, _dp,
                                         _dp, C.c_int, C.c_uint32, _dp, _dp, _i32p, _dp]
             L.oracle_lm_fit.restype = C.c_int
+            L.oracle_fill_profile.argtypes = [_linep, C.POINTER(FillLine), C.c_double,
+                                              C.c_double, _dp]
+            L.oracle_fill_profile.restype = C.c_int
+            L.oracle_me_synth_fill.argtypes = [_dp, _dp, C.c_int64, _linep, C.c_int, _dp,
+                                               C.POINTER(Fill), _dp]
+            L.oracle_me_synth_fill.restype = C.c_int
+            L.oracle_chi2_fill.argtypes = [_dp, C.c_int64, C.c_int, _linep, C.c_int, _dp, _dp,
+                                           _dp, C.POINTER(Fill), _dp, _dp]
+            L.oracle_chi2_fill.restype = None
             L.oracle_num_threads.restype = C.c_int
             _LIB = L
     return _LIB
@@ -293,15 +329,19 @@ def ga_step(genes_in, fitness, k, p_cross, p_mut, seed, pixel, gen):
 
 def ga_invert(obs, sigma, lines, lo, hi, pop, generations, k, p_cross, p_mut, seed,
               mu=None, pixel_base=0, want_population=False, n_seeded=0, seed_jitter=0,
-              seed_params=None, init_mode=0, restart_every=0, pixel_box=None):
+              seed_params=None, init_mode=0, restart_every=0, pixel_box=None, fill=None):
     """Algorithm 1 for npix pixels; pixel_box [npix, 2, 9] (lo row, hi row)
-    gives each pixel its own search box (status 3 where it is invalid)."""
+    gives each pixel its own search box (status 3 where it is invalid); fill
+    (a Fill) makes the fitness the chi-square at the best fill fraction and
+    adds 'alpha' [npix] to the result (status 4 where the field-free profile
+    is invalid)."""
     o = _f64(obs)
     s = _f64(sigma)
     npix = o.shape[0]
     lo = _f64(lo)
     hi = _f64(hi)
     pb = None if pixel_box is None else _f64(pixel_box).reshape(npix, 2, NPAR)
+    ba = np.empty(npix, np.float64)
     bp = np.empty((npix, NPAR), np.float64)
     bc = np.empty(npix, np.float64)
     st = np.empty(npix, np.int32)
@@ -312,7 +352,8 @@ def ga_invert(obs, sigma, lines, lo, hi, pop, generations, k, p_cross, p_mut, se
     sp = None if n_seeded == 0 else _f64(seed_params).reshape(npix, NPAR)
     rc = lib().oracle_ga_invert(
         _ptr(o, _dp), _ptr(s, _dp), None if m is None else _ptr(m, _dp), npix, lp, len(lines),
-        _ptr(lo, _dp), _ptr(hi, _dp), None if pb is None else _ptr(pb, _dp), int(pop),
+        _ptr(lo, _dp), _ptr(hi, _dp), None if pb is None else _ptr(pb, _dp),
+        None if fill is None else C.byref(fill), None if fill is None else _ptr(ba, _dp), int(pop),
         int(generations), int(k), float(p_cross),
         float(p_mut), int(seed), int(pixel_base), int(n_seeded), int(seed_jitter),
         None if sp is None else _ptr(sp, _dp), int(init_mode), int(restart_every), _ptr(bp, _dp), _ptr(bc, _dp), _ptr(st, _i32p),
@@ -320,9 +361,51 @@ def ga_invert(obs, sigma, lines, lo, hi, pop, generations, k, p_cross, p_mut, se
     if rc != 0:
         raise ValueError("oracle_ga_invert rejected its arguments")
     res = dict(params=bp, chi2=bc, status=st)
+    if fill is not None:
+        res["alpha"] = ba
     if want_population:
         res.update(genes=fg, fitness=ff)
     return res
+
+
+def fill_profile(line, fill_line, mu, vlos):
+    """Normalised field-free profile N [nlam] of one line (oracle_fill.c)."""
+    out = np.empty(line.nlam, np.float64)
+    if lib().oracle_fill_profile(C.byref(line), C.byref(fill_line), float(mu), float(vlos),
+                                 _ptr(out, _dp)) != 0:
+        raise ValueError("field-free profile invalid at this mu")
+    return out
+
+
+def me_synth_fill(params, alpha, lines, fill, mu=None):
+    """alpha M + (1 - alpha) I_c N e: Stokes [n, 4, L] for params [n, 9] and
+    alpha [n] (FP64)."""
+    p = _f64(params).reshape(-1, NPAR)
+    n = p.shape[0]
+    a = _f64(np.broadcast_to(alpha, (n,)))
+    L = sum(ln.nlam for ln in lines)
+    out = np.empty((n, 4, L), np.float64)
+    arr, lp = _lines_array(lines)
+    m = None if mu is None else _f64(np.broadcast_to(mu, (n,)))
+    lib().oracle_me_synth_fill(_ptr(p, _dp), _ptr(a, _dp), n, lp, len(lines),
+                               None if m is None else _ptr(m, _dp), C.byref(fill), _ptr(out, _dp))
+    return out
+
+
+def chi2_fill(params, obs, sigma, lines, fill, mu=None):
+    """(chi-square, best alpha) [npix, pop] of params [npix, pop, 9] (nu = 4L - 10)."""
+    p = _f64(params)
+    npix, pop = p.shape[0], p.shape[1]
+    o = _f64(obs)
+    s = _f64(sigma)
+    c = np.empty((npix, pop), np.float64)
+    a = np.empty((npix, pop), np.float64)
+    arr, lp = _lines_array(lines)
+    m = None if mu is None else _f64(np.broadcast_to(mu, (npix,)))
+    lib().oracle_chi2_fill(_ptr(p, _dp), npix, pop, lp, len(lines), _ptr(o, _dp), _ptr(s, _dp),
+                           None if m is None else _ptr(m, _dp), C.byref(fill), _ptr(c, _dp),
+                           _ptr(a, _dp))
+    return c, a
 
 
 def lm_refine(obs, sigma, lines, lo, hi, params_in, iterations, mu=None, free_mask=0x1FF):

@@ -35,6 +35,8 @@
 
 #define ORACLE_NPAR 9
 #define ORACLE_MAXCOMP 64
+#define ORACLE_MAXLINES 8
+#define ORACLE_C_KMS 299792.458          /* speed of light [km/s] */
 
 typedef struct {
     double lambda0;                    /* rest wavelength [Angstrom] */
@@ -71,6 +73,32 @@ void oracle_me_synth(const double *par, int64_t n, const oracle_line *lines, int
  * par [npix][pop][9], obs [npix][4][L], sigma [npix][4], chi2 [npix][pop]. */
 void oracle_chi2(const double *par, int64_t npix, int pop, const oracle_line *lines, int nlines,
                  const double *obs, const double *sigma, const double *mu, double *chi2);
+
+/* Fill fraction (Sec. 5.2, see oracle_fill.c): the field-free profile of
+ * each line as cubic polynomials in mu of its depth, width [A] and damping,
+ * and the range of alpha. */
+typedef struct {
+    double depth[4], width[4], damp[4];
+} oracle_fill_line;
+typedef struct {
+    double alpha_lo, alpha_hi;
+    oracle_fill_line line[ORACLE_MAXLINES];
+} oracle_fill;
+
+/* N [nlam] of one line at mu for the model velocity vlos; 0, or -1 when the
+ * width is not positive or the damping outside [0, 1.5] at this mu. */
+int oracle_fill_profile(const oracle_line *ln, const oracle_fill_line *f, double mu, double vlos,
+                        double *N);
+/* alpha M(p) + (1 - alpha) I_c N e for n models (par [n][9], alpha [n],
+ * mu [n] or NULL) -> out [n][4][L]; -1 (and NaN rows) where N is invalid. */
+int oracle_me_synth_fill(const double *par, const double *alpha, int64_t n,
+                         const oracle_line *lines, int nlines, const double *mu,
+                         const oracle_fill *fill, double *out);
+/* chi-square at the best alpha of each model and that alpha
+ * (par [npix][pop][9] -> chi2, alpha [npix][pop]); nu = 4L - 10. */
+void oracle_chi2_fill(const double *par, int64_t npix, int pop, const oracle_line *lines,
+                      int nlines, const double *obs, const double *sigma, const double *mu,
+                      const oracle_fill *fill, double *chi2, double *alpha);
 
 /* Philox4x32-10 (Salmon et al. 2011). */
 void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -121,10 +149,14 @@ int oracle_ga_step(const uint16_t *genes_in, const double *fit, int pop, int k,
  * n_seeded > 0 seeds generation 0 of pixel p from seed_params [npix][9] as
  * oracle_ga_init does.  pixel_box [npix][2][9] (lo row, then hi row; may be
  * NULL) replaces [lo, hi] for each pixel: decoding, seeding and the result
- * use the pixel's box.  Returns 0 or -1. */
+ * use the pixel's box.  fill (may be NULL) makes the fitness the chi-square
+ * at each individual's best fill fraction (oracle_fill.c); best_alpha [npix]
+ * (needed then) receives the best individual's alpha, and a pixel whose
+ * field-free profile is invalid at its mu gets status 4.  Returns 0 or -1. */
 int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, int64_t npix,
                      const oracle_line *lines, int nlines, const double *lo, const double *hi,
-                     const double *pixel_box, int pop, int generations, int k, double p_cross, double p_mut,
+                     const double *pixel_box, const oracle_fill *fill, double *best_alpha,
+                     int pop, int generations, int k, double p_cross, double p_mut,
                      uint64_t seed, uint32_t pixel_base, int n_seeded, int seed_jitter,
                      const double *seed_params, int init_mode, int restart_every,
                      double *best_params, double *best_chi2, int32_t *status,

@@ -49,6 +49,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+double oracle__chi2_fill_single(const double *par, double mu, const oracle_line *lines,
+                                int nlines, const double *obs, const double *sigma,
+                                const oracle_fill *fill, double *scratch, double *alpha_out);
 double oracle__chi2_single(const double *par, double mu, const oracle_line *lines, int nlines,
                            const double *obs, const double *sigma, double *scratch);
 int oracle__total_samples(const oracle_line *lines, int nlines);
@@ -399,7 +402,8 @@ int oracle_ga_step(const uint16_t *genes_in, const double *fit, int pop, int k,
  * the decoded model against the pixel's observation. */
 int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, int64_t npix,
                      const oracle_line *lines, int nlines, const double *lo_all,
-                     const double *hi_all, const double *pixel_box, int pop, int generations, int k, double p_cross, double p_mut,
+                     const double *hi_all, const double *pixel_box, const oracle_fill *fill,
+                     double *best_alpha, int pop, int generations, int k, double p_cross, double p_mut,
                      uint64_t seed, uint32_t pixel_base, int n_seeded, int seed_jitter,
                      const double *seed_params, int init_mode, int restart_every,
                      double *best_params, double *best_chi2, int32_t *status,
@@ -411,6 +415,10 @@ int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, i
         return -1;
     if ((init_mode != 0 && init_mode != 1) || restart_every < 0)
         return -1;
+    if (fill && (!best_alpha || nlines > ORACLE_MAXLINES ||
+                 !(0.0 <= fill->alpha_lo && fill->alpha_lo <= fill->alpha_hi &&
+                   fill->alpha_hi <= 1.0)))
+        return -1;
     const int L = oracle__total_samples(lines, nlines);
     int err = 0;
 #pragma omp parallel
@@ -421,7 +429,8 @@ int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, i
         int32_t *par2 = (int32_t *)malloc(sizeof(int32_t) * 2 * (size_t)pop);
         int32_t *xp = (int32_t *)malloc(sizeof(int32_t) * (size_t)pop);
         double *fit = (double *)malloc(sizeof(double) * (size_t)pop);
-        double *scratch = (double *)malloc(sizeof(double) * 4 * (size_t)L);
+        double *scratch = (double *)malloc(sizeof(double) * 5 * (size_t)L);
+        double *alph = (double *)malloc(sizeof(double) * (size_t)pop);
 #pragma omp for schedule(dynamic, 1)
         for (int64_t p = 0; p < npix; ++p) {
             const double *o = obs + p * 4 * L;
@@ -441,11 +450,18 @@ int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, i
                 for (int j = 0; j < NGENE; ++j)
                     if (!(isfinite(lo[j]) && isfinite(hi[j]) && hi[j] >= lo[j]))
                         st = st ? st : 3;
+            const double m = mu ? mu[p] : 1.0;
+            if (fill && !st)
+                for (int l = 0; l < nlines; ++l)
+                    if (oracle_fill_profile(&lines[l], &fill->line[l], m, 0.0, scratch) != 0)
+                        st = 4;
             status[p] = st;
             if (st) {
                 for (int j = 0; j < NGENE; ++j)
                     best_params[p * NGENE + j] = NAN;
                 best_chi2[p] = NAN;
+                if (fill)
+                    best_alpha[p] = NAN;
                 if (final_genes)
                     memset(final_genes + p * (int64_t)pop * NGENE, 0,
                            sizeof(uint16_t) * NGENE * (size_t)pop);
@@ -455,13 +471,17 @@ int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, i
                 continue;
             }
             const uint32_t pix = pixel_base + (uint32_t)p;
-            const double m = mu ? mu[p] : 1.0;
             double par[NGENE];
+            /* F of the decoded individual i (Sec. 5 chi-square, at its best
+               fill fraction when fill is given) */
+#define FITNESS(i)                                                                         \
+    (fill ? oracle__chi2_fill_single(par, m, lines, nlines, o, s, fill, scratch, &alph[i]) \
+          : oracle__chi2_single(par, m, lines, nlines, o, s, scratch))
             oracle_ga_init(seed, pix, pop, n_seeded, seed_jitter,
                            seed_params ? seed_params + p * NGENE : NULL, lo, hi, init_mode, g0);
             for (int i = 0; i < pop; ++i) {
                 oracle_decode(g0 + i * NGENE, lo, hi, par);
-                fit[i] = oracle__chi2_single(par, m, lines, nlines, o, s, scratch);
+                fit[i] = FITNESS(i);
             }
             for (int t = 1; t <= generations; ++t) {
                 if (restart_every > 0 && t - 1 > 0 && (t - 1) % restart_every == 0) {
@@ -470,7 +490,7 @@ int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, i
                     for (int i = 0; i < pop; ++i)
                         if (xp[i]) {
                             oracle_decode(g1 + i * NGENE, lo, hi, par);
-                            fit[i] = oracle__chi2_single(par, m, lines, nlines, o, s, scratch);
+                            fit[i] = FITNESS(i);
                         }
                     uint16_t *tmp = g0;
                     g0 = g1;
@@ -488,15 +508,18 @@ int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, i
                 g1 = tmp;
                 for (int i = 0; i < pop; ++i) {
                     oracle_decode(g0 + i * NGENE, lo, hi, par);
-                    fit[i] = oracle__chi2_single(par, m, lines, nlines, o, s, scratch);
+                    fit[i] = FITNESS(i);
                 }
             }
+#undef FITNESS
             int b = 0;
             for (int i = 1; i < pop; ++i)
                 if (ranks_before(fit, i, b))
                     b = i;
             oracle_decode(g0 + b * NGENE, lo, hi, best_params + p * NGENE);
             best_chi2[p] = fit[b];
+            if (fill)
+                best_alpha[p] = alph[b];
             if (final_genes)
                 memcpy(final_genes + p * (int64_t)pop * NGENE, g0,
                        sizeof(uint16_t) * NGENE * (size_t)pop);
@@ -505,6 +528,7 @@ int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, i
         }
         free(g0);
         free(g1);
+        free(alph);
         free(masks);
         free(par2);
         free(xp);

@@ -15,7 +15,6 @@
 #include <omp.h>
 #endif
 
-#define ORACLE_C_KMS 299792.458          /* speed of light [km/s] */
 #define ORACLE_ZEEMAN_K 4.6686e-13       /* e / (4 pi m_e c^2) [1/(Angstrom G)] */
 
 /* ------------------------------------------------------------------------ */

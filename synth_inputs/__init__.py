@@ -57,6 +57,33 @@ def line_set(name: str):
     raise KeyError(name)
 
 
+# Stand-in for the centre-to-limb variation of the field-free (quiet-Sun)
+# Stokes I profile that the fill-fraction model mixes in (Sec. 5.2): the paper
+# fits its depth, width and damping with cubic polynomials in mu from
+# measurements that are not published.  These coefficients (mu^0 .. mu^3) are
+# invented: at disc centre a depth of 0.67 (6301.5) and 0.60 (6302.5) of the
+# continuum, Doppler width 0.030 A, damping 0.22, weakening, widening and
+# more damped towards the limb.
+FILL_CLV = {
+    "depth": {"6301": (0.50, 0.25, -0.10, 0.02), "6302": (0.45, 0.22, -0.08, 0.01)},
+    "width": {"6301": (0.036, -0.008, 0.002, 0.0), "6302": (0.036, -0.008, 0.002, 0.0)},
+    "damp": {"6301": (0.30, -0.10, 0.02, 0.0), "6302": (0.30, -0.10, 0.02, 0.0)},
+}
+
+
+def fill_coefficients(name: str):
+    """(depth, width, damp) [nlines, 4] of the stand-in profile for a line set."""
+    keys = ["6301" if abs(ln["lambda0"] - FE6301["lambda0"]) < 0.5 else "6302"
+            for ln, _ in line_set(name)]
+    return tuple(np.array([FILL_CLV[q][k] for k in keys]) for q in ("depth", "width", "damp"))
+
+
+def draw_alpha(npix: int, seed: int, lo: float = 0.25, hi: float = 1.0) -> np.ndarray:
+    """Fill fractions uniform in [lo, hi] (Table 4 bounds alpha below by 0.25
+    in umbrae and penumbrae)."""
+    return np.random.default_rng(seed + 7777).uniform(lo, hi, npix)
+
+
 def draw_truth(npix: int, seed: int) -> np.ndarray:
     """Truth parameters [npix, 9] drawn iid from the priors (float64)."""
     rng = np.random.Generator(np.random.Philox(key=seed))
