@@ -159,7 +159,7 @@ const char *me_last_error(void);
 int genesis_abi_version(void);
 /* sizeof of the argument structs as compiled into the library, for bindings
  * to check their own layouts against: which = 0 me_line, 1 me_grid,
- * 2 me_bounds, 3 ga_config; 0 for any other value. */
+ * 2 me_bounds, 3 ga_config, 4 me_fill; 0 for any other value. */
 size_t genesis_struct_size(int32_t which);
 
 /* ---- line data (host only, no device work) ------------------------------ */
@@ -282,6 +282,55 @@ int ga_invert_f64(const double *obs, const double *sigma, const double *mu, int6
                   const me_bounds *bounds, const ga_config *cfg, double *best_params,
                   double *best_chi2, int32_t *status, uint16_t *final_genes,
                   double *final_fitness, void *workspace, size_t ws_bytes, void *stream);
+
+/* ---- magnetic fill fraction (Sec. 5.2) ------------------------------------ */
+
+/* A fraction alpha of the pixel is magnetic and the rest field-free: the
+ * Stokes vector is alpha M(p) + (1 - alpha) I_c N(lambda) e, with M the
+ * Milne-Eddington vector of the nine parameters, I_c = S0 + mu S1 its
+ * continuum, e = (1, 0, 0, 0) and N the normalised field-free Stokes I
+ * profile, a Voigt profile centred on the model's line centre:
+ *   N = 1 - d(mu) H(v, a(mu)) / H(0, a(mu)),
+ *   v = (lambda - lambda0 (1 + v_los / c)) / w(mu),
+ * whose depth d, width w [A] and damping a are cubic polynomials in mu
+ * (coefficients of mu^0 .. mu^3 per line; the paper fits them to measured
+ * centre-to-limb variations it does not publish, so they are inputs).  A
+ * pixel whose w(mu) <= 0 or a(mu) outside [0, 1.5] is invalid (status 4).
+ * alpha is restricted to [alpha_lo, alpha_hi] within [0, 1]. */
+typedef struct {
+    double alpha_lo, alpha_hi;
+    double depth[GENESIS_MAX_LINES][4];
+    double width[GENESIS_MAX_LINES][4];
+    double damp[GENESIS_MAX_LINES][4];
+} me_fill;
+
+/* Stokes vectors [n][4][L] of models params [n][9] with fill fractions
+ * alpha [n] (mu [n] or NULL); NaN rows where the field-free profile is invalid. */
+int me_synth_fill(const float *params, const float *alpha, int64_t n, const me_line *lines,
+                  const me_grid *grids, int32_t nlines, const float *mu, const me_fill *fill,
+                  float *stokes, void *stream);
+int me_synth_fill_f64(const double *params, const double *alpha, int64_t n,
+                      const me_line *lines, const me_grid *grids, int32_t nlines,
+                      const double *mu, const me_fill *fill, double *stokes, void *stream);
+
+/* ga_invert with the fill fraction as a tenth fitted parameter.  alpha enters
+ * the model linearly, so every individual takes the alpha in [alpha_lo,
+ * alpha_hi] that minimises its chi-square, in closed form, and its fitness is
+ * that minimum (nu = 4L - 10); the genes, operators and outputs are those of
+ * ga_invert, plus best_alpha [npix], the best individual's alpha.  Status 4
+ * (NaN outputs) for a pixel whose field-free profile is invalid at its mu.
+ * Native synthesis only (ME_EINVAL for GENESIS_SYNTH_FP16). */
+int ga_invert_fill(const float *obs, const float *sigma, const float *mu, int64_t npix,
+                   const me_line *lines, const me_grid *grids, int32_t nlines,
+                   const me_bounds *bounds, const ga_config *cfg, const me_fill *fill,
+                   float *best_params, float *best_alpha, float *best_chi2, int32_t *status,
+                   uint16_t *final_genes, float *final_fitness, void *stream);
+int ga_invert_fill_f64(const double *obs, const double *sigma, const double *mu, int64_t npix,
+                       const me_line *lines, const me_grid *grids, int32_t nlines,
+                       const me_bounds *bounds, const ga_config *cfg, const me_fill *fill,
+                       double *best_params, double *best_alpha, double *best_chi2,
+                       int32_t *status, uint16_t *final_genes, double *final_fitness,
+                       void *stream);
 
 /* ---- FP64 refinement of a solution (non-linear least squares) ----------- */
 

@@ -48,6 +48,26 @@ class MeBounds(C.Structure):
     _fields_ = [("lo", C.c_double * NPAR), ("hi", C.c_double * NPAR)]
 
 
+class MeFill(C.Structure):
+    """Fill fraction (Sec. 5.2): alpha range and per line the cubic-in-mu
+    coefficients of the field-free profile's depth, width [A] and damping."""
+    _fields_ = [("alpha_lo", C.c_double), ("alpha_hi", C.c_double),
+                ("depth", (C.c_double * 4) * MAX_LINES), ("width", (C.c_double * 4) * MAX_LINES),
+                ("damp", (C.c_double * 4) * MAX_LINES)]
+
+
+def fill(alpha_lo, alpha_hi, depth, width, damp) -> MeFill:
+    """MeFill from [nlines, 4] coefficient arrays (mu^0 .. mu^3)."""
+    f = MeFill()
+    f.alpha_lo, f.alpha_hi = float(alpha_lo), float(alpha_hi)
+    for l in range(len(depth)):
+        for k in range(4):
+            f.depth[l][k] = float(depth[l][k])
+            f.width[l][k] = float(width[l][k])
+            f.damp[l][k] = float(damp[l][k])
+    return f
+
+
 SYNTH_NATIVE = 0
 SYNTH_FP16 = 1
 
@@ -144,6 +164,14 @@ _SIGS = {
     "me_refine_f64": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _i32, _vp, _vp, _vp, _vp, _vp],
                       C.c_int),
     "me_first_guess": ([_vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _vp], C.c_int),
+    "me_synth_fill": ([_vp, _vp, _i64, _lp, _gp, _i32, _vp, C.POINTER(MeFill), _vp, _vp],
+                      C.c_int),
+    "me_synth_fill_f64": ([_vp, _vp, _i64, _lp, _gp, _i32, _vp, C.POINTER(MeFill), _vp, _vp],
+                          C.c_int),
+    "ga_invert_fill": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _cp, C.POINTER(MeFill), _vp,
+                        _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "ga_invert_fill_f64": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _cp, C.POINTER(MeFill),
+                            _vp, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "me_prefit_f64": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _i32, _vp, _vp, _vp, _vp],
                       C.c_int),
     "me_search_box": ([_vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, C.c_double, _vp, _vp],
@@ -174,7 +202,7 @@ _SIGS = {
 
 EXPORTED = tuple(_SIGS)
 STRUCTS = (("me_line", MeLine), ("me_grid", MeGrid), ("me_bounds", MeBounds),
-           ("ga_config", GaConfigC))
+           ("ga_config", GaConfigC), ("me_fill", MeFill))
 
 
 def lib_path() -> str:
@@ -286,9 +314,11 @@ def _real(t: torch.Tensor):
 # --------------------------------------------------------------------------- #
 # forward model
 
-def me_synth(params: torch.Tensor, lines, grids, mu=None, out=None, fp16=False):
+def me_synth(params: torch.Tensor, lines, grids, mu=None, out=None, fp16=False, alpha=None,
+             fill: Optional[MeFill] = None):
     """Stokes [n, 4, L] from params [n, 9] (Sec. 5 analytic solution).
-    fp16=True (float32 tensors only): profiles in packed FP16 (me_synth_f16)."""
+    fp16=True (float32 tensors only): profiles in packed FP16 (me_synth_f16).
+    fill and alpha [n]: the fill-fraction mixture of Sec. 5.2 (me_synth_fill)."""
     dt = _real(params)
     n = params.shape[0]
     L = total_samples(grids)
@@ -298,6 +328,14 @@ def me_synth(params: torch.Tensor, lines, grids, mu=None, out=None, fp16=False):
         out = torch.empty((n, 4, L), dtype=dt, device=params.device)
     _dev(out, dt, "out", (n, 4, L))
     la, ga, nl = _lines(lines, grids)
+    if fill is not None:
+        if fp16:
+            raise ValueError("the fill fraction needs the native synthesis")
+        _dev(alpha, dt, "alpha", (n,))
+        f = lib().me_synth_fill if dt == torch.float32 else lib().me_synth_fill_f64
+        _check(f(_ptr(params), _ptr(alpha), n, la, ga, nl, _ptr(mu), C.byref(fill), _ptr(out),
+                 _stream(params)))
+        return out
     if fp16:
         if dt != torch.float32:
             raise ValueError("fp16 synthesis takes float32 parameters")
@@ -409,8 +447,10 @@ def ga_workspace_bytes(npix: int, cfg: GAConfig) -> int:
 
 
 def ga_invert(obs, sigma, lines, grids, bnds: MeBounds, cfg: GAConfig, mu=None,
-              want_population=False, want_status=True):
-    """Whole inversion (Algorithm 1) in one launch; returns a dict of tensors."""
+              want_population=False, want_status=True, fill: Optional[MeFill] = None):
+    """Whole inversion (Algorithm 1) in one launch; returns a dict of tensors.
+    fill: the fill fraction of Sec. 5.2 as a tenth fitted parameter
+    (ga_invert_fill); the result then has 'alpha' [npix]."""
     dt = _real(obs)
     npix = obs.shape[0]
     L = total_samples(grids)
@@ -427,6 +467,14 @@ def ga_invert(obs, sigma, lines, grids, bnds: MeBounds, cfg: GAConfig, mu=None,
         res["fitness"] = torch.empty((npix, cfg.pop), dtype=dt, device=dev)
     la, ga, nl = _lines(lines, grids)
     c = cfg.c(npix)
+    if fill is not None:
+        res["alpha"] = torch.empty((npix,), dtype=dt, device=dev)
+        f = lib().ga_invert_fill if dt == torch.float32 else lib().ga_invert_fill_f64
+        _check(f(_ptr(obs), _ptr(sigma), _ptr(mu), npix, la, ga, nl, C.byref(bnds), C.byref(c),
+                 C.byref(fill), _ptr(res["params"]), _ptr(res["alpha"]), _ptr(res["chi2"]),
+                 _ptr(res.get("status")), _ptr(res.get("genes")), _ptr(res.get("fitness")),
+                 _stream(obs)))
+        return res
     f = lib().ga_invert if dt == torch.float32 else lib().ga_invert_f64
     _check(f(_ptr(obs), _ptr(sigma), _ptr(mu), npix, la, ga, nl, C.byref(bnds), C.byref(c),
              _ptr(res["params"]), _ptr(res["chi2"]), _ptr(res.get("status")),

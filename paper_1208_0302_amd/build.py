@@ -39,9 +39,11 @@ def hipcc():
 # Code placement of the hot kernels (see code_shift in csrc/genesis_common.h):
 # switch -> mangled-name pattern of the kernel it moves.
 PLACEMENT = {
-    "GENESIS_PAD_INVERT_F32": r"k_ga_invertIfLi0E",
-    "GENESIS_PAD_INVERT_F16": r"k_ga_invertIfLi1E",
-    "GENESIS_PAD_INVERT_F64": r"k_ga_invertIdLi0E",
+    "GENESIS_PAD_INVERT_F32": r"k_ga_invertIfLi0ELb0E",
+    "GENESIS_PAD_INVERT_F16": r"k_ga_invertIfLi1ELb0E",
+    "GENESIS_PAD_INVERT_F64": r"k_ga_invertIdLi0ELb0E",
+    "GENESIS_PAD_FILL_F32": r"k_ga_invertIfLi0ELb1E",
+    "GENESIS_PAD_FILL_F64": r"k_ga_invertIdLi0ELb1E",
     "GENESIS_PAD_ADVANCE": r"k_ga_advance",
     "GENESIS_PAD_REFINE": r"k_refine_f64",
 }

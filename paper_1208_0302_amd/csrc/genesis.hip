@@ -49,6 +49,27 @@ int check_launch(const char *what)
     return ME_OK;
 }
 
+int pack_fill(const me_fill *fill, int nlines, FillConst &fc)
+{
+    if (!fill)
+        return fail(ME_EINVAL, "fill must not be NULL");
+    if (!(fill->alpha_lo >= 0.0 && fill->alpha_lo <= fill->alpha_hi && fill->alpha_hi <= 1.0))
+        return fail(ME_EINVAL, "fill fraction range [%g, %g] must lie in [0, 1]", fill->alpha_lo,
+                    fill->alpha_hi);
+    fc.alpha_lo = fill->alpha_lo;
+    fc.alpha_hi = fill->alpha_hi;
+    for (int l = 0; l < GENESIS_MAX_LINES; ++l)
+        for (int k = 0; k < 4; ++k) {
+            if (l < nlines && !(std::isfinite(fill->depth[l][k]) &&
+                                std::isfinite(fill->width[l][k]) && std::isfinite(fill->damp[l][k])))
+                return fail(ME_EINVAL, "fill coefficients of line %d must be finite", l);
+            fc.depth[l][k] = fill->depth[l][k];
+            fc.width[l][k] = fill->width[l][k];
+            fc.damp[l][k] = fill->damp[l][k];
+        }
+    return ME_OK;
+}
+
 int pack_bounds(const me_bounds *b, Bounds &out)
 {
     if (!b)
@@ -430,8 +451,18 @@ struct SynLines<GENESIS_SYNTH_FP16> {
     DevLinesH lh;
 };
 
-template <typename Real, int SYN = GENESIS_SYNTH_NATIVE>
-struct InvertArgs : SynLines<SYN> {
+// fill-fraction constants and output, present in the fill kernels only
+template <typename Real, bool FILL>
+struct FillArgs {
+};
+template <typename Real>
+struct FillArgs<Real, true> {
+    FillConst fc;
+    Real *best_alpha;
+};
+
+template <typename Real, int SYN = GENESIS_SYNTH_NATIVE, bool FILL = false>
+struct InvertArgs : SynLines<SYN>, FillArgs<Real, FILL> {
     const Real *obs, *sigma, *mu;
     int64_t npix;
     int32_t generations;
@@ -446,26 +477,36 @@ struct InvertArgs : SynLines<SYN> {
 // The whole of Algorithm 1 for one pixel per workgroup: the population
 // lives in LDS (two buffers: parents and children), lane i owns
 // individual i.
-template <typename Real, int SYN>
-__global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN> a)
+template <typename Real, int SYN, bool FILL>
+__global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN, FILL> a)
 {
-    code_shift<SYN == GENESIS_SYNTH_FP16 ? GENESIS_PAD_INVERT_F16
-                                         : (sizeof(Real) == 8 ? GENESIS_PAD_INVERT_F64
-                                                              : GENESIS_PAD_INVERT_F32)>();
+    code_shift<FILL ? (sizeof(Real) == 8 ? GENESIS_PAD_FILL_F64 : GENESIS_PAD_FILL_F32)
+                    : SYN == GENESIS_SYNTH_FP16
+                          ? GENESIS_PAD_INVERT_F16
+                          : (sizeof(Real) == 8 ? GENESIS_PAD_INVERT_F64 : GENESIS_PAD_INVERT_F32)>();
     extern __shared__ __align__(16) unsigned char smem[];
     const int pop = a.ga.pop;
     const int L = a.ls.L;
     const GaLds<Real> s = ga_lds<Real>(smem, L, pop);
     const int tid = threadIdx.x;
     const bool active = tid < pop;
-    const Real inv_nu = (Real)(1.0 / (4.0 * L - GENESIS_NPAR));
+    // nu = 4L - 9, or 4L - 10 with the fill fraction as a tenth parameter
+    const Real inv_nu = (Real)(1.0 / (4.0 * L - (FILL ? GENESIS_NPAR + 1 : GENESIS_NPAR)));
+    FillPix<Real> &fp = *reinterpret_cast<FillPix<Real> *>(s.fill);
     for (int64_t p = blockIdx.x; p < a.npix; p += gridDim.x) {
-        if (tid == 0)
+        const double mu = a.mu ? (double)a.mu[p] : 1.0;
+        if (tid == 0) {
             stage_box(a.b, a.ga.pixel_bounds, p, *s.box);
+            if constexpr (FILL)
+                fill_setup(a.fc, a.ls.nlines, mu, fp);
+        }
         Real w2[4];
         int st = stage_pixel(a.obs + p * 4 * (int64_t)L, a.sigma + p * 4, L, s.obs, w2);
         if (st == 0 && a.ga.pixel_bounds)
             st = box_status(*s.box, SYN == GENESIS_SYNTH_FP16);
+        if constexpr (FILL)
+            if (st == 0)
+                st = fp.status;
         if (st != 0) {
             if (tid == 0) {
                 for (int j = 0; j < GENESIS_NPAR; ++j)
@@ -473,6 +514,8 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN> a)
                 a.best_chi2[p] = (Real)NAN;
                 if (a.status)
                     a.status[p] = st;
+                if constexpr (FILL)
+                    a.best_alpha[p] = (Real)NAN;
             }
             if (active) {
                 if (a.final_fitness)
@@ -484,7 +527,6 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN> a)
             __syncthreads();
             continue;
         }
-        const double mu = a.mu ? (double)a.mu[p] : 1.0;
         const uint32_t pix = a.ga.pixel_base + (uint32_t)p;
         const int gstride = GENESIS_NPAR * pop;
         int cur = 0;  // offset of the current generation's gene buffer
@@ -502,12 +544,18 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN> a)
         for (int t = 0;;) {
             // evaluate generation t (each lane reads only its own genes)
             if (eval) {
-                if constexpr (SYN == GENESIS_SYNTH_FP16)
+                if constexpr (FILL) {
+                    Real al;
+                    f = evaluate_fill(s.genes + cur, pop, tid, *s.box, mu, a.ls, fp,
+                                      (Real)a.fc.alpha_lo, (Real)a.fc.alpha_hi, s.obs, w2, inv_nu,
+                                      al);
+                } else if constexpr (SYN == GENESIS_SYNTH_FP16) {
                     f = evaluate_lds_h(s.genes + cur, pop, tid, *s.box, mu, a.ls, a.lh, s.obs,
                                        w2, inv_nu);
-                else
+                } else {
                     f = evaluate_lds(s.genes + cur, pop, tid, *s.box, mu, a.ls, s.obs, w2,
                                      inv_nu);
+                }
                 s.fit[tid] = f;
             }
             __syncthreads();
@@ -551,6 +599,15 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN> a)
             for (int j = 0; j < GENESIS_NPAR; ++j)
                 a.best_params[p * GENESIS_NPAR + j] = (Real)par[j];
             a.best_chi2[p] = s.fit[e];
+            if constexpr (FILL) {
+                // the best individual's alpha: the same evaluation again
+                Model<Real> m;
+                model_setup(par, mu, m);
+                Real al;
+                (void)chi2_fill_of(m, a.ls, fp, (Real)a.fc.alpha_lo, (Real)a.fc.alpha_hi, s.obs,
+                                   w2, inv_nu, al);
+                a.best_alpha[p] = al;
+            }
             if (a.status)
                 a.status[p] = 0;
         }
@@ -610,6 +667,74 @@ __device__ double guess_reduce(double v, bool take_max, double *red)
     for (int k = 1; k < kGuessThreads / 64; ++k)
         t = take_max ? fmax(t, red[k]) : t + red[k];
     return t;
+}
+
+// Stokes vector of models with a fill fraction (Sec. 5.2), one thread per
+// model and sample: alpha M + (1 - alpha) I_c N e.  A model whose field-free
+// profile is invalid at its mu gets NaN.
+template <typename Real>
+__global__ void k_me_synth_fill(const Real *__restrict__ params, const Real *__restrict__ alpha,
+                                int64_t n, DevLines<Real> ls, const Real *__restrict__ mu,
+                                FillConst fc, Real *__restrict__ out)
+{
+    const int L = ls.L;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * L)
+        return;
+    const int64_t i = t / L;
+    const int j = (int)(t - i * L);
+    int l = 0;
+    while (l + 1 < ls.nlines && j >= ls.l[l + 1].off)
+        ++l;
+    const DevLine<Real> &ln = ls.l[l];
+    const int jj = j - ln.off;
+    double par[GENESIS_NPAR];
+    for (int k = 0; k < GENESIS_NPAR; ++k)
+        par[k] = (double)params[i * GENESIS_NPAR + k];
+    const double mu_i = mu ? (double)mu[i] : 1.0;
+    Real *o = out + i * 4 * (int64_t)L;
+    FillLine<Real> f;
+    if (!fill_setup_line(fc, l, mu_i, f)) {
+        o[j] = o[L + j] = o[2 * L + j] = o[3 * L + j] = (Real)NAN;
+        return;
+    }
+    Model<Real> m;
+    model_setup(par, mu_i, m);
+    Real I, Q, U, V;
+    stokes_at(m, ln, jj, I, Q, U, V);
+    const Real x = fma(ln.step, (Real)jj, ln.off0);
+    const Real N = fma(-f.scale, fill_h(f, (x - m.vlos * ln.dop_kms) * f.inv_w), (Real)1);
+    const Real a = alpha[i];
+    o[j] = fma(a, I, ((Real)1 - a) * ((m.S0 + m.muS1) * N));
+    o[L + j] = a * Q;
+    o[2 * L + j] = a * U;
+    o[3 * L + j] = a * V;
+}
+
+template <typename Real>
+int synth_fill_impl(const Real *params, const Real *alpha, int64_t n, const me_line *lines,
+                    const me_grid *grids, int32_t nlines, const Real *mu, const me_fill *fill,
+                    Real *stokes, void *stream)
+{
+    DevLines<Real> ls;
+    if (int rc = pack_lines(lines, grids, nlines, ls))
+        return rc;
+    FillConst fc;
+    if (int rc = pack_fill(fill, nlines, fc))
+        return rc;
+    if (n < 0)
+        return fail(ME_EINVAL, "n must be >= 0");
+    if (n == 0)
+        return ME_OK;
+    if (!params || !alpha || !stokes)
+        return fail(ME_EINVAL, "params, alpha and stokes must not be NULL");
+    const int bs = 256;
+    const int64_t blocks = (n * ls.L + bs - 1) / bs;
+    if (blocks > kMaxGrid)
+        return fail(ME_EINVAL, "n too large");
+    hipLaunchKernelGGL(k_me_synth_fill<Real>, dim3((unsigned)blocks), dim3(bs), 0,
+                       as_stream(stream), params, alpha, n, ls, mu, fc, stokes);
+    return check_launch("me_synth_fill");
 }
 
 // ---- per-pixel search boxes (Sec. 5.3 pre-fit ranges, Sec. 5.5 polarity)
@@ -1226,13 +1351,14 @@ int step_impl(const uint16_t *genes_in, const Real *fitness, int64_t npix, const
     return check_launch("ga_step");
 }
 
-template <typename Real, int SYN>
+template <typename Real, int SYN, bool FILL = false>
 int invert_impl(const Real *obs, const Real *sigma, const Real *mu, int64_t npix,
                 const me_line *lines, const me_grid *grids, int nlines, const me_bounds *bounds,
                 const ga_config *cfg, Real *best_params, Real *best_chi2, int32_t *status,
-                uint16_t *final_genes, Real *final_fitness, void *stream)
+                uint16_t *final_genes, Real *final_fitness, void *stream,
+                const me_fill *fill = nullptr, Real *best_alpha = nullptr)
 {
-    InvertArgs<Real, SYN> a{};
+    InvertArgs<Real, SYN, FILL> a{};
     if (int rc = pack_lines(lines, grids, nlines, a.ls))
         return rc;
     if (int rc = pack_bounds(bounds, a.b))
@@ -1244,8 +1370,16 @@ int invert_impl(const Real *obs, const Real *sigma, const Real *mu, int64_t npix
                     kHalfMaxDamping);
     if (npix < 0)
         return fail(ME_EINVAL, "npix must be >= 0");
-    if (4 * a.ls.L <= GENESIS_NPAR)
-        return fail(ME_EINVAL, "need 4 L > 9 wavelength samples for nu > 0");
+    if (4 * a.ls.L <= GENESIS_NPAR + (FILL ? 1 : 0))
+        return fail(ME_EINVAL, "need 4 L > %d wavelength samples for nu > 0",
+                    GENESIS_NPAR + (FILL ? 1 : 0));
+    if constexpr (FILL) {
+        if (int rc = pack_fill(fill, nlines, a.fc))
+            return rc;
+        if (npix > 0 && !best_alpha)
+            return fail(ME_EINVAL, "best_alpha must not be NULL");
+        a.best_alpha = best_alpha;
+    }
     const size_t lds = ga_lds_bytes<Real>(a.ls.L, cfg->pop);
     if (lds > kMaxLds)
         return fail(ME_ENOMEM, "L = %d, pop = %d need %zu B of LDS (> %zu)", a.ls.L, cfg->pop,
@@ -1266,7 +1400,7 @@ int invert_impl(const Real *obs, const Real *sigma, const Real *mu, int64_t npix
     a.final_fitness = final_fitness;
     if constexpr (SYN == GENESIS_SYNTH_FP16)
         pack_lines_h(a.ls, a.lh);
-    hipLaunchKernelGGL((k_ga_invert<Real, SYN>), dim3(grid_for(npix)),
+    hipLaunchKernelGGL((k_ga_invert<Real, SYN, FILL>), dim3(grid_for(npix)),
                        dim3(block_for_pop(cfg->pop)), lds, as_stream(stream), a);
     return check_launch("ga_invert");
 }
@@ -1387,6 +1521,7 @@ size_t genesis_struct_size(int32_t which)
     case 1: return sizeof(me_grid);
     case 2: return sizeof(me_bounds);
     case 3: return sizeof(ga_config);
+    case 4: return sizeof(me_fill);
     default: return 0;
     }
 }
@@ -1599,6 +1734,49 @@ size_t ga_workspace_bytes(int64_t npix, const ga_config *cfg)
     (void)npix;
     (void)cfg;
     return 0;
+}
+
+int ga_invert_fill(const float *obs, const float *sigma, const float *mu, int64_t npix,
+                   const me_line *lines, const me_grid *grids, int32_t nlines,
+                   const me_bounds *bounds, const ga_config *cfg, const me_fill *fill,
+                   float *best_params, float *best_alpha, float *best_chi2, int32_t *status,
+                   uint16_t *final_genes, float *final_fitness, void *stream)
+{
+    if (cfg && cfg->synth_precision != GENESIS_SYNTH_NATIVE)
+        return fail(ME_EINVAL, "the fill fraction needs the native synthesis");
+    return invert_impl<float, GENESIS_SYNTH_NATIVE, true>(
+        obs, sigma, mu, npix, lines, grids, nlines, bounds, cfg, best_params, best_chi2, status,
+        final_genes, final_fitness, stream, fill, best_alpha);
+}
+
+int ga_invert_fill_f64(const double *obs, const double *sigma, const double *mu, int64_t npix,
+                       const me_line *lines, const me_grid *grids, int32_t nlines,
+                       const me_bounds *bounds, const ga_config *cfg, const me_fill *fill,
+                       double *best_params, double *best_alpha, double *best_chi2,
+                       int32_t *status, uint16_t *final_genes, double *final_fitness,
+                       void *stream)
+{
+    if (cfg && cfg->synth_precision != GENESIS_SYNTH_NATIVE)
+        return fail(ME_EINVAL, "the fill fraction needs the native synthesis");
+    return invert_impl<double, GENESIS_SYNTH_NATIVE, true>(
+        obs, sigma, mu, npix, lines, grids, nlines, bounds, cfg, best_params, best_chi2, status,
+        final_genes, final_fitness, stream, fill, best_alpha);
+}
+
+int me_synth_fill(const float *params, const float *alpha, int64_t n, const me_line *lines,
+                  const me_grid *grids, int32_t nlines, const float *mu, const me_fill *fill,
+                  float *stokes, void *stream)
+{
+    return synth_fill_impl<float>(params, alpha, n, lines, grids, nlines, mu, fill, stokes,
+                                  stream);
+}
+
+int me_synth_fill_f64(const double *params, const double *alpha, int64_t n,
+                      const me_line *lines, const me_grid *grids, int32_t nlines,
+                      const double *mu, const me_fill *fill, double *stokes, void *stream)
+{
+    return synth_fill_impl<double>(params, alpha, n, lines, grids, nlines, mu, fill, stokes,
+                                   stream);
 }
 
 int ga_invert(const float *obs, const float *sigma, const float *mu, int64_t npix,

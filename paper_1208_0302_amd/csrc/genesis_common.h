@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <type_traits>
 
 #include "genesis_device.h"
 #include "genesis_half.h"
@@ -105,6 +106,12 @@ inline int pack_lines(const me_line *lines, const me_grid *grids, int nlines, De
 #ifndef GENESIS_PAD_INVERT_F64
 #define GENESIS_PAD_INVERT_F64 0
 #endif
+#ifndef GENESIS_PAD_FILL_F32
+#define GENESIS_PAD_FILL_F32 0
+#endif
+#ifndef GENESIS_PAD_FILL_F64
+#define GENESIS_PAD_FILL_F64 0
+#endif
 #ifndef GENESIS_PAD_ADVANCE
 #define GENESIS_PAD_ADVANCE 0
 #endif
@@ -147,6 +154,157 @@ __device__ __forceinline__ int stage_pixel(const Real *__restrict__ obs_p,
     return bad ? 1 : (bad_sig ? 2 : 0);
 }
 
+// ---- magnetic fill fraction (Sec. 5.2) --------------------------------------
+// A fraction alpha of the pixel is magnetic, the rest field-free:
+//   alpha M(p) + (1 - alpha) I_c N(lambda) e,   I_c = S0 + mu S1,
+// N = 1 - d(mu) H(v, a(mu)) / H(0, a(mu)), v = (lambda - lambda0 (1 + v_los/c))
+// / w(mu), with depth d, width w and damping a cubic polynomials in mu (inputs:
+// the paper's centre-to-limb fits are not published).  alpha enters linearly,
+// so each model takes its chi-square-optimal alpha in [alpha_lo, alpha_hi] in
+// closed form; with e = O - M (the residual at alpha = 1) and D = M - I_c N e,
+//   chi2(beta) nu = sum w^2 e.e + 2 beta sum w^2 e.D + beta^2 sum w^2 D.D,
+// beta = 1 - alpha, minimised at beta = -sum w^2 e.D / sum w^2 D.D (clamped;
+// alpha_hi where sum w^2 D.D = 0); nu = 4L - 10.
+
+struct FillConst {
+    double alpha_lo, alpha_hi;
+    double depth[GENESIS_MAX_LINES][4], width[GENESIS_MAX_LINES][4], damp[GENESIS_MAX_LINES][4];
+};
+
+template <typename Real>
+struct FillLine;
+template <>
+struct FillLine<float> {
+    VoigtF32 vc;            // rational-approximation coefficients at a(mu)
+    float scale, inv_w, a;  // d / H(0, a), 1 / w, a
+};
+template <>
+struct FillLine<double> {
+    double a, scale, inv_w;
+};
+
+template <typename Real>
+struct FillPix {
+    FillLine<Real> l[GENESIS_MAX_LINES];
+    int status;  // 0, or 4 when the field-free profile is invalid at this mu
+};
+
+__device__ __forceinline__ double cubic_mu(const double (&c)[4], double mu)
+{
+    return c[0] + mu * (c[1] + mu * (c[2] + mu * c[3]));
+}
+
+// The field-free profile constants of line l at this mu; false when the
+// width is not positive or the damping outside [0, 1.5].
+template <typename Real>
+__device__ __forceinline__ bool fill_setup_line(const FillConst &fc, int l, double mu,
+                                                FillLine<Real> &f)
+{
+    const double d = cubic_mu(fc.depth[l], mu), w = cubic_mu(fc.width[l], mu),
+                 a = cubic_mu(fc.damp[l], mu);
+    if (!(isfinite(d) && isfinite(w) && isfinite(a) && w > 0.0 && a >= 0.0 && a <= 1.5))
+        return false;
+    if constexpr (std::is_same<Real, float>::value) {
+        f.vc = voigt_setup_f32(a);
+        f.a = (float)a;
+        float h0 = 0.0f, l0 = 0.0f;
+        voigt_acc_f32(f.vc, 0.0f, 1.0f, h0, l0);
+        f.scale = (float)d / h0;
+    } else {
+        double h0, l0;
+        voigt_f64(a, 0.0, h0, l0);
+        f.a = a;
+        f.scale = d / h0;
+    }
+    f.inv_w = (Real)(1.0 / w);
+    return true;
+}
+
+// ... of every line (one thread).
+template <typename Real>
+__device__ __forceinline__ void fill_setup(const FillConst &fc, int nlines, double mu,
+                                           FillPix<Real> &fp)
+{
+    fp.status = 0;
+    for (int l = 0; l < nlines; ++l)
+        if (!fill_setup_line(fc, l, mu, fp.l[l])) {
+            fp.status = 4;
+            return;
+        }
+}
+
+__device__ __forceinline__ float fill_h(const FillLine<float> &f, float v)
+{
+    // The rational's |Q|^2 grows like v^16 and overflows FP32 from |v| ~ 250,
+    // which a field-free width near zero reaches (the magnetic profiles stay
+    // below |v| ~ 50).  Beyond |v| = 100 the Lorentzian wing a / (sqrt(pi)
+    // (v^2 + a^2)) is good to ~1e-4 relative, ~1e-9 absolute.
+    if (fabsf(v) > 100.0f)
+        return f.a * 0.5641895835f / fmaf(v, v, f.a * f.a);
+    float h = 0.0f, l = 0.0f;
+    voigt_acc_f32(f.vc, v, 1.0f, h, l);
+    return h;
+}
+
+__device__ __forceinline__ double fill_h(const FillLine<double> &f, double v)
+{
+    double h, l;
+    voigt_f64(f.a, v, h, l);
+    return h;
+}
+
+// Accumulates sum w^2 e.e, e.D and D.D of one model against the staged
+// observation while the Stokes vector is synthesised.
+template <typename Real>
+struct FillSink {
+    const Vec4<Real> *obs;
+    const FillLine<Real> *fl;
+    const DevLine<Real> *ln;
+    Real vshift, ic;
+    Real w2[4];
+    Real see, sed, sdd;
+    __device__ __forceinline__ void operator()(int j, Real I, Real Q, Real U, Real V)
+    {
+        const Real x = fma(ln->step, (Real)(j - ln->off), ln->off0);
+        const Real N = fma(-fl->scale, fill_h(*fl, (x - vshift) * fl->inv_w), (Real)1);
+        const Real dI = fma(-ic, N, I);  // D_I = I - I_c N; D_Q,U,V = Q, U, V
+        const Vec4<Real> o = obs[j];
+        const Real eI = o.x - I, eQ = o.y - Q, eU = o.z - U, eV = o.w - V;
+        const Real wI = w2[0] * eI, wQ = w2[1] * eQ, wU = w2[2] * eU, wV = w2[3] * eV;
+        see = fma(wI, eI, fma(wQ, eQ, fma(wU, eU, fma(wV, eV, see))));
+        sed = fma(wI, dI, fma(wQ, Q, fma(wU, U, fma(wV, V, sed))));
+        sdd = fma(w2[0] * dI, dI, fma(w2[1] * Q, Q, fma(w2[2] * U, U, fma(w2[3] * V, V, sdd))));
+    }
+};
+
+// chi-square at the model's best fill fraction, and that fraction.
+template <typename Real>
+__device__ __forceinline__ Real chi2_fill_of(const Model<Real> &m, const DevLines<Real> &ls,
+                                             const FillPix<Real> &fp, Real alo, Real ahi,
+                                             const Vec4<Real> *obs_s, const Real (&w2)[4],
+                                             Real inv_nu, Real &alpha)
+{
+    FillSink<Real> s;
+    s.obs = obs_s;
+    s.ic = m.S0 + m.muS1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        s.w2[k] = w2[k];
+    s.see = s.sed = s.sdd = (Real)0;
+    for (int l = 0; l < ls.nlines; ++l) {
+        const DevLine<Real> &ln = ls.l[l];
+        s.ln = &ln;
+        s.fl = &fp.l[l];
+        s.vshift = m.vlos * ln.dop_kms;
+        synth_line_range(m, ln, s, 0, ln.nlam);
+    }
+    const Real bmin = (Real)1 - ahi, bmax = (Real)1 - alo;
+    Real beta = s.sdd > (Real)0 ? -s.sed / s.sdd : bmin;
+    beta = fmin(fmax(beta, bmin), bmax);
+    alpha = (Real)1 - beta;
+    return fma(beta, fma(beta, s.sdd, (Real)2 * s.sed), s.see) * inv_nu;
+}
+
 // LDS of the GA kernels: observation [L] x 4, fitness [pop], argmin
 // scratch, two gene buffers [9][pop] (parents, children) and the pixel's
 // search box.
@@ -157,6 +315,7 @@ struct GaLds {
     int *red_i;
     uint16_t *genes;  // two buffers [9][pop] back to back
     Bounds *box;
+    void *fill;       // FillPix<Real> of the pixel (fill-fraction kernels)
 };
 
 // The search box of pixel p, written by one thread: its row of
@@ -203,6 +362,7 @@ __host__ __device__ inline size_t ga_lds_bytes(int L, int pop)
     o += (sizeof(Real) + sizeof(int)) * 16;
     o = align16(o + 2 * sizeof(uint16_t) * GENESIS_NPAR * (size_t)pop);
     o = align16(o + sizeof(Bounds));
+    o = align16(o + sizeof(FillPix<Real>));
     return o;
 }
 
@@ -222,6 +382,8 @@ __device__ __forceinline__ GaLds<Real> ga_lds(unsigned char *base, int L, int po
     s.genes = reinterpret_cast<uint16_t *>(base + o);
     o = align16(o + 2 * sizeof(uint16_t) * GENESIS_NPAR * (size_t)pop);
     s.box = reinterpret_cast<Bounds *>(base + o);
+    o = align16(o + sizeof(Bounds));
+    s.fill = base + o;
     return s;
 }
 
@@ -251,6 +413,24 @@ __device__ __forceinline__ Real evaluate_lds(const uint16_t *genes_s, int pop, i
     Model<Real> m;
     model_setup(par, mu, m);
     return chi2_of(m, ls, obs_s, w2, inv_nu);
+}
+
+template <typename Real>
+__device__ __forceinline__ Real evaluate_fill(const uint16_t *genes_s, int pop, int i,
+                                              const Bounds &b, double mu,
+                                              const DevLines<Real> &ls, const FillPix<Real> &fp,
+                                              Real alo, Real ahi, const Vec4<Real> *obs_s,
+                                              const Real (&w2)[4], Real inv_nu, Real &alpha)
+{
+    uint32_t g[GENESIS_NPAR];
+#pragma unroll
+    for (int j = 0; j < GENESIS_NPAR; ++j)
+        g[j] = genes_s[j * pop + i];
+    double par[GENESIS_NPAR];
+    decode(g, b, par);
+    Model<Real> m;
+    model_setup(par, mu, m);
+    return chi2_fill_of(m, ls, fp, alo, ahi, obs_s, w2, inv_nu, alpha);
 }
 
 // FP16-synthesis variant of evaluate_lds (FP32 decode set-up and chi-square).
