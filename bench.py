@@ -486,6 +486,89 @@ def disc(args):
     print(json.dumps(out), flush=True)
 
 
+# FP32 flops per wavelength that the fill fraction adds to an evaluation
+# (Sec. 5.2): the field-free profile (offset 4, Voigt H 42, N 2), D_I 2, and
+# the three weighted sums e.e, e.D, D.D (36) in place of the plain
+# chi-square's 12.
+FLOP_FILL_PER_LAMBDA = 4 + 42 + 2 + 2 + 36 - 12
+
+
+def fill_workload(args):
+    """Fill fraction (Sec. 5.2): 2048 slit pixels whose magnetic fraction alpha
+    is drawn from U(0.25, 1), mu from U(0.3, 1), mixed with the field-free
+    stand-in profile (FILL_CLV), noise 1e-3 Ic.  The GA with the fill fraction
+    (alpha in [0, 1] solved per individual) against the plain GA on the same
+    observations: time, alpha and field-strength errors."""
+    import torch
+    import paper_1208_0302_amd as g
+    import synth_inputs as si
+
+    dev = torch.device("cuda:0")
+    npix = 2048
+    lines, grids = [], []
+    for ln, n in si.line_set("slit"):
+        start, step = si.grid(ln, n)
+        lines.append(g.line_from_terms(ln["lambda0"], ln["Jl"], ln["gl"], ln["Ju"], ln["gu"]))
+        grids.append(g.grid(start, step, n))
+    fill = g.fill(0.0, 1.0, *si.fill_coefficients("slit"))
+    truth = si.draw_truth(npix, 77)
+    alpha = si.draw_alpha(npix, 77)
+    mu_np = np.random.default_rng(78).uniform(0.3, 1.0, npix)
+    t32 = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device=dev)
+    mu = t32(mu_np)
+    obs = g.me_synth(t32(truth), lines, grids, mu=mu, alpha=t32(alpha), fill=fill)
+    sig_np = si.sigma_for(truth, mu=mu_np)
+    sig = t32(sig_np)
+    obs += t32(sig_np[:, :, None] * si.std_normal(tuple(obs.shape), 79))
+    b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
+    cfg = g.GAConfig(pop=128, generations=200, tournament_k=4, p_cross=0.85, p_mut=0.05, seed=0)
+    stream = torch.cuda.current_stream(dev)
+    res, ms = {}, {}
+    for name, f in (("fill", fill), ("plain", None)):
+        g.ga_invert(obs[:256], sig[:256], lines, grids, b, cfg, mu=mu[:256], fill=f)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        res[name] = g.ga_invert(obs, sig, lines, grids, b, cfg, mu=mu, fill=f)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        ms[name] = ev[0].elapsed_time(ev[1])
+        print("fill: %s GA %.1f ms" % (name, ms[name]), file=sys.stderr, flush=True)
+
+    def pct(x):
+        return {"p50": float(np.percentile(x, 50)), "p90": float(np.percentile(x, 90))}
+
+    strong = truth[:, 0] >= 500.0
+    acc = {}
+    for name in res:
+        B = res[name]["params"][:, 0].cpu().numpy().astype(np.float64)
+        acc[name] = {"abs_dB_G": pct(np.abs(B - truth[:, 0])),
+                     "abs_dB_G_strong": pct(np.abs(B - truth[:, 0])[strong]),
+                     "median_chi2": float(res[name]["chi2"].median().item())}
+    da = np.abs(res["fill"]["alpha"].cpu().numpy().astype(np.float64) - alpha)
+    acc["fill"]["abs_dalpha"] = pct(da)
+    acc["fill"]["abs_dalpha_strong"] = pct(da[strong])
+    L = sum(gr.n for gr in grids)
+    fpe = flops_per_eval(list(zip(lines, grids))) + FLOP_FILL_PER_LAMBDA * L
+    evals = npix * 128 * 201
+    ga_s = ms["fill"] / 1e3
+    out = {"metric": "pixel inversions/s with the magnetic fill fraction (GA, FP32)",
+           "value": npix / ga_s, "unit": "pixels/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "ms_per_step": ms["fill"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (truth from the priors, alpha U(0.25, 1), mu U(0.3, 1), "
+                   "field-free stand-in profile, noise 1e-3 Ic)",
+           "config": {"workload": "fill fraction: 2048 px x 2 lines x 128, pop 128, G 200, "
+                                  "alpha in [0, 1] solved per individual", "npix": npix},
+           "plain_ga_ms": ms["plain"], "accuracy": acc,
+           "roofline": {"bound": "alu", "achieved": evals * fpe / ga_s / 1e12,
+                        "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                        "frac": evals * fpe / ga_s / PEAK_FP32_VALU, "traffic": None,
+                        "kernel": "k_ga_invert<float, fill>", "flop_per_eval": fpe,
+                        "evals_per_launch": evals}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -531,6 +614,9 @@ def main():
         return
     if args.workload == "disc":
         disc(args)
+        return
+    if args.workload == "fill":
+        fill_workload(args)
         return
     import paper_1208_0302_amd as g
     import synth_inputs as si
