@@ -45,7 +45,6 @@ __device__ __forceinline__ uint16_t f2bf(float f)
     u += 0x7FFFu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
 }
-__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 template <typename T>
 __device__ __forceinline__ T to_store(float x);
@@ -53,12 +52,6 @@ template <>
 __device__ __forceinline__ uint16_t to_store<uint16_t>(float x) { return f2bf(x); }
 template <>
 __device__ __forceinline__ float to_store<float>(float x) { return x; }
-template <typename T>
-__device__ __forceinline__ float load_f(T x);
-template <>
-__device__ __forceinline__ float load_f<uint16_t>(uint16_t x) { return bf2f(x); }
-template <>
-__device__ __forceinline__ float load_f<float>(float x) { return x; }
 
 __device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_d(float x)
@@ -501,8 +494,8 @@ __global__ void k_features(const float *obs, int64_t npix, int L, float *x)
         mx = fmaxf(mx, obs[p * 4 * L + j]);
     red[threadIdx.x] = mx;
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s)
+    for (int s = (int)blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
             red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
         __syncthreads();
     }
