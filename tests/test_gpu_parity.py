@@ -179,7 +179,8 @@ def test_ga_decode_exact():
 
 @pytest.mark.parametrize("pop,k,pc,pm", [(64, 4, 0.85, 0.05), (128, 4, 0.85, 0.05),
                                          (70, 1, 0.0, 0.3), (33, 8, 1.0, 0.0),
-                                         (2, 2, 0.5, 0.05), (200, 3, 0.85, 1.0)])
+                                         (2, 2, 0.5, 0.05), (200, 3, 0.85, 1.0),
+                                         (1024, 8, 0.85, 0.05)])
 @pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
 def test_ga_step_bit_exact(pop, k, pc, pm, dtype):
     npix = 6
@@ -242,6 +243,59 @@ def test_fused_loop_equals_stepwise_composition(dtype, pop):
     gb = genes.cpu().numpy()[np.arange(len(e)), e]
     dec = oracle.decode(gb, si.PRIOR_LO, si.PRIOR_HI).astype(dtype)
     assert np.array_equal(fused["params"].cpu().numpy(), dec)
+
+
+def test_fused_loop_at_the_largest_population():
+    # GENESIS_MAX_POP = 1024 lanes: sixteen waves per workgroup
+    lines, grids, olines, truth, obs, sig = _problem("slit", 3, 14)
+    b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
+    cfg = g.GAConfig(pop=1024, generations=3, tournament_k=8, seed=4, init_mode=1,
+                     restart_every=2)
+    obs_t, sig_t = torch.tensor(obs, device=DEV), torch.tensor(sig, device=DEV)
+    fused = g.ga_invert(obs_t, sig_t, lines, grids, b, cfg, want_population=True)
+    genes = g.ga_init(3, cfg, b)
+    fit = g.ga_evaluate(genes, b, obs_t, sig_t, lines, grids)
+    for t in range(1, cfg.generations + 1):
+        if t - 1 > 0 and (t - 1) % cfg.restart_every == 0:
+            genes = g.ga_restart(genes, fit, cfg, t - 1)
+            fit = g.ga_evaluate(genes, b, obs_t, sig_t, lines, grids)
+        genes = g.ga_step(genes, fit, cfg, t, diagnostics=False)["genes"]
+        fit = g.ga_evaluate(genes, b, obs_t, sig_t, lines, grids)
+    assert torch.equal(fused["genes"], genes)
+    assert torch.equal(fused["fitness"], fit)
+
+
+def test_long_ragged_lines():
+    # 2 x 1001 samples (L = 2002, not a multiple of the 64-lane waves): the
+    # staged observation fills 32 KB of LDS; the loop equals its composition
+    # and its fitness is the oracle's chi-square of the decoded genes
+    lines, grids, olines = [], [], []
+    for ln in (si.FE6301, si.FE6302):
+        st, sp = si.grid(ln, 1001, half_width=0.6)
+        lines.append(g.line_from_terms(ln["lambda0"], ln["Jl"], ln["gl"], ln["Ju"], ln["gu"]))
+        grids.append(g.grid(st, sp, 1001))
+        olines.append(oracle.make_line(ln["lambda0"], ln["Jl"], ln["gl"], ln["Ju"], ln["gu"],
+                                       st, sp, 1001))
+    truth = si.draw_truth(3, 15)
+    obs = oracle.me_synth(truth, olines)
+    sig = si.sigma_for(truth)
+    obs = (obs + sig[:, :, None] * si.std_normal(obs.shape, 15)).astype(np.float32)
+    sig = sig.astype(np.float32)
+    b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
+    cfg = g.GAConfig(pop=64, generations=2, seed=6)
+    obs_t, sig_t = torch.tensor(obs, device=DEV), torch.tensor(sig, device=DEV)
+    fused = g.ga_invert(obs_t, sig_t, lines, grids, b, cfg, want_population=True)
+    genes, fit = _stepwise(obs_t, sig_t, lines, grids, b, cfg)
+    assert torch.equal(fused["genes"], genes) and torch.equal(fused["fitness"], fit)
+    par = oracle.decode(genes.cpu().numpy().reshape(-1, 9), si.PRIOR_LO,
+                        si.PRIOR_HI).reshape(3, 64, 9)
+    o64, s64 = obs.astype(np.float64), sig.astype(np.float64)
+    ref = oracle.chi2(par, o64, s64, olines)
+    L = obs.shape[-1]
+    models = oracle.me_synth(par.reshape(-1, 9), olines).reshape(3, 64, 4, L)
+    # FP32 accumulation over 2002 samples per Stokes parameter: 8x the slit row's allowance
+    tol = _chi2_tol(o64, models, s64, _ic(truth), 4 * L - 9, FWD_TOL_F32) + 8e-5 * ref
+    assert np.all(np.abs(fit.cpu().numpy() - ref) <= tol)
 
 
 def test_fitness_matches_oracle_on_decoded_genes():
