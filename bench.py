@@ -276,15 +276,22 @@ def proposal(args):
     torch.cuda.synchronize()
     pass_s = ev[0].elapsed_time(ev[1]) / reps / 1e3
     pass_flop = batch * MLP_TRAIN_FLOP
+    res = _heldout(args, g, si, net, lines, grids, b, stream, dev)
+    _proposal_report(args, g, si, batch, lr, wall, train_ms, losses, pass_flop, pass_s, *res)
 
-    # held-out comparison
+
+def _heldout(args, g, si, net, lines, grids, b, stream, dev):
+    """Initial-population strategies on held-out noisy pixels: median
+    chi-square and fraction at the target after G generations."""
+    import torch
     npix = args.heldout
     truth = si.draw_truth(npix, seed=123)
     obs = g.me_synth(torch.tensor(truth, dtype=torch.float32, device=dev), lines, grids)
     sig_np = si.sigma_for(truth)
-    obs += torch.tensor(sig_np[:, :, None] * si.std_normal(tuple(obs.shape), 123),
-                        dtype=torch.float32, device=dev)
     sig = torch.tensor(sig_np, dtype=torch.float32, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(123)
+    obs += sig[:, :, None] * torch.randn(obs.shape, generator=gen, device=dev)
     ei = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ei[0].record(stream)
     guess = net.predict(obs, grids, b)
@@ -292,15 +299,58 @@ def proposal(args):
     torch.cuda.synchronize()
     infer_ms = ei[0].elapsed_time(ei[1])
     target = args.chi2_target
-    # physics first guesses (weak-field, centre-of-gravity) for B, inclination
-    # and v_los, the parameters those approximations estimate; NaN elsewhere
-    obs64 = obs.double().contiguous()
-    sig64 = sig.double().contiguous()
+    wanted = args.strategies.split(",")
+    need_phys = any(w in ("physics", "polarity_box", "prefit_box", "physics_in_box")
+                    for w in wanted)
+    obs64 = obs.double().contiguous() if need_phys else None
+    sig64 = sig.double().contiguous() if need_phys else None
+    phys = box_pf = box_pol = None
+    box_stats = None
+    if need_phys:
+        phys, box_pf, box_pol, box_stats = _physics_inputs(g, si, obs64, sig64, lines, grids, b,
+                                                           truth, stream)
+    strategies = tuple((n, e) for n, e in (
+        ("random", {}),
+        ("seeded", dict(n_seeded=32, seed_jitter=512, seed_params=guess)),
+        ("physics", dict(n_seeded=32, seed_jitter=512, seed_params=phys)),
+        ("polarity_box", dict(pixel_bounds=box_pol)),
+        ("prefit_box", dict(pixel_bounds=box_pf)),
+        ("physics_in_box", dict(n_seeded=32, seed_jitter=512, seed_params=phys,
+                                pixel_bounds=box_pf)),
+        ("sobol", dict(init_mode=1)),
+        ("sobol_restart", dict(init_mode=1, restart_every=50))) if n in wanted)
+    table = []
+    for gens in (0, 10, 25, 50, 100, 150, 200):
+        row = {"generations": gens}
+        for name, extra in strategies:
+            cfg = g.GAConfig(pop=128, generations=gens, tournament_k=4, p_cross=0.85,
+                             p_mut=0.05, seed=7, **extra)
+            r = g.ga_invert(obs, sig, lines, grids, b, cfg)
+            c = r["chi2"].cpu().numpy()
+            row[name + "_median_chi2"] = float(np.median(c))
+            row[name + "_frac_at_target"] = float((c <= target).mean())
+            if gens == 200:
+                ref = g.me_refine_f64(obs.double(), sig.double(), lines, grids, b,
+                                      r["params"].double().contiguous(), REFINE_ITERS)
+                cr = ref["chi2"].cpu().numpy()
+                row[name + "_refined_median_chi2"] = float(np.median(cr))
+                row[name + "_refined_frac_at_target"] = float((cr <= target).mean())
+                del ref
+            del r
+        table.append(row)
+        print("proposal: G=%d %s" % (gens, row), file=sys.stderr, flush=True)
+    return table, strategies, box_stats, infer_ms, guess, truth, npix
+
+
+def _physics_inputs(g, si, obs64, sig64, lines, grids, b, truth, stream):
+    """Physics first guesses (weak-field, centre-of-gravity) for B,
+    inclination and v_los (NaN elsewhere), and the per-pixel search boxes:
+    the V-lobe polarity alone, and with the ranges of the non-magnetic
+    pre-fit (Sec. 5.3, 5.5)."""
+    import torch
     guess9 = g.me_first_guess(obs64, lines, grids, b)
     phys = guess9.clone()
     phys[:, [2, 4, 5, 6, 7, 8]] = float("nan")
-    # per-pixel search boxes: the V-lobe polarity alone, and with the ranges
-    # of the non-magnetic pre-fit (Sec. 5.3, 5.5)
     eb = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     eb[0].record(stream)
     pre = g.me_prefit_f64(obs64, sig64, lines, grids, b, guess9.double().contiguous(), 20)
@@ -321,33 +371,12 @@ def proposal(args):
                      (bp[:, 1, j] - bp[:, 0, j]) / (si.PRIOR_HI[j] - si.PRIOR_LO[j])))
                      for j in (1, 4, 5, 6, 8)}}
     print("proposal: search boxes %s" % box_stats, file=sys.stderr, flush=True)
-    strategies = (("random", {}),
-                  ("seeded", dict(n_seeded=32, seed_jitter=512, seed_params=guess)),
-                  ("physics", dict(n_seeded=32, seed_jitter=512, seed_params=phys)),
-                  ("polarity_box", dict(pixel_bounds=box_pol)),
-                  ("prefit_box", dict(pixel_bounds=box_pf)),
-                  ("physics_in_box", dict(n_seeded=32, seed_jitter=512, seed_params=phys,
-                                          pixel_bounds=box_pf)),
-                  ("sobol", dict(init_mode=1)),
-                  ("sobol_restart", dict(init_mode=1, restart_every=50)))
-    table = []
-    for gens in (0, 10, 25, 50, 100, 150, 200):
-        row = {"generations": gens}
-        for name, extra in strategies:
-            cfg = g.GAConfig(pop=128, generations=gens, tournament_k=4, p_cross=0.85,
-                             p_mut=0.05, seed=7, **extra)
-            r = g.ga_invert(obs, sig, lines, grids, b, cfg)
-            c = r["chi2"].cpu().numpy()
-            row[name + "_median_chi2"] = float(np.median(c))
-            row[name + "_frac_at_target"] = float((c <= target).mean())
-            if gens == 200:
-                ref = g.me_refine_f64(obs.double(), sig.double(), lines, grids, b,
-                                      r["params"].double().contiguous(), REFINE_ITERS)
-                cr = ref["chi2"].cpu().numpy()
-                row[name + "_refined_median_chi2"] = float(np.median(cr))
-                row[name + "_refined_frac_at_target"] = float((cr <= target).mean())
-        table.append(row)
-        print("proposal: G=%d %s" % (gens, row), file=sys.stderr, flush=True)
+    return phys, box_pf, box_pol, box_stats
+
+
+def _proposal_report(args, g, si, batch, lr, wall, train_ms, losses, pass_flop, pass_s, table,
+                     strategies, box_stats, infer_ms, guess, truth, npix):
+    target = args.chi2_target
 
     def first_reaching(name):
         for row in table:
@@ -375,6 +404,12 @@ def proposal(args):
                                                np.median(err, axis=0).round(4).tolist())),
            "chi2_target": target,
            "generations_to_median_target": {n: first_reaching(n) for n, _ in strategies},
+           # the first checkpoint at which each strategy's median chi-square is at or
+           # below the random population's after the last generation
+           "generations_to_random_final_median": {
+               n: next((row["generations"] for row in table
+                        if row[n + "_median_chi2"] <= table[-1]["random_median_chi2"]), None)
+               for n, _ in strategies} if any(n == "random" for n, _ in strategies) else None,
            "search_boxes": box_stats,
            "seeding_table": table,
            "roofline": {"bound": "mfma", "achieved": pass_flop / pass_s / 1e12,
@@ -584,6 +619,9 @@ def main():
                     help="disc: keep every n-th on-disc pixel of the 2048^2 map")
     ap.add_argument("--batch", type=int, default=1024, help="proposal: training batch")
     ap.add_argument("--heldout", type=int, default=16384, help="proposal: held-out pixels")
+    ap.add_argument("--strategies", default="random,seeded,physics,polarity_box,prefit_box,"
+                    "physics_in_box,sobol,sobol_restart",
+                    help="proposal: initial-population strategies to compare")
     ap.add_argument("--chi2-target", type=float, default=1.2,
                     help="proposal: reduced chi-square target")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
