@@ -320,23 +320,28 @@ def _heldout(args, g, si, net, lines, grids, b, stream, dev):
         ("sobol", dict(init_mode=1)),
         ("sobol_restart", dict(init_mode=1, restart_every=50))) if n in wanted)
     table = []
+    o64, s64 = obs.double(), sig.double()
     for gens in (0, 10, 25, 50, 100, 150, 200):
         row = {"generations": gens}
         for name, extra in strategies:
             cfg = g.GAConfig(pop=128, generations=gens, tournament_k=4, p_cross=0.85,
                              p_mut=0.05, seed=7, **extra)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record(stream)
             r = g.ga_invert(obs, sig, lines, grids, b, cfg)
+            ev[1].record(stream)
+            ref = g.me_refine_f64(o64, s64, lines, grids, b, r["params"].double().contiguous(),
+                                  REFINE_ITERS)
+            ev[2].record(stream)
             c = r["chi2"].cpu().numpy()
+            cr = ref["chi2"].cpu().numpy()
             row[name + "_median_chi2"] = float(np.median(c))
             row[name + "_frac_at_target"] = float((c <= target).mean())
-            if gens == 200:
-                ref = g.me_refine_f64(obs.double(), sig.double(), lines, grids, b,
-                                      r["params"].double().contiguous(), REFINE_ITERS)
-                cr = ref["chi2"].cpu().numpy()
-                row[name + "_refined_median_chi2"] = float(np.median(cr))
-                row[name + "_refined_frac_at_target"] = float((cr <= target).mean())
-                del ref
-            del r
+            row[name + "_refined_median_chi2"] = float(np.median(cr))
+            row[name + "_refined_frac_at_target"] = float((cr <= target).mean())
+            row[name + "_ga_ms"] = ev[0].elapsed_time(ev[1])
+            row[name + "_refine_ms"] = ev[1].elapsed_time(ev[2])
+            del ref, r
         table.append(row)
         print("proposal: G=%d %s" % (gens, row), file=sys.stderr, flush=True)
     return table, strategies, box_stats, infer_ms, guess, truth, npix
@@ -348,7 +353,10 @@ def _physics_inputs(g, si, obs64, sig64, lines, grids, b, truth, stream):
     the V-lobe polarity alone, and with the ranges of the non-magnetic
     pre-fit (Sec. 5.3, 5.5)."""
     import torch
+    ef = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ef[0].record(stream)
     guess9 = g.me_first_guess(obs64, lines, grids, b)
+    ef[1].record(stream)
     phys = guess9.clone()
     phys[:, [2, 4, 5, 6, 7, 8]] = float("nan")
     eb = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
@@ -363,7 +371,8 @@ def _physics_inputs(g, si, obs64, sig64, lines, grids, b, truth, stream):
     prefit_ms, box_ms = eb[0].elapsed_time(eb[1]), eb[1].elapsed_time(eb[2])
     bp = box_pf.cpu().numpy()
     inside = (truth >= bp[:, 0]) & (truth <= bp[:, 1])
-    box_stats = {"prefit_ms": prefit_ms, "search_box_ms": box_ms,
+    box_stats = {"first_guess_ms": ef[0].elapsed_time(ef[1]), "prefit_ms": prefit_ms,
+                 "search_box_ms": box_ms,
                  "polarity_restricted_frac": float(((bp[:, 1, 1] - bp[:, 0, 1]) <= 90.0).mean()),
                  "truth_inside_frac": {si.PARAM_NAMES[j]: float(inside[:, j].mean())
                                        for j in (1, 4, 5, 6, 8)},
@@ -372,6 +381,31 @@ def _physics_inputs(g, si, obs64, sig64, lines, grids, b, truth, stream):
                      for j in (1, 4, 5, 6, 8)}}
     print("proposal: search boxes %s" % box_stats, file=sys.stderr, flush=True)
     return phys, box_pf, box_pol, box_stats
+
+
+def _equal_accuracy(table, strategies, infer_ms, box_stats):
+    if not any(n == "random" for n, _ in strategies):
+        return None
+    # preparation each strategy needs before its search
+    fg = box_stats["first_guess_ms"] if box_stats else 0.0
+    pf = (box_stats["prefit_ms"] + box_stats["search_box_ms"]) if box_stats else 0.0
+    prep = {"seeded": infer_ms, "physics": fg,
+            "polarity_box": box_stats["search_box_ms"] if box_stats else 0.0,
+            "prefit_box": fg + pf, "physics_in_box": fg + pf}
+    last = table[-1]
+    goal = last["random_refined_frac_at_target"]
+    t_random = last["random_ga_ms"] + last["random_refine_ms"]
+    out = {"random_generations": last["generations"], "random_refined_frac_at_target": goal,
+           "random_ms": t_random}
+    for n, extra in strategies:
+        row = next((r for r in table if r[n + "_refined_frac_at_target"] >= goal), None)
+        if row is None:
+            out[n] = None
+            continue
+        t = row[n + "_ga_ms"] + row[n + "_refine_ms"] + prep.get(n, 0.0)
+        out[n] = {"generations": row["generations"], "ms": t, "speedup": t_random / t,
+                  "refined_frac_at_target": row[n + "_refined_frac_at_target"]}
+    return out
 
 
 def _proposal_report(args, g, si, batch, lr, wall, train_ms, losses, pass_flop, pass_s, table,
@@ -406,6 +440,10 @@ def _proposal_report(args, g, si, batch, lr, wall, train_ms, losses, pass_flop, 
            "generations_to_median_target": {n: first_reaching(n) for n, _ in strategies},
            # the first checkpoint at which each strategy's median chi-square is at or
            # below the random population's after the last generation
+           # equal accuracy: the fewest generations after which GA + refinement puts
+           # at least as many pixels at the target as the random population's last
+           # checkpoint does, and the time ratio (the seeded forms include inference)
+           "equal_accuracy_vs_random": _equal_accuracy(table, strategies, infer_ms, box_stats),
            "generations_to_random_final_median": {
                n: next((row["generations"] for row in table
                         if row[n + "_median_chi2"] <= table[-1]["random_median_chi2"]), None)
