@@ -233,7 +233,7 @@ def proposal(args):
     import synth_inputs as si
 
     dev = torch.device("cuda:0")
-    batch, lr = args.batch, 1e-3
+    batch, lr = args.batch, args.lr
     lines, grids = [], []
     for ln, n in si.line_set("slit"):
         start, step = si.grid(ln, n)
@@ -655,7 +655,8 @@ def main():
     ap.add_argument("--gens-per-step", type=int, default=10, help="serving: generations per launch")
     ap.add_argument("--disc-stride", type=int, default=16,
                     help="disc: keep every n-th on-disc pixel of the 2048^2 map")
-    ap.add_argument("--batch", type=int, default=1024, help="proposal: training batch")
+    ap.add_argument("--batch", type=int, default=4096, help="proposal: training batch")
+    ap.add_argument("--lr", type=float, default=2e-3, help="proposal: Adam learning rate")
     ap.add_argument("--heldout", type=int, default=16384, help="proposal: held-out pixels")
     ap.add_argument("--strategies", default="random,seeded,physics,polarity_box,prefit_box,"
                     "physics_in_box,sobol,sobol_restart",
