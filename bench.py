@@ -136,7 +136,8 @@ def serving(args):
     import synth_inputs as si
 
     dev = torch.device("cuda:0")
-    sched = si.serving_schedule(args.rate, args.window, seed=0)
+    sched = si.serving_schedule(args.rate, args.window, seed=0, median_px=args.tile_median,
+                                min_px=min(256, int(args.tile_median)))
     b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
     linesets = {}
     for name in ("slit", "slit1"):
@@ -157,7 +158,8 @@ def serving(args):
     torch.cuda.synchronize()
     print("serving: %d requests, %d pixels synthesised" % (len(reqs), sum(r["npix"] for r in reqs)),
           file=sys.stderr, flush=True)
-    sess = g.ServingSession(budget_bytes=200 * 10 ** 9, gens_per_step=args.gens_per_step)
+    sess = g.ServingSession(budget_bytes=200 * 10 ** 9, gens_per_step=args.gens_per_step,
+                            max_resident_pixels=args.max_resident_pixels)
     pending, lat, done_px, launches = {}, [], 0, 0
     nxt = 0
     t0 = time.perf_counter()
@@ -190,18 +192,48 @@ def serving(args):
     makespan = time.perf_counter() - t0
     sess.close()
     lat = np.array(lat)
+    # the plain GA on the same stream: a first-come-first-served loop that runs
+    # each request's ga_invert to completion before taking the next (the same
+    # results: each service result equals its standalone inversion)
+    lat_p, done_p = [], 0
+    t0 = time.perf_counter()
+    last = t0
+    for r in reqs:
+        now = time.perf_counter() - t0
+        if r["t"] > now:
+            time.sleep(r["t"] - now)
+        cfg = g.GAConfig(pop=128, generations=r["generations"], tournament_k=4,
+                         p_cross=0.85, p_mut=0.05, seed=r["seed"])
+        g.ga_invert(r["obs"], r["sig"], r["ls"], r["gs"], b, cfg, want_status=False)
+        torch.cuda.synchronize()
+        lat_p.append(time.perf_counter() - t0 - r["t"])
+        done_p += r["npix"]
+        if time.perf_counter() - last > 5.0:
+            last = time.perf_counter()
+            print("serving (plain loop): t=%.1f s, done %d" % (last - t0, len(lat_p)),
+                  file=sys.stderr, flush=True)
+    makespan_p = time.perf_counter() - t0
+    lat_p = np.array(lat_p)
     out = {"metric": METRIC + " (serving)", "value": done_px / makespan, "unit": "pixels/s",
            "n_gpus": 1, "steps": launches, "warmup": 0, "ms_per_step": makespan * 1e3 / launches,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic (Poisson request stream, truth from the priors)",
            "config": {"workload": "serving: Poisson %.2f req/s over %.0f s, tiles "
-                                  "clip(lognormal(ln 4096, 1.2), 256, 65536) px, 1-2 lines x 128, "
-                                  "G ~ U{50..300}, pop 128, %d generations per launch, 200 GB budget"
-                                  % (args.rate, args.window, args.gens_per_step),
+                                  "clip(lognormal(ln %g, 1.2), %d, 65536) px, 1-2 lines x 128, "
+                                  "G ~ U{50..300}, pop 128, %d generations per launch, 200 GB "
+                                  "budget, resident-pixel cap %s"
+                                  % (args.rate, args.window, args.tile_median,
+                                     min(256, int(args.tile_median)), args.gens_per_step,
+                                     args.max_resident_pixels or "none"),
                       "requests": len(reqs)},
            "latency_s_p50": float(np.percentile(lat, 50)),
            "latency_s_p99": float(np.percentile(lat, 99)),
-           "makespan_s": makespan}
+           "makespan_s": makespan,
+           "plain_fcfs": {"pixels_per_s": done_p / makespan_p,
+                          "latency_s_p50": float(np.percentile(lat_p, 50)),
+                          "latency_s_p99": float(np.percentile(lat_p, 99)),
+                          "makespan_s": makespan_p},
+           "speedup_vs_plain": (done_px / makespan) / (done_p / makespan_p)}
     print(json.dumps(out), flush=True)
 
 
@@ -653,6 +685,10 @@ def main():
     ap.add_argument("--rate", type=float, default=2.0, help="serving: requests per second")
     ap.add_argument("--window", type=float, default=20.0, help="serving: arrival window [s]")
     ap.add_argument("--gens-per-step", type=int, default=10, help="serving: generations per launch")
+    ap.add_argument("--tile-median", type=float, default=4096.0,
+                    help="serving: median tile size in pixels (lognormal, sigma 1.2)")
+    ap.add_argument("--max-resident-pixels", type=int, default=0,
+                    help="serving: resident-pixel cap of the admission (0: memory budget only)")
     ap.add_argument("--disc-stride", type=int, default=16,
                     help="disc: keep every n-th on-disc pixel of the 2048^2 map")
     ap.add_argument("--batch", type=int, default=4096, help="proposal: training batch")

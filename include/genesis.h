@@ -494,6 +494,15 @@ int gs_submit(void *session, const float *obs, const float *sigma, const float *
               const me_bounds *bounds, const ga_config *cfg, float *best_params,
               float *best_chi2, int32_t *status, uint64_t *request_id);
 int gs_step(void *session, void *stream);
+/* Admission by compute as well as memory: with max_pixels > 0 a queued request
+ * is admitted only while the resident pixels (plus its own) stay within
+ * max_pixels, or when nothing is resident.  Every resident request shares each
+ * launch, so admitting everything the memory budget allows makes all of them
+ * finish late when the device is already full; a cap near the pixels that
+ * fill the device (one workgroup each, about 2048 on 256 compute units) keeps
+ * completions close to arrival order while small tiles still share launches.
+ * 0 (the default) removes the cap.  Takes effect at the next gs_step. */
+int gs_set_max_resident_pixels(void *session, int64_t max_pixels);
 int gs_poll(void *session, uint64_t request_id, int32_t *done);
 int gs_cancel(void *session, uint64_t request_id);
 int gs_stats(void *session, int64_t *queued, int64_t *resident, size_t *bytes_in_use);

@@ -193,6 +193,7 @@ _SIGS = {
     "gs_submit": ([_vp, _vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _cp, _vp, _vp, _vp,
                    C.POINTER(C.c_uint64)], C.c_int),
     "gs_step": ([_vp, _vp], C.c_int),
+    "gs_set_max_resident_pixels": ([_vp, _i64], C.c_int),
     "gs_poll": ([_vp, C.c_uint64, C.POINTER(_i32)], C.c_int),
     "gs_cancel": ([_vp, C.c_uint64], C.c_int),
     "gs_stats": ([_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)],
@@ -570,11 +571,14 @@ class ServingSession:
     returns them.  Output tensors are allocated here and kept alive until the
     session is closed."""
 
-    def __init__(self, budget_bytes: int, gens_per_step: int = 10, device="cuda"):
+    def __init__(self, budget_bytes: int, gens_per_step: int = 10, device="cuda",
+                 max_resident_pixels: int = 0):
         self._h = _vp()
         self.device = torch.device(device)
         _check(lib().gs_create(int(budget_bytes), int(gens_per_step), C.byref(self._h)))
         self._req = {}
+        if max_resident_pixels:
+            _check(lib().gs_set_max_resident_pixels(self._h, int(max_resident_pixels)))
 
     def submit(self, obs, sigma, lines, grids, bnds: MeBounds, cfg: GAConfig, mu=None):
         npix = obs.shape[0]

@@ -193,6 +193,7 @@ struct Request {
 
 struct Session {
     size_t budget = 0, in_use = 0;
+    int64_t max_pixels = 0, pixels = 0;  // resident-pixel cap (0: none) and count
     int gens_per_step = 1;
     int device = 0;
     uint64_t next_id = 1;
@@ -292,6 +293,18 @@ int gs_submit(void *session, const float *obs, const float *sigma, const float *
     return ME_OK;
 }
 
+int gs_set_max_resident_pixels(void *session, int64_t max_pixels)
+{
+    auto *s = static_cast<Session *>(session);
+    if (!s)
+        return fail(ME_EINVAL, "session must not be NULL");
+    if (max_pixels < 0)
+        return fail(ME_EINVAL, "max_pixels must be >= 0");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->max_pixels = max_pixels;
+    return ME_OK;
+}
+
 int gs_step(void *session, void *stream)
 {
     auto *s = static_cast<Session *>(session);
@@ -304,14 +317,19 @@ int gs_step(void *session, void *stream)
         if ((*it)->cancel) {
             release(**it, st);
             s->in_use -= (*it)->bytes;
+            s->pixels -= (*it)->desc.npix;
             (*it)->state = kCancelled;
             it = s->resident.erase(it);
         } else {
             ++it;
         }
     }
-    // admission in arrival order while the budget allows
-    while (!s->queue.empty() && s->in_use + s->queue.front()->bytes <= s->budget) {
+    // admission in arrival order while the memory budget allows and, with a
+    // pixel cap, while the resident pixels stay within it (a request is
+    // always admitted into an empty session)
+    while (!s->queue.empty() && s->in_use + s->queue.front()->bytes <= s->budget &&
+           (s->max_pixels == 0 || s->resident.empty() ||
+            s->pixels + s->queue.front()->desc.npix <= s->max_pixels)) {
         auto r = s->queue.front();
         s->queue.pop_front();
         const size_t gb = (size_t)r->desc.npix * r->desc.ga.pop * GENESIS_NPAR * sizeof(uint16_t);
@@ -323,6 +341,7 @@ int gs_step(void *session, void *stream)
             return fail(ME_ENOMEM, "device allocation of %zu B failed", r->bytes);
         }
         s->in_use += r->bytes;
+        s->pixels += r->desc.npix;
         r->state = kResident;
         s->resident.push_back(r);
     }
@@ -373,6 +392,7 @@ int gs_step(void *session, void *stream)
             (void)hipEventRecord(r.done_ev, st);
             release(r, st);
             s->in_use -= r.bytes;
+            s->pixels -= r.desc.npix;
             r.state = kDone;
             it = s->resident.erase(it);
         } else {

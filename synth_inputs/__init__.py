@@ -150,10 +150,12 @@ def disc_mask(n: int = 2048, radius: float = 1024.0) -> np.ndarray:
     return (x - c) ** 2 + (y - c) ** 2 <= radius ** 2
 
 
-def serving_schedule(rate_per_s: float, window_s: float, seed: int):
+def serving_schedule(rate_per_s: float, window_s: float, seed: int, median_px: float = 4096.0,
+                     min_px: int = 256, max_px: int = 65536):
     """Poisson arrivals at `rate_per_s` over `window_s` seconds.  Each request:
-    tile pixels clip(lognormal(ln 4096, 1.2), 256, 65536), one line (6302.5)
-    or both lines with probability 1/2 each, generations uniform in 50..300.
+    tile pixels clip(lognormal(ln median_px, 1.2), min_px, max_px) (by default
+    the serving configuration's 4096, 256, 65536), one line (6302.5) or both
+    lines with probability 1/2 each, generations uniform in 50..300.
     Returns a list of dicts (t, npix, lines, generations, seed)."""
     rng = np.random.Generator(np.random.Philox(key=seed + 424242))
     t = 0.0
@@ -163,7 +165,7 @@ def serving_schedule(rate_per_s: float, window_s: float, seed: int):
         t += rng.exponential(1.0 / rate_per_s)
         if t > window_s:
             break
-        npix = int(np.clip(np.round(rng.lognormal(np.log(4096.0), 1.2)), 256, 65536))
+        npix = int(np.clip(np.round(rng.lognormal(np.log(median_px), 1.2)), min_px, max_px))
         lines = "slit" if rng.uniform() < 0.5 else "slit1"
         gens = int(rng.integers(50, 301))
         out.append(dict(t=t, npix=npix, lines=lines, generations=gens, seed=seed * 100003 + i))

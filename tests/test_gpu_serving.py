@@ -124,3 +124,31 @@ def test_budget_admission_and_cancel():
     with pytest.raises(g.GenesisError):
         sess.submit(big[2], big[3], big[0], big[1], b, cfg)
     sess.close()
+
+
+def test_pixel_cap_admission():
+    # a 250-pixel cap: requests of 200, 150 and 100 pixels are admitted one
+    # or two at a time in arrival order (a request is always admitted into an
+    # empty session, even above the cap), with unchanged results
+    b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
+    cfg = g.GAConfig(pop=64, generations=10, seed=21)
+    rs = [_request("tiny", 200, 31), _request("tiny", 150, 32), _request("tiny", 100, 33),
+          _request("tiny", 300, 34)]
+    sess = g.ServingSession(budget_bytes=1 << 30, gens_per_step=5, max_resident_pixels=250)
+    ids = [sess.submit(r[2], r[3], r[0], r[1], b, cfg) for r in rs]
+    sess.step()
+    st = sess.stats()
+    assert st["resident"] == 1 and st["queued"] == 3        # 200 + 150 > 250
+    resident_seen = []
+    for _ in range(100):
+        sess.step()
+        torch.cuda.synchronize()
+        resident_seen.append(sess.stats()["resident"])
+        if all(sess.poll(i) == 1 for i in ids):
+            break
+    assert max(resident_seen) <= 2                          # 150 + 100 fit together
+    for r, rid in zip(rs, ids):
+        assert _same(sess.result(rid), _alone(r, cfg)), rid
+    assert g.lib().gs_set_max_resident_pixels(sess._h, -1) != 0
+    assert g.lib().gs_set_max_resident_pixels(None, 10) != 0
+    sess.close()
