@@ -946,6 +946,7 @@ struct RefineArgs {
 };
 
 struct RefineShared {
+    Model<double> jm[GENESIS_NPAR + 1];  // models at x and at x + h_k e_k (Jacobian)
     double x[GENESIS_NPAR], xt[GENESIS_NPAR];
     double red[kRefineThreads / 64][kNA + GENESIS_NPAR + 1];
     double tot[kNA + GENESIS_NPAR + 1];
@@ -1139,15 +1140,21 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
 #pragma unroll
             for (int j = 0; j < GENESIS_NPAR; ++j)
                 hx[j] = (sh.x[j] + h <= 1.0) ? h : -h;
+            // the model at x (slot 0) and the nine forward-difference models
+            // (slot k + 1), set up once per iteration for every wavelength
+            if (tid <= GENESIS_NPAR) {
+                double xk[GENESIS_NPAR];
+#pragma unroll
+                for (int j = 0; j < GENESIS_NPAR; ++j)
+                    xk[j] = sh.x[j] + (j == tid - 1 ? hx[j] : 0.0);
+                model_from_x(a, xk, mu, sh.jm[tid]);
+            }
+            __syncthreads();
             for (int l = 0; l < a.ls.nlines; ++l) {
                 const DevLine<double> &ln = a.ls.l[l];
                 for (int jj = tid; jj < ln.nlam; jj += kRefineThreads) {
                     double M0[4], Jm[GENESIS_NPAR][4];
-                    {
-                        Model<double> m;
-                        model_from_x(a, sh.x, mu, m);
-                        stokes_at(m, ln, jj, M0[0], M0[1], M0[2], M0[3]);
-                    }
+                    stokes_at(sh.jm[0], ln, jj, M0[0], M0[1], M0[2], M0[3]);
                     for (int k = 0; k < GENESIS_NPAR; ++k) {
                         if (!((a.free_mask >> k) & 1u)) {
                             // a held parameter: zero column, so A_kk = 0 and d_k = 0
@@ -1156,14 +1163,8 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
                                 Jm[k][s4] = 0.0;
                             continue;
                         }
-                        double xk[GENESIS_NPAR];
-#pragma unroll
-                        for (int j = 0; j < GENESIS_NPAR; ++j)
-                            xk[j] = sh.x[j] + (j == k ? hx[k] : 0.0);
-                        Model<double> m;
-                        model_from_x(a, xk, mu, m);
                         double Mk[4];
-                        stokes_at(m, ln, jj, Mk[0], Mk[1], Mk[2], Mk[3]);
+                        stokes_at(sh.jm[k + 1], ln, jj, Mk[0], Mk[1], Mk[2], Mk[3]);
 #pragma unroll
                         for (int s4 = 0; s4 < 4; ++s4)
                             Jm[k][s4] = (Mk[s4] - M0[s4]) / (hx[k] * sig[s4]);
