@@ -1153,8 +1153,10 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
             for (int l = 0; l < a.ls.nlines; ++l) {
                 const DevLine<double> &ln = a.ls.l[l];
                 for (int jj = tid; jj < ln.nlam; jj += kRefineThreads) {
-                    double M0[4], Jm[GENESIS_NPAR][4];
-                    stokes_at(sh.jm[0], ln, jj, M0[0], M0[1], M0[2], M0[3]);
+                    double M0[4], Jm[GENESIS_NPAR][4], pr0[6];
+                    profiles_at(sh.jm[0], ln, jj, pr0);
+                    unno_rachkovsky(sh.jm[0], pr0[0], pr0[1], pr0[2], pr0[3], pr0[4], pr0[5],
+                                    M0[0], M0[1], M0[2], M0[3]);
                     for (int k = 0; k < GENESIS_NPAR; ++k) {
                         if (!((a.free_mask >> k) & 1u)) {
                             // a held parameter: zero column, so A_kk = 0 and d_k = 0
@@ -1164,7 +1166,15 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
                             continue;
                         }
                         double Mk[4];
-                        stokes_at(sh.jm[k + 1], ln, jj, Mk[0], Mk[1], Mk[2], Mk[3]);
+                        if (k == 0 || (k >= 3 && k <= 5)) {
+                            // B, v_los, Doppler width, damping: new profiles
+                            stokes_at(sh.jm[k + 1], ln, jj, Mk[0], Mk[1], Mk[2], Mk[3]);
+                        } else {
+                            // the angles, eta0, S0, S1 leave every Voigt argument
+                            // unchanged: the base profiles, the perturbed algebra
+                            unno_rachkovsky(sh.jm[k + 1], pr0[0], pr0[1], pr0[2], pr0[3],
+                                            pr0[4], pr0[5], Mk[0], Mk[1], Mk[2], Mk[3]);
+                        }
 #pragma unroll
                         for (int s4 = 0; s4 < 4; ++s4)
                             Jm[k][s4] = (Mk[s4] - M0[s4]) / (hx[k] * sig[s4]);

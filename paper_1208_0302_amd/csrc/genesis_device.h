@@ -428,18 +428,31 @@ __device__ __forceinline__ void synthesize(const Model<Real> &m, const DevLines<
 
 // Stokes vector of one model at sample jj of one line (used where each lane
 // owns a wavelength instead of an individual).
+// The three group profiles (h, l of blue, pi, red) of one model at sample jj.
+// They depend on the model only through B, v_los, the Doppler width and the
+// damping.
 template <typename Real>
-__device__ __forceinline__ void stokes_at(const Model<Real> &m, const DevLine<Real> &ln, int jj,
-                                          Real &I, Real &Q, Real &U, Real &V)
+__device__ __forceinline__ void profiles_at(const Model<Real> &m, const DevLine<Real> &ln, int jj,
+                                            Real (&pr)[6])
 {
     const Real xb = (ln.off0 - m.vlos * ln.dop_kms) * m.inv_dop;
     const Real x0 = fma((Real)jj, ln.step * m.inv_dop, xb);
     const Real zb = ln.zee_G * m.B * m.inv_dop;
-    Real hb = 0, lb = 0, hp = 0, lp = 0, hr = 0, lr = 0;
-    group<-1>(m, ln, 0, ln.nb, x0, zb, hb, lb);
-    group<-1>(m, ln, ln.nb, ln.np, x0, zb, hp, lp);
-    group<-1>(m, ln, ln.nb + ln.np, ln.nr, x0, zb, hr, lr);
-    unno_rachkovsky(m, hb, lb, hp, lp, hr, lr, I, Q, U, V);
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        pr[i] = 0;
+    group<-1>(m, ln, 0, ln.nb, x0, zb, pr[0], pr[1]);
+    group<-1>(m, ln, ln.nb, ln.np, x0, zb, pr[2], pr[3]);
+    group<-1>(m, ln, ln.nb + ln.np, ln.nr, x0, zb, pr[4], pr[5]);
+}
+
+template <typename Real>
+__device__ __forceinline__ void stokes_at(const Model<Real> &m, const DevLine<Real> &ln, int jj,
+                                          Real &I, Real &Q, Real &U, Real &V)
+{
+    Real pr[6];
+    profiles_at(m, ln, jj, pr);
+    unno_rachkovsky(m, pr[0], pr[1], pr[2], pr[3], pr[4], pr[5], I, Q, U, V);
 }
 
 // chi-square accumulator against an observation staged in LDS as
