@@ -35,7 +35,8 @@ METRIC = "pixel inversions/s at fixed param accuracy; ME evals/s vs VALU peak; p
 # Unno-Rachkovsky closed form, chi-square terms).
 FLOP_PER_COMP_LAMBDA = 42
 FLOP_PER_LAMBDA = 71
-PEAK_FP32_VALU = 157.3e12     # MI355X published FP32 vector peak
+PEAK_FP32_VALU = 157.3e12     # MI355X published FP32 vector peak (reached without packed
+                              # instructions: two-operand VOP2 FP32 issues in about 2 cycles)
 PEAK_FP64_VALU = 78.6e12
 
 
@@ -52,7 +53,7 @@ TRAFFIC_SLIT_BYTES = 190.34e6
 TRAFFIC_SOURCES = ("csrc/genesis.hip", "csrc/genesis_device.h", "csrc/genesis_common.h",
                    "csrc/genesis_half.h", "csrc/voigt_rational.h", "csrc/weideman36.h",
                    "build.py")
-TRAFFIC_SOURCES_SHA256 = "22f962eff87bacd594fb5007f68b07692a492123ae2efad03043c6da20319b75"
+TRAFFIC_SOURCES_SHA256 = "c197e78cf0b23a5504ef5a427c88feb010a3ade54f7df5abf6a11c14810cb898"
 
 
 def kernel_sources_sha256():
@@ -802,7 +803,6 @@ def main():
     mean_s = float(ga_ms.mean()) / 1e3
     achieved = flop_launch / mean_s
     peak = PEAK_FP32_VALU if dt == torch.float32 else PEAK_FP64_VALU
-    unpacked = PEAK_FP64_VALU            # non-packed FP32 issue rate equals the FP64 rate
     out = {
         "metric": METRIC,
         "value": npix * args.steps / wall,
@@ -830,9 +830,7 @@ def main():
                      "traffic": (TRAFFIC_SLIT_BYTES if w["name"] == "slit" and dt == torch.float32
                                  and kernel_sources_sha256() == TRAFFIC_SOURCES_SHA256 else None),
                      "kernel": "k_ga_invert<%s>" % ("float" if dt == torch.float32 else "double"),
-                     "flop_per_eval": fpe, "evals_per_launch": evals,
-                     "peak_unpacked_fp32": unpacked / 1e12,
-                     "frac_unpacked": achieved / unpacked},
+                     "flop_per_eval": fpe, "evals_per_launch": evals},
     }
     if not args.no_cpu_baseline:
         import oracle

@@ -18,7 +18,8 @@ ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libgenesis_hip.so")
 SRCS = [os.path.join(HERE, "csrc", f) for f in ("genesis.hip", "serving.hip", "mlp.hip")]
 DEPS = SRCS + [os.path.join(HERE, "csrc", f) for f in
-               ("genesis_device.h", "genesis_common.h", "voigt_rational.h", "weideman36.h")] + \
+               ("genesis_device.h", "genesis_common.h", "genesis_half.h", "voigt_rational.h",
+                "voigt_rational_h.h", "weideman36.h")] + \
        [os.path.join(ROOT, "include", "genesis.h")]
 
 HIPCC_FLAGS = [

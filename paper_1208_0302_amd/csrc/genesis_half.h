@@ -3,24 +3,28 @@
 // lane per instruction (v_pk_fma_f16), with the reduced wavelength formed in
 // FP32, the Unno-Rachkovsky solution and the chi-square in FP32.
 //
-// The FP32 rational w = P(Z)/Q(Z) of the library (degree n-1 / n in
-// Z = a - i v, n = 7) gives, per individual, H = NH(u)/D(u) and
-// L = v NL(u)/D(u) with u = v^2, NH and NL of degree n-1 and D of degree n.
-// Their values span many orders of magnitude over the line window, beyond
-// FP16's range, so each is mapped to the compact variable t = 1/(1 + u/s)
-// in (0, 1]:
+// FP16 rounding alone limits the profiles to a few 1e-3, so this path uses
+// its own low-degree rational w = P(Z)/Q(Z) (voigt_rational_h.h: degree
+// n-1 / n in Z = a - i v with n = 4, error 1.5e-4 for every damping) rather
+// than the FP32 kernels' degree-7 one.  Per individual it gives
+// H = NH(u)/D(u) and L = v NL(u)/D(u) with u = v^2, NH and NL of degree n-1
+// and D of degree n.  Their values span many orders of magnitude over the
+// line window, beyond FP16's range, so each is mapped to the compact variable
+// t = 1/(1 + u/s) in (0, 1]:
 //   X~(t) = t^n X(s (1 - t)/t) = sum_k x_k s^k (1 - t)^k t^(n - k),
 // a degree-n polynomial in t whose ratio NH~/D~ is still H.  Numerators and
 // denominator are scaled by the same factor 1/sqrt(D~(0) D~(1)), which keeps
-// every coefficient and value of the three polynomials within about 10^(+-3)
-// for damping a <= 1.  Per component and pair of wavelengths: 2 mixed-precision
-// FMAs for v, 1 multiply and 1 FMA for t's denominator, 2 reciprocals, 3 n
-// Horner FMAs, 2 reciprocals for 1/D~, and 4 operations to accumulate the
+// every coefficient within [1.4e-3, 4.3] for damping a <= 1 (normal FP16
+// numbers).  Per component and pair of wavelengths: 2 mixed-precision FMAs
+// for v, 1 multiply and 1 FMA for t's denominator, 2 reciprocals, 3 n Horner
+// FMAs, 2 reciprocals for 1/D~, and 4 operations to accumulate the
 // strength-weighted H and L.  Simulated worst error of the FP16 evaluation
-// over a in [0, 1], |v| <= 300: about 4e-3 in H and L (1 = H(0, 0)).
+// over a in [0, 1], |v| <= 300: about 4.4e-3 in H and 2.7e-3 in L
+// (1 = H(0, 0)).
 #pragma once
 
 #include "genesis_device.h"
+#include "voigt_rational_h.h"
 
 namespace genesis {
 
@@ -30,7 +34,15 @@ typedef half_t h2 __attribute__((ext_vector_type(2)));
 constexpr double kHalfS = 2.0;        // u scale of the compact variable
 constexpr double kHalfMaxDamping = 1.0;
 
-constexpr int kDegH = kNQ - 1;  // degree n of D in u
+constexpr int kHNP = GENESIS_VRH_NP, kHNQ = GENESIS_VRH_NQ;  // coefficient counts of P, Q
+constexpr int kHEP = (kHNP + 1) / 2, kHOP = kHNP / 2;          // even / odd parts in u
+constexpr int kHEQ = (kHNQ + 1) / 2, kHOQ = kHNQ / 2;
+constexpr double kVrhP[kHNP] = {GENESIS_VRH_P_INIT};
+constexpr double kVrhQ[kHNQ] = {GENESIS_VRH_Q_INIT};
+constexpr ShiftTable<kHNP> kShiftPH = shift_table(kVrhP);
+constexpr ShiftTable<kHNQ> kShiftQH = shift_table(kVrhQ);
+
+constexpr int kDegH = kHNQ - 1;  // degree n of D in u
 constexpr int kNH = kDegH + 1;   // coefficients per compact polynomial
 
 // T[m][k]: coefficient of t^m contributed by u^k, s^k C(k, i) (-1)^i with
@@ -77,37 +89,51 @@ __device__ __forceinline__ void to_t(const float (&x)[kNH], float (&y)[kNH])
 
 __device__ __forceinline__ VoigtH voigt_setup_h(double a)
 {
-    const VoigtF32 f = voigt_setup_f32(a);
+    // P(a - i v) = EP(u) - i v OP(u), Q(a - i v) = EQ(u) - i v OQ(u), as in
+    // the FP32 setup but from the degree-4 table
+    float ep[kHEP], op[kHOP], eq[kHEQ], oq[kHOQ];
+#pragma unroll
+    for (int m = 0; m < kHEP; ++m)
+        ep[m] = ((m & 1) ? -1.0f : 1.0f) * shifted(kShiftPH, 2 * m, a);
+#pragma unroll
+    for (int m = 0; m < kHOP; ++m)
+        op[m] = ((m & 1) ? -1.0f : 1.0f) * shifted(kShiftPH, 2 * m + 1, a);
+#pragma unroll
+    for (int m = 0; m < kHEQ; ++m)
+        eq[m] = ((m & 1) ? -1.0f : 1.0f) * shifted(kShiftQH, 2 * m, a);
+#pragma unroll
+    for (int m = 0; m < kHOQ; ++m)
+        oq[m] = ((m & 1) ? -1.0f : 1.0f) * shifted(kShiftQH, 2 * m + 1, a);
     float nh[kNH] = {}, nl[kNH] = {}, d[kNH] = {};
     // NH = EP EQ + u OP OQ, NL = EP OQ - OP EQ, D = EQ^2 + u OQ^2
 #pragma unroll
-    for (int i = 0; i < kEP; ++i) {
+    for (int i = 0; i < kHEP; ++i) {
 #pragma unroll
-        for (int j = 0; j < kEQ; ++j)
-            nh[i + j] = fmaf(f.ep[i], f.eq[j], nh[i + j]);
+        for (int j = 0; j < kHEQ; ++j)
+            nh[i + j] = fmaf(ep[i], eq[j], nh[i + j]);
 #pragma unroll
-        for (int j = 0; j < kOQ; ++j)
-            nl[i + j] = fmaf(f.ep[i], f.oq[j], nl[i + j]);
+        for (int j = 0; j < kHOQ; ++j)
+            nl[i + j] = fmaf(ep[i], oq[j], nl[i + j]);
     }
 #pragma unroll
-    for (int i = 0; i < kOP; ++i) {
+    for (int i = 0; i < kHOP; ++i) {
 #pragma unroll
-        for (int j = 0; j < kOQ; ++j)
-            nh[i + j + 1] = fmaf(f.op[i], f.oq[j], nh[i + j + 1]);
+        for (int j = 0; j < kHOQ; ++j)
+            nh[i + j + 1] = fmaf(op[i], oq[j], nh[i + j + 1]);
 #pragma unroll
-        for (int j = 0; j < kEQ; ++j)
-            nl[i + j] = fmaf(-f.op[i], f.eq[j], nl[i + j]);
+        for (int j = 0; j < kHEQ; ++j)
+            nl[i + j] = fmaf(-op[i], eq[j], nl[i + j]);
     }
 #pragma unroll
-    for (int i = 0; i < kEQ; ++i)
+    for (int i = 0; i < kHEQ; ++i)
 #pragma unroll
-        for (int j = 0; j < kEQ; ++j)
-            d[i + j] = fmaf(f.eq[i], f.eq[j], d[i + j]);
+        for (int j = 0; j < kHEQ; ++j)
+            d[i + j] = fmaf(eq[i], eq[j], d[i + j]);
 #pragma unroll
-    for (int i = 0; i < kOQ; ++i)
+    for (int i = 0; i < kHOQ; ++i)
 #pragma unroll
-        for (int j = 0; j < kOQ; ++j)
-            d[i + j + 1] = fmaf(f.oq[i], f.oq[j], d[i + j + 1]);
+        for (int j = 0; j < kHOQ; ++j)
+            d[i + j + 1] = fmaf(oq[i], oq[j], d[i + j + 1]);
     float th[kNH], tl[kNH], td[kNH];
     to_t(nh, th);
     to_t(nl, tl);

@@ -1,15 +1,15 @@
 """Reduced-precision synthesis (packed FP16 profiles, FP32 Unno-Rachkovsky
 and chi-square) through the C ABI, against the FP64 oracle.
 
-Tolerance.  The FP16 evaluation of the compactified rational is good to
-4e-3 in H and 3.2e-3 in L (H(0,0) = 1) for damping <= 1, worst case over
-|v| <= 300; each group profile is a strength-weighted mean of components
-(weights summing to 1), so the group profiles carry the same absolute error.
-Propagated through the Unno-Rachkovsky solution this moved the Stokes vector
-by at most 7e-4 Ic in an FP16-rounding simulation of 60 random models; the
-per-sample bound used here is 5e-3 Ic, with an RMS bound of 1e-3 Ic over all
-samples, and the chi-square against noisy data must stay within a few per cent
-of the FP32 path's."""
+Tolerance.  The FP16 path evaluates its own degree-4 rational (error 1.5e-4
+for every damping); in FP16 the compactified evaluation is good to 4.4e-3 in
+H and 2.7e-3 in L (H(0,0) = 1) for damping <= 1, worst case over |v| <= 300
+in an FP16-rounding simulation.  Each group profile is a strength-weighted
+mean of components (weights summing to 1), so the group profiles carry the
+same absolute error; the test prints the deviation it measures in the
+Stokes vector.  The per-sample bound used here is 5e-3 Ic,
+with an RMS bound of 1e-3 Ic over all samples, and the chi-square against
+noisy data must stay within a few per cent of the FP32 path's."""
 import numpy as np
 import pytest
 import torch
@@ -65,6 +65,7 @@ def test_fp16_synthesis_matches_oracle(kind, nlam):
     ic = (p[:, 7] + mu * p[:, 8])[:, None, None]
     err = np.abs(got.cpu().numpy() - ref) / ic
     assert np.isfinite(err).all()
+    print("%s/%s: max %.2e Ic, rms %.2e Ic" % (kind, nlam, err.max(), np.sqrt((err ** 2).mean())))
     assert err.max() <= TOL_MAX, err.max()
     assert np.sqrt((err ** 2).mean()) <= TOL_RMS
     # odd sample counts: the last wavelength is synthesised alone
