@@ -472,7 +472,22 @@ struct InvertArgs : SynLines<SYN>, FillArgs<Real, FILL> {
     Real *best_params, *best_chi2, *final_fitness;
     int32_t *status;
     uint16_t *final_genes;
+    // > 0 when every workgroup of the launch is resident at once: the number
+    // of CUs, the dispatch stride between workgroups that share a CU
+    int32_t prio_mate;
 };
+
+// Issue priority of the calling wave, 0 (lowest) to 3; the instruction takes
+// an immediate, so the four values are four branches (uniform per wave).
+__device__ __forceinline__ void set_issue_priority(int r)
+{
+    switch (r & 3) {
+    case 0: __builtin_amdgcn_s_setprio(0); break;
+    case 1: __builtin_amdgcn_s_setprio(1); break;
+    case 2: __builtin_amdgcn_s_setprio(2); break;
+    default: __builtin_amdgcn_s_setprio(3); break;
+    }
+}
 
 // The whole of Algorithm 1 for one pixel per workgroup: the population
 // lives in LDS (two buffers: parents and children), lane i owns
@@ -542,6 +557,14 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN, FILL> 
         // only the replaced lanes to evaluate
         bool eval = active, restarted = false;
         for (int t = 0;;) {
+            // In a launch that is resident all at once, a SIMD issues oldest
+            // first, so the first-dispatched workgroups run ahead and finish
+            // early and the launch ends on SIMDs holding one or two waves.
+            // Rotating the issue priority among the workgroups that share a
+            // CU every generation keeps their progress even.  It changes the
+            // issue order only, never a result.
+            if (a.prio_mate > 0)
+                set_issue_priority(t + (int)blockIdx.x + (int)blockIdx.x / a.prio_mate);
             // evaluate generation t (each lane reads only its own genes)
             if (eval) {
                 if constexpr (FILL) {
@@ -1362,6 +1385,21 @@ int step_impl(const uint16_t *genes_in, const Real *fitness, int64_t npix, const
     return check_launch("ga_step");
 }
 
+// The number of CUs when all `nblocks` workgroups of `kernel` fit on the
+// device at once (occupancy at this block size and LDS), else 0.  A failed
+// query only turns the priority rotation off.
+int single_round_stride(const void *kernel, int block, size_t lds, int64_t nblocks)
+{
+    int dev = 0, ncu = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, lds) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return ncu > 0 && per_cu > 0 && nblocks <= (int64_t)ncu * per_cu ? ncu : 0;
+}
+
 template <typename Real, int SYN, bool FILL = false>
 int invert_impl(const Real *obs, const Real *sigma, const Real *mu, int64_t npix,
                 const me_line *lines, const me_grid *grids, int nlines, const me_bounds *bounds,
@@ -1411,6 +1449,8 @@ int invert_impl(const Real *obs, const Real *sigma, const Real *mu, int64_t npix
     a.final_fitness = final_fitness;
     if constexpr (SYN == GENESIS_SYNTH_FP16)
         pack_lines_h(a.ls, a.lh);
+    a.prio_mate = single_round_stride((const void *)k_ga_invert<Real, SYN, FILL>,
+                                      block_for_pop(cfg->pop), lds, npix);
     hipLaunchKernelGGL((k_ga_invert<Real, SYN, FILL>), dim3(grid_for(npix)),
                        dim3(block_for_pop(cfg->pop)), lds, as_stream(stream), a);
     return check_launch("ga_invert");
