@@ -53,7 +53,7 @@ TRAFFIC_SLIT_BYTES = 204.12e6
 TRAFFIC_SOURCES = ("csrc/genesis.hip", "csrc/genesis_device.h", "csrc/genesis_common.h",
                    "csrc/genesis_half.h", "csrc/voigt_rational.h", "csrc/weideman36.h",
                    "build.py")
-TRAFFIC_SOURCES_SHA256 = "b0e2dfb4c44b18a5614eefc224491ed3afb1b09d5b62d96357e3939e8c4e9ad0"
+TRAFFIC_SOURCES_SHA256 = "03882eacb494f62294dd370ce4cfd1b3c06fd3fde2fc50384c29072c383536cd"
 
 
 def kernel_sources_sha256():

@@ -14,8 +14,8 @@
 //   X~(t) = t^n X(s (1 - t)/t) = sum_k x_k s^k (1 - t)^k t^(n - k),
 // a degree-n polynomial in t whose ratio NH~/D~ is still H.  Numerators and
 // denominator are scaled by the same factor 1/sqrt(D~(0) D~(1)), which keeps
-// every coefficient within [1.4e-3, 4.3] for damping a <= 1 (normal FP16
-// numbers).  Per component and pair of wavelengths: 2 mixed-precision FMAs
+// every coefficient at most 4.3 in magnitude for damping a <= 1, so FP16
+// rounds each by at most 2e-3.  Per component and pair of wavelengths: 2 mixed-precision FMAs
 // for v, 1 multiply and 1 FMA for t's denominator, 2 reciprocals, 3 n Horner
 // FMAs, 2 reciprocals for 1/D~, and 4 operations to accumulate the
 // strength-weighted H and L.  Simulated worst error of the FP16 evaluation
