@@ -340,6 +340,25 @@ def test_loop_determinism_pixel_base_and_status():
     assert r0["params"].shape == (0, 9)
 
 
+def test_issue_priority_rotation_leaves_results_unchanged():
+    # A launch with more pixels than the device holds at once (16,384 one-wave
+    # workgroups against 256 CUs x 16) keeps the default issue priority; one
+    # that fits (256 pixels) rotates it every generation.  Priority orders
+    # instruction issue only, so every pixel's result is the same either way.
+    lines, grids, _ = _setup("tiny")
+    npix = 16384
+    truth = si.draw_truth(npix, 31)
+    obs = g.me_synth(torch.tensor(truth, dtype=torch.float32, device=DEV), lines, grids)
+    sig = torch.tensor(si.sigma_for(truth), dtype=torch.float32, device=DEV)
+    b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
+    cfg = g.GAConfig(pop=64, generations=3, seed=7)
+    big = g.ga_invert(obs, sig, lines, grids, b, cfg, want_population=True)
+    part = g.ga_invert(obs[:256].contiguous(), sig[:256].contiguous(), lines, grids, b, cfg,
+                       want_population=True)
+    for k in ("genes", "params", "chi2", "status"):
+        assert torch.equal(part[k], big[k][:256]), k
+
+
 def test_loop_generation_zero_is_the_initial_population():
     lines, grids, olines, truth, obs, sig = _problem("tiny", 3, 6)
     b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
