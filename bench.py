@@ -705,9 +705,8 @@ def main():
                          "HBM byte counters can be scaled against a kernel of known traffic")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU; pixels are independent, so N GPUs would "
-              "each invert their own share (see the design notes). Run with --gpus 1.",
-              file=sys.stderr)
+        print("bench.py measures one GPU: pixels are independent, so N GPUs would each invert "
+              "their own share of the map. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
