@@ -113,3 +113,17 @@ def test_fp16_compact_coefficients_are_small():
         w = wofz(v + 1j * a)
         assert np.abs(H - w.real).max() < 2e-4 and np.abs(L - w.imag).max() < 2e-4
     assert hi <= 4.3, hi
+
+
+@pytest.mark.parametrize("n,name,pre", [(7, "voigt_rational.h", "GENESIS_VR"),
+                                        (4, "voigt_rational_h.h", "GENESIS_VRH")])
+def test_tables_come_from_the_generator(n, name, pre):
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "gen_voigt_rational", os.path.join(CSRC, "gen_voigt_rational.py"))
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    m, p, q = gen.fit(n)
+    ph, qh, mh = _table(name, pre)
+    assert np.allclose(p, ph, rtol=1e-9, atol=0) and np.allclose(q, qh, rtol=1e-9, atol=0)
+    assert m == pytest.approx(mh, rel=1e-5)
