@@ -127,3 +127,24 @@ def test_tables_come_from_the_generator(n, name, pre):
     ph, qh, mh = _table(name, pre)
     assert np.allclose(p, ph, rtol=1e-9, atol=0) and np.allclose(q, qh, rtol=1e-9, atol=0)
     assert m == pytest.approx(mh, rel=1e-5)
+
+
+def test_weideman_table_of_the_fp64_kernels():
+    # w(z) = r (2 p(Z) r + 1/sqrt(pi)), r = 1/(L - i z), Z = (L + i z) r,
+    # p(Z) = sum c_n Z^n (Weideman 1994, N = 36), as the FP64 kernels evaluate it
+    text = open(os.path.join(CSRC, "weideman36.h")).read()
+    n = int(re.search(r"#define GENESIS_WD_N (\d+)", text).group(1))
+    WL = float(re.search(r"#define GENESIS_WD_L (\S+)", text).group(1))
+    c = np.array([float(x) for x in
+                  re.findall(r"[-+]?\d\.\d+e[-+]\d+", text[text.index("genesis_wd_c"):])])
+    assert n == 36 and len(c) == n
+    worst = 0.0
+    v = np.linspace(-60, 60, 24001)
+    for a in (0.0, 1e-4, 0.01, 0.1, 0.5, 1.0, 2.0, 5.0):
+        z = v + 1j * a
+        r = 1.0 / (WL - 1j * z)
+        Z = (WL + 1j * z) * r
+        p = np.polyval(c[::-1], Z)
+        w = r * (2.0 * p * r + 1.0 / np.sqrt(np.pi))
+        worst = max(worst, np.abs(w - wofz(z)).max())
+    assert worst < 1e-13, worst
