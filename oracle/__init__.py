@@ -23,7 +23,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _SRC = [os.path.join(_HERE, f) for f in ("oracle_me.c", "oracle_ga.c", "oracle_lm.c",
-                                          "oracle_fill.c")]
+                                          "oracle_fill.c", "oracle_unc.c")]
 _LOCK = threading.Lock()
 _LIB = None
 
@@ -87,6 +87,7 @@ _u16p = C.POINTER(C.c_uint16)
 _i32p = C.POINTER(C.c_int32)
 _u32p = C.POINTER(C.c_uint32)
 _linep = C.POINTER(Line)
+OBJECTIVE = C.CFUNCTYPE(C.c_double, C.POINTER(C.c_double), C.c_void_p)
 
 
 def lib():
@@ -127,11 +128,22 @@ def lib():
                                            C.c_int, C.c_int, _dp, _dp, _i32p, _u16p, _dp]
             L.oracle_ga_invert.restype = C.c_int
             L.oracle_lm_refine.argtypes = [_dp, _dp, _dp, C.c_int64, _linep, C.c_int, _dp, _dp,
-                                           _dp, C.c_int, _dp, _dp, _i32p, _dp]
+                                           _dp, C.c_int, _dp, _dp, _i32p]
             L.oracle_lm_refine.restype = C.c_int
             L.oracle_lm_fit.argtypes = [_dp, _dp, _dp, C.c_int64, _linep, C.c_int, _dp, _dp,
-                                        _dp, C.c_int, C.c_uint32, _dp, _dp, _i32p, _dp]
+                                        _dp, C.c_int, C.c_uint32, _dp, _dp, _i32p]
             L.oracle_lm_fit.restype = C.c_int
+            L.oracle_uncertainty.argtypes = [_dp, _dp, _dp, C.c_int64, _linep, C.c_int, _dp,
+                                             _dp, _dp, _dp, C.c_uint32, _dp, _dp, _dp, _dp]
+            L.oracle_uncertainty.restype = C.c_int
+            L.oracle_population_steps.argtypes = [_u16p, _dp, C.c_int64, C.c_int, _dp, _dp,
+                                                  _dp, _dp]
+            L.oracle_population_steps.restype = C.c_int
+            L.oracle_sec6_hessian.argtypes = [OBJECTIVE, C.c_void_p, C.c_int, _dp, _dp, _i32p,
+                                              _dp, _dp]
+            L.oracle_sec6_hessian.restype = C.c_int
+            L.oracle_sec6_sigmas.argtypes = [_dp, _i32p, C.c_double, C.c_int, _dp]
+            L.oracle_sec6_sigmas.restype = C.c_int
             L.oracle_fill_profile.argtypes = [_linep, C.POINTER(FillLine), C.c_double,
                                               C.c_double, _dp]
             L.oracle_fill_profile.restype = C.c_int
@@ -409,9 +421,8 @@ def chi2_fill(params, obs, sigma, lines, fill, mu=None):
 
 
 def lm_refine(obs, sigma, lines, lo, hi, params_in, iterations, mu=None, free_mask=0x1FF):
-    """FP64 Levenberg-Marquardt refinement; returns dict(params, chi2, iters,
-    sigma): sigma [npix, 9] are the Sec. 6 uncertainties at the result.  Only
-    the parameters in free_mask (bit j = parameter j) are adjusted."""
+    """FP64 Levenberg-Marquardt refinement; returns dict(params, chi2, iters).
+    Only the parameters in free_mask (bit j = parameter j) are adjusted."""
     o = _f64(obs)
     s = _f64(sigma)
     npix = o.shape[0]
@@ -421,16 +432,88 @@ def lm_refine(obs, sigma, lines, lo, hi, params_in, iterations, mu=None, free_ma
     po = np.empty((npix, NPAR), np.float64)
     co = np.empty(npix, np.float64)
     it = np.empty(npix, np.int32)
-    sg = np.empty((npix, NPAR), np.float64)
     arr, lp = _lines_array(lines)
     m = None if mu is None else _f64(np.broadcast_to(mu, (npix,)))
     rc = lib().oracle_lm_fit(_ptr(o, _dp), _ptr(s, _dp), None if m is None else _ptr(m, _dp),
                              npix, lp, len(lines), _ptr(lo, _dp), _ptr(hi, _dp),
                              _ptr(p0, _dp), int(iterations), int(free_mask), _ptr(po, _dp),
-                             _ptr(co, _dp), _ptr(it, _i32p), _ptr(sg, _dp))
+                             _ptr(co, _dp), _ptr(it, _i32p))
     if rc != 0:
         raise ValueError("oracle_lm_fit rejected its arguments")
-    return dict(params=po, chi2=co, iters=it, sigma=sg)
+    return dict(params=po, chi2=co, iters=it)
+
+
+def uncertainty(obs, sigma, lines, lo, hi, p_opt, steps, mu=None, free_mask=0x1FF):
+    """Sec. 6 uncertainties at p_opt [npix, 9] from initial steps [npix, 9];
+    returns dict(sigma, hess, hess_err, steps) (see oracle_unc.c)."""
+    o = _f64(obs)
+    s = _f64(sigma)
+    npix = o.shape[0]
+    q = _f64(p_opt).reshape(npix, NPAR)
+    h = _f64(steps).reshape(npix, NPAR)
+    lo = _f64(lo)
+    hi = _f64(hi)
+    sg = np.empty((npix, NPAR), np.float64)
+    H = np.empty((npix, NPAR, NPAR), np.float64)
+    He = np.empty((npix, NPAR, NPAR), np.float64)
+    hu = np.empty((npix, NPAR), np.float64)
+    arr, lp = _lines_array(lines)
+    m = None if mu is None else _f64(np.broadcast_to(mu, (npix,)))
+    rc = lib().oracle_uncertainty(_ptr(o, _dp), _ptr(s, _dp), None if m is None else _ptr(m, _dp),
+                                  npix, lp, len(lines), _ptr(lo, _dp), _ptr(hi, _dp),
+                                  _ptr(q, _dp), _ptr(h, _dp), int(free_mask), _ptr(sg, _dp),
+                                  _ptr(H, _dp), _ptr(He, _dp), _ptr(hu, _dp))
+    if rc != 0:
+        raise ValueError("oracle_uncertainty rejected its arguments")
+    return dict(sigma=sg, hess=H, hess_err=He, steps=hu)
+
+
+def population_steps(genes, fitness, lo, hi, p_opt):
+    """Sec. 6 initial steps [npix, 9] from a final population genes [npix,
+    pop, 9] (uint16), fitness [npix, pop]."""
+    g = np.ascontiguousarray(genes, np.uint16)
+    npix, pop = g.shape[0], g.shape[1]
+    f = _f64(fitness).reshape(npix, pop)
+    q = _f64(p_opt).reshape(npix, NPAR)
+    out = np.empty((npix, NPAR), np.float64)
+    rc = lib().oracle_population_steps(_ptr(g, _u16p), _ptr(f, _dp), npix, pop,
+                                       _ptr(_f64(lo), _dp), _ptr(_f64(hi), _dp), _ptr(q, _dp),
+                                       _ptr(out, _dp))
+    if rc != 0:
+        raise ValueError("oracle_population_steps rejected its arguments")
+    return out
+
+
+def sec6_hessian(f, p, h, active=None):
+    """The Sec. 6 Hessian (same tableaux) of a Python objective f(p) of n <= 9
+    variables at p with initial steps h; returns (H, error estimates)."""
+    n = len(p)
+    q = _f64(p)
+    hh = _f64(h)
+    act = np.ones(n, np.int32) if active is None else np.ascontiguousarray(active, np.int32)
+    H = np.empty((n, n), np.float64)
+    He = np.empty((n, n), np.float64)
+
+    def cb(ptr, ctx):
+        return float(f(np.ctypeslib.as_array(ptr, shape=(n,)).copy()))
+    fn = OBJECTIVE(cb)
+    rc = lib().oracle_sec6_hessian(fn, None, n, _ptr(q, _dp), _ptr(hh, _dp), _ptr(act, _i32p),
+                                   _ptr(H, _dp), _ptr(He, _dp))
+    if rc != 0:
+        raise ValueError("oracle_sec6_hessian rejected its arguments")
+    return H, He
+
+
+def sec6_sigmas(H, active, chi2, M):
+    """sigma_j = sqrt([H^-1]_jj chi2 / M) over the active parameters of a 9 x 9 H."""
+    Hm = _f64(H).reshape(NPAR, NPAR)
+    act = np.ascontiguousarray(active, np.int32)
+    out = np.empty(NPAR, np.float64)
+    rc = lib().oracle_sec6_sigmas(_ptr(Hm, _dp), _ptr(act, _i32p), float(chi2), int(M),
+                                  _ptr(out, _dp))
+    if rc != 0:
+        raise ValueError("oracle_sec6_sigmas rejected its arguments")
+    return out
 
 
 PREFIT_FREE = 0x1F8   # v_los, Doppler width, damping, eta0, S0, S1

@@ -169,15 +169,40 @@ int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, i
 int oracle_lm_refine(const double *obs, const double *sigma, const double *mu, int64_t npix,
                      const oracle_line *lines, int nlines, const double *lo, const double *hi,
                      const double *params_in, int iterations, double *params_out,
-                     double *chi2_out, int32_t *iters_done, double *sigma_params);
+                     double *chi2_out, int32_t *iters_done);
 
 /* The same fit with only the parameters in free_mask (bit j = parameter j)
  * adjusted; the others keep their (clamped) starting values. */
 int oracle_lm_fit(const double *obs, const double *sigma, const double *mu, int64_t npix,
                   const oracle_line *lines, int nlines, const double *lo, const double *hi,
                   const double *params_in, int iterations, uint32_t free_mask,
-                  double *params_out, double *chi2_out, int32_t *iters_done,
-                  double *sigma_params);
+                  double *params_out, double *chi2_out, int32_t *iters_done);
+
+/* Sec. 6 uncertainties at p_opt [npix][9] (see oracle_unc.c): initial steps
+ * steps [npix][9] (parameter units; e.g. oracle_population_steps), bounded
+ * there as described; free_mask as for oracle_lm_fit.  Outputs sigma_out
+ * [npix][9]; hess, hess_err [npix][9][9] (the symmetrised Hessian of the
+ * merit function and the tableaux' error estimates) and steps_used [npix][9]
+ * may be NULL.  Returns 0 or -1 (empty bounds, no free parameter). */
+int oracle_uncertainty(const double *obs, const double *sigma, const double *mu, int64_t npix,
+                       const oracle_line *lines, int nlines, const double *lo, const double *hi,
+                       const double *p_opt, const double *steps, uint32_t free_mask,
+                       double *sigma_out, double *hess, double *hess_err, double *steps_used);
+
+/* Initial steps of Sec. 6 from a final population: genes [npix][pop][9],
+ * fitness [npix][pop] -> steps [npix][9], the RMS deviation from p_opt over
+ * the best max(2, pop/4) individuals (all of them if pop < 2). */
+int oracle_population_steps(const uint16_t *genes, const double *fitness, int64_t npix, int pop,
+                            const double *lo, const double *hi, const double *p_opt,
+                            double *steps);
+
+/* The same Hessian for any objective f of n <= 9 variables (for the pins),
+ * and the variances from a Hessian: sigma_j^2 = [H^-1]_jj chi2 / M over the
+ * active parameters (NaN inactive, +inf where H_jj = 0). */
+int oracle_sec6_hessian(double (*f)(const double *, void *), void *ctx, int n, const double *p,
+                        const double *h, const int32_t *active, double *hess, double *hess_err);
+int oracle_sec6_sigmas(const double *hess, const int32_t *active, double chi2, int M,
+                       double *out);
 
 /* Threads the OpenMP loops would use. */
 int oracle_num_threads(void);

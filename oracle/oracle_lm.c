@@ -19,19 +19,13 @@
  *   whole iteration fails.  lambda starts at 1e-3.
  *
  * A parameter outside free_mask (bit j = parameter j) is held: its Jacobian
- * column is zero, so it is treated like A_jj = 0 (d_j = 0, uncertainty
- * +infinity).  The non-magnetic pre-fit of Sec. 5.3 is this fit with B held
+ * column is zero, so it is treated like A_jj = 0 (d_j = 0).  The
+ * non-magnetic pre-fit of Sec. 5.3 is this fit with B held
  * at 0 (the model then does not depend on the two field angles) and v_los,
  * the Doppler width, damping, eta0, S0 and S1 free.
  *
- * Uncertainties (Sec. 6): sigma_j^2 = [H^-1]_jj chi2(p_opt) / M with H the
- * Hessian of the reduced chi-square at the refined optimum in its
- * Gauss-Newton form, H = (2/nu) J_p^T J_p (J_p the Jacobian of the weighted
- * residuals in parameter units, from the same forward differences), so
- * [H^-1]_jj = (nu/2) (hi_j - lo_j)^2 [A^-1]_jj with A the normalised-
- * coordinate J^T J.  A parameter the model does not depend on (A_jj = 0)
- * gets +infinity and is left out of the inverse of the others; a matrix
- * that is not positive definite gives NaN for every parameter.
+ * The uncertainties of Sec. 6 at the result are computed separately
+ * (oracle_unc.c).
  */
 #include "oracle.h"
 
@@ -145,17 +139,16 @@ static int cholesky_solve(double *M, const double *g, double *d)
 int oracle_lm_refine(const double *obs, const double *sigma, const double *mu, int64_t npix,
                      const oracle_line *lines, int nlines, const double *lo, const double *hi,
                      const double *params_in, int iterations, double *params_out,
-                     double *chi2_out, int32_t *iters_done, double *sigma_params)
+                     double *chi2_out, int32_t *iters_done)
 {
     return oracle_lm_fit(obs, sigma, mu, npix, lines, nlines, lo, hi, params_in, iterations,
-                         0x1ffu, params_out, chi2_out, iters_done, sigma_params);
+                         0x1ffu, params_out, chi2_out, iters_done);
 }
 
 int oracle_lm_fit(const double *obs, const double *sigma, const double *mu, int64_t npix,
                   const oracle_line *lines, int nlines, const double *lo, const double *hi,
                   const double *params_in, int iterations, uint32_t free_mask,
-                  double *params_out, double *chi2_out, int32_t *iters_done,
-                  double *sigma_params)
+                  double *params_out, double *chi2_out, int32_t *iters_done)
 {
     if (iterations < 0)
         return -1;
@@ -243,38 +236,6 @@ int oracle_lm_fit(const double *obs, const double *sigma, const double *mu, int6
             chi2_out[p] = c;
             if (iters_done)
                 iters_done[p] = it;
-            if (sigma_params) {
-                double A[NP * NP], g[NP];
-                normal_equations(x, lo, hi, m, lines, nlines, o, s, L, free_mask, m0, m1, J, A, g);
-                double *sg = sigma_params + p * NP;
-                int keep[NP];
-                for (int a = 0; a < NP; ++a)
-                    keep[a] = A[a * NP + a] != 0.0;
-                int ok = 1;
-                for (int k = 0; k < NP && ok; ++k) {
-                    if (!keep[k]) {
-                        sg[k] = INFINITY;
-                        continue;
-                    }
-                    double M[NP * NP], e[NP], y[NP];
-                    for (int a = 0; a < NP; ++a) {
-                        for (int b = 0; b < NP; ++b)
-                            M[a * NP + b] = (keep[a] && keep[b]) ? A[a * NP + b]
-                                                                  : (a == b ? 1.0 : 0.0);
-                        e[a] = a == k ? 1.0 : 0.0;
-                    }
-                    if (cholesky_solve(M, e, y) != 0) {
-                        ok = 0;
-                        break;
-                    }
-                    const double span = hi[k] - lo[k];
-                    const double nu = (double)(R - NP);
-                    sg[k] = sqrt(0.5 * nu * span * span * y[k] * c / (double)NP);
-                }
-                if (!ok)
-                    for (int k = 0; k < NP; ++k)
-                        sg[k] = NAN;
-            }
         }
         free(m0);
         free(m1);

@@ -95,73 +95,3 @@ def test_refine_bad_pixels_and_bad_arguments():
     assert np.isnan(r["chi2"][1]) and np.isfinite(r["chi2"][[0, 2]]).all()
     with pytest.raises(ValueError):
         oracle.lm_refine(obs, sig, lines, LO, LO, truth, 5)
-
-
-# ---- uncertainties (Sec. 6) ---------------------------------------------------
-
-def _tiny_lines():
-    import synth_inputs as si
-    return [oracle.make_line(l["lambda0"], l["Jl"], l["gl"], l["Ju"], l["gu"], *si.grid(l, n), n)
-            for l, n in si.line_set("tiny")]
-
-
-def _strong_truth(n, seed):
-    import synth_inputs as si
-    t = si.draw_truth(n, seed)
-    t[:, 0] = 1200.0 + 600.0 * np.arange(n) / max(n - 1, 1)
-    t[:, 1] = 35.0 + 10.0 * np.arange(n) % 90
-    t[:, 6] = 8.0
-    return t
-
-
-def test_uncertainty_matches_finite_difference_hessian():
-    """sigma_j^2 = [H^-1]_jj chi2 / M with H the Hessian of the reduced
-    chi-square: the oracle's Gauss-Newton H against a central-difference
-    Hessian of the chi-square itself, at the optimum of noisy data (the two
-    differ only by the residual-weighted curvature, a few per cent)."""
-    import synth_inputs as si
-    lines = _tiny_lines()
-    truth = _strong_truth(3, 8)
-    obs = oracle.me_synth(truth, lines)
-    sig = si.sigma_for(truth)
-    obs = obs + sig[:, :, None] * si.std_normal(obs.shape, 8)
-    r = oracle.lm_refine(obs, sig, lines, si.PRIOR_LO, si.PRIOR_HI, truth, 60)
-    span = si.PRIOR_HI - si.PRIOR_LO
-    M = 9
-    for p in range(3):
-        p0 = r["params"][p]
-        h = 2e-4 * span
-
-        def chi(q):
-            return oracle.chi2(q[None, None, :], obs[p:p + 1], sig[p:p + 1], lines)[0, 0]
-
-        H = np.empty((M, M))
-        for a in range(M):
-            for b in range(M):
-                ea = np.eye(M)[a] * h[a]
-                eb = np.eye(M)[b] * h[b]
-                H[a, b] = (chi(p0 + ea + eb) - chi(p0 + ea - eb) - chi(p0 - ea + eb)
-                           + chi(p0 - ea - eb)) / (4 * h[a] * h[b])
-        sfd = np.sqrt(np.diag(np.linalg.inv(H)) * r["chi2"][p] / M)
-        rel = np.abs(r["sigma"][p] - sfd) / sfd
-        assert np.all(np.isfinite(r["sigma"][p])) and np.all(r["sigma"][p] > 0)
-        assert np.all(rel < 0.15), rel
-
-
-def test_uncertainty_tracks_the_scatter_of_repeated_inversions():
-    """Monte Carlo: the textbook covariance (J_p^T J_p)^-1 that the formula
-    scales by (nu/2)(chi2/M) matches the scatter of refined parameters over
-    independent noise draws."""
-    import synth_inputs as si
-    lines = _tiny_lines()
-    truth = np.repeat(_strong_truth(1, 9), 120, axis=0)
-    clean = oracle.me_synth(truth, lines)
-    sig = si.sigma_for(truth)
-    obs = clean + sig[:, :, None] * si.std_normal(clean.shape, 19)
-    r = oracle.lm_refine(obs, sig, lines, si.PRIOR_LO, si.PRIOR_HI, truth, 60)
-    nu = 4 * 100 - 9
-    textbook = r["sigma"] * np.sqrt(2 * 9 / (nu * r["chi2"][:, None]))
-    pred = np.median(textbook, axis=0)
-    spread = r["params"].std(axis=0)
-    for j in (0, 1, 3, 4, 6):      # B, inclination, v_los, Doppler width, eta0
-        assert 0.75 < spread[j] / pred[j] < 1.33, (j, spread[j], pred[j])
