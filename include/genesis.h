@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define GENESIS_ABI_VERSION 2
+#define GENESIS_ABI_VERSION 4
 #define GENESIS_NPAR 9
 #define GENESIS_MAX_COMP 32   /* Zeeman components per line */
 #define GENESIS_MAX_LINES 4
@@ -364,16 +364,50 @@ int me_first_guess(const double *obs, const double *mu, int64_t npix, const me_l
  * outputs params_out [npix][9], chi2_out [npix] (FP64 model, same merit
  * function), iters_done [npix] (may be NULL).  Bounds need hi > lo for all
  * nine parameters.  Pixels with non-finite observations or sigma <= 0 give
- * NaN.  sigma_params [npix][9] (may be NULL): the uncertainties of Sec. 6,
- * sigma_j^2 = [H^-1]_jj chi2 / M (M = 9) with H the Hessian of the reduced
- * chi-square at the result in Gauss-Newton form (2/nu) J^T J (same forward
- * differences, one more Jacobian at the final model); +infinity for a
- * parameter the model does not depend on, NaN when J^T J is singular. */
+ * NaN.  The uncertainties of Sec. 6 at the result: me_uncertainty_f64. */
 int me_refine_f64(const double *obs, const double *sigma, const double *mu, int64_t npix,
                   const me_line *lines, const me_grid *grids, int32_t nlines,
                   const me_bounds *bounds, const double *params_in, int32_t iterations,
-                  double *params_out, double *chi2_out, int32_t *iters_done,
-                  double *sigma_params, void *stream);
+                  double *params_out, double *chi2_out, int32_t *iters_done, void *stream);
+
+/* Uncertainties of the fitted parameters (Sec. 6), FP64.  The Hessian H of
+ * the merit function (the Sec. 5 chi-square, reduced by nu = 4L - 9) at
+ * params_opt [npix][9] is the Jacobian of its gradient; both derivatives are
+ * central differences extrapolated to zero step in a Neville tableau
+ * (Ridders: steps h/1.4^k, k < 10, the entry of least estimated error, a
+ * component stops once its diagonal moves by twice that error), the
+ * gradient with one tableau per parameter, each Hessian column with one
+ * tableau per gradient component on the gradients at p +- t e_j; H is then
+ * symmetrised.  sigma_params [npix][9] = sqrt([H^-1]_jj chi2(p_opt) / M), M
+ * the number of parameters in free_mask (bit j = parameter j; others held).
+ * steps [npix][9] are the initial steps in parameter units (Sec. 6 takes
+ * them from the spread of the final population: ga_population_steps); each
+ * is bounded to [1e-4, 0.1] (hi - lo) and to half the distance to the
+ * nearer bound, and a parameter within 1e-4 (hi - lo) of a bound is held.
+ * Per parameter: NaN if held, +infinity if H_jj = 0 (the merit function does
+ * not depend on it; left out of the inverse), NaN for all when the rest of H
+ * is not positive definite; NaN for pixels with non-finite observations or
+ * parameters or sigma <= 0.  Optional outputs (may be NULL): hessian and
+ * hessian_err [npix][9][9] (H and the tableaux' error estimates; 0 in the
+ * rows and columns of held parameters), steps_used [npix][9].  About 1e4
+ * merit-function evaluations per pixel (once per pixel, after the search). */
+int me_uncertainty_f64(const double *obs, const double *sigma, const double *mu, int64_t npix,
+                       const me_line *lines, const me_grid *grids, int32_t nlines,
+                       const me_bounds *bounds, const double *params_opt, const double *steps,
+                       uint32_t free_mask, double *sigma_params, double *hessian,
+                       double *hessian_err, double *steps_used, void *stream);
+
+/* Initial steps of Sec. 6 from a final population (ga_invert's final_genes
+ * [npix][pop][9] and final_fitness [npix][pop]): steps [npix][9] = the
+ * root-mean-square deviation from params_opt [npix][9] of each parameter
+ * over the best max(2, pop/4) individuals (fitness order, NaN last, ties to
+ * the lower index; every individual if pop < 2), decoded in `bounds`. */
+int ga_population_steps(const uint16_t *genes, const float *fitness, int64_t npix, int32_t pop,
+                        const me_bounds *bounds, const double *params_opt, double *steps,
+                        void *stream);
+int ga_population_steps_f64(const uint16_t *genes, const double *fitness, int64_t npix,
+                            int32_t pop, const me_bounds *bounds, const double *params_opt,
+                            double *steps, void *stream);
 
 /* Non-magnetic pre-fit (Sec. 5.3): before the genetic search the paper fits
  * a non-magnetic model to the observed Stokes I by Levenberg-Marquardt and
@@ -487,7 +521,10 @@ int mlp_train(float *master, float *m, float *v, int32_t first_step, int32_t ste
  * queued request at once and a resident one at the next step.  All calls
  * on one session are serialised by a lock; calls of different sessions on
  * one device may overlap.  gs_submit returns ME_ENOMEM for a request larger
- * than the whole budget. */
+ * than the whole budget.  The budget counts only what the session owns (the
+ * resident populations), not the caller's input and output arrays.
+ * Each gs_step waits on the device for the session's previous step, on
+ * whatever stream that one ran, so steps may come on different streams. */
 int gs_create(size_t hbm_budget_bytes, int32_t gens_per_step, void **session);
 int gs_submit(void *session, const float *obs, const float *sigma, const float *mu, int64_t npix,
               const me_line *lines, const me_grid *grids, int32_t nlines,
@@ -505,7 +542,17 @@ int gs_step(void *session, void *stream);
 int gs_set_max_resident_pixels(void *session, int64_t max_pixels);
 int gs_poll(void *session, uint64_t request_id, int32_t *done);
 int gs_cancel(void *session, uint64_t request_id);
+/* Forget a request whose outputs are complete (gs_poll gave 1) or that was
+ * cancelled (-1): the session drops its record, after which its id is
+ * unknown; the caller may then reuse or free the request's arrays.  A
+ * long-running session must release what it has collected, or its records
+ * grow without bound.  ME_EBUSY while the request is queued, resident or
+ * still running on the device. */
+int gs_release(void *session, uint64_t request_id);
 int gs_stats(void *session, int64_t *queued, int64_t *resident, size_t *bytes_in_use);
+/* Number of requests the session still holds records of (queued, resident,
+ * and finished or cancelled but not yet released). */
+int gs_tracked(void *session, int64_t *n);
 int gs_destroy(void *session);
 
 #ifdef __cplusplus

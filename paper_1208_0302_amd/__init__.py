@@ -161,8 +161,12 @@ _SIGS = {
                    C.c_size_t, _vp], C.c_int),
     "ga_invert_f64": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _cp, _vp, _vp, _vp, _vp, _vp,
                        _vp, C.c_size_t, _vp], C.c_int),
-    "me_refine_f64": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _i32, _vp, _vp, _vp, _vp, _vp],
+    "me_refine_f64": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _i32, _vp, _vp, _vp, _vp],
                       C.c_int),
+    "me_uncertainty_f64": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _vp, C.c_uint32, _vp,
+                            _vp, _vp, _vp, _vp], C.c_int),
+    "ga_population_steps": ([_vp, _vp, _i64, _i32, _bp, _vp, _vp, _vp], C.c_int),
+    "ga_population_steps_f64": ([_vp, _vp, _i64, _i32, _bp, _vp, _vp, _vp], C.c_int),
     "me_first_guess": ([_vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _vp], C.c_int),
     "me_synth_fill": ([_vp, _vp, _i64, _lp, _gp, _i32, _vp, C.POINTER(MeFill), _vp, _vp],
                       C.c_int),
@@ -196,12 +200,15 @@ _SIGS = {
     "gs_set_max_resident_pixels": ([_vp, _i64], C.c_int),
     "gs_poll": ([_vp, C.c_uint64, C.POINTER(_i32)], C.c_int),
     "gs_cancel": ([_vp, C.c_uint64], C.c_int),
+    "gs_release": ([_vp, C.c_uint64], C.c_int),
     "gs_stats": ([_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)],
                  C.c_int),
+    "gs_tracked": ([_vp, C.POINTER(C.c_int64)], C.c_int),
     "gs_destroy": ([_vp], C.c_int),
 }
 
 EXPORTED = tuple(_SIGS)
+ABI_VERSION = 4
 STRUCTS = (("me_line", MeLine), ("me_grid", MeGrid), ("me_bounds", MeBounds),
            ("ga_config", GaConfigC), ("me_fill", MeFill))
 
@@ -224,6 +231,10 @@ def lib():
                 f = getattr(L, name)
                 f.argtypes = args
                 f.restype = res
+            if L.genesis_abi_version() != ABI_VERSION:
+                raise RuntimeError(
+                    "libgenesis_hip.so has ABI version %d, this binding expects %d; rebuild "
+                    "the library from these sources" % (L.genesis_abi_version(), ABI_VERSION))
             # a struct laid out differently here than in the library would
             # hand the device garbage pointers: refuse to run instead
             for which, (sname, struct) in enumerate(STRUCTS):
@@ -498,11 +509,9 @@ def me_first_guess(obs, lines, grids, bnds: MeBounds, mu=None):
     return out
 
 
-def me_refine_f64(obs, sigma, lines, grids, bnds: MeBounds, params_in, iterations=50, mu=None,
-                  want_sigma=False):
+def me_refine_f64(obs, sigma, lines, grids, bnds: MeBounds, params_in, iterations=50, mu=None):
     """FP64 Levenberg-Marquardt refinement of params_in [npix, 9]; returns a
-    dict(params, chi2, iters[, sigma]).  obs, sigma, mu and params_in are
-    float64; want_sigma adds the Sec. 6 uncertainties [npix, 9]."""
+    dict(params, chi2, iters).  obs, sigma, mu and params_in are float64."""
     npix = obs.shape[0]
     L = total_samples(grids)
     _dev(obs, torch.float64, "obs", (npix, 4, L))
@@ -513,14 +522,57 @@ def me_refine_f64(obs, sigma, lines, grids, bnds: MeBounds, params_in, iteration
     res = dict(params=torch.empty((npix, NPAR), dtype=torch.float64, device=dev),
                chi2=torch.empty((npix,), dtype=torch.float64, device=dev),
                iters=torch.empty((npix,), dtype=torch.int32, device=dev))
-    if want_sigma:
-        res["sigma"] = torch.empty((npix, NPAR), dtype=torch.float64, device=dev)
     la, ga, nl = _lines(lines, grids)
     _check(lib().me_refine_f64(_ptr(obs), _ptr(sigma), _ptr(mu), npix, la, ga, nl,
                                C.byref(bnds), _ptr(params_in), int(iterations),
                                _ptr(res["params"]), _ptr(res["chi2"]), _ptr(res["iters"]),
-                               _ptr(res.get("sigma")), _stream(obs)))
+                               _stream(obs)))
     return res
+
+
+def me_uncertainty_f64(obs, sigma, lines, grids, bnds: MeBounds, params_opt, steps, mu=None,
+                       free_mask=0x1FF, want_hessian=False):
+    """Sec. 6 uncertainties [npix, 9] at params_opt [npix, 9] from initial
+    steps [npix, 9] (e.g. ga_population_steps); returns dict(sigma, steps[,
+    hessian, hessian_err]).  All float64."""
+    npix = obs.shape[0]
+    L = total_samples(grids)
+    _dev(obs, torch.float64, "obs", (npix, 4, L))
+    _dev(sigma, torch.float64, "sigma", (npix, 4))
+    _dev(mu, torch.float64, "mu", (npix,))
+    _dev(params_opt, torch.float64, "params_opt", (npix, NPAR))
+    _dev(steps, torch.float64, "steps", (npix, NPAR))
+    dev = obs.device
+    res = dict(sigma=torch.empty((npix, NPAR), dtype=torch.float64, device=dev),
+               steps=torch.empty((npix, NPAR), dtype=torch.float64, device=dev))
+    if want_hessian:
+        res["hessian"] = torch.empty((npix, NPAR, NPAR), dtype=torch.float64, device=dev)
+        res["hessian_err"] = torch.empty((npix, NPAR, NPAR), dtype=torch.float64, device=dev)
+    la, ga, nl = _lines(lines, grids)
+    _check(lib().me_uncertainty_f64(_ptr(obs), _ptr(sigma), _ptr(mu), npix, la, ga, nl,
+                                    C.byref(bnds), _ptr(params_opt), _ptr(steps),
+                                    int(free_mask), _ptr(res["sigma"]), _ptr(res.get("hessian")),
+                                    _ptr(res.get("hessian_err")), _ptr(res["steps"]),
+                                    _stream(obs)))
+    return res
+
+
+def ga_population_steps(genes, fitness, bnds: MeBounds, params_opt):
+    """Sec. 6 initial steps [npix, 9] (float64) from a final population:
+    genes [npix, pop, 9] uint16, fitness [npix, pop] float32 or float64,
+    params_opt [npix, 9] float64."""
+    npix, pop = genes.shape[0], genes.shape[1]
+    _dev(genes, torch.uint16, "genes", (npix, pop, NPAR))
+    _dev(params_opt, torch.float64, "params_opt", (npix, NPAR))
+    if fitness.dtype not in (torch.float32, torch.float64):
+        raise TypeError("fitness must be float32 or float64")
+    _dev(fitness, fitness.dtype, "fitness", (npix, pop))
+    out = torch.empty((npix, NPAR), dtype=torch.float64, device=genes.device)
+    f = {torch.float32: lib().ga_population_steps,
+         torch.float64: lib().ga_population_steps_f64}[fitness.dtype]
+    _check(f(_ptr(genes), _ptr(fitness), npix, pop, C.byref(bnds), _ptr(params_opt), _ptr(out),
+             _stream(genes)))
+    return out
 
 
 def me_prefit_f64(obs, sigma, lines, grids, bnds: MeBounds, params_in, iterations=30, mu=None):
@@ -568,8 +620,10 @@ class ServingSession:
     submit() queues a tile and returns its id; step() admits what fits in the
     memory budget and advances every resident tile by `gens_per_step`
     generations; poll() tells when a tile's outputs are ready; result()
-    returns them.  Output tensors are allocated here and kept alive until the
-    session is closed."""
+    returns them and releases the request (the session then holds no
+    reference to its tensors); release() forgets a cancelled request.  The
+    input tensors of a request are kept alive here until then, because the
+    device reads them until the request finishes."""
 
     def __init__(self, budget_bytes: int, gens_per_step: int = 10, device="cuda",
                  max_resident_pixels: int = 0):
@@ -595,7 +649,8 @@ class ServingSession:
         _check(lib().gs_submit(self._h, _ptr(obs), _ptr(sigma), _ptr(mu), npix, la, ga, nl,
                                C.byref(bnds), C.byref(c), _ptr(out["params"]), _ptr(out["chi2"]),
                                _ptr(out["status"]), C.byref(rid)))
-        # keep the inputs alive with the outputs until the session ends
+        # the device reads the inputs and writes the outputs until the request
+        # is done: keep them alive until it is released
         self._req[rid.value] = dict(out=out, keep=(obs, sigma, mu, cfg.seed_params,
                                                     cfg.pixel_bounds))
         return rid.value
@@ -616,8 +671,30 @@ class ServingSession:
         _check(lib().gs_stats(self._h, C.byref(q), C.byref(r), C.byref(b)))
         return dict(queued=q.value, resident=r.value, bytes_in_use=b.value)
 
+    def tracked(self) -> int:
+        """Requests the library still holds records of."""
+        n = C.c_int64()
+        _check(lib().gs_tracked(self._h, C.byref(n)))
+        return int(n.value)
+
+    def held(self) -> int:
+        """Requests whose tensors this object still keeps alive."""
+        return len(self._req)
+
+    def release(self, rid):
+        """Forget a finished (poll() == 1) or cancelled (-1) request and drop
+        the references to its tensors."""
+        _check(lib().gs_release(self._h, C.c_uint64(rid)))
+        self._req.pop(rid, None)
+
     def result(self, rid):
-        return self._req[rid]["out"]
+        """Outputs of a finished request (poll() must have given 1); the
+        request is released."""
+        if self.poll(rid) != 1:
+            raise GenesisError(ME_EBUSY, "request %d is not finished" % rid)
+        out = self._req[rid]["out"]
+        self.release(rid)
+        return out
 
     def close(self):
         if self._h:

@@ -963,7 +963,6 @@ struct RefineArgs {
     double lo[GENESIS_NPAR], span[GENESIS_NPAR];
     double *params_out, *chi2_out;
     int32_t *iters_done;
-    double *sigma_out;  // [npix][9] uncertainties, or nullptr
     uint32_t free_mask;  // bit j: parameter j is adjusted (held otherwise)
     int32_t zero_field;  // start (and, with bit 0 clear, hold) B at 0
 };
@@ -1066,44 +1065,6 @@ __device__ bool cholesky9(double (&M)[GENESIS_NPAR][GENESIS_NPAR], const double 
     return true;
 }
 
-// Uncertainties (Sec. 6): sigma_j^2 = [H^-1]_jj chi2 / M, H the Hessian of the
-// reduced chi-square at the refined optimum in Gauss-Newton form,
-// (2/nu) J_p^T J_p, so [H^-1]_jj = (nu/2) span_j^2 [A^-1]_jj for the
-// normalised-coordinate A = J^T J in sh.nrm.  A_jj = 0 gives +infinity and
-// leaves j out; a matrix that is not positive definite gives NaN.
-__device__ void refine_sigma(const RefineArgs &a, const RefineShared &sh, double inv_nu,
-                             double *out)
-{
-    double A[GENESIS_NPAR][GENESIS_NPAR];
-    int q = 0;
-    for (int i = 0; i < GENESIS_NPAR; ++i)
-        for (int j = i; j < GENESIS_NPAR; ++j, ++q)
-            A[i][j] = A[j][i] = sh.nrm[q];
-    bool keep[GENESIS_NPAR];
-    for (int i = 0; i < GENESIS_NPAR; ++i)
-        keep[i] = A[i][i] != 0.0;
-    for (int i = 0; i < GENESIS_NPAR; ++i)
-        for (int j = 0; j < GENESIS_NPAR; ++j)
-            if (!(keep[i] && keep[j]))
-                A[i][j] = i == j ? 1.0 : 0.0;
-    const double chi2_nu = sh.chi2 * inv_nu;
-    for (int k = 0; k < GENESIS_NPAR; ++k) {
-        if (!keep[k]) {
-            out[k] = INFINITY;
-            continue;
-        }
-        double e[GENESIS_NPAR], y[GENESIS_NPAR];
-        for (int i = 0; i < GENESIS_NPAR; ++i)
-            e[i] = i == k ? 1.0 : 0.0;
-        if (!cholesky9(A, e, y)) {
-            for (int i = 0; i < GENESIS_NPAR; ++i)
-                out[i] = NAN;
-            return;
-        }
-        out[k] = sqrt(0.5 / inv_nu * a.span[k] * a.span[k] * y[k] * chi2_nu / GENESIS_NPAR);
-    }
-}
-
 __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
 {
     code_shift<GENESIS_PAD_REFINE>();
@@ -1147,13 +1108,7 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
             __syncthreads();
         }
         int it = 0;
-        // one Jacobian per iteration; after the last one (iteration limit, or
-        // an iteration without an accepted trial) the normal matrix at the
-        // final x gives the uncertainties
-        for (;; ++it) {
-            const bool last = it >= a.iterations;
-            if (last && !a.sigma_out)
-                break;
+        for (; it < a.iterations; ++it) {
             // ---- Jacobian and normal equations
             double acc[kNA + GENESIS_NPAR];
 #pragma unroll
@@ -1226,7 +1181,7 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
             __syncthreads();
             // ---- damped trials
             bool accepted = false;
-            for (int trial = 0; trial < 10 && !last; ++trial) {
+            for (int trial = 0; trial < 10; ++trial) {
                 if (tid == 0) {
                     double Mx[GENESIS_NPAR][GENESIS_NPAR], g[GENESIS_NPAR], d[GENESIS_NPAR];
                     int q = 0;
@@ -1279,11 +1234,8 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
                 if (accepted)
                     break;
             }
-            if (accepted)
-                continue;
-            if (a.sigma_out && tid == 0)
-                refine_sigma(a, sh, inv_nu, a.sigma_out + p * GENESIS_NPAR);
-            break;
+            if (!accepted)
+                break;
         }
         if (tid < GENESIS_NPAR)
             a.params_out[p * GENESIS_NPAR + tid] = a.lo[tid] + a.span[tid] * sh.x[tid];
@@ -1484,8 +1436,8 @@ int invert_dispatch(const Real *obs, const Real *sigma, const Real *mu, int64_t 
 int refine_impl(const double *obs, const double *sigma, const double *mu, int64_t npix,
                 const me_line *lines, const me_grid *grids, int nlines, const me_bounds *bounds,
                 const double *params_in, int iterations, double *params_out, double *chi2_out,
-                int32_t *iters_done, double *sigma_params, void *stream,
-                uint32_t free_mask = 0x1ffu, bool zero_field = false)
+                int32_t *iters_done, void *stream, uint32_t free_mask = 0x1ffu,
+                bool zero_field = false)
 {
     RefineArgs a{};
     if (int rc = pack_lines(lines, grids, nlines, a.ls))
@@ -1521,7 +1473,6 @@ int refine_impl(const double *obs, const double *sigma, const double *mu, int64_
     a.params_out = params_out;
     a.chi2_out = chi2_out;
     a.iters_done = iters_done;
-    a.sigma_out = sigma_params;
     a.free_mask = free_mask;
     a.zero_field = zero_field ? 1 : 0;
     hipLaunchKernelGGL(k_refine_f64, dim3(grid_for(npix)), dim3(kRefineThreads), lds,
@@ -1932,11 +1883,10 @@ int me_first_guess(const double *obs, const double *mu, int64_t npix, const me_l
 int me_refine_f64(const double *obs, const double *sigma, const double *mu, int64_t npix,
                   const me_line *lines, const me_grid *grids, int32_t nlines,
                   const me_bounds *bounds, const double *params_in, int32_t iterations,
-                  double *params_out, double *chi2_out, int32_t *iters_done,
-                  double *sigma_params, void *stream)
+                  double *params_out, double *chi2_out, int32_t *iters_done, void *stream)
 {
     return refine_impl(obs, sigma, mu, npix, lines, grids, nlines, bounds, params_in, iterations,
-                       params_out, chi2_out, iters_done, sigma_params, stream);
+                       params_out, chi2_out, iters_done, stream);
 }
 
 int me_prefit_f64(const double *obs, const double *sigma, const double *mu, int64_t npix,
@@ -1949,7 +1899,7 @@ int me_prefit_f64(const double *obs, const double *sigma, const double *mu, int6
     // v_los, Doppler width, damping, eta0, S0, S1 free; B held at 0 (the angles
     // then do not enter the model)
     return refine_impl(obs, sigma, mu, npix, lines, grids, nlines, bounds, params_in, iterations,
-                       params_out, chi2_out, iters_done, nullptr, stream, 0x1f8u, true);
+                       params_out, chi2_out, iters_done, stream, 0x1f8u, true);
 }
 
 }  // extern "C"

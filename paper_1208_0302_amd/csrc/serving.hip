@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "genesis_common.h"
+#include "scheduler.h"
 
 namespace genesis {
 
@@ -180,26 +181,22 @@ __global__ __launch_bounds__(1024) void k_ga_advance(const ReqDesc *__restrict__
     }
 }
 
-enum State { kQueued = 0, kResident = 1, kDone = 2, kCancelled = 3 };
-
-struct Request {
-    uint64_t id = 0;
+// What the session keeps per request beside the scheduler's bookkeeping.
+struct Payload {
     ReqDesc desc{};
-    size_t bytes = 0;
-    int state = kQueued;
-    bool cancel = false;
     hipEvent_t done_ev = nullptr;
 };
+using Req = SchedReq<Payload>;
 
 struct Session {
-    size_t budget = 0, in_use = 0;
-    int64_t max_pixels = 0, pixels = 0;  // resident-pixel cap (0: none) and count
-    int gens_per_step = 1;
+    explicit Session(size_t budget, int gens) : sched(budget, gens) {}
+    Scheduler<Payload> sched;
     int device = 0;
-    uint64_t next_id = 1;
-    std::deque<std::shared_ptr<Request>> queue;
-    std::vector<std::shared_ptr<Request>> resident;
-    std::unordered_map<uint64_t, std::shared_ptr<Request>> all;
+    // every launch of the session waits for the previous one, whatever stream
+    // it came on, so memory freed stream-ordered after a launch is never
+    // still in use by a kernel of an earlier step on another stream
+    hipEvent_t last_ev = nullptr;
+    bool last_valid = false;
     std::mutex mu;
 };
 
@@ -211,14 +208,14 @@ size_t request_bytes(int64_t npix, int pop)
            align256((size_t)npix * pop * sizeof(float));
 }
 
-void release(Request &r, hipStream_t st)
+void free_population(Req &r, hipStream_t st)
 {
-    if (r.desc.genes)
-        (void)hipFreeAsync(r.desc.genes, st);
-    if (r.desc.fit)
-        (void)hipFreeAsync(r.desc.fit, st);
-    r.desc.genes = nullptr;
-    r.desc.fit = nullptr;
+    if (r.p.desc.genes)
+        (void)hipFreeAsync(r.p.desc.genes, st);
+    if (r.p.desc.fit)
+        (void)hipFreeAsync(r.p.desc.fit, st);
+    r.p.desc.genes = nullptr;
+    r.p.desc.fit = nullptr;
 }
 
 }  // namespace
@@ -233,12 +230,14 @@ int gs_create(size_t hbm_budget_bytes, int32_t gens_per_step, void **session)
         return fail(ME_EINVAL, "gens_per_step must be >= 1");
     if (hbm_budget_bytes == 0)
         return fail(ME_EINVAL, "the memory budget must be positive");
-    auto *s = new Session();
-    s->budget = hbm_budget_bytes;
-    s->gens_per_step = gens_per_step;
+    auto *s = new Session(hbm_budget_bytes, gens_per_step);
     if (hipGetDevice(&s->device) != hipSuccess) {
         delete s;
         return fail(ME_EHIP, "hipGetDevice failed");
+    }
+    if (hipEventCreateWithFlags(&s->last_ev, hipEventDisableTiming) != hipSuccess) {
+        delete s;
+        return fail(ME_EHIP, "hipEventCreate failed");
     }
     *session = s;
     return ME_OK;
@@ -252,8 +251,8 @@ int gs_submit(void *session, const float *obs, const float *sigma, const float *
     auto *s = static_cast<Session *>(session);
     if (!s || !request_id)
         return fail(ME_EINVAL, "session and request_id must not be NULL");
-    auto r = std::make_shared<Request>();
-    ReqDesc &d = r->desc;
+    auto r = std::make_shared<Req>();
+    ReqDesc &d = r->p.desc;
     if (int rc = pack_lines(lines, grids, nlines, d.ls))
         return rc;
     if (int rc = pack_bounds(bounds, d.b))
@@ -275,20 +274,19 @@ int gs_submit(void *session, const float *obs, const float *sigma, const float *
     d.mu = mu;
     d.npix = npix;
     d.generations = cfg->generations;
-    d.gen_done = -1;
     d.best_params = best_params;
     d.best_chi2 = best_chi2;
     d.status = status;
+    r->npix = npix;
+    r->generations = cfg->generations;
     r->bytes = request_bytes(npix, cfg->pop);
     std::lock_guard<std::mutex> lk(s->mu);
-    if (r->bytes > s->budget)
+    if (r->bytes > s->sched.budget())
         return fail(ME_ENOMEM, "request needs %zu B, more than the whole budget %zu B", r->bytes,
-                    s->budget);
-    if (hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming) != hipSuccess)
+                    s->sched.budget());
+    if (hipEventCreateWithFlags(&r->p.done_ev, hipEventDisableTiming) != hipSuccess)
         return fail(ME_EHIP, "hipEventCreate failed");
-    r->id = s->next_id++;
-    s->queue.push_back(r);
-    s->all[r->id] = r;
+    (void)s->sched.submit(r);
     *request_id = r->id;
     return ME_OK;
 }
@@ -301,7 +299,7 @@ int gs_set_max_resident_pixels(void *session, int64_t max_pixels)
     if (max_pixels < 0)
         return fail(ME_EINVAL, "max_pixels must be >= 0");
     std::lock_guard<std::mutex> lk(s->mu);
-    s->max_pixels = max_pixels;
+    s->sched.set_max_pixels(max_pixels);
     return ME_OK;
 }
 
@@ -312,64 +310,63 @@ int gs_step(void *session, void *stream)
         return fail(ME_EINVAL, "session must not be NULL");
     hipStream_t st = as_stream(stream);
     std::lock_guard<std::mutex> lk(s->mu);
-    // drop cancelled residents
-    for (auto it = s->resident.begin(); it != s->resident.end();) {
-        if ((*it)->cancel) {
-            release(**it, st);
-            s->in_use -= (*it)->bytes;
-            s->pixels -= (*it)->desc.npix;
-            (*it)->state = kCancelled;
-            it = s->resident.erase(it);
-        } else {
-            ++it;
-        }
+    // order this step after the session's previous one (frees below are
+    // stream-ordered on `st`)
+    if (s->last_valid && hipStreamWaitEvent(st, s->last_ev, 0) != hipSuccess)
+        return fail(ME_EHIP, "hipStreamWaitEvent failed");
+    auto free_on_st = [st](Req &r) { free_population(r, st); };
+    std::vector<Req *> res;
+    const bool admitted_all = s->sched.plan(
+        [st](Req &r) {
+            ReqDesc &d = r.p.desc;
+            const size_t gb = (size_t)d.npix * d.ga.pop * GENESIS_NPAR * sizeof(uint16_t);
+            const size_t fb = (size_t)d.npix * d.ga.pop * sizeof(float);
+            if (hipMallocAsync((void **)&d.genes, gb, st) != hipSuccess ||
+                hipMallocAsync((void **)&d.fit, fb, st) != hipSuccess) {
+                free_population(r, st);
+                return false;
+            }
+            return true;
+        },
+        free_on_st, res);
+    auto record_last = [&]() {
+        if (hipEventRecord(s->last_ev, st) == hipSuccess)
+            s->last_valid = true;
+    };
+    if (!admitted_all) {
+        record_last();
+        return fail(ME_ENOMEM, "device allocation for a queued request failed");
     }
-    // admission in arrival order while the memory budget allows and, with a
-    // pixel cap, while the resident pixels stay within it (a request is
-    // always admitted into an empty session)
-    while (!s->queue.empty() && s->in_use + s->queue.front()->bytes <= s->budget &&
-           (s->max_pixels == 0 || s->resident.empty() ||
-            s->pixels + s->queue.front()->desc.npix <= s->max_pixels)) {
-        auto r = s->queue.front();
-        s->queue.pop_front();
-        const size_t gb = (size_t)r->desc.npix * r->desc.ga.pop * GENESIS_NPAR * sizeof(uint16_t);
-        const size_t fb = (size_t)r->desc.npix * r->desc.ga.pop * sizeof(float);
-        if (hipMallocAsync((void **)&r->desc.genes, gb, st) != hipSuccess ||
-            hipMallocAsync((void **)&r->desc.fit, fb, st) != hipSuccess) {
-            release(*r, st);
-            s->queue.push_front(r);
-            return fail(ME_ENOMEM, "device allocation of %zu B failed", r->bytes);
-        }
-        s->in_use += r->bytes;
-        s->pixels += r->desc.npix;
-        r->state = kResident;
-        s->resident.push_back(r);
-    }
-    if (s->resident.empty())
+    if (res.empty()) {
+        record_last();
         return ME_OK;
+    }
     // descriptors of this launch
-    const int nreq = (int)s->resident.size();
+    const int nreq = (int)res.size();
     std::vector<ReqDesc> descs(nreq);
     std::vector<int64_t> first(nreq + 1);
-    int max_pop = 2, max_L = 1;
+    int max_pop = 2;
     size_t lds = 0;
     first[0] = 0;
     for (int i = 0; i < nreq; ++i) {
-        ReqDesc &d = s->resident[i]->desc;
-        const int from = d.gen_done < 0 ? 0 : d.gen_done;
-        d.gen_to = std::min(from + s->gens_per_step, d.generations);
+        ReqDesc &d = res[i]->p.desc;
+        d.gen_done = res[i]->gen_done;
+        d.gen_to = res[i]->gen_to;
         descs[i] = d;
         first[i + 1] = first[i] + d.npix;
         max_pop = std::max(max_pop, d.ga.pop);
-        max_L = std::max(max_L, d.ls.L);
         lds = std::max(lds, ga_lds_bytes<float>(d.ls.L, d.ga.pop));
     }
-    if (first[nreq] > kMaxGrid)
+    if (first[nreq] > kMaxGrid) {
+        record_last();
         return fail(ME_EINVAL, "more than 2^30 resident pixels");
+    }
     void *dbuf = nullptr;
     const size_t dbytes = align256(sizeof(ReqDesc) * nreq) + sizeof(int64_t) * (nreq + 1);
-    if (hipMallocAsync(&dbuf, dbytes, st) != hipSuccess)
+    if (hipMallocAsync(&dbuf, dbytes, st) != hipSuccess) {
+        record_last();
         return fail(ME_ENOMEM, "descriptor allocation failed");
+    }
     ReqDesc *d_descs = (ReqDesc *)dbuf;
     int64_t *d_first = (int64_t *)((char *)dbuf + align256(sizeof(ReqDesc) * nreq));
     if (hipMemcpyAsync(d_descs, descs.data(), sizeof(ReqDesc) * nreq, hipMemcpyHostToDevice,
@@ -377,28 +374,20 @@ int gs_step(void *session, void *stream)
         hipMemcpyAsync(d_first, first.data(), sizeof(int64_t) * (nreq + 1), hipMemcpyHostToDevice,
                        st) != hipSuccess) {
         (void)hipFreeAsync(dbuf, st);
+        record_last();
         return fail(ME_EHIP, "descriptor upload failed");
     }
     hipLaunchKernelGGL(k_ga_advance, dim3((unsigned)first[nreq]), dim3(block_for_pop(max_pop)),
                        lds, st, d_descs, d_first, nreq);
-    if (int rc = check_launch("gs_step"))
+    if (int rc = check_launch("gs_step")) {
+        (void)hipFreeAsync(dbuf, st);
+        record_last();
         return rc;
-    (void)hipFreeAsync(dbuf, st);
-    // bookkeeping: finished requests leave and return their memory
-    for (auto it = s->resident.begin(); it != s->resident.end();) {
-        Request &r = **it;
-        r.desc.gen_done = r.desc.gen_to;
-        if (r.desc.gen_done == r.desc.generations) {
-            (void)hipEventRecord(r.done_ev, st);
-            release(r, st);
-            s->in_use -= r.bytes;
-            s->pixels -= r.desc.npix;
-            r.state = kDone;
-            it = s->resident.erase(it);
-        } else {
-            ++it;
-        }
     }
+    (void)hipFreeAsync(dbuf, st);
+    // finished requests leave and return their memory
+    s->sched.commit([st](Req &r) { (void)hipEventRecord(r.p.done_ev, st); }, free_on_st);
+    record_last();
     return ME_OK;
 }
 
@@ -408,14 +397,13 @@ int gs_poll(void *session, uint64_t request_id, int32_t *done)
     if (!s || !done)
         return fail(ME_EINVAL, "session and done must not be NULL");
     std::lock_guard<std::mutex> lk(s->mu);
-    auto it = s->all.find(request_id);
-    if (it == s->all.end())
+    Req *r = s->sched.find(request_id);
+    if (!r)
         return fail(ME_EINVAL, "unknown request %llu", (unsigned long long)request_id);
-    Request &r = *it->second;
     *done = 0;
-    if (r.state == kDone)
-        *done = hipEventQuery(r.done_ev) == hipSuccess ? 1 : 0;
-    else if (r.state == kCancelled)
+    if (r->state == kDone)
+        *done = hipEventQuery(r->p.done_ev) == hipSuccess ? 1 : 0;
+    else if (r->state == kCancelled)
         *done = -1;
     return ME_OK;
 }
@@ -426,20 +414,30 @@ int gs_cancel(void *session, uint64_t request_id)
     if (!s)
         return fail(ME_EINVAL, "session must not be NULL");
     std::lock_guard<std::mutex> lk(s->mu);
-    auto it = s->all.find(request_id);
-    if (it == s->all.end())
+    if (!s->sched.cancel(request_id))
         return fail(ME_EINVAL, "unknown request %llu", (unsigned long long)request_id);
-    Request &r = *it->second;
-    if (r.state == kQueued) {
-        for (auto q = s->queue.begin(); q != s->queue.end(); ++q)
-            if ((*q)->id == request_id) {
-                s->queue.erase(q);
-                break;
-            }
-        r.state = kCancelled;
-    } else if (r.state == kResident) {
-        r.cancel = true;
-    }
+    return ME_OK;
+}
+
+int gs_release(void *session, uint64_t request_id)
+{
+    auto *s = static_cast<Session *>(session);
+    if (!s)
+        return fail(ME_EINVAL, "session must not be NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    Req *r = s->sched.find(request_id);
+    if (!r)
+        return fail(ME_EINVAL, "unknown request %llu", (unsigned long long)request_id);
+    if (r->state == kDone && hipEventQuery(r->p.done_ev) != hipSuccess)
+        return fail(ME_EBUSY, "request %llu is still running on the device",
+                    (unsigned long long)request_id);
+    const bool ok = s->sched.release(request_id, [](Req &q) {
+        if (q.p.done_ev)
+            (void)hipEventDestroy(q.p.done_ev);
+        q.p.done_ev = nullptr;
+    });
+    if (!ok)
+        return fail(ME_EBUSY, "request %llu is queued or resident", (unsigned long long)request_id);
     return ME_OK;
 }
 
@@ -450,11 +448,21 @@ int gs_stats(void *session, int64_t *queued, int64_t *resident, size_t *bytes_in
         return fail(ME_EINVAL, "session must not be NULL");
     std::lock_guard<std::mutex> lk(s->mu);
     if (queued)
-        *queued = (int64_t)s->queue.size();
+        *queued = (int64_t)s->sched.queued();
     if (resident)
-        *resident = (int64_t)s->resident.size();
+        *resident = (int64_t)s->sched.resident();
     if (bytes_in_use)
-        *bytes_in_use = s->in_use;
+        *bytes_in_use = s->sched.in_use();
+    return ME_OK;
+}
+
+int gs_tracked(void *session, int64_t *n)
+{
+    auto *s = static_cast<Session *>(session);
+    if (!s || !n)
+        return fail(ME_EINVAL, "session and n must not be NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    *n = (int64_t)s->sched.tracked();
     return ME_OK;
 }
 
@@ -466,11 +474,14 @@ int gs_destroy(void *session)
     (void)hipDeviceSynchronize();
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        for (auto &r : s->resident)
-            release(*r, nullptr);
-        for (auto &kv : s->all)
-            if (kv.second->done_ev)
-                (void)hipEventDestroy(kv.second->done_ev);
+        s->sched.for_each_resident([](Req &r) { free_population(r, nullptr); });
+        s->sched.for_each([](Req &r) {
+            if (r.p.done_ev)
+                (void)hipEventDestroy(r.p.done_ev);
+            r.p.done_ev = nullptr;
+        });
+        if (s->last_ev)
+            (void)hipEventDestroy(s->last_ev);
     }
     (void)hipDeviceSynchronize();
     delete s;

@@ -1,6 +1,8 @@
 """Continuous-batching service: every request's result is bit-identical to a
 standalone ga_invert of the same request, alone or mixed with others arriving
-at different times; admission respects the memory budget; cancellation."""
+at different times, and every served number agrees with the FP64 oracle
+re-evaluated on it; admission respects the memory budget; cancellation;
+released requests leave no memory behind."""
 import numpy as np
 import pytest
 import torch
@@ -8,6 +10,7 @@ import torch
 import oracle
 import synth_inputs as si
 from conftest import gpu_available
+from tolerances import FWD_TOL_F32, chi2_tol, ic_of, recover_genes
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a HIP device")]
@@ -32,11 +35,41 @@ def _request(kind, npix, seed, bad=False):
     sig = sig.astype(np.float32)
     if bad:
         obs[npix // 2, 1, 3] = np.nan
-    return (lines, grids, torch.tensor(obs, device=DEV), torch.tensor(sig, device=DEV))
+        sig[npix // 3, 2] = 0.0
+    return (lines, grids, torch.tensor(obs, device=DEV), torch.tensor(sig, device=DEV), olines,
+            truth)
+
+
+def _oracle_leg(req, cfg, out):
+    """Every served pixel against the oracle: the best parameters decode from
+    16-bit genes inside the box, the reported chi-square is the oracle's
+    chi-square of those genes within the forward-model bound, and the status
+    codes are the oracle's (0 ok, 1 non-finite observation, 2 sigma <= 0)."""
+    lines, grids, obs, sig, olines, truth = req
+    lo, hi = np.asarray(si.PRIOR_LO), np.asarray(si.PRIOR_HI)
+    o64 = obs.cpu().numpy().astype(np.float64)
+    s64 = sig.cpu().numpy().astype(np.float64)
+    par = out["params"].cpu().numpy()
+    chi = out["chi2"].cpu().numpy().astype(np.float64)
+    st = out["status"].cpu().numpy()
+    ref = oracle.ga_invert(o64, s64, olines, lo, hi, pop=2, generations=0, k=1, p_cross=0.0,
+                           p_mut=0.0, seed=0)["status"]
+    assert np.array_equal(st, ref)
+    ok = st == 0
+    assert np.isnan(par[~ok]).all() and np.isnan(chi[~ok]).all()
+    genes = recover_genes(par[ok], lo, hi)
+    dec = oracle.decode(genes, lo, hi)
+    assert np.array_equal(dec.astype(np.float32), par[ok])
+    L = o64.shape[-1]
+    ref_chi = oracle.chi2(dec[:, None, :], o64[ok], s64[ok], olines)[:, 0]
+    models = oracle.me_synth(dec, olines)[:, None]
+    tol = chi2_tol(o64[ok], models, s64[ok], ic_of(truth[ok]), 4 * L - 9, FWD_TOL_F32)[:, 0]
+    tol += 1e-5 * ref_chi
+    assert np.all(np.abs(chi[ok] - ref_chi) <= tol), np.max(np.abs(chi[ok] - ref_chi) / tol)
 
 
 def _alone(req, cfg):
-    lines, grids, obs, sig = req
+    lines, grids, obs, sig = req[:4]
     return g.ga_invert(obs, sig, lines, grids, g.bounds(si.PRIOR_LO, si.PRIOR_HI), cfg)
 
 
@@ -61,8 +94,11 @@ def test_single_request_equals_ga_invert():
     sess = g.ServingSession(budget_bytes=1 << 30, gens_per_step=7)
     rid = sess.submit(req[2], req[3], req[0], req[1], g.bounds(si.PRIOR_LO, si.PRIOR_HI), cfg)
     _drain(sess, [rid])
-    assert _same(sess.result(rid), _alone(req, cfg))
+    out = sess.result(rid)
+    assert _same(out, _alone(req, cfg))
+    _oracle_leg(req, cfg, out)
     assert sess.stats() == dict(queued=0, resident=0, bytes_in_use=0)
+    assert sess.tracked() == 0 and sess.held() == 0
     sess.close()
 
 
@@ -85,7 +121,10 @@ def test_mixed_requests_equal_their_standalone_runs():
         sess.step()
     _drain(sess, ids)
     for (r, c), rid in zip(reqs, ids):
-        assert _same(sess.result(rid), _alone(r, c)), rid
+        out = sess.result(rid)
+        assert _same(out, _alone(r, c)), rid
+        _oracle_leg(r, c, out)
+    assert sess.tracked() == 0
     sess.close()
 
 
@@ -104,6 +143,11 @@ def test_budget_admission_and_cancel():
     assert st["resident"] == 1 and st["queued"] == 2 and st["bytes_in_use"] <= budget
     sess.cancel(i3)                           # queued: dropped at once
     assert sess.stats()["queued"] == 1 and sess.poll(i3) == -1
+    sess.release(i3)
+    with pytest.raises(g.GenesisError):       # released: unknown
+        sess.poll(i3)
+    with pytest.raises(g.GenesisError):       # queued or resident: cannot be released
+        sess.release(i2)
     peak = 0
     for _ in range(100):
         sess.step()
@@ -119,6 +163,8 @@ def test_budget_admission_and_cancel():
     sess.cancel(i4)
     sess.step()
     assert sess.poll(i4) == -1 and sess.stats()["bytes_in_use"] == 0
+    sess.release(i4)
+    assert sess.tracked() == 0 and sess.held() == 0
     # larger than the whole budget
     big = _request("tiny", 400, 14)
     with pytest.raises(g.GenesisError):
@@ -151,4 +197,48 @@ def test_pixel_cap_admission():
         assert _same(sess.result(rid), _alone(r, cfg)), rid
     assert g.lib().gs_set_max_resident_pixels(sess._h, -1) != 0
     assert g.lib().gs_set_max_resident_pixels(None, 10) != 0
+    sess.close()
+
+
+def test_released_requests_leave_no_memory_behind():
+    # a long stream of small requests, each fetched when done: the session
+    # holds no records or tensors of fetched requests, and the device memory
+    # torch has allocated stays flat
+    b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
+    cfg = g.GAConfig(pop=32, generations=3, seed=3)
+    req = _request("tiny", 16, 41)
+    sess = g.ServingSession(budget_bytes=1 << 26, gens_per_step=2)
+    torch.cuda.synchronize()
+    base = None
+    for k in range(60):
+        # fresh input tensors per request, as a service receiving data would have
+        rid = sess.submit(req[2].clone(), req[3].clone(), req[0], req[1], b, cfg)
+        _drain(sess, [rid])
+        out = sess.result(rid)
+        del out
+        torch.cuda.synchronize()
+        if k == 5:
+            base = torch.cuda.memory_allocated()
+        if k > 5:
+            assert torch.cuda.memory_allocated() <= base, k
+    assert sess.tracked() == 0 and sess.held() == 0
+    sess.close()
+
+
+def test_steps_on_alternating_streams():
+    # steps issued on two streams alternately: each waits for the previous
+    # one, so results equal the standalone inversion
+    b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
+    cfg = g.GAConfig(pop=64, generations=17, seed=8)
+    reqs = [_request("tiny", 40, 51), _request("tiny", 23, 52)]
+    sess = g.ServingSession(budget_bytes=1 << 30, gens_per_step=3)
+    ids = [sess.submit(r[2], r[3], r[0], r[1], b, cfg) for r in reqs]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for k in range(40):
+        with torch.cuda.stream(streams[k % 2]):
+            sess.step()
+    torch.cuda.synchronize()
+    assert all(sess.poll(i) == 1 for i in ids)
+    for r, rid in zip(reqs, ids):
+        assert _same(sess.result(rid), _alone(r, cfg))
     sess.close()
