@@ -111,7 +111,7 @@ def lib():
             L.oracle_rng_word.argtypes = [C.c_uint64] + [C.c_uint32] * 5
             L.oracle_rng_word.restype = C.c_uint32
             L.oracle_decode.argtypes = [_u16p, _dp, _dp, _dp]
-            L.oracle_ga_init.argtypes = [C.c_uint64, C.c_uint32, C.c_int, C.c_int, C.c_int, _dp,
+            L.oracle_ga_init.argtypes = [C.c_uint64, C.c_uint32, C.c_int, C.c_int, C.c_int, C.c_int, _dp,
                                          _dp, _dp, C.c_int, _u16p]
             L.oracle_sobol_polys.argtypes = [_u32p, C.c_int]
             L.oracle_sobol_polys.restype = C.c_int
@@ -124,8 +124,8 @@ def lib():
             L.oracle_ga_step.restype = C.c_int
             L.oracle_ga_invert.argtypes = [_dp, _dp, _dp, C.c_int64, _linep, C.c_int, _dp, _dp,
                                            _dp, C.POINTER(Fill), _dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
-                                           C.c_uint64, C.c_uint32, C.c_int, C.c_int, _dp,
-                                           C.c_int, C.c_int, _dp, _dp, _i32p, _u16p, _dp]
+                                           C.c_uint64, C.c_uint32, C.c_int, C.c_int, C.c_int,
+                                           _dp, C.c_int, C.c_int, _dp, _dp, _i32p, _u16p, _dp]
             L.oracle_ga_invert.restype = C.c_int
             L.oracle_lm_refine.argtypes = [_dp, _dp, _dp, C.c_int64, _linep, C.c_int, _dp, _dp,
                                            _dp, C.c_int, _dp, _dp, _i32p]
@@ -283,13 +283,16 @@ def decode(genes, lo, hi):
 def ga_init(seed, pixel, pop, n_seeded=0, jitter=0, seed_params=None, lo=None, hi=None,
             init_mode=0):
     """Generation 0 of one pixel; the first n_seeded individuals encode the
-    first guess seed_params [9] inside the box [lo, hi] (Sec. 5.5); the rest
-    are uniform random (init_mode 0) or shifted Sobol points (1, Sec. 5.6)."""
+    first guesses seed_params [9] or [S, 9] inside the box [lo, hi] (Sec.
+    5.5; individual i takes guess i mod S); the rest are uniform random
+    (init_mode 0) or shifted Sobol points (1, Sec. 5.6)."""
     g = np.empty((pop, NPAR), np.uint16)
     sp = lo_ = hi_ = None
+    S = 1
     if n_seeded > 0:
-        sp, lo_, hi_ = _f64(seed_params).reshape(NPAR), _f64(lo), _f64(hi)
-    lib().oracle_ga_init(int(seed), int(pixel), int(pop), int(n_seeded), int(jitter),
+        sp, lo_, hi_ = _f64(seed_params).reshape(-1, NPAR), _f64(lo), _f64(hi)
+        S = sp.shape[0]
+    lib().oracle_ga_init(int(seed), int(pixel), int(pop), int(n_seeded), int(jitter), int(S),
                          None if sp is None else _ptr(sp, _dp),
                          None if lo_ is None else _ptr(lo_, _dp),
                          None if hi_ is None else _ptr(hi_, _dp), int(init_mode), _ptr(g, _u16p))
@@ -342,7 +345,8 @@ def ga_step(genes_in, fitness, k, p_cross, p_mut, seed, pixel, gen):
 def ga_invert(obs, sigma, lines, lo, hi, pop, generations, k, p_cross, p_mut, seed,
               mu=None, pixel_base=0, want_population=False, n_seeded=0, seed_jitter=0,
               seed_params=None, init_mode=0, restart_every=0, pixel_box=None, fill=None):
-    """Algorithm 1 for npix pixels; pixel_box [npix, 2, 9] (lo row, hi row)
+    """Algorithm 1 for npix pixels; seed_params [npix, 9] or [npix, S, 9]
+    (S first guesses per pixel); pixel_box [npix, 2, 9] (lo row, hi row)
     gives each pixel its own search box (status 3 where it is invalid); fill
     (a Fill) makes the fitness the chi-square at the best fill fraction and
     adds 'alpha' [npix] to the result (status 4 where the field-free profile
@@ -361,13 +365,14 @@ def ga_invert(obs, sigma, lines, lo, hi, pop, generations, k, p_cross, p_mut, se
     ff = np.empty((npix, pop), np.float64) if want_population else None
     arr, lp = _lines_array(lines)
     m = None if mu is None else _f64(np.broadcast_to(mu, (npix,)))
-    sp = None if n_seeded == 0 else _f64(seed_params).reshape(npix, NPAR)
+    sp = None if n_seeded == 0 else _f64(seed_params).reshape(npix, -1, NPAR)
+    S = 1 if sp is None else sp.shape[1]
     rc = lib().oracle_ga_invert(
         _ptr(o, _dp), _ptr(s, _dp), None if m is None else _ptr(m, _dp), npix, lp, len(lines),
         _ptr(lo, _dp), _ptr(hi, _dp), None if pb is None else _ptr(pb, _dp),
         None if fill is None else C.byref(fill), None if fill is None else _ptr(ba, _dp), int(pop),
         int(generations), int(k), float(p_cross),
-        float(p_mut), int(seed), int(pixel_base), int(n_seeded), int(seed_jitter),
+        float(p_mut), int(seed), int(pixel_base), int(n_seeded), int(seed_jitter), int(S),
         None if sp is None else _ptr(sp, _dp), int(init_mode), int(restart_every), _ptr(bp, _dp), _ptr(bc, _dp), _ptr(st, _i32p),
         None if fg is None else _ptr(fg, _u16p), None if ff is None else _ptr(ff, _dp))
     if rc != 0:

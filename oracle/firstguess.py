@@ -123,3 +123,128 @@ def first_guess(obs, lines, lo, hi, mu=None):
         g9 = np.minimum(np.maximum(g9, lo), hi)
         out[p] = g9
     return out
+
+
+# --------------------------------------------------------------------------- #
+# The separate seeds of Sec. 5.5
+
+SEED_NAMES = ("weak_field", "integral", "centre_of_gravity", "non_magnetic")
+
+
+def _thermo(obs_p, lines, lo, hi, mu):
+    """v_los, Doppler width, damping, eta0, S0, S1 of first_guess (the
+    centre of gravity, half-depth width and core depth estimates)."""
+    return first_guess(obs_p[None], lines, lo, hi, mu=np.array([mu]))[0][3:]
+
+
+def seeds(obs, lines, lo, hi, mu=None, box=None):
+    """The four first guesses of Sec. 5.5 per pixel: [npix, 4, 9] in the
+    order of SEED_NAMES; a NaN entry is a parameter the seed leaves random.
+    Shared by all four: the thermodynamic estimates of first_guess.  Per
+    line (x, I_c, I', I'', C, gbar as in first_guess; a = C^2 gbar^2):
+      weak field (Auer et al.): the least squares of the weak-field relations
+        V = -C gbar B_par I' and (Q, U) = -(1/4) a B_perp^2 (cos 2chi,
+        sin 2chi) I'' over the samples of every line:
+        B_par = -sum V I' C gbar / sum (C gbar I')^2,
+        q = -4 sum a Q I'' / sum (a I'')^2 (u likewise), B_perp =
+        sqrt(hypot(q, u)), chi = atan2(u, q) / 2;
+      integral relations (Ronan et al.): the same relations integrated over
+        the profiles, |B_par| = sum |V| / sum C gbar |I'|, with the sign of
+        -sum V I' (the order of the V lobes), B_perp^2 = 4 sum sqrt(Q^2 +
+        U^2) / sum a |I''|; the azimuth from the integrated second moments of
+        the linear polarisation, whose principal axis is chi0 = atan2(2 sum
+        Q U, sum (Q^2 - U^2)) / 4 (Q, U ~ cos 2chi, sin 2chi at every sample
+        when magneto-optical mixing is small), chi0 or chi0 + 90 deg: the one
+        whose projection Q cos 2chi + U sin 2chi summed over the three samples
+        around each line's minimum of I is not positive (at the line centre
+        the pi component gives Q ~ -cos 2chi);
+      centre of gravity (Rees and Semel): B = |B_par| of first_guess's
+        centre-of-gravity estimate, inclination 0 for B_par >= 0 and 180
+        otherwise, azimuth unseeded;
+      non-magnetic: B = 0, both angles unseeded.
+    For the first three, B = hypot(B_par, B_perp) and inclination =
+    atan2(B_perp, B_par).  Every seed is then made consistent with the
+    pixel's box (box [npix, 2, 9], e.g. the polarity restriction): an
+    inclination outside the box's range becomes 180 - inclination; then
+    every seeded value is clamped into the box (the azimuth wrapped into
+    [0, 180) first); a non-finite estimate is replaced by the middle of the
+    box."""
+    obs = np.asarray(obs, np.float64)
+    npix = obs.shape[0]
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    mus = np.ones(npix) if mu is None else np.broadcast_to(np.asarray(mu, np.float64), (npix,))
+    comb = first_guess(obs, lines, lo, hi, mu=mus)
+    out = np.full((npix, 4, 9), np.nan)
+    for p in range(npix):
+        blo = lo if box is None else np.asarray(box[p, 0], np.float64)
+        bhi = hi if box is None else np.asarray(box[p, 1], np.float64)
+        Ic = obs[p, 0].max()
+        off = 0
+        s = dict(vI=0.0, I2=0.0, aQ=0.0, aU=0.0, a2=0.0, absV=0.0, absI1=0.0, L=0.0, absI2=0.0,
+                 QU=0.0, QQUU=0.0, cQ=0.0, cU=0.0)
+        for ln in lines:
+            n = ln.nlam
+            I, Q, U, V = (obs[p, k, off:off + n] for k in range(4))
+            off += n
+            d1, d2 = _derivs(I, ln.step)
+            C = ZEEMAN * ln.lambda0 ** 2
+            g = gbar_of(ln)
+            cg = C * g
+            a = cg * cg
+            s["vI"] += (V * d1).sum() * cg
+            s["I2"] += ((cg * d1) ** 2).sum()
+            s["aQ"] += a * (Q * d2).sum()
+            s["aU"] += a * (U * d2).sum()
+            s["a2"] += ((a * d2) ** 2).sum()
+            s["absV"] += np.abs(V).sum()
+            s["absI1"] += cg * np.abs(d1).sum()
+            s["L"] += np.sqrt(Q * Q + U * U).sum()
+            s["absI2"] += a * np.abs(d2).sum()
+            s["QU"] += (Q * U).sum()
+            s["QQUU"] += (Q * Q - U * U).sum()
+            c = int(np.argmin(I))
+            s["cQ"] += Q[max(c - 1, 0):c + 2].sum()
+            s["cU"] += U[max(c - 1, 0):c + 2].sum()
+        th = comb[p, 3:]
+        # weak field
+        bpar = -s["vI"] / s["I2"]
+        q = -4.0 * s["aQ"] / s["a2"]
+        u = -4.0 * s["aU"] / s["a2"]
+        bperp = np.sqrt(np.hypot(q, u))
+        wf = [np.hypot(bpar, bperp), np.degrees(np.arctan2(bperp, bpar)),
+              np.degrees(0.5 * np.arctan2(u, q))]
+        # integral relations
+        ipar = np.abs(s["absV"] / s["absI1"]) * (1.0 if -s["vI"] >= 0 else -1.0)
+        iperp = np.sqrt(4.0 * s["L"] / s["absI2"])
+        chi0 = 0.25 * np.arctan2(2.0 * s["QU"], s["QQUU"])
+        if s["cQ"] * np.cos(2 * chi0) + s["cU"] * np.sin(2 * chi0) > 0:
+            chi0 += 0.5 * np.pi
+        ir = [np.hypot(ipar, iperp), np.degrees(np.arctan2(iperp, ipar)), np.degrees(chi0)]
+        # centre of gravity: the longitudinal estimate of first_guess
+        cb = comb[p, 0] * np.cos(np.radians(comb[p, 1]))   # B_par as first_guess formed it
+        cog = [abs(cb), 0.0 if cb >= 0 else 180.0, np.nan]
+        for k, mag in enumerate((wf, ir, cog, [0.0, np.nan, np.nan])):
+            v = np.concatenate([np.asarray(mag, np.float64), th])
+            out[p, k] = _consistent(v, blo, bhi)
+    return out
+
+
+def _consistent(v, blo, bhi):
+    """Polarity consistency, azimuth wrap, non-finite -> middle, clamp (NaN
+    angles stay unseeded)."""
+    v = v.copy()
+    seeded = ~np.isnan(v)
+    seeded[0] = True
+    v[0] = v[0] if np.isfinite(v[0]) else 0.5 * (blo[0] + bhi[0])
+    for j in (1, 2):
+        if seeded[j] and not np.isfinite(v[j]):
+            v[j] = 0.5 * (blo[j] + bhi[j])
+    if seeded[2]:
+        v[2] = v[2] % 180.0
+    if seeded[1] and not (blo[1] <= v[1] <= bhi[1]):
+        v[1] = 180.0 - v[1]
+    for j in range(3, 9):
+        if not np.isfinite(v[j]):
+            v[j] = 0.5 * (blo[j] + bhi[j])
+    return np.where(seeded, np.minimum(np.maximum(v, blo), bhi), np.nan)

@@ -109,13 +109,14 @@ uint32_t oracle_rng_word(uint64_t seed, uint32_t pixel, uint32_t gen, uint32_t i
 /* Decoding operator E^-1 (Sec. 3, decode equation) for 16-bit genes. */
 void oracle_decode(const uint16_t *genes, const double *lo, const double *hi, double *par);
 
-/* Generation-0 population: genes [pop][9].  Individuals below n_seeded encode
- * the first guess seed_par [9] in the box [lo, hi] (exactly for individual 0,
- * jittered by up to +-jitter codes per gene for the others); the rest are
- * uniform random codes.  seed_par, lo and hi may be NULL when n_seeded = 0. */
+/* Generation-0 population: genes [pop][9].  Individual i below n_seeded
+ * encodes first guess i mod S of seed_par [S][9] (S = seed_sets, 0 reads as 1)
+ * in the box [lo, hi] (exactly for i < S, jittered by up to +-jitter codes per
+ * gene for the others); the rest are uniform random codes (or Sobol points).
+ * seed_par, lo and hi may be NULL when n_seeded = 0. */
 void oracle_ga_init(uint64_t seed, uint32_t pixel, int pop, int n_seeded, int jitter,
-                    const double *seed_par, const double *lo, const double *hi, int init_mode,
-                    uint16_t *genes);
+                    int seed_sets, const double *seed_par, const double *lo, const double *hi,
+                    int init_mode, uint16_t *genes);
 
 /* Sobol points (Sec. 5.6 initialisation and restarts): the first n primitive
  * polynomials over GF(2) (bit k = coefficient of x^k; returns how many were
@@ -146,8 +147,8 @@ int oracle_ga_step(const uint16_t *genes_in, const double *fit, int pop, int k,
  * best_params [npix][9], best_chi2 [npix], status [npix] (0 ok, 1 non-finite
  * observation, 2 sigma <= 0 or non-finite, 3 invalid pixel box);
  * final_genes [npix][pop][9] and final_fit [npix][pop] may be NULL.
- * n_seeded > 0 seeds generation 0 of pixel p from seed_params [npix][9] as
- * oracle_ga_init does.  pixel_box [npix][2][9] (lo row, then hi row; may be
+ * n_seeded > 0 seeds generation 0 of pixel p from seed_params
+ * [npix][S][9] (S = seed_sets, 0 reads as 1) as oracle_ga_init does.  pixel_box [npix][2][9] (lo row, then hi row; may be
  * NULL) replaces [lo, hi] for each pixel: decoding, seeding and the result
  * use the pixel's box.  fill (may be NULL) makes the fitness the chi-square
  * at each individual's best fill fraction (oracle_fill.c); best_alpha [npix]
@@ -158,7 +159,7 @@ int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, i
                      const double *pixel_box, const oracle_fill *fill, double *best_alpha,
                      int pop, int generations, int k, double p_cross, double p_mut,
                      uint64_t seed, uint32_t pixel_base, int n_seeded, int seed_jitter,
-                     const double *seed_params, int init_mode, int restart_every,
+                     int seed_sets, const double *seed_params, int init_mode, int restart_every,
                      double *best_params, double *best_chi2, int32_t *status,
                      uint16_t *final_genes, double *final_fit);
 

@@ -25,11 +25,12 @@
  *  - elitism: the best individual is copied unchanged into slot 0; slots
  *    1 .. pop-1 hold the children of pairs (2p+1, 2p+2).
  *  - seeding (Sec. 5.5: first guesses placed in the initial population):
- *    individuals 0 .. n_seeded-1 of generation 0 encode a first guess p of
- *    the pixel, gene = floor(65535 clamp((p - u) / (v - u), 0, 1) + 0.5),
- *    the inverse of the decoding equation rounded to the nearest code;
- *    individual 0 keeps it exactly, individual i >= 1 adds to gene j the
- *    integer d - J, d uniform in [0, 2J] from word j of stream purpose 5
+ *    a pixel has S >= 1 first guesses (seed_sets); individual i of
+ *    0 .. n_seeded-1 of generation 0 encodes guess i mod S,
+ *    gene = floor(65535 clamp((p - u) / (v - u), 0, 1) + 0.5), the inverse of
+ *    the decoding equation rounded to the nearest code; individuals i < S
+ *    keep their guess exactly, individual i >= S adds to gene j the integer
+ *    d - J, d uniform in [0, 2J] from word j of stream purpose 5
  *    (J = seed_jitter), clamped to [0, 65535]; a NaN first guess leaves that
  *    parameter's gene as drawn for an unseeded individual.
  *  - Sobol initialisation and restarts (Sec. 5.6): Sobol points (Bratley &
@@ -220,9 +221,10 @@ static uint16_t encode(double p, double lo, double hi)
 }
 
 void oracle_ga_init(uint64_t seed, uint32_t pixel, int pop, int n_seeded, int jitter,
-                    const double *seed_par, const double *lo, const double *hi, int init_mode,
-                    uint16_t *genes)
+                    int seed_sets, const double *seed_par, const double *lo, const double *hi,
+                    int init_mode, uint16_t *genes)
 {
+    const int S = seed_sets < 1 ? 1 : seed_sets;
     for (int i = 0; i < pop; ++i) {
         uint16_t *g = genes + i * NGENE;
         if (init_mode == 1)
@@ -233,11 +235,12 @@ void oracle_ga_init(uint64_t seed, uint32_t pixel, int pop, int n_seeded, int ji
                                   16);
         if (!(i < n_seeded && seed_par))
             continue;
+        const double *guess = seed_par + (i % S) * NGENE;
         for (int j = 0; j < NGENE; ++j) {
-            if (isnan(seed_par[j]))
+            if (isnan(guess[j]))
                 continue;              /* no first guess for this parameter */
-            int v = encode(seed_par[j], lo[j], hi[j]);
-            if (i > 0) {
+            int v = encode(guess[j], lo[j], hi[j]);
+            if (i >= S) {
                 const uint32_t w = oracle_rng_word(seed, pixel, 0u, (uint32_t)i, 5u, (uint32_t)j);
                 v += (int)uniform_upto(w, 2u * (uint32_t)jitter) - jitter;
                 v = v < 0 ? 0 : (v > 65535 ? 65535 : v);
@@ -405,13 +408,14 @@ int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, i
                      const double *hi_all, const double *pixel_box, const oracle_fill *fill,
                      double *best_alpha, int pop, int generations, int k, double p_cross, double p_mut,
                      uint64_t seed, uint32_t pixel_base, int n_seeded, int seed_jitter,
-                     const double *seed_params, int init_mode, int restart_every,
+                     int seed_sets, const double *seed_params, int init_mode, int restart_every,
                      double *best_params, double *best_chi2, int32_t *status,
                      uint16_t *final_genes, double *final_fit)
 {
     if (pop < 2 || k < 1 || k > pop || k > 64 || generations < 0)
         return -1;
-    if (n_seeded < 0 || n_seeded > pop || seed_jitter < 0 || (n_seeded > 0 && !seed_params))
+    if (n_seeded < 0 || n_seeded > pop || seed_jitter < 0 || (n_seeded > 0 && !seed_params) ||
+        seed_sets < 0)
         return -1;
     if ((init_mode != 0 && init_mode != 1) || restart_every < 0)
         return -1;
@@ -420,6 +424,7 @@ int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, i
                    fill->alpha_hi <= 1.0)))
         return -1;
     const int L = oracle__total_samples(lines, nlines);
+    const int S = seed_sets < 1 ? 1 : seed_sets;
     int err = 0;
 #pragma omp parallel
     {
@@ -477,8 +482,9 @@ int oracle_ga_invert(const double *obs, const double *sigma, const double *mu, i
 #define FITNESS(i)                                                                         \
     (fill ? oracle__chi2_fill_single(par, m, lines, nlines, o, s, fill, scratch, &alph[i]) \
           : oracle__chi2_single(par, m, lines, nlines, o, s, scratch))
-            oracle_ga_init(seed, pix, pop, n_seeded, seed_jitter,
-                           seed_params ? seed_params + p * NGENE : NULL, lo, hi, init_mode, g0);
+            oracle_ga_init(seed, pix, pop, n_seeded, seed_jitter, S,
+                           seed_params ? seed_params + p * S * NGENE : NULL, lo, hi, init_mode,
+                           g0);
             for (int i = 0; i < pop; ++i) {
                 oracle_decode(g0 + i * NGENE, lo, hi, par);
                 fit[i] = FITNESS(i);
