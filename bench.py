@@ -1,17 +1,24 @@
-"""Benchmark: GA Milne-Eddington inversion of a synthetic slit row on one MI355X.
+"""Benchmark: GA Milne-Eddington inversion of a synthetic full-disc map on one MI355X.
 
-One step = the whole inversion of the workload: one ga_invert launch (every
-pixel runs the full genetic algorithm: init, evaluate, then G generations of
-selection, crossover, mutation, decode and evaluate, in FP32) followed by one
-me_refine_f64 launch (10 FP64 Levenberg-Marquardt iterations polishing each
-pixel's best individual, the fewest that hold the accuracy gate with margin).  Inputs are resident in HBM before the timed region.  Prints ONE
-JSON line.
+Default workload ('disc'): the on-disc pixels of a 2048 x 2048 map (3,294,288
+pixels; smooth random parameter fields plus strong-field patches, mu from the
+disc position) x 2 lines (Fe I 6301.5 full 12-component pattern, Fe I 6302.5
+triplet) x 128 samples over +-0.4 A; FP32 GA with population 128, 150
+generations, tournament 4, mutation rate 0.05, crossover 0.85, then 10 FP64
+Levenberg-Marquardt iterations polishing each pixel's best individual.  The
+map is split into 20 contiguous scanline blocks of equal pixel count; one step
+inverts one block (one ga_invert launch with pixel_base = the block's first
+pixel, so every pixel draws the random numbers it would in a single launch,
+then one me_refine_f64 launch), so 20 steps invert the whole disc once.
+Observations are noise-free (the accuracy gate, p90 |dB| <= 10 G, is defined
+on noise-free truth), synthesised on the device by the FP64 forward model and
+certified against the FP64 CPU oracle on a seeded 4096-pixel subset before the
+timed region; the GA reads them rounded to FP32.  Inputs are resident in HBM
+before the timed region.  Prints ONE JSON line.
 
-Workload (default, 'slit'): 2048 pixels x 2 lines (Fe I 6301.5 full 12-component
-pattern, Fe I 6302.5 triplet) x 128 samples over +-0.4 A, FP32, population 128,
-200 generations, tournament 4, mutation rate 0.05, crossover 0.85; truth drawn
-from the priors, observations synthesised by the library's forward model
-(noise-free, so that the recovered-parameter accuracy can be gated).
+Other workloads: 'slit' (2048 px, G 200), 'tiny' (64 px, FP64), 'precision'
+(FP32 against FP16 synthesis on a strided disc sample, noisy), 'serving',
+'proposal', 'fill'.
 """
 from __future__ import annotations
 
@@ -56,6 +63,19 @@ TRAFFIC_SOURCES = ("csrc/genesis.hip", "csrc/genesis_device.h", "csrc/genesis_co
 TRAFFIC_SOURCES_SHA256 = "03882eacb494f62294dd370ce4cfd1b3c06fd3fde2fc50384c29072c383536cd"
 
 
+# HBM bytes per launch of k_ga_invert<float> on one full-disc block, from the
+# same counters (profiles/k_ga_invert_disc_counters.md); None until measured
+# on the current sources.
+TRAFFIC_DISC_BLOCK_BYTES = None
+TRAFFIC_DISC_SOURCES_SHA256 = None
+
+
+def disc_traffic(edges):
+    if TRAFFIC_DISC_BLOCK_BYTES is None or kernel_sources_sha256() != TRAFFIC_DISC_SOURCES_SHA256:
+        return None
+    return TRAFFIC_DISC_BLOCK_BYTES
+
+
 def kernel_sources_sha256():
     import hashlib
     h = hashlib.sha256()
@@ -92,39 +112,41 @@ def describe(w, lines):
                w["p_mut"], w["p_cross"], w["dtype"].upper(), w["refine"]))
 
 
-def cpu_baseline(w, truth, olines, budget_s=20.0):
+def cpu_baseline(w, truth, olines, budget_s=20.0, mu=None):
     """The FP64 oracle's GA on a bounded sample of the same workload, on the
-    host cores: `nthr` pixels (their observations synthesised by the oracle
-    itself), generations chosen so the run takes roughly `budget_s`; scaled
-    to full inversions per second."""
+    host cores: `nthr` pixels of `truth` (their observations synthesised by
+    the oracle itself, with mu if given), generations chosen so the run takes
+    roughly `budget_s`; scaled to full inversions per second."""
     import oracle
     import synth_inputs as si
     nthr = oracle.num_threads()
-    npx = min(max(nthr, 1), w["npix"])
-    obs_np = oracle.me_synth(truth[:npx], olines)
-    sig_np = si.sigma_for(truth[:npx])
+    npx = min(max(nthr, 1), len(truth))
+    m = None if mu is None else mu[:npx]
+    obs_np = oracle.me_synth(truth[:npx], olines, m)
+    sig_np = si.sigma_for(truth[:npx], mu=m)
     # probe: one generation
     t0 = time.perf_counter()
     oracle.ga_invert(obs_np[:npx], sig_np[:npx], olines, si.PRIOR_LO, si.PRIOR_HI,
                      pop=w["pop"], generations=0, k=w["k"], p_cross=w["p_cross"],
-                     p_mut=w["p_mut"], seed=w["seed"])
+                     p_mut=w["p_mut"], seed=w["seed"], mu=m)
     t_gen = time.perf_counter() - t0
     gs = int(max(0, min(w["generations"], budget_s / max(t_gen, 1e-6) - 1)))
     t0 = time.perf_counter()
     ga = oracle.ga_invert(obs_np[:npx], sig_np[:npx], olines, si.PRIOR_LO, si.PRIOR_HI,
                           pop=w["pop"], generations=gs, k=w["k"], p_cross=w["p_cross"],
-                          p_mut=w["p_mut"], seed=w["seed"])
+                          p_mut=w["p_mut"], seed=w["seed"], mu=m)
     dt_ga = time.perf_counter() - t0
     t0 = time.perf_counter()
     oracle.lm_refine(obs_np[:npx], sig_np[:npx], olines, si.PRIOR_LO, si.PRIOR_HI,
-                     ga["params"], w["refine"])
+                     ga["params"], w["refine"], mu=m)
     dt_lm = time.perf_counter() - t0
     t_full = dt_ga * (w["generations"] + 1) / (gs + 1) + dt_lm
     return {"value": npx / t_full, "unit": "pixels/s", "cores": nthr, "kind": "oracle",
-            "sample": "%d pixels: %d of %d GA generations (pop %d, %.1f s, scaled by (G+1)) "
-                      "plus %d LM iterations (%.1f s) of the same workload, FP64 oracle with "
+            "sample": "%d pixels of the %s workload: %d of %d GA generations (pop %d, %.1f s, "
+                      "scaled by (G+1)) plus %d LM iterations (%.1f s), FP64 oracle with "
                       "OpenMP over pixels"
-                      % (npx, gs + 1, w["generations"] + 1, w["pop"], dt_ga, w["refine"], dt_lm)}
+                      % (npx, w["name"], gs + 1, w["generations"] + 1, w["pop"], dt_ga,
+                         w["refine"], dt_lm)}
 
 
 def serving(args):
@@ -182,6 +204,7 @@ def serving(args):
         launches += 1
         tnow = time.perf_counter() - t0
         for rid in [i for i in pending if sess.poll(i) == 1]:
+            sess.release(rid)
             r = pending.pop(rid)
             lat.append(tnow - r["t"])
             done_px += r["npix"]
@@ -313,6 +336,10 @@ def proposal(args):
     _proposal_report(args, g, si, batch, lr, wall, train_ms, losses, pass_flop, pass_s, *res)
 
 
+# one strategy per Sec. 5.5 seed (me_seeds order), each alone in 32 slots
+SEED_STRATEGIES = ("seed_weak_field", "seed_integral", "seed_cog", "seed_nonmagnetic")
+
+
 def _heldout(args, g, si, net, lines, grids, b, stream, dev):
     """Initial-population strategies on held-out noisy pixels: median
     chi-square and fraction at the target after G generations."""
@@ -334,14 +361,34 @@ def _heldout(args, g, si, net, lines, grids, b, stream, dev):
     target = args.chi2_target
     wanted = args.strategies.split(",")
     need_phys = any(w in ("physics", "polarity_box", "prefit_box", "physics_in_box")
-                    for w in wanted)
+                    or w in SEED_STRATEGIES or w.startswith("four_seeds") for w in wanted)
     obs64 = obs.double().contiguous() if need_phys else None
     sig64 = sig.double().contiguous() if need_phys else None
     phys = box_pf = box_pol = None
     box_stats = None
+    seeds = seeds_pol = None
     if need_phys:
         phys, box_pf, box_pol, box_stats = _physics_inputs(g, si, obs64, sig64, lines, grids, b,
                                                            truth, stream)
+        es = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        es[0].record(stream)
+        seeds = g.me_seeds(obs64, lines, grids, b)
+        es[1].record(stream)
+        seeds_pol = g.me_seeds(obs64, lines, grids, b, pixel_bounds=box_pol)
+        torch.cuda.synchronize()
+        box_stats["seeds_ms"] = es[0].elapsed_time(es[1])
+        sp = seeds.cpu().numpy()
+        box_stats["seed_errors"] = {
+            name: {"p50_abs_dB_G": float(np.median(np.abs(sp[:, k, 0] - truth[:, 0]))),
+                   "p50_abs_dincl_deg_B_ge_300G": (float(np.median(np.abs(
+                       sp[truth[:, 0] >= 300, k, 1] - truth[truth[:, 0] >= 300, 1])))
+                       if k < 3 else None)}
+            for k, name in enumerate(g.SEED_NAMES)}
+        print("proposal: Sec. 5.5 seeds %s" % box_stats["seed_errors"], file=sys.stderr,
+              flush=True)
+    one = {name: dict(n_seeded=32, seed_jitter=512,
+                      seed_params=None if seeds is None else seeds[:, k].contiguous())
+           for k, name in enumerate(SEED_STRATEGIES)}
     strategies = tuple((n, e) for n, e in (
         ("random", {}),
         ("seeded", dict(n_seeded=32, seed_jitter=512, seed_params=guess)),
@@ -351,7 +398,11 @@ def _heldout(args, g, si, net, lines, grids, b, stream, dev):
         ("physics_in_box", dict(n_seeded=32, seed_jitter=512, seed_params=phys,
                                 pixel_bounds=box_pf)),
         ("sobol", dict(init_mode=1)),
-        ("sobol_restart", dict(init_mode=1, restart_every=50))) if n in wanted)
+        ("sobol_restart", dict(init_mode=1, restart_every=50)),
+        *((n, one[n]) for n in SEED_STRATEGIES),
+        ("four_seeds", dict(n_seeded=32, seed_jitter=512, seed_params=seeds)),
+        ("four_seeds_polarity", dict(n_seeded=32, seed_jitter=512, seed_params=seeds_pol,
+                                     pixel_bounds=box_pol))) if n in wanted)
     table = []
     o64, s64 = obs.double(), sig.double()
     for gens in (0, 10, 25, 50, 100, 150, 200):
@@ -422,9 +473,12 @@ def _equal_accuracy(table, strategies, infer_ms, box_stats):
     # preparation each strategy needs before its search
     fg = box_stats["first_guess_ms"] if box_stats else 0.0
     pf = (box_stats["prefit_ms"] + box_stats["search_box_ms"]) if box_stats else 0.0
+    sd = box_stats.get("seeds_ms", 0.0) if box_stats else 0.0
     prep = {"seeded": infer_ms, "physics": fg,
             "polarity_box": box_stats["search_box_ms"] if box_stats else 0.0,
-            "prefit_box": fg + pf, "physics_in_box": fg + pf}
+            "prefit_box": fg + pf, "physics_in_box": fg + pf, "four_seeds": sd,
+            "four_seeds_polarity": sd + (box_stats["search_box_ms"] if box_stats else 0.0)}
+    prep.update({n: sd for n in SEED_STRATEGIES})
     last = table[-1]
     goal = last["random_refined_frac_at_target"]
     t_random = last["random_ga_ms"] + last["random_refine_ms"]
@@ -492,7 +546,7 @@ def _proposal_report(args, g, si, batch, lr, wall, train_ms, losses, pass_flop, 
     print(json.dumps(out), flush=True)
 
 
-def disc(args):
+def precision_study(args):
     """Precision study on the full-disc configuration: on-disc pixels of a
     2048 x 2048 map (every `disc_stride`-th), parameters from smooth random
     fields plus strong-field patches, mu from the disc position, 2 lines x
@@ -567,14 +621,16 @@ def disc(args):
     lines_grids = list(zip(lines, grids))
     evals = npix * 128 * 151
     fpe = flops_per_eval(lines_grids)
-    ga_s = times["fp16"]["ga_ms"] / 1e3
+    # the counted FP32 work of the degree-7 formula over the FP32 kernel's
+    # time (the FP16 kernel evaluates a different, degree-4 rational)
+    ga_s = times["fp32"]["ga_ms"] / 1e3
     out = {"metric": "pixel inversions/s, full-disc precision study (FP16 synthesis + FP64 refine)",
            "value": npix / times["fp16"]["wall_s"], "unit": "pixels/s", "n_gpus": 1, "steps": 1,
            "warmup": 1, "ms_per_step": times["fp16"]["wall_s"] * 1e3, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f16",
            "data": "synthetic (smooth random parameter fields + strong-field patches on a "
                    "2048^2 disc, mu from the disc position, noise 1e-3 Ic)",
-           "config": {"workload": "full disc 2048^2 (every %d-th of the on-disc pixels), "
+           "config": {"workload": "precision study: full disc 2048^2 (every %d-th of the on-disc pixels), "
                                   "2 lines x 128, pop 128, G 150, FP32 vs FP16 synthesis, "
                                   "FP32 chi-square, %d FP64 L-M iterations"
                                   % (args.disc_stride, REFINE_ITERS),
@@ -582,13 +638,12 @@ def disc(args):
            "fp32_pixels_per_s": npix / times["fp32"]["wall_s"],
            "times_ms": times,
            "error_table": rows,
+           "timed_pixels": npix,
            "roofline": {"bound": "alu", "achieved": evals * fpe / ga_s / 1e12,
                         "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
                         "frac": evals * fpe / ga_s / PEAK_FP32_VALU, "traffic": None,
-                        "kernel": "k_ga_invert<float, FP16 synthesis>",
-                        "flop_per_eval": fpe, "evals_per_launch": evals,
-                        "peak_note": "packed FP16 FMA issues at the published 157.3 TFLOP/s "
-                                     "vector rate"}}
+                        "kernel": "k_ga_invert<float> (FP32 synthesis)",
+                        "flop_per_eval": fpe, "evals_per_launch": evals}}
     print(json.dumps(out), flush=True)
 
 
@@ -675,12 +730,190 @@ def fill_workload(args):
     print(json.dumps(out), flush=True)
 
 
+DISC_BLOCKS = 20          # contiguous scanline blocks of the full disc; one step = one block
+DISC_CERT_PIXELS = 4096   # seeded subset of the observations certified against the oracle
+DISC_GA = dict(pop=128, generations=150, k=4, p_mut=0.05, p_cross=0.85, seed=0,
+               refine=REFINE_ITERS)
+
+
+def _lineset(g, si, name="slit"):
+    import oracle
+    lines, grids, olines = [], [], []
+    for ln, n in si.line_set(name):
+        start, step = si.grid(ln, n)
+        lines.append(g.line_from_terms(ln["lambda0"], ln["Jl"], ln["gl"], ln["Ju"], ln["gu"]))
+        grids.append(g.grid(start, step, n))
+        olines.append(oracle.make_line(ln["lambda0"], ln["Jl"], ln["gl"], ln["Ju"], ln["gu"],
+                                       start, step, n))
+    return lines, grids, olines
+
+
+def _errors(params, truth):
+    """p50/p90/p99 of |estimate - truth| per parameter (azimuth modulo 180
+    deg; the angles only where B_truth >= 100 G)."""
+    d = np.abs(params - truth)
+    d[:, 2] = np.minimum(d[:, 2], 180.0 - d[:, 2])
+    strong = truth[:, 0] >= 100.0
+    import synth_inputs as si
+    out = {}
+    for j, name in enumerate(si.PARAM_NAMES):
+        x = d[strong, j] if name in ("incl", "azim") else d[:, j]
+        out[name] = {q: float(np.percentile(x, int(q[1:]))) for q in ("p50", "p90", "p99")}
+    return out
+
+
+def disc_workload(args):
+    """The full-disc map in DISC_BLOCKS scanline blocks (see the module
+    docstring); returns the JSON record."""
+    import torch
+    import oracle
+    import paper_1208_0302_amd as g
+    from paper_1208_0302_amd import build as gbuild
+    import synth_inputs as si
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    truth, mu_np, _ = si.full_disc(2048, seed=0, stride=1)
+    npix = truth.shape[0]
+    print("disc: %d on-disc pixels (%.1f s)" % (npix, time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+    lines, grids, olines = _lineset(g, si)
+    f64 = dict(dtype=torch.float64, device=dev)
+    mu64 = torch.tensor(mu_np, **f64)
+    obs64 = g.me_synth(torch.tensor(truth, **f64), lines, grids, mu=mu64)
+    sig64 = torch.tensor(si.sigma_for(truth, mu=mu_np), **f64)
+    obs32, sig32, mu32 = obs64.float(), sig64.float(), mu64.float()
+    torch.cuda.synchronize()
+    # certify a seeded subset of the device-made observations against the oracle
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(npix, DISC_CERT_PIXELS, replace=False))
+    ref = oracle.me_synth(truth[idx], olines, mu_np[idx])
+    ic = (truth[idx, 7] + mu_np[idx] * truth[idx, 8])[:, None, None]
+    it = torch.tensor(idx, device=dev)
+    cert64 = float(np.max(np.abs(obs64[it].cpu().numpy() - ref) / ic))
+    cert32 = float(np.max(np.abs(obs32[it].double().cpu().numpy() - ref) / ic))
+    print("disc: observations vs oracle on %d pixels: FP64 %.2e Ic, as FP32 %.2e Ic"
+          % (DISC_CERT_PIXELS, cert64, cert32), file=sys.stderr, flush=True)
+    assert cert64 < 1e-10 and cert32 < 1e-6, (cert64, cert32)
+
+    w = DISC_GA
+    b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
+    edges = [npix * k // DISC_BLOCKS for k in range(DISC_BLOCKS + 1)]
+
+    def launch(k):
+        s0, s1 = edges[k], edges[k + 1]
+        cfg = g.GAConfig(pop=w["pop"], generations=w["generations"], tournament_k=w["k"],
+                         p_cross=w["p_cross"], p_mut=w["p_mut"], seed=w["seed"], pixel_base=s0)
+        r = g.ga_invert(obs32[s0:s1], sig32[s0:s1], lines, grids, b, cfg, mu=mu32[s0:s1],
+                        want_status=False)
+        return r
+
+    def refine(k, r):
+        s0, s1 = edges[k], edges[k + 1]
+        return g.me_refine_f64(obs64[s0:s1], sig64[s0:s1], lines, grids, b,
+                               r["params"].double(), w["refine"], mu=mu64[s0:s1])
+
+    for i in range(args.warmup):
+        refine(i % DISC_BLOCKS, launch(i % DISC_BLOCKS))
+        torch.cuda.synchronize()
+        print("warmup %d done" % i, file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream(dev)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    ga_out, ref_out = {}, {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done_px = 0
+    for i in range(args.steps):
+        k = i % DISC_BLOCKS
+        ev[i][0].record(stream)
+        r = launch(k)
+        ev[i][1].record(stream)
+        m = refine(k, r)
+        ev[i][2].record(stream)
+        ga_out[k], ref_out[k] = r["params"], m["params"]
+        done_px += edges[k + 1] - edges[k]
+        if i + 1 < args.steps:
+            # progress line from the work itself: the previous step has ended
+            ev[i][0].synchronize()
+            print("step %d/%d (block %d) issued; step %d done" % (i + 1, args.steps, k, i),
+                  file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ga_ms = np.array([e[0].elapsed_time(e[1]) for e in ev])
+    step_ms = np.array([e[0].elapsed_time(e[2]) for e in ev])
+    print("steps done: ga kernel ms %s, step ms %s" % (np.round(ga_ms, 1).tolist(),
+                                                       np.round(step_ms, 1).tolist()),
+          file=sys.stderr, flush=True)
+    blocks = sorted(ref_out)
+    sel = np.concatenate([np.arange(edges[k], edges[k + 1]) for k in blocks])
+    est = np.concatenate([ref_out[k].cpu().numpy() for k in blocks])
+    est_ga = np.concatenate([ga_out[k].double().cpu().numpy() for k in blocks])
+    acc = _errors(est, truth[sel])
+    acc_ga = _errors(est_ga, truth[sel])
+    dB = acc["B"]
+    accuracy = {"p50_abs_dB_G": dB["p50"], "p90_abs_dB_G": dB["p90"], "p99_abs_dB_G": dB["p99"],
+                "gate_p90_dB_le_10G": bool(dB["p90"] <= 10.0), "pixels": int(len(sel)),
+                "per_parameter": acc, "ga_only": acc_ga,
+                "observations_vs_oracle_max_over_Ic": {"fp64": cert64, "fp32": cert32,
+                                                       "pixels": DISC_CERT_PIXELS}}
+    lg = list(zip(lines, grids))
+    fpe = flops_per_eval(lg)
+    evals = np.array([(edges[(i % DISC_BLOCKS) + 1] - edges[i % DISC_BLOCKS])
+                      * w["pop"] * (w["generations"] + 1) for i in range(args.steps)])
+    achieved = float((evals * fpe).sum() / (ga_ms.sum() / 1e3))
+    desc = ("full disc 2048^2: %d on-disc px in %d scanline blocks of %d-%d px x [%s], pop %d, "
+            "G %d, k %d, p_mut %.2f, p_cross %.2f, FP32 GA + %d FP64 Levenberg-Marquardt "
+            "iterations, noise-free observations"
+            % (npix, DISC_BLOCKS, min(np.diff(edges)), max(np.diff(edges)),
+               "; ".join("%.4f A (%d comp) x %d" % (ln.lambda0_A, ln.ncomp, gr.n)
+                         for ln, gr in lg),
+               w["pop"], w["generations"], w["k"], w["p_mut"], w["p_cross"], w["refine"]))
+    out = {
+        "metric": METRIC,
+        "value": done_px / wall,
+        "unit": "pixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (smooth random parameter fields with 20-px correlation plus 1 % "
+                "strong-field patches on a 2048^2 disc, mu from the disc position, noise-free "
+                "observations from the FP64 forward model)",
+        "config": {"workload": desc, "npix": npix, "blocks": DISC_BLOCKS,
+                   "pixels_timed": done_px, "pop": w["pop"], "generations": w["generations"],
+                   "seed": w["seed"], "refine_iterations": w["refine"]},
+        "me_evals_per_s": float(evals.sum() / (ga_ms.sum() / 1e3)),
+        "tile_ms_p50": float(np.percentile(step_ms, 50)),
+        "tile_ms_p99": float(np.percentile(step_ms, 99)),
+        "ga_kernel_ms": float(ga_ms.mean()),
+        "refine_ms": float((step_ms - ga_ms).mean()),
+        "accuracy": accuracy,
+        "layout": gbuild.layout(),
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12,
+                     "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VALU,
+                     "traffic": disc_traffic(edges),
+                     "kernel": "k_ga_invert<float>", "flop_per_eval": fpe,
+                     "evals_per_launch": float(evals.mean())},
+    }
+    if not args.no_cpu_baseline:
+        sample = idx[np.random.default_rng(1).permutation(len(idx))]
+        out["cpu_baseline"] = cpu_baseline(dict(w, name="disc"), truth[sample], olines,
+                                           args.cpu_budget, mu=mu_np[sample])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=DISC_BLOCKS)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="slit")
+    ap.add_argument("--workload", default="disc",
+                    help="disc (default), slit, tiny, precision, serving, proposal, fill")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--rate", type=float, default=2.0, help="serving: requests per second")
@@ -691,12 +924,13 @@ def main():
     ap.add_argument("--max-resident-pixels", type=int, default=0,
                     help="serving: resident-pixel cap of the admission (0: memory budget only)")
     ap.add_argument("--disc-stride", type=int, default=16,
-                    help="disc: keep every n-th on-disc pixel of the 2048^2 map")
+                    help="precision: keep every n-th on-disc pixel of the 2048^2 map")
     ap.add_argument("--batch", type=int, default=4096, help="proposal: training batch")
     ap.add_argument("--lr", type=float, default=2e-3, help="proposal: Adam learning rate")
     ap.add_argument("--heldout", type=int, default=16384, help="proposal: held-out pixels")
     ap.add_argument("--strategies", default="random,seeded,physics,polarity_box,prefit_box,"
-                    "physics_in_box,sobol,sobol_restart",
+                    "physics_in_box,sobol,sobol_restart," + ",".join(SEED_STRATEGIES) +
+                    ",four_seeds,four_seeds_polarity",
                     help="proposal: initial-population strategies to compare")
     ap.add_argument("--chi2-target", type=float, default=1.2,
                     help="proposal: reduced chi-square target")
@@ -725,8 +959,11 @@ def main():
     if args.workload == "proposal":
         proposal(args)
         return
+    if args.workload == "precision":
+        precision_study(args)
+        return
     if args.workload == "disc":
-        disc(args)
+        print(json.dumps(disc_workload(args)), flush=True)
         return
     if args.workload == "fill":
         fill_workload(args)
@@ -824,6 +1061,7 @@ def main():
         "ga_kernel_ms": float(ga_ms.mean()),
         "refine_ms": float((step_ms - ga_ms).mean()),
         "accuracy": acc,
+        "layout": __import__("paper_1208_0302_amd.build", fromlist=["layout"]).layout(),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": (TRAFFIC_SLIT_BYTES if w["name"] == "slit" and dt == torch.float32

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define GENESIS_ABI_VERSION 4
+#define GENESIS_ABI_VERSION 5
 #define GENESIS_NPAR 9
 #define GENESIS_MAX_COMP 32   /* Zeeman components per line */
 #define GENESIS_MAX_LINES 4
@@ -90,11 +90,12 @@ typedef struct {
  *  generations  G >= 0 iterations after the initial evaluation
  *  tournament_k contestants per tournament, 1 .. min(pop, GENESIS_MAX_K)
  *  n_seeded     individuals 0 .. n_seeded-1 of generation 0 start from a
- *               first guess per pixel instead of random genes (Sec. 5.5
- *               seeds the population with first guesses): individual 0 is
- *               seed_params[p] encoded exactly, individual i >= 1 adds to
- *               each gene a uniform integer in [-seed_jitter, seed_jitter]
- *               (stream purpose 5), clamped to [0, 65535]; 0 = no seeding
+ *               first guess of the pixel instead of random genes (Sec. 5.5
+ *               seeds the population with first guesses): individual i
+ *               encodes guess i mod S of the pixel's S = seed_sets guesses,
+ *               exactly for i < S; individual i >= S adds to each gene a
+ *               uniform integer in [-seed_jitter, seed_jitter] (stream
+ *               purpose 5), clamped to [0, 65535]; 0 = no seeding
  *  p_cross      probability of single-point crossover of a pair
  *  p_mut        mean per-bit mutation probability r; bit k (0 = MSB) flips
  *               with probability 2 r (k + 1) / 17
@@ -103,9 +104,11 @@ typedef struct {
  *               pixel_base + p, so a map split into calls reproduces the
  *               single-call result
  *  seed_jitter  see n_seeded, 0 .. 32767
- *  seed_params  [npix][9] device array of first guesses (parameter units),
- *               used when n_seeded > 0; a NaN entry leaves that parameter's
- *               gene as drawn for an unseeded individual
+ *  seed_params  [npix][S][9] device array of first guesses (parameter
+ *               units), used when n_seeded > 0; a NaN entry leaves that
+ *               parameter's gene as drawn for an unseeded individual
+ *  seed_sets    S, the first guesses per pixel in seed_params (0 reads as 1;
+ *               at most GENESIS_MAX_POP); e.g. the four me_seeds guesses
  *  synth_precision  arithmetic of the profile synthesis inside ga_invert:
  *               GENESIS_SYNTH_NATIVE (that of the entry point) or
  *               GENESIS_SYNTH_FP16 (FP32 entry point only: Voigt and
@@ -147,7 +150,7 @@ typedef struct {
     int32_t synth_precision;
     int32_t init_mode;
     int32_t restart_every;
-    int32_t reserved[1];
+    int32_t seed_sets;
     const float *pixel_bounds;
 } ga_config;
 
@@ -351,6 +354,36 @@ int ga_invert_fill_f64(const double *obs, const double *sigma, const double *mu,
 int me_first_guess(const double *obs, const double *mu, int64_t npix, const me_line *lines,
                    const me_grid *grids, int32_t nlines, const me_bounds *bounds, float *params,
                    void *stream);
+
+/* The four separate first guesses of Sec. 5.5, seeds [npix][4][9] (float,
+ * parameter units; NaN = a parameter the seed leaves to the random draw),
+ * for ga_config.seed_params with seed_sets = 4.  All four share the
+ * thermodynamic estimates of me_first_guess (v_los, Doppler width, damping,
+ * eta0, S0, S1); per line with I', I'' the sample differences (I' one-sided
+ * at the window ends, I'' = 0 there), cg = C gbar, a = cg^2, summed over the
+ * samples of every line:
+ *   0 weak field (Auer et al.): least squares of V = -cg B_par I' and
+ *     (Q, U) = -(1/4) a B_perp^2 (cos 2chi, sin 2chi) I'';
+ *   1 integral relations (Ronan et al.): the same relations integrated,
+ *     |B_par| = sum |V| / sum cg |I'| with the sign of -sum cg V I',
+ *     B_perp^2 = 4 sum sqrt(Q^2 + U^2) / sum a |I''|, and the azimuth from the
+ *     principal axis of the (Q, U) second moments, chi0 = atan2(2 sum QU,
+ *     sum (Q^2 - U^2)) / 4 or chi0 + 90 deg, whichever has a projection
+ *     Q cos 2chi + U sin 2chi <= 0 over the three samples around each line's
+ *     minimum of I (where the pi component makes Q ~ -cos 2chi);
+ *   2 centre of gravity (Rees & Semel): B = |B_par| of me_first_guess,
+ *     inclination 0 or 180 by its sign, azimuth NaN;
+ *   3 non-magnetic (full-disc runs): B = 0, both angles NaN.
+ * Seeds 0 and 1 take B = hypot(B_par, B_perp), inclination atan2(B_perp,
+ * B_par).  Each seed is made consistent with the pixel's box (pixel_bounds
+ * [npix][2][9] as in ga_config, e.g. the polarity restriction, or the common
+ * box when NULL): a non-finite B or thermodynamic value becomes the middle of
+ * the box, the azimuth wraps into [0, 180), an inclination outside the box
+ * becomes 180 minus itself, and every seeded value is clamped into the box.
+ * Same requirements as me_first_guess. */
+int me_seeds(const double *obs, const double *mu, int64_t npix, const me_line *lines,
+             const me_grid *grids, int32_t nlines, const me_bounds *bounds,
+             const float *pixel_bounds, float *seeds, void *stream);
 
 /* Levenberg-Marquardt refinement in FP64 of one model per pixel, the local
  * least-squares polish of the genetic algorithm's best individual (the

@@ -207,6 +207,7 @@ def seeds(obs, lines, lo, hi, mu=None, box=None):
             s["cQ"] += Q[max(c - 1, 0):c + 2].sum()
             s["cU"] += U[max(c - 1, 0):c + 2].sum()
         th = comb[p, 3:]
+        cb = _cog_bpar(obs[p], lines)
         # weak field
         bpar = -s["vI"] / s["I2"]
         q = -4.0 * s["aQ"] / s["a2"]
@@ -222,12 +223,35 @@ def seeds(obs, lines, lo, hi, mu=None, box=None):
             chi0 += 0.5 * np.pi
         ir = [np.hypot(ipar, iperp), np.degrees(np.arctan2(iperp, ipar)), np.degrees(chi0)]
         # centre of gravity: the longitudinal estimate of first_guess
-        cb = comb[p, 0] * np.cos(np.radians(comb[p, 1]))   # B_par as first_guess formed it
         cog = [abs(cb), 0.0 if cb >= 0 else 180.0, np.nan]
         for k, mag in enumerate((wf, ir, cog, [0.0, np.nan, np.nan])):
             v = np.concatenate([np.asarray(mag, np.float64), th])
             out[p, k] = _consistent(v, blo, bhi)
     return out
+
+
+def _cog_bpar(obs_p, lines):
+    """first_guess's centre-of-gravity longitudinal field of one pixel: the
+    per-line estimates (x_cog(d+) - x_cog(d-)) / (2 C gbar) combined with the
+    weights W gbar."""
+    Ic = obs_p[0].max()
+    off = 0
+    Wg = WgB = 0.0
+    for ln in lines:
+        n = ln.nlam
+        I, V = obs_p[0, off:off + n], obs_p[3, off:off + n]
+        off += n
+        x = (ln.start - ln.lambda0) + ln.step * np.arange(n)
+        d = Ic - I
+        dp = Ic - (I + V)
+        dm = Ic - (I - V)
+        C = ZEEMAN * ln.lambda0 ** 2
+        g = gbar_of(ln)
+        bpar = ((x * dp).sum() / dp.sum() - (x * dm).sum() / dm.sum()) / (2 * C * g)
+        W = ln.step * d.sum()
+        Wg += W * g
+        WgB += W * g * bpar
+    return WgB / Wg
 
 
 def _consistent(v, blo, bhi):

@@ -78,7 +78,7 @@ class GaConfigC(C.Structure):
                 ("seed", C.c_uint64), ("pixel_base", C.c_uint32), ("seed_jitter", C.c_int32),
                 ("seed_params", C.c_void_p), ("synth_precision", C.c_int32),
                 ("init_mode", C.c_int32), ("restart_every", C.c_int32),
-                ("reserved", C.c_int32 * 1), ("pixel_bounds", C.c_void_p)]
+                ("seed_sets", C.c_int32), ("pixel_bounds", C.c_void_p)]
 
 
 @dataclasses.dataclass
@@ -93,7 +93,7 @@ class GAConfig:
     pixel_base: int = 0
     n_seeded: int = 0
     seed_jitter: int = 0
-    seed_params: Optional[torch.Tensor] = None   # [npix, 9] float32 device tensor
+    seed_params: Optional[torch.Tensor] = None   # [npix, 9] or [npix, S, 9] float32 device tensor
     synth_precision: int = 0                     # SYNTH_NATIVE or SYNTH_FP16
     init_mode: int = 0                           # 0 uniform random, 1 Sobol
     restart_every: int = 0                       # 0: no restarts
@@ -115,9 +115,12 @@ class GAConfig:
         cfg.init_mode = self.init_mode
         cfg.restart_every = self.restart_every
         if self.seed_params is not None:
-            _dev(self.seed_params, torch.float32, "seed_params",
-                 None if npix is None else (npix, NPAR))
-            cfg.seed_params = self.seed_params.data_ptr()
+            sp = self.seed_params
+            S = 1 if sp.dim() == 2 else sp.shape[1]
+            _dev(sp, torch.float32, "seed_params",
+                 None if npix is None else ((npix, NPAR) if sp.dim() == 2 else (npix, S, NPAR)))
+            cfg.seed_params = sp.data_ptr()
+            cfg.seed_sets = S
         if self.pixel_bounds is not None:
             _dev(self.pixel_bounds, torch.float32, "pixel_bounds",
                  None if npix is None else (npix, 2, NPAR))
@@ -168,6 +171,7 @@ _SIGS = {
     "ga_population_steps": ([_vp, _vp, _i64, _i32, _bp, _vp, _vp, _vp], C.c_int),
     "ga_population_steps_f64": ([_vp, _vp, _i64, _i32, _bp, _vp, _vp, _vp], C.c_int),
     "me_first_guess": ([_vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _vp], C.c_int),
+    "me_seeds": ([_vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _vp, _vp], C.c_int),
     "me_synth_fill": ([_vp, _vp, _i64, _lp, _gp, _i32, _vp, C.POINTER(MeFill), _vp, _vp],
                       C.c_int),
     "me_synth_fill_f64": ([_vp, _vp, _i64, _lp, _gp, _i32, _vp, C.POINTER(MeFill), _vp, _vp],
@@ -208,7 +212,7 @@ _SIGS = {
 }
 
 EXPORTED = tuple(_SIGS)
-ABI_VERSION = 4
+ABI_VERSION = 5
 STRUCTS = (("me_line", MeLine), ("me_grid", MeGrid), ("me_bounds", MeBounds),
            ("ga_config", GaConfigC), ("me_fill", MeFill))
 
@@ -506,6 +510,25 @@ def me_first_guess(obs, lines, grids, bnds: MeBounds, mu=None):
     la, ga, nl = _lines(lines, grids)
     _check(lib().me_first_guess(_ptr(obs), _ptr(mu), npix, la, ga, nl, C.byref(bnds), _ptr(out),
                                 _stream(obs)))
+    return out
+
+
+SEED_NAMES = ("weak_field", "integral", "centre_of_gravity", "non_magnetic")
+
+
+def me_seeds(obs, lines, grids, bnds: MeBounds, mu=None, pixel_bounds=None):
+    """The four Sec. 5.5 first guesses [npix, 4, 9] (float32; order
+    SEED_NAMES, NaN = left random) of observations [npix, 4, L] (float64),
+    consistent with pixel_bounds [npix, 2, 9] (float32) when given."""
+    npix = obs.shape[0]
+    L = total_samples(grids)
+    _dev(obs, torch.float64, "obs", (npix, 4, L))
+    _dev(mu, torch.float64, "mu", (npix,))
+    _dev(pixel_bounds, torch.float32, "pixel_bounds", (npix, 2, NPAR))
+    out = torch.empty((npix, 4, NPAR), dtype=torch.float32, device=obs.device)
+    la, ga, nl = _lines(lines, grids)
+    _check(lib().me_seeds(_ptr(obs), _ptr(mu), npix, la, ga, nl, C.byref(bnds),
+                          _ptr(pixel_bounds), _ptr(out), _stream(obs)))
     return out
 
 

@@ -119,6 +119,9 @@ int pack_ga(const ga_config *cfg, GaConst &ga)
         return fail(ME_EINVAL, "seed_jitter = %d outside [0, 32767]", cfg->seed_jitter);
     if (cfg->n_seeded > 0 && !cfg->seed_params)
         return fail(ME_EINVAL, "n_seeded > 0 needs seed_params");
+    if (cfg->seed_sets < 0 || cfg->seed_sets > GENESIS_MAX_POP)
+        return fail(ME_EINVAL, "seed_sets = %d outside [0, %d]", cfg->seed_sets,
+                    GENESIS_MAX_POP);
     if (cfg->synth_precision != GENESIS_SYNTH_NATIVE && cfg->synth_precision != GENESIS_SYNTH_FP16)
         return fail(ME_EINVAL, "synth_precision = %d is not a GENESIS_SYNTH_* value",
                     cfg->synth_precision);
@@ -131,6 +134,7 @@ int pack_ga(const ga_config *cfg, GaConst &ga)
     ga.n_seeded = cfg->n_seeded;
     ga.seed_jitter = cfg->seed_jitter;
     ga.seed_params = cfg->n_seeded > 0 ? cfg->seed_params : nullptr;
+    ga.seed_sets = cfg->seed_sets > 0 ? cfg->seed_sets : 1;
     ga.pixel_bounds = cfg->pixel_bounds;
     return ME_OK;
 }
@@ -853,85 +857,252 @@ __global__ __launch_bounds__(kGuessThreads) void k_search_box(BoxArgs a)
     }
 }
 
+// The first guesses of one pixel (all threads call; the result is valid on
+// thread 0): g9 clamped into the common box, and the centre-of-gravity
+// longitudinal field before any clamping.
+__device__ void first_guess_pixel(const GuessArgs &a, int64_t p, double *red,
+                                  double (&g9)[GENESIS_NPAR], double &bpar_cog)
+{
+    const int L = a.ls.L;
+    const double *I = a.obs + p * 4 * (int64_t)L, *Q = I + L, *U = I + 2 * L, *V = I + 3 * L;
+    double m = -INFINITY;
+    for (int j = threadIdx.x; j < L; j += kGuessThreads)
+        m = fmax(m, I[j]);
+    const double Ic = guess_reduce(m, true, red);
+    double W = 0, Wv = 0, Wg = 0, WgB = 0, Wg2 = 0, Wq = 0, Wu = 0, Whw = 0, depth = 0;
+    for (int l = 0; l < a.ls.nlines; ++l) {
+        const DevLine<double> &ln = a.ls.l[l];
+        const double *Il = I + ln.off;
+        double mx = -INFINITY;
+        for (int j = threadIdx.x; j < ln.nlam; j += kGuessThreads)
+            mx = fmax(mx, Ic - Il[j]);
+        const double dmax = guess_reduce(mx, true, red);
+        double acc[kGuessSums] = {};
+        for (int j = threadIdx.x; j < ln.nlam; j += kGuessThreads) {
+            const double x = ln.off0 + ln.step * j;
+            const double i0 = Il[j], v = V[ln.off + j];
+            const double d = Ic - i0, dp = Ic - (i0 + v), dm = Ic - (i0 - v);
+            const double d2 = (j > 0 && j + 1 < ln.nlam)
+                                  ? (Il[j + 1] - 2.0 * i0 + Il[j - 1]) / (ln.step * ln.step)
+                                  : 0.0;
+            acc[0] += d;
+            acc[1] += x * d;
+            acc[2] += dp;
+            acc[3] += x * dp;
+            acc[4] += dm;
+            acc[5] += x * dm;
+            acc[6] += Q[ln.off + j] * d2;
+            acc[7] += U[ln.off + j] * d2;
+            acc[8] += d2 * d2;
+            acc[9] += d >= 0.5 * dmax ? 1.0 : 0.0;
+        }
+        double tot[kGuessSums];
+#pragma unroll
+        for (int k = 0; k < kGuessSums; ++k)
+            tot[k] = guess_reduce(acc[k], false, red);
+        const double lam0 = ln.dop_kms * kCkms;
+        const double C = kZeeman * lam0 * lam0, g = a.gbar[l];
+        const double xc = tot[1] / tot[0];
+        const double bpar = (tot[3] / tot[2] - tot[5] / tot[4]) / (2.0 * C * g);
+        const double qq = -4.0 * tot[6] / (C * C * g * g * tot[8]);
+        const double uu = -4.0 * tot[7] / (C * C * g * g * tot[8]);
+        const double hw = 0.5 * ln.step * tot[9];
+        const double Wl = ln.step * tot[0];
+        W += Wl;
+        Wv += Wl * kCkms * xc / lam0;
+        Wg += Wl * g;
+        WgB += Wl * g * bpar;
+        Wg2 += Wl * g * g;
+        Wq += Wl * g * g * qq;
+        Wu += Wl * g * g * uu;
+        Whw += Wl * hw;
+        depth = fmax(depth, dmax / Ic);
+    }
+    const double bpar = WgB / Wg, q = Wq / Wg2, u = Wu / Wg2;
+    bpar_cog = bpar;
+    const double bperp = sqrt(hypot(q, u));
+    double azim = 0.5 * atan2(u, q) * (180.0 / kPi);
+    azim = fmod(azim + 180.0, 180.0);
+    const double Dp = fmin(depth / 0.75, 0.97);
+    const double eta0 = Dp / (1.0 - Dp);
+    const double mu = a.mu ? a.mu[p] : 1.0;
+    const double raw[GENESIS_NPAR] = {hypot(bpar, bperp),
+                                      atan2(bperp, bpar) * (180.0 / kPi),
+                                      azim,
+                                      Wv / W,
+                                      Whw / W / sqrt(log(eta0 + 2.0)),
+                                      0.5 * (a.lo[5] + a.hi[5]),
+                                      eta0,
+                                      0.25 * Ic,
+                                      0.75 * Ic / mu};
+    for (int j = 0; j < GENESIS_NPAR; ++j) {
+        const double v = isfinite(raw[j]) ? raw[j] : 0.5 * (a.lo[j] + a.hi[j]);
+        g9[j] = fmin(fmax(v, a.lo[j]), a.hi[j]);
+    }
+}
+
 __global__ __launch_bounds__(kGuessThreads) void k_first_guess(GuessArgs a)
 {
     __shared__ double red[kGuessThreads / 64];
+    for (int64_t p = blockIdx.x; p < a.npix; p += gridDim.x) {
+        double g9[GENESIS_NPAR], bpar;
+        first_guess_pixel(a, p, red, g9, bpar);
+        if (threadIdx.x == 0)
+            for (int j = 0; j < GENESIS_NPAR; ++j)
+                a.params[p * GENESIS_NPAR + j] = (float)g9[j];
+        __syncthreads();
+    }
+}
+
+// ---- the four separate seeds of Sec. 5.5 ---------------------------------
+//
+// Per pixel, with the thermodynamic estimates of the first guesses (v_los,
+// Doppler width, damping, eta0, S0, S1) shared by all four, per line I', I''
+// the differences of the first guesses (I' one-sided at the window ends),
+// cg = C gbar and a = cg^2, summed over every line's samples:
+//  0 weak field: B_par = -sum cg V I' / sum (cg I')^2, q = -4 sum a Q I'' /
+//    sum (a I'')^2 (u likewise), B_perp = sqrt(hypot(q, u)), azimuth
+//    atan2(u, q) / 2;
+//  1 integral relations: |B_par| = sum |V| / sum cg |I'| with the sign of
+//    -sum cg V I', B_perp = sqrt(4 sum sqrt(Q^2 + U^2) / sum a |I''|), and
+//    the azimuth chi0 = atan2(2 sum Q U, sum (Q^2 - U^2)) / 4 or chi0 + 90
+//    deg, the one whose projection Q cos 2chi + U sin 2chi over the three
+//    samples around each line's minimum of I is not positive;
+//  2 centre of gravity: B = |B_par| of the first guesses, inclination 0 (B_par
+//    >= 0) or 180, azimuth unseeded (NaN);
+//  3 non-magnetic: B = 0, both angles unseeded;
+// B = hypot(B_par, B_perp), inclination atan2(B_perp, B_par) for 0 and 1.
+// Then, in the pixel's box (pixel_bounds, else the common box): a non-finite
+// B or thermodynamic value becomes the middle of the box, the azimuth is
+// wrapped into [0, 180), an inclination outside the box becomes 180 minus
+// itself, and every seeded value is clamped into the box.
+constexpr int kSeedSums = 13;
+
+struct SeedArgs {
+    GuessArgs g;
+    const float *box;  // [npix][2][9] or nullptr
+    float *seeds;      // [npix][4][9]
+};
+
+__global__ __launch_bounds__(kGuessThreads) void k_seeds(SeedArgs sa)
+{
+    const GuessArgs &a = sa.g;
+    __shared__ double red[kGuessThreads / 64];
     const int L = a.ls.L;
     for (int64_t p = blockIdx.x; p < a.npix; p += gridDim.x) {
+        double g9[GENESIS_NPAR], bcog;
+        first_guess_pixel(a, p, red, g9, bcog);
         const double *I = a.obs + p * 4 * (int64_t)L, *Q = I + L, *U = I + 2 * L, *V = I + 3 * L;
-        double m = -INFINITY;
-        for (int j = threadIdx.x; j < L; j += kGuessThreads)
-            m = fmax(m, I[j]);
-        const double Ic = guess_reduce(m, true, red);
-        double W = 0, Wv = 0, Wg = 0, WgB = 0, Wg2 = 0, Wq = 0, Wu = 0, Whw = 0, depth = 0;
+        double tot[kSeedSums] = {};
         for (int l = 0; l < a.ls.nlines; ++l) {
             const DevLine<double> &ln = a.ls.l[l];
+            const int n = ln.nlam;
             const double *Il = I + ln.off;
-            double mx = -INFINITY;
-            for (int j = threadIdx.x; j < ln.nlam; j += kGuessThreads)
-                mx = fmax(mx, Ic - Il[j]);
-            const double dmax = guess_reduce(mx, true, red);
-            double acc[kGuessSums] = {};
-            for (int j = threadIdx.x; j < ln.nlam; j += kGuessThreads) {
-                const double x = ln.off0 + ln.step * j;
-                const double i0 = Il[j], v = V[ln.off + j];
-                const double d = Ic - i0, dp = Ic - (i0 + v), dm = Ic - (i0 - v);
-                const double d2 = (j > 0 && j + 1 < ln.nlam)
-                                      ? (Il[j + 1] - 2.0 * i0 + Il[j - 1]) / (ln.step * ln.step)
-                                      : 0.0;
-                acc[0] += d;
-                acc[1] += x * d;
-                acc[2] += dp;
-                acc[3] += x * dp;
-                acc[4] += dm;
-                acc[5] += x * dm;
-                acc[6] += Q[ln.off + j] * d2;
-                acc[7] += U[ln.off + j] * d2;
-                acc[8] += d2 * d2;
-                acc[9] += d >= 0.5 * dmax ? 1.0 : 0.0;
-            }
-            double tot[kGuessSums];
-#pragma unroll
-            for (int k = 0; k < kGuessSums; ++k)
-                tot[k] = guess_reduce(acc[k], false, red);
+            // the line's minimum of I, first sample on ties
+            double mn = -INFINITY;
+            for (int j = threadIdx.x; j < n; j += kGuessThreads)
+                mn = fmax(mn, -Il[j]);
+            mn = guess_reduce(mn, true, red);
+            double ci = -INFINITY;
+            for (int j = threadIdx.x; j < n; j += kGuessThreads)
+                if (-Il[j] == mn)
+                    ci = fmax(ci, -(double)j);
+            const int c = (int)(-guess_reduce(ci, true, red));
             const double lam0 = ln.dop_kms * kCkms;
-            const double C = kZeeman * lam0 * lam0, g = a.gbar[l];
-            const double xc = tot[1] / tot[0];
-            const double bpar = (tot[3] / tot[2] - tot[5] / tot[4]) / (2.0 * C * g);
-            const double qq = -4.0 * tot[6] / (C * C * g * g * tot[8]);
-            const double uu = -4.0 * tot[7] / (C * C * g * g * tot[8]);
-            const double hw = 0.5 * ln.step * tot[9];
-            const double Wl = ln.step * tot[0];
-            W += Wl;
-            Wv += Wl * kCkms * xc / lam0;
-            Wg += Wl * g;
-            WgB += Wl * g * bpar;
-            Wg2 += Wl * g * g;
-            Wq += Wl * g * g * qq;
-            Wu += Wl * g * g * uu;
-            Whw += Wl * hw;
-            depth = fmax(depth, dmax / Ic);
+            const double C = kZeeman * lam0 * lam0, cg = C * a.gbar[l], aa = cg * cg;
+            const double st = ln.step;
+            double acc[kSeedSums] = {};
+            for (int j = threadIdx.x; j < n; j += kGuessThreads) {
+                const double i0 = Il[j], q = Q[ln.off + j], u = U[ln.off + j], v = V[ln.off + j];
+                const double d1 = j == 0       ? (Il[1] - Il[0]) / st
+                                  : j == n - 1 ? (Il[n - 1] - Il[n - 2]) / st
+                                               : (Il[j + 1] - Il[j - 1]) / (2.0 * st);
+                const double d2 = (j > 0 && j + 1 < n) ? (Il[j + 1] - 2.0 * i0 + Il[j - 1]) / (st * st)
+                                                       : 0.0;
+                acc[0] += v * d1;
+                acc[1] += (cg * d1) * (cg * d1);
+                acc[2] += q * d2;
+                acc[3] += u * d2;
+                acc[4] += (aa * d2) * (aa * d2);
+                acc[5] += fabs(v);
+                acc[6] += fabs(d1);
+                acc[7] += sqrt(q * q + u * u);
+                acc[8] += fabs(d2);
+                acc[9] += q * u;
+                acc[10] += q * q - u * u;
+                if (j >= c - 1 && j <= c + 1) {
+                    acc[11] += q;
+                    acc[12] += u;
+                }
+            }
+            double t[kSeedSums];
+#pragma unroll
+            for (int k = 0; k < kSeedSums; ++k)
+                t[k] = guess_reduce(acc[k], false, red);
+            tot[0] += t[0] * cg;
+            tot[1] += t[1];
+            tot[2] += aa * t[2];
+            tot[3] += aa * t[3];
+            tot[4] += t[4];
+            tot[5] += t[5];
+            tot[6] += cg * t[6];
+            tot[7] += t[7];
+            tot[8] += aa * t[8];
+            tot[9] += t[9];
+            tot[10] += t[10];
+            tot[11] += t[11];
+            tot[12] += t[12];
         }
         if (threadIdx.x == 0) {
-            const double bpar = WgB / Wg, q = Wq / Wg2, u = Wu / Wg2;
-            const double bperp = sqrt(hypot(q, u));
-            double azim = 0.5 * atan2(u, q) * (180.0 / kPi);
-            azim = fmod(azim + 180.0, 180.0);
-            const double Dp = fmin(depth / 0.75, 0.97);
-            const double eta0 = Dp / (1.0 - Dp);
-            const double mu = a.mu ? a.mu[p] : 1.0;
-            const double g9[GENESIS_NPAR] = {hypot(bpar, bperp),
-                                             atan2(bperp, bpar) * (180.0 / kPi),
-                                             azim,
-                                             Wv / W,
-                                             Whw / W / sqrt(log(eta0 + 2.0)),
-                                             0.5 * (a.lo[5] + a.hi[5]),
-                                             eta0,
-                                             0.25 * Ic,
-                                             0.75 * Ic / mu};
+            const double r2d = 180.0 / kPi;
+            double blo[GENESIS_NPAR], bhi[GENESIS_NPAR];
             for (int j = 0; j < GENESIS_NPAR; ++j) {
-                const double v = isfinite(g9[j]) ? g9[j] : 0.5 * (a.lo[j] + a.hi[j]);
-                a.params[p * GENESIS_NPAR + j] = (float)fmin(fmax(v, a.lo[j]), a.hi[j]);
+                blo[j] = sa.box ? (double)sa.box[(p * 2) * GENESIS_NPAR + j] : a.lo[j];
+                bhi[j] = sa.box ? (double)sa.box[(p * 2 + 1) * GENESIS_NPAR + j] : a.hi[j];
+            }
+            // weak field
+            const double bpar = -tot[0] / tot[1];
+            const double q = -4.0 * tot[2] / tot[4], u = -4.0 * tot[3] / tot[4];
+            const double bperp = sqrt(hypot(q, u));
+            // integral relations
+            const double ipar = fabs(tot[5] / tot[6]) * (-tot[0] >= 0.0 ? 1.0 : -1.0);
+            const double iperp = sqrt(4.0 * tot[7] / tot[8]);
+            double chi0 = 0.25 * atan2(2.0 * tot[9], tot[10]);
+            if (tot[11] * cos(2.0 * chi0) + tot[12] * sin(2.0 * chi0) > 0.0)
+                chi0 += 0.5 * kPi;
+            const double mag[4][3] = {
+                {hypot(bpar, bperp), atan2(bperp, bpar) * r2d, 0.5 * atan2(u, q) * r2d},
+                {hypot(ipar, iperp), atan2(iperp, ipar) * r2d, chi0 * r2d},
+                {fabs(bcog), bcog >= 0.0 ? 0.0 : 180.0, NAN},
+                {0.0, NAN, NAN}};
+            for (int k = 0; k < 4; ++k) {
+                double v[GENESIS_NPAR];
+                for (int j = 0; j < 3; ++j)
+                    v[j] = mag[k][j];
+                for (int j = 3; j < GENESIS_NPAR; ++j)
+                    v[j] = g9[j];
+                bool seeded[GENESIS_NPAR];
+                for (int j = 0; j < GENESIS_NPAR; ++j)
+                    seeded[j] = !isnan(v[j]);
+                seeded[0] = true;
+                if (!isfinite(v[0]))
+                    v[0] = 0.5 * (blo[0] + bhi[0]);
+                for (int j = 1; j <= 2; ++j)
+                    if (seeded[j] && !isfinite(v[j]))
+                        v[j] = 0.5 * (blo[j] + bhi[j]);
+                if (seeded[2]) {
+                    v[2] = fmod(v[2], 180.0);
+                    if (v[2] < 0.0)
+                        v[2] += 180.0;
+                }
+                if (seeded[1] && !(blo[1] <= v[1] && v[1] <= bhi[1]))
+                    v[1] = 180.0 - v[1];
+                for (int j = 3; j < GENESIS_NPAR; ++j)
+                    if (!isfinite(v[j]))
+                        v[j] = 0.5 * (blo[j] + bhi[j]);
+                float *o = sa.seeds + (p * 4 + k) * GENESIS_NPAR;
+                for (int j = 0; j < GENESIS_NPAR; ++j)
+                    o[j] = seeded[j] ? (float)fmin(fmax(v[j], blo[j]), bhi[j]) : NAN;
             }
         }
         __syncthreads();
@@ -1510,6 +1681,42 @@ int restart_impl(const uint16_t *genes_in, const Real *fitness, int64_t npix,
 }
 
 
+namespace {
+
+int pack_guess(const double *obs, const double *mu, int64_t npix, const me_line *lines,
+               const me_grid *grids, int32_t nlines, const me_bounds *bounds, GuessArgs &a)
+{
+    if (int rc = pack_lines(lines, grids, nlines, a.ls))
+        return rc;
+    Bounds b;
+    if (int rc = pack_bounds(bounds, b))
+        return rc;
+    for (int l = 0; l < nlines; ++l) {
+        double g = 0.0;
+        for (int c = 0; c < lines[l].ncomp; ++c)
+            if (lines[l].q[c] == 1)
+                g += (double)lines[l].strength[c] * (double)lines[l].shift[c];
+        if (!(g > 0.0))
+            return fail(ME_EINVAL, "line %d has no Zeeman splitting (first moment of the red "
+                                   "sigma group %g)", l, g);
+        a.gbar[l] = g;
+        if (grids[l].n < 3)
+            return fail(ME_EINVAL, "line %d: need at least 3 samples", l);
+    }
+    for (int j = 0; j < GENESIS_NPAR; ++j) {
+        a.lo[j] = bounds->lo[j];
+        a.hi[j] = bounds->hi[j];
+    }
+    if (npix < 0)
+        return fail(ME_EINVAL, "npix must be >= 0");
+    a.obs = obs;
+    a.mu = mu;
+    a.npix = npix;
+    return ME_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *me_last_error(void) { return g_err.c_str(); }
@@ -1839,41 +2046,35 @@ int me_search_box(const double *obs, const double *sigma, int64_t npix, const me
     return check_launch("me_search_box");
 }
 
+int me_seeds(const double *obs, const double *mu, int64_t npix, const me_line *lines,
+             const me_grid *grids, int32_t nlines, const me_bounds *bounds,
+             const float *pixel_bounds, float *seeds, void *stream)
+{
+    SeedArgs sa{};
+    if (int rc = pack_guess(obs, mu, npix, lines, grids, nlines, bounds, sa.g))
+        return rc;
+    if (npix == 0)
+        return ME_OK;
+    if (!obs || !seeds)
+        return fail(ME_EINVAL, "NULL array argument");
+    sa.box = pixel_bounds;
+    sa.seeds = seeds;
+    hipLaunchKernelGGL(k_seeds, dim3(grid_for(npix)), dim3(kGuessThreads), 0, as_stream(stream),
+                       sa);
+    return check_launch("me_seeds");
+}
+
 int me_first_guess(const double *obs, const double *mu, int64_t npix, const me_line *lines,
                    const me_grid *grids, int32_t nlines, const me_bounds *bounds, float *params,
                    void *stream)
 {
     GuessArgs a{};
-    if (int rc = pack_lines(lines, grids, nlines, a.ls))
+    if (int rc = pack_guess(obs, mu, npix, lines, grids, nlines, bounds, a))
         return rc;
-    Bounds b;
-    if (int rc = pack_bounds(bounds, b))
-        return rc;
-    for (int l = 0; l < nlines; ++l) {
-        double g = 0.0;
-        for (int c = 0; c < lines[l].ncomp; ++c)
-            if (lines[l].q[c] == 1)
-                g += (double)lines[l].strength[c] * (double)lines[l].shift[c];
-        if (!(g > 0.0))
-            return fail(ME_EINVAL, "line %d has no Zeeman splitting (first moment of the red "
-                                   "sigma group %g)", l, g);
-        a.gbar[l] = g;
-        if (grids[l].n < 3)
-            return fail(ME_EINVAL, "line %d: need at least 3 samples", l);
-    }
-    for (int j = 0; j < GENESIS_NPAR; ++j) {
-        a.lo[j] = bounds->lo[j];
-        a.hi[j] = bounds->hi[j];
-    }
-    if (npix < 0)
-        return fail(ME_EINVAL, "npix must be >= 0");
     if (npix == 0)
         return ME_OK;
     if (!obs || !params)
         return fail(ME_EINVAL, "NULL array argument");
-    a.obs = obs;
-    a.mu = mu;
-    a.npix = npix;
     a.params = params;
     hipLaunchKernelGGL(k_first_guess, dim3(grid_for(npix)), dim3(kGuessThreads), 0,
                        as_stream(stream), a);

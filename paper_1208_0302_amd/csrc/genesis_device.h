@@ -506,7 +506,8 @@ struct GaConst {
     Key key;
     uint32_t pixel_base;
     int32_t n_seeded, seed_jitter;
-    const float *seed_params;    // [npix][9] first guesses, or nullptr
+    const float *seed_params;    // [npix][seed_sets][9] first guesses, or nullptr
+    int32_t seed_sets;           // first guesses per pixel (>= 1)
     int32_t init_mode;           // 0 Philox-uniform genes, 1 Sobol points
     int32_t restart_every;       // 0: no restarts
     const float *pixel_bounds;   // [npix][2][9] per-pixel boxes (lo, hi), or nullptr
@@ -642,8 +643,8 @@ __device__ __forceinline__ void sobol_genes(uint32_t pix, uint32_t n, const Key 
 // The nine genes of individual i of pixel p (call-local index) in generation
 // 0: random (stream purpose 0) or Sobol point i (init_mode 1); for
 // i < n_seeded, every parameter whose first guess is not NaN instead takes
-// the encoded guess (exact for i = 0, integer-jittered for i >= 1, stream
-// purpose 5).
+// the encoded guess i mod S of the pixel's S = seed_sets guesses (exact for
+// i < S, integer-jittered for i >= S, stream purpose 5).
 __device__ __forceinline__ void initial_genes(uint32_t pix, int64_t p, int i, const GaConst &ga,
                                               const Bounds &b, uint32_t (&g)[GENESIS_NPAR])
 {
@@ -663,6 +664,8 @@ __device__ __forceinline__ void initial_genes(uint32_t pix, int64_t p, int i, co
     }
     if (!(i < ga.n_seeded && ga.seed_params))
         return;
+    const int S = ga.seed_sets;
+    const float *guess = ga.seed_params + (p * S + i % S) * GENESIS_NPAR;
     // seeded slot: every parameter with a finite first guess takes its code
 #pragma unroll
     for (int blk = 0; blk < 3; ++blk) {
@@ -673,13 +676,13 @@ __device__ __forceinline__ void initial_genes(uint32_t pix, int64_t p, int i, co
             const int j = 4 * blk + q;
             if (j >= GENESIS_NPAR)
                 continue;
-            const float sp = ga.seed_params[p * GENESIS_NPAR + j];
+            const float sp = guess[j];
             if (isnan(sp))
                 continue;
             double u = ((double)sp - b.lo[j]) / (b.span[j] > 0.0 ? b.span[j] : 1.0);
             u = u < 0.0 ? 0.0 : (u > 1.0 ? 1.0 : u);
             int v = (int)floor(u * 65535.0 + 0.5);
-            if (i > 0) {
+            if (i >= S) {
                 v += (int)uniform_upto(ws[q], 2u * (uint32_t)ga.seed_jitter) - ga.seed_jitter;
                 v = v < 0 ? 0 : (v > 65535 ? 65535 : v);
             }

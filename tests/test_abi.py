@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared:
         assert hasattr(L, name), name
     assert sorted(g.EXPORTED) == declared
-    assert L.genesis_abi_version() == g.ABI_VERSION == 4
+    assert L.genesis_abi_version() == g.ABI_VERSION == 5
 
 
 def test_binding_structs_match_the_library():
