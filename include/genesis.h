@@ -337,6 +337,21 @@ int ga_invert_fill_f64(const double *obs, const double *sigma, const double *mu,
 
 /* ---- FP64 refinement of a solution (non-linear least squares) ----------- */
 
+/* Inverse-max weights of Sec. 5.4 as the sigma = 1 / w that the chi-square
+ * calls take (sigma [npix][4], same precision as obs): for I the span of the
+ * observed I of the pixel (largest minus smallest over every sample of every
+ * line: continuum minus line core), for Q, U and V the largest |Q|, |U|,
+ * |V|; each at least `floor` (finite, >= 0; a Stokes parameter without
+ * signal, e.g. Q = U = V = 0 at zero field, would otherwise weigh
+ * infinitely).  obs [npix][4][L] with L the grids' total samples; a pixel
+ * with a non-finite sample gets four NaN (which ga_invert reports as status
+ * 1).  Pass the result as the sigma of ga_invert, me_chi2 or me_refine_f64
+ * to invert with this weighting instead of noise weights. */
+int me_invmax_sigma(const float *obs, int64_t npix, const me_grid *grids, int32_t nlines,
+                    double floor, float *sigma, void *stream);
+int me_invmax_sigma_f64(const double *obs, int64_t npix, const me_grid *grids, int32_t nlines,
+                        double floor, double *sigma, void *stream);
+
 /* Heuristic first guesses [npix][9] (float) from the observed Stokes vectors
  * obs [npix][4][L] (FP64), for ga_config.seed_params: the paper seeds its
  * population with weak-field, centre-of-gravity and integral estimates

@@ -172,6 +172,8 @@ _SIGS = {
     "ga_population_steps_f64": ([_vp, _vp, _i64, _i32, _bp, _vp, _vp, _vp], C.c_int),
     "me_first_guess": ([_vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _vp], C.c_int),
     "me_seeds": ([_vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _vp, _vp], C.c_int),
+    "me_invmax_sigma": ([_vp, _i64, _gp, _i32, C.c_double, _vp, _vp], C.c_int),
+    "me_invmax_sigma_f64": ([_vp, _i64, _gp, _i32, C.c_double, _vp, _vp], C.c_int),
     "me_synth_fill": ([_vp, _vp, _i64, _lp, _gp, _i32, _vp, C.POINTER(MeFill), _vp, _vp],
                       C.c_int),
     "me_synth_fill_f64": ([_vp, _vp, _i64, _lp, _gp, _i32, _vp, C.POINTER(MeFill), _vp, _vp],
@@ -510,6 +512,21 @@ def me_first_guess(obs, lines, grids, bnds: MeBounds, mu=None):
     la, ga, nl = _lines(lines, grids)
     _check(lib().me_first_guess(_ptr(obs), _ptr(mu), npix, la, ga, nl, C.byref(bnds), _ptr(out),
                                 _stream(obs)))
+    return out
+
+
+def me_invmax_sigma(obs, grids, floor=1e-6):
+    """Inverse-max weights of Sec. 5.4 as sigma [npix, 4] (the dtype of obs,
+    float32 or float64) for observations [npix, 4, L]: the span of I and the
+    largest |Q|, |U|, |V| of each pixel, each at least `floor`."""
+    npix = obs.shape[0]
+    L = total_samples(grids)
+    dt = _real(obs)
+    _dev(obs, dt, "obs", (npix, 4, L))
+    out = torch.empty((npix, 4), dtype=dt, device=obs.device)
+    ga = (MeGrid * len(grids))(*grids)
+    f = lib().me_invmax_sigma if dt == torch.float32 else lib().me_invmax_sigma_f64
+    _check(f(_ptr(obs), npix, ga, len(grids), float(floor), _ptr(out), _stream(obs)))
     return out
 
 

@@ -650,6 +650,53 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN, FILL> 
 }
 
 
+// ---- inverse-max weights (Sec. 5.4) -------------------------------------
+//
+// sigma = 1 / w per pixel and Stokes parameter: for I the span of the
+// observed I over every sample of the pixel (continuum minus line core), for
+// Q, U, V the largest magnitude; each at least `floor`; NaN for all four when
+// a sample of the pixel is not finite.  One wavefront per pixel; max and min
+// are exact, so the result does not depend on the reduction order.
+template <typename Real>
+__global__ __launch_bounds__(64) void k_invmax_sigma(const Real *__restrict__ obs, int64_t npix,
+                                                     int L, Real floor, Real *__restrict__ sigma)
+{
+    for (int64_t p = blockIdx.x; p < npix; p += gridDim.x) {
+        const Real *o = obs + p * 4 * (int64_t)L;
+        Real imax = -INFINITY, imin = INFINITY, q = 0, u = 0, v = 0;
+        int bad = 0;
+        for (int j = threadIdx.x; j < L; j += 64) {
+            const Real I = o[j], Q = o[L + j], U = o[2 * L + j], V = o[3 * L + j];
+            bad |= !(isfinite(I) && isfinite(Q) && isfinite(U) && isfinite(V));
+            imax = fmax(imax, I);
+            imin = fmin(imin, I);
+            q = fmax(q, fabs(Q));
+            u = fmax(u, fabs(U));
+            v = fmax(v, fabs(V));
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            imax = fmax(imax, __shfl_xor(imax, off));
+            imin = fmin(imin, __shfl_xor(imin, off));
+            q = fmax(q, __shfl_xor(q, off));
+            u = fmax(u, __shfl_xor(u, off));
+            v = fmax(v, __shfl_xor(v, off));
+            bad |= __shfl_xor(bad, off);
+        }
+        if (threadIdx.x == 0) {
+            Real *s = sigma + p * 4;
+            if (bad) {
+                s[0] = s[1] = s[2] = s[3] = (Real)NAN;
+            } else {
+                s[0] = fmax(imax - imin, floor);
+                s[1] = fmax(q, floor);
+                s[2] = fmax(u, floor);
+                s[3] = fmax(v, floor);
+            }
+        }
+    }
+}
+
 // ---- heuristic first guesses (Sec. 5.5 seeds) ---------------------------
 //
 // One workgroup of 256 per pixel, FP64.  Per line (x the offset of a sample
@@ -1683,6 +1730,33 @@ int restart_impl(const uint16_t *genes_in, const Real *fitness, int64_t npix,
 
 namespace {
 
+template <typename Real>
+int invmax_impl(const Real *obs, int64_t npix, const me_grid *grids, int32_t nlines, double floor,
+                Real *sigma, void *stream)
+{
+    if (!grids || nlines < 1 || nlines > GENESIS_MAX_LINES)
+        return fail(ME_EINVAL, "need 1..%d grids", GENESIS_MAX_LINES);
+    int64_t L = 0;
+    for (int l = 0; l < nlines; ++l) {
+        if (grids[l].n < 1)
+            return fail(ME_EINVAL, "grid %d has %d samples", l, grids[l].n);
+        L += grids[l].n;
+    }
+    if (L > (1 << 28))
+        return fail(ME_EINVAL, "%lld samples per pixel are too many", (long long)L);
+    if (!(floor >= 0.0) || !std::isfinite(floor))
+        return fail(ME_EINVAL, "floor must be finite and >= 0");
+    if (npix < 0)
+        return fail(ME_EINVAL, "npix must be >= 0");
+    if (npix == 0)
+        return ME_OK;
+    if (!obs || !sigma)
+        return fail(ME_EINVAL, "NULL array argument");
+    hipLaunchKernelGGL(k_invmax_sigma<Real>, dim3(grid_for(npix)), dim3(64), 0, as_stream(stream),
+                       obs, npix, (int)L, (Real)floor, sigma);
+    return check_launch("me_invmax_sigma");
+}
+
 int pack_guess(const double *obs, const double *mu, int64_t npix, const me_line *lines,
                const me_grid *grids, int32_t nlines, const me_bounds *bounds, GuessArgs &a)
 {
@@ -2044,6 +2118,18 @@ int me_search_box(const double *obs, const double *sigma, int64_t npix, const me
     hipLaunchKernelGGL(k_search_box, dim3(grid_for(npix)), dim3(kGuessThreads), 0,
                        as_stream(stream), a);
     return check_launch("me_search_box");
+}
+
+int me_invmax_sigma(const float *obs, int64_t npix, const me_grid *grids, int32_t nlines,
+                    double floor, float *sigma, void *stream)
+{
+    return invmax_impl(obs, npix, grids, nlines, floor, sigma, stream);
+}
+
+int me_invmax_sigma_f64(const double *obs, int64_t npix, const me_grid *grids, int32_t nlines,
+                        double floor, double *sigma, void *stream)
+{
+    return invmax_impl(obs, npix, grids, nlines, floor, sigma, stream);
 }
 
 int me_seeds(const double *obs, const double *mu, int64_t npix, const me_line *lines,

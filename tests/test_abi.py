@@ -132,6 +132,14 @@ def test_invalid_arguments_fail_before_device_work():
     assert L.ga_invert(None, None, None, 3, la4, ga4, 4, C.byref(b), C.byref(cfg), None, None,
                        None, None, None, None, 0, None) == g.ME_ENOMEM
     assert L.ga_workspace_bytes(100, C.byref(cfg)) == 0
+    # inverse-max weights: a negative or non-finite floor, no grids, an empty grid
+    assert L.me_invmax_sigma(None, 3, ga, 1, -1.0, None, None) == g.ME_EINVAL
+    assert L.me_invmax_sigma_f64(None, 3, ga, 1, float("nan"), None, None) == g.ME_EINVAL
+    assert L.me_invmax_sigma(None, 3, ga, 0, 1e-3, None, None) == g.ME_EINVAL
+    assert L.me_invmax_sigma(None, 3, (g.MeGrid * 1)(g.grid(6302.1, 0.008, 0)), 1, 1e-3, None,
+                             None) == g.ME_EINVAL
+    assert L.me_invmax_sigma(None, 3, ga, 1, 1e-3, None, None) == g.ME_EINVAL   # NULL arrays
+    assert L.me_invmax_sigma(None, 0, ga, 1, 1e-3, None, None) == g.ME_OK       # empty
 
 
 def test_product_and_oracle_are_independent():
