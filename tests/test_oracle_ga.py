@@ -293,3 +293,64 @@ def test_seeded_init_nan_leaves_a_parameter_unseeded():
                               seed_params=np.nan_to_num(guess), lo=lo, hi=hi, init_mode=mode)
         keep = [0, 1, 2, 3, 7, 8]
         assert np.array_equal(g[:, keep], full[:, keep])
+
+
+def _gen0(npix=300, pop=128, seed=11):
+    return np.stack([oracle.ga_init(seed, p, pop) for p in range(npix)])   # [npix, pop, 9]
+
+
+def test_initial_population_genes_are_uniform():
+    # Algorithm 1 starts from a random population: every gene is a uniform
+    # 16-bit value, so each of its bits is a fair coin and its top six bits
+    # fall evenly into 64 bins; the decoded parameter is uniform on [lo, hi]
+    g = _gen0().reshape(-1, si.NPAR).astype(np.int64)
+    n = g.shape[0]
+    tests = 0
+    pmin = 1.0
+    for j in range(si.NPAR):
+        counts = np.bincount(g[:, j] >> 10, minlength=64)
+        pmin = min(pmin, stats.chisquare(counts).pvalue)
+        for b in range(16):
+            ones = int(((g[:, j] >> b) & 1).sum())
+            pmin = min(pmin, stats.binomtest(ones, n, 0.5).pvalue)
+        tests += 17
+    assert pmin > 1e-4 / tests, pmin
+    par = oracle.decode(g[:4000].astype(np.uint16), si.PRIOR_LO, si.PRIOR_HI)
+    for j in range(si.NPAR):
+        u = (par[:, j] - si.PRIOR_LO[j]) / (si.PRIOR_HI[j] - si.PRIOR_LO[j])
+        assert stats.kstest(u, "uniform").pvalue > 1e-4 / si.NPAR
+
+
+def test_initial_population_genes_are_pairwise_independent():
+    # independent draws: the joint 8 x 8 histogram of the top three bits of any
+    # two genes of one individual, of one gene in neighbouring individuals and
+    # in neighbouring pixels is the product of the marginals (a dropped index
+    # in the random stream's counter would repeat values and fail here)
+    g = _gen0().astype(np.int64) >> 13                    # [npix, pop, 9] in 0..7
+    pairs = []
+    for a in range(si.NPAR):
+        for b in range(a + 1, si.NPAR):
+            pairs.append((g[:, :, a].ravel(), g[:, :, b].ravel()))
+    for j in range(si.NPAR):
+        pairs.append((g[:, :-1, j].ravel(), g[:, 1:, j].ravel()))
+        pairs.append((g[:-1, :, j].ravel(), g[1:, :, j].ravel()))
+    pmin = 1.0
+    for x, y in pairs:
+        table = np.zeros((8, 8), np.int64)
+        np.add.at(table, (x, y), 1)
+        pmin = min(pmin, stats.chi2_contingency(table, correction=False).pvalue)
+    assert pmin > 1e-4 / len(pairs), pmin
+    # no two individuals of a pixel and no two pixels share a genotype
+    full = _gen0(npix=50, pop=128)
+    rows = {bytes(r) for r in full.reshape(-1, si.NPAR).astype(np.uint16)}
+    assert len(rows) == 50 * 128
+
+
+def test_initial_population_depends_on_seed_and_pixel_only():
+    a = oracle.ga_init(5, 17, 64)
+    assert np.array_equal(a, oracle.ga_init(5, 17, 64))
+    assert not np.array_equal(a, oracle.ga_init(6, 17, 64))
+    assert not np.array_equal(a, oracle.ga_init(5, 18, 64))
+    # a larger population extends the smaller one (individual i's genes
+    # depend on i, not on the population size)
+    assert np.array_equal(oracle.ga_init(5, 17, 128)[:64], a)
