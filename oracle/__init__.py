@@ -133,6 +133,10 @@ def lib():
             L.oracle_lm_fit.argtypes = [_dp, _dp, _dp, C.c_int64, _linep, C.c_int, _dp, _dp,
                                         _dp, C.c_int, C.c_uint32, _dp, _dp, _i32p]
             L.oracle_lm_fit.restype = C.c_int
+            L.oracle_lm_fit_fill.argtypes = [_dp, _dp, _dp, C.c_int64, _linep, C.c_int, _dp,
+                                             _dp, C.POINTER(Fill), _dp, _dp, C.c_int,
+                                             C.c_uint32, _dp, _dp, _dp, _i32p]
+            L.oracle_lm_fit_fill.restype = C.c_int
             L.oracle_uncertainty.argtypes = [_dp, _dp, _dp, C.c_int64, _linep, C.c_int, _dp,
                                              _dp, _dp, _dp, C.c_uint32, _dp, _dp, _dp, _dp]
             L.oracle_uncertainty.restype = C.c_int
@@ -446,6 +450,34 @@ def lm_refine(obs, sigma, lines, lo, hi, params_in, iterations, mu=None, free_ma
     if rc != 0:
         raise ValueError("oracle_lm_fit rejected its arguments")
     return dict(params=po, chi2=co, iters=it)
+
+
+def lm_refine_fill(obs, sigma, lines, lo, hi, fill, params_in, alpha_in, iterations, mu=None,
+                   free_mask=0x3FF):
+    """FP64 Levenberg-Marquardt refinement of the fill-fraction model (Sec.
+    5.2) over the nine parameters and alpha (bit 9 of free_mask); returns
+    dict(params, alpha, chi2, iters) with nu = 4L - 10."""
+    o = _f64(obs)
+    s = _f64(sigma)
+    npix = o.shape[0]
+    p0 = _f64(params_in).reshape(npix, NPAR)
+    a0 = _f64(np.broadcast_to(alpha_in, (npix,)))
+    lo = _f64(lo)
+    hi = _f64(hi)
+    po = np.empty((npix, NPAR), np.float64)
+    ao = np.empty(npix, np.float64)
+    co = np.empty(npix, np.float64)
+    it = np.empty(npix, np.int32)
+    arr, lp = _lines_array(lines)
+    m = None if mu is None else _f64(np.broadcast_to(mu, (npix,)))
+    rc = lib().oracle_lm_fit_fill(_ptr(o, _dp), _ptr(s, _dp), None if m is None else _ptr(m, _dp),
+                                  npix, lp, len(lines), _ptr(lo, _dp), _ptr(hi, _dp),
+                                  C.byref(fill), _ptr(p0, _dp), _ptr(a0, _dp), int(iterations),
+                                  int(free_mask), _ptr(po, _dp), _ptr(ao, _dp), _ptr(co, _dp),
+                                  _ptr(it, _i32p))
+    if rc != 0:
+        raise ValueError("oracle_lm_fit_fill rejected its arguments")
+    return dict(params=po, alpha=ao, chi2=co, iters=it)
 
 
 def uncertainty(obs, sigma, lines, lo, hi, p_opt, steps, mu=None, free_mask=0x1FF):

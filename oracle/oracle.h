@@ -179,6 +179,19 @@ int oracle_lm_fit(const double *obs, const double *sigma, const double *mu, int6
                   const double *params_in, int iterations, uint32_t free_mask,
                   double *params_out, double *chi2_out, int32_t *iters_done);
 
+/* The fit with the fill fraction of Sec. 5.2 as a tenth coordinate (see
+ * oracle_lm.c): the model alpha M(p) + (1 - alpha) I_c N e of oracle_fill.c,
+ * alpha in [fill->alpha_lo, fill->alpha_hi] from alpha_in [npix];
+ * free_mask bits 0..8 the parameters, bit 9 alpha.  Outputs params_out
+ * [npix][9], alpha_out [npix], chi2_out [npix] (nu = 4L - 10), iters_done
+ * [npix] (may be NULL).  A pixel whose field-free profile is invalid at its
+ * mu (or at its starting v_los) gives NaN like a bad observation. */
+int oracle_lm_fit_fill(const double *obs, const double *sigma, const double *mu, int64_t npix,
+                       const oracle_line *lines, int nlines, const double *lo, const double *hi,
+                       const oracle_fill *fill, const double *params_in, const double *alpha_in,
+                       int iterations, uint32_t free_mask, double *params_out,
+                       double *alpha_out, double *chi2_out, int32_t *iters_done);
+
 /* Sec. 6 uncertainties at p_opt [npix][9] (see oracle_unc.c): initial steps
  * steps [npix][9] (parameter units; e.g. oracle_population_steps), bounded
  * there as described; free_mask as for oracle_lm_fit.  Outputs sigma_out

@@ -149,3 +149,88 @@ def test_ga_with_fill_uses_the_fill_merit():
                          p_mut=0.05, seed=1, fill=bad, mu=np.array([0.5, 0.9, 1.0]))
     assert list(r["status"]) == [0, 4, 4]
     assert np.isnan(r["alpha"][1]) and np.isfinite(r["alpha"][0])
+
+
+# ---- the Levenberg-Marquardt fit with alpha as a tenth coordinate ---------
+
+def _fill_problem(npix=6, seed=3, alpha=None, kind="tiny"):
+    lines = _lines(kind)
+    f = _fill(kind, 0.1, 1.0)
+    truth = si.draw_truth(npix, seed)
+    al = np.linspace(0.35, 0.9, npix) if alpha is None else np.full(npix, alpha)
+    mu = np.linspace(0.45, 1.0, npix)
+    obs = oracle.me_synth_fill(truth, al, lines, f, mu=mu)
+    sig = si.sigma_for(truth, mu=mu)
+    return lines, f, truth, al, mu, obs, sig
+
+
+def test_fill_fit_with_alpha_held_at_one_is_the_plain_fit():
+    # at alpha = 1 the fill model is the Milne-Eddington vector itself, so the
+    # ten-coordinate fit with alpha held takes the plain fit's steps; only nu
+    # (4L - 10 against 4L - 9) rescales its chi-square
+    lines = _lines("tiny")
+    f = _fill("tiny", 0.0, 1.0)
+    truth = si.draw_truth(5, 8)
+    obs = oracle.me_synth(truth, lines)
+    sig = si.sigma_for(truth)
+    start = np.clip(truth + 0.03 * (si.PRIOR_HI - si.PRIOR_LO), si.PRIOR_LO, si.PRIOR_HI)
+    plain = oracle.lm_refine(obs, sig, lines, LO, HI, start, 6)
+    fill = oracle.lm_refine_fill(obs, sig, lines, LO, HI, f, start, np.ones(5), 6,
+                                 free_mask=0x1FF)
+    assert np.array_equal(fill["params"], plain["params"])
+    assert np.array_equal(fill["iters"], plain["iters"])
+    assert np.all(fill["alpha"] == 1.0)
+    L = sum(ln.nlam for ln in lines)
+    assert np.allclose(fill["chi2"] * (4 * L - 10), plain["chi2"] * (4 * L - 9), rtol=1e-12,
+                       atol=0)
+
+
+def test_fill_fit_recovers_noise_free_truth():
+    lines, f, truth, al, mu, obs, sig = _fill_problem()
+    # start from the truth moved by 1 % of every range and alpha moved by 0.1
+    start = np.clip(truth + 0.01 * (si.PRIOR_HI - si.PRIOR_LO), si.PRIOR_LO, si.PRIOR_HI)
+    r = oracle.lm_refine_fill(obs, sig, lines, LO, HI, f, start, al - 0.1, 60, mu=mu)
+    assert np.all(r["chi2"] < 1e-10), r["chi2"]
+    assert np.allclose(r["alpha"], al, rtol=0, atol=1e-6)
+    assert np.allclose(r["params"][:, 0], truth[:, 0], rtol=1e-5, atol=1e-3)
+    # the chi-square of the result is the merit function of Sec. 5 at (p, alpha)
+    m = oracle.me_synth_fill(r["params"], r["alpha"], lines, f, mu=mu)
+    L = m.shape[2]
+    direct = (((obs - m) / sig[:, :, None]) ** 2).sum(axis=(1, 2)) / (4 * L - 10)
+    assert np.allclose(direct, r["chi2"], rtol=1e-9, atol=1e-300)
+
+
+def test_fill_fit_alpha_is_stationary_at_the_closed_form_best():
+    # with noise, the fitted alpha (interior) is where d chi2 / d alpha = 0 at
+    # the fitted parameters: the closed-form best alpha of the GA's merit
+    # (pinned above against a brute-force scan) at the same parameters
+    lines, f, truth, al, mu, obs, sig = _fill_problem(npix=5, seed=11)
+    rng = np.random.default_rng(4)
+    noisy = obs + sig[:, :, None] * rng.standard_normal(obs.shape)
+    start = np.clip(truth + 0.01 * (si.PRIOR_HI - si.PRIOR_LO), si.PRIOR_LO, si.PRIOR_HI)
+    r = oracle.lm_refine_fill(noisy, sig, lines, LO, HI, f, start, al, 80, mu=mu)
+    c_best, a_best = oracle.chi2_fill(r["params"][:, None, :], noisy, sig, lines, f, mu=mu)
+    inner = (r["alpha"] > 0.1 + 1e-3) & (r["alpha"] < 1 - 1e-3)
+    assert inner.sum() >= 4
+    assert np.allclose(r["alpha"][inner], a_best[inner, 0], rtol=0, atol=2e-5)
+    # and the fit's chi-square is that merit's minimum over alpha
+    assert np.allclose(r["chi2"], c_best[:, 0], rtol=1e-7, atol=0)
+    # the refinement never raises the chi-square of its start
+    c0, _ = oracle.chi2_fill(start[:, None, :], noisy, sig, lines, f, mu=mu)
+    m0 = oracle.me_synth_fill(start, al, lines, f, mu=mu)
+    L = m0.shape[2]
+    chi_start = (((noisy - m0) / sig[:, :, None]) ** 2).sum(axis=(1, 2)) / (4 * L - 10)
+    assert np.all(r["chi2"] <= chi_start)
+
+
+def test_fill_fit_bad_pixels_and_arguments():
+    lines, f, truth, al, mu, obs, sig = _fill_problem(npix=3)
+    obs = obs.copy()
+    obs[1, 0, 4] = np.nan
+    r = oracle.lm_refine_fill(obs, sig, lines, LO, HI, f, truth, al, 3, mu=mu)
+    assert np.isnan(r["chi2"][1]) and np.isnan(r["alpha"][1]) and np.isnan(r["params"][1]).all()
+    assert np.isfinite(r["chi2"][[0, 2]]).all()
+    with pytest.raises(ValueError):
+        oracle.lm_refine_fill(obs, sig, lines, LO, HI, _fill("tiny", 0.5, 0.5), truth, al, 3)
+    with pytest.raises(ValueError):
+        oracle.lm_refine_fill(obs, sig, lines, LO, HI, f, truth, al, -1)
