@@ -418,6 +418,21 @@ int me_refine_f64(const double *obs, const double *sigma, const double *mu, int6
                   const me_bounds *bounds, const double *params_in, int32_t iterations,
                   double *params_out, double *chi2_out, int32_t *iters_done, void *stream);
 
+/* me_refine_f64 for the fill-fraction model of Sec. 5.2: alpha M(p) +
+ * (1 - alpha) I_c N e (see me_fill), with alpha as a tenth coordinate
+ * x_9 = (alpha - alpha_lo)/(alpha_hi - alpha_lo) fitted by the same steps;
+ * nu = 4L - 10.  alpha_in [npix] starts it (e.g. ga_invert_fill's
+ * best_alpha), alpha_out [npix] receives it; free_mask bits 0..8 are the
+ * nine parameters, bit 9 alpha (0x3ff: all).  A pixel whose field-free
+ * profile is invalid at its mu gives NaN like a bad observation.  Needs
+ * alpha_hi > alpha_lo. */
+int me_refine_fill_f64(const double *obs, const double *sigma, const double *mu, int64_t npix,
+                       const me_line *lines, const me_grid *grids, int32_t nlines,
+                       const me_bounds *bounds, const me_fill *fill, const double *params_in,
+                       const double *alpha_in, int32_t iterations, uint32_t free_mask,
+                       double *params_out, double *alpha_out, double *chi2_out,
+                       int32_t *iters_done, void *stream);
+
 /* Uncertainties of the fitted parameters (Sec. 6), FP64.  The Hessian H of
  * the merit function (the Sec. 5 chi-square, reduced by nu = 4L - 9) at
  * params_opt [npix][9] is the Jacobian of its gradient; both derivatives are

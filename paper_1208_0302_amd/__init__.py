@@ -166,6 +166,8 @@ _SIGS = {
                        _vp, C.c_size_t, _vp], C.c_int),
     "me_refine_f64": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _i32, _vp, _vp, _vp, _vp],
                       C.c_int),
+    "me_refine_fill_f64": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, C.POINTER(MeFill), _vp,
+                            _vp, _i32, C.c_uint32, _vp, _vp, _vp, _vp, _vp], _i32),
     "me_uncertainty_f64": ([_vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _vp, _vp, C.c_uint32, _vp,
                             _vp, _vp, _vp, _vp], C.c_int),
     "ga_population_steps": ([_vp, _vp, _i64, _i32, _bp, _vp, _vp, _vp], C.c_int),
@@ -567,6 +569,32 @@ def me_refine_f64(obs, sigma, lines, grids, bnds: MeBounds, params_in, iteration
                                C.byref(bnds), _ptr(params_in), int(iterations),
                                _ptr(res["params"]), _ptr(res["chi2"]), _ptr(res["iters"]),
                                _stream(obs)))
+    return res
+
+
+def me_refine_fill_f64(obs, sigma, lines, grids, bnds: MeBounds, fill_: MeFill, params_in,
+                       alpha_in, iterations=50, mu=None, free_mask=0x3FF):
+    """FP64 Levenberg-Marquardt refinement of the fill-fraction model (Sec.
+    5.2) over params_in [npix, 9] and alpha_in [npix] (bit 9 of free_mask is
+    alpha); returns dict(params, alpha, chi2, iters).  All float64."""
+    npix = obs.shape[0]
+    L = total_samples(grids)
+    _dev(obs, torch.float64, "obs", (npix, 4, L))
+    _dev(sigma, torch.float64, "sigma", (npix, 4))
+    _dev(mu, torch.float64, "mu", (npix,))
+    _dev(params_in, torch.float64, "params_in", (npix, NPAR))
+    _dev(alpha_in, torch.float64, "alpha_in", (npix,))
+    dev = obs.device
+    res = dict(params=torch.empty((npix, NPAR), dtype=torch.float64, device=dev),
+               alpha=torch.empty((npix,), dtype=torch.float64, device=dev),
+               chi2=torch.empty((npix,), dtype=torch.float64, device=dev),
+               iters=torch.empty((npix,), dtype=torch.int32, device=dev))
+    la, ga, nl = _lines(lines, grids)
+    _check(lib().me_refine_fill_f64(_ptr(obs), _ptr(sigma), _ptr(mu), npix, la, ga, nl,
+                                    C.byref(bnds), C.byref(fill_), _ptr(params_in),
+                                    _ptr(alpha_in), int(iterations), int(free_mask),
+                                    _ptr(res["params"]), _ptr(res["alpha"]), _ptr(res["chi2"]),
+                                    _ptr(res["iters"]), _stream(obs)))
     return res
 
 

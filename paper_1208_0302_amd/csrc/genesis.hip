@@ -1170,8 +1170,30 @@ __global__ __launch_bounds__(kGuessThreads) void k_seeds(SeedArgs sa)
 // 1e-12), else lambda *= 10 (cap 1e12), at most 10 trials per iteration;
 // lambda starts at 1e-3; the loop stops after an iteration without an
 // accepted trial.
+//
+// With the fill fraction (Sec. 5.2) the model is alpha M + (1 - alpha) I_c N e
+// and alpha in [alpha_lo, alpha_hi] is a tenth coordinate fitted the same
+// way (nu = 4L - 10).
+//
+// The normal equations are a Gram matrix, [J r]^T [J r], so they go to the
+// FP64 matrix cores: each thread forms its sample's four weighted Jacobian
+// rows (one per Stokes parameter) and residuals in registers; one Stokes
+// parameter at a time, every wavefront writes its 64 rows to LDS and
+// accumulates them with 16 v_mfma_f64_16x16x4 (4 rows each; lane l supplies
+// row l / 16, column l % 16 as both operands, the columns past the residual
+// read as 0).  The 16 x 16 accumulator of each wavefront holds J^T J, J^T r
+// (and r^T r) of its rows; the wavefronts' accumulators are added in
+// wavefront order.
 constexpr int kRefineThreads = 128;
-constexpr int kNA = GENESIS_NPAR * (GENESIS_NPAR + 1) / 2;  // packed upper triangle of A
+constexpr int kRefineWaves = kRefineThreads / 64;
+
+typedef double v4f64 __attribute__((ext_vector_type(4)));
+
+template <bool FILL>
+struct RefineDims {
+    static constexpr int NP = GENESIS_NPAR + (FILL ? 1 : 0);  // fitted coordinates
+    static constexpr int NC = NP + 1;                         // + the residual column
+};
 
 struct RefineArgs {
     const double *obs, *sigma, *mu, *params_in;
@@ -1181,17 +1203,26 @@ struct RefineArgs {
     double lo[GENESIS_NPAR], span[GENESIS_NPAR];
     double *params_out, *chi2_out;
     int32_t *iters_done;
-    uint32_t free_mask;  // bit j: parameter j is adjusted (held otherwise)
+    uint32_t free_mask;  // bit j: coordinate j is adjusted (held otherwise)
     int32_t zero_field;  // start (and, with bit 0 clear, hold) B at 0
+    // fill fraction
+    FillConst fc;
+    const double *alpha_in;
+    double *alpha_out;
 };
 
+template <bool FILL>
 struct RefineShared {
+    static constexpr int NP = RefineDims<FILL>::NP, NC = RefineDims<FILL>::NC;
     Model<double> jm[GENESIS_NPAR + 1];  // models at x and at x + h_k e_k (Jacobian)
-    double x[GENESIS_NPAR], xt[GENESIS_NPAR];
-    double red[kRefineThreads / 64][kNA + GENESIS_NPAR + 1];
-    double tot[kNA + GENESIS_NPAR + 1];
-    double nrm[kNA + GENESIS_NPAR];  // J^T J (packed) and J^T r at x
+    double x[NP], xt[NP];
+    double alpha[NP + 1];                // fill: alpha of each of those models
+    double red[kRefineWaves];
+    double rows[kRefineWaves][64 * NC];  // one Stokes parameter's rows per wavefront
+    double gram[kRefineWaves][NP][NC];   // each wavefront's J^T [J r]
+    double nrm[NP][NC];                  // J^T J and J^T r at x
     double lam, chi2;
+    FillPix<double> fp;
     int flag;
 };
 
@@ -1205,56 +1236,76 @@ __device__ __forceinline__ void model_from_x(const RefineArgs &a, const double *
     model_setup(p, mu, m);
 }
 
-// Sum `n` per-thread values over the workgroup into sh.tot[0 .. n)
-// (fixed order: wavefront butterflies, then wavefronts in index order).
-template <int N>
-__device__ __forceinline__ void block_sum(double (&v)[N], RefineShared &sh)
+__device__ __forceinline__ double alpha_of(const RefineArgs &a, double x)
+{
+    return a.fc.alpha_lo + (a.fc.alpha_hi - a.fc.alpha_lo) * x;
+}
+
+// Sum of one per-thread value over the workgroup (fixed order: wavefront
+// butterflies, then wavefronts in index order); every thread gets it.
+template <bool FILL>
+__device__ __forceinline__ double block_sum1(double v, RefineShared<FILL> &sh)
 {
 #pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1)
-            v[i] += __shfl_xor(v[i], off);
-    const int w = threadIdx.x >> 6;
+    for (int off = 32; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off);
     if ((threadIdx.x & 63) == 0)
-#pragma unroll
-        for (int i = 0; i < N; ++i)
-            sh.red[w][i] = v[i];
+        sh.red[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (threadIdx.x < N) {
-        double t = 0.0;
-        for (int k = 0; k < kRefineThreads / 64; ++k)
-            t += sh.red[k][threadIdx.x];
-        sh.tot[threadIdx.x] = t;
-    }
+    double t = 0.0;
+    for (int k = 0; k < kRefineWaves; ++k)
+        t += sh.red[k];
     __syncthreads();
+    return t;
+}
+
+// Field-free profile N of line ln at sample jj for line-of-sight velocity vlos.
+__device__ __forceinline__ double fill_n(const FillLine<double> &f, const DevLine<double> &ln,
+                                         int jj, double vlos)
+{
+    const double xw = fma(ln.step, (double)jj, ln.off0);
+    return fma(-f.scale, fill_h(f, (xw - vlos * ln.dop_kms) * f.inv_w), 1.0);
+}
+
+// alpha M + (1 - alpha) I_c N e in place.
+__device__ __forceinline__ void fill_mix(double al, double ic, double N, double (&M)[4])
+{
+    M[0] = fma(al, M[0], (1.0 - al) * (ic * N));
+    M[1] *= al;
+    M[2] *= al;
+    M[3] *= al;
 }
 
 // chi2 * nu contribution of this thread's wavelengths at normalised x
-__device__ __forceinline__ double chi2_part(const RefineArgs &a, const double *x, double mu,
+template <bool FILL>
+__device__ __forceinline__ double chi2_part(const RefineArgs &a, const RefineShared<FILL> &sh,
+                                            const double *x, double mu,
                                             const Vec4<double> *obs_s, const double (&w2)[4])
 {
     Model<double> m;
     model_from_x(a, x, mu, m);
+    const double al = FILL ? alpha_of(a, x[GENESIS_NPAR]) : 1.0;
     double acc = 0.0;
     for (int l = 0; l < a.ls.nlines; ++l) {
         const DevLine<double> &ln = a.ls.l[l];
         for (int jj = threadIdx.x; jj < ln.nlam; jj += kRefineThreads) {
-            double I, Q, U, V;
-            stokes_at(m, ln, jj, I, Q, U, V);
+            double M[4];
+            stokes_at(m, ln, jj, M[0], M[1], M[2], M[3]);
+            if constexpr (FILL)
+                fill_mix(al, m.S0 + m.muS1, fill_n(sh.fp.l[l], ln, jj, m.vlos), M);
             const Vec4<double> o = obs_s[ln.off + jj];
-            const double dI = o.x - I, dQ = o.y - Q, dU = o.z - U, dV = o.w - V;
+            const double dI = o.x - M[0], dQ = o.y - M[1], dU = o.z - M[2], dV = o.w - M[3];
             acc += w2[0] * dI * dI + w2[1] * dQ * dQ + w2[2] * dU * dU + w2[3] * dV * dV;
         }
     }
     return acc;
 }
 
-__device__ bool cholesky9(double (&M)[GENESIS_NPAR][GENESIS_NPAR], const double (&g)[GENESIS_NPAR],
-                          double (&d)[GENESIS_NPAR])
+template <int N>
+__device__ bool cholesky_n(double (&M)[N][N], const double (&g)[N], double (&d)[N])
 {
-    double Lm[GENESIS_NPAR][GENESIS_NPAR];
-    for (int i = 0; i < GENESIS_NPAR; ++i)
+    double Lm[N][N];
+    for (int i = 0; i < N; ++i)
         for (int j = 0; j <= i; ++j) {
             double s = M[i][j];
             for (int k = 0; k < j; ++k)
@@ -1267,39 +1318,112 @@ __device__ bool cholesky9(double (&M)[GENESIS_NPAR][GENESIS_NPAR], const double 
                 Lm[i][j] = s / Lm[j][j];
             }
         }
-    double y[GENESIS_NPAR];
-    for (int i = 0; i < GENESIS_NPAR; ++i) {
+    double y[N];
+    for (int i = 0; i < N; ++i) {
         double s = g[i];
         for (int k = 0; k < i; ++k)
             s -= Lm[i][k] * y[k];
         y[i] = s / Lm[i][i];
     }
-    for (int i = GENESIS_NPAR - 1; i >= 0; --i) {
+    for (int i = N - 1; i >= 0; --i) {
         double s = y[i];
-        for (int k = i + 1; k < GENESIS_NPAR; ++k)
+        for (int k = i + 1; k < N; ++k)
             s -= Lm[k][i] * d[k];
         d[i] = s / Lm[i][i];
     }
     return true;
 }
 
+// The weighted Jacobian rows J[k][s] (k < NP) and residuals r[s] of one sample
+// (zero when the thread has no sample).
+template <bool FILL>
+__device__ __forceinline__ void jacobian_rows(const RefineArgs &a, const RefineShared<FILL> &sh,
+                                              int l, int jj, const double (&hx)[RefineDims<FILL>::NP],
+                                              const double (&sig)[4], const Vec4<double> *obs_s,
+                                              double (&J)[RefineDims<FILL>::NP][4], double (&r)[4])
+{
+    constexpr int NP = RefineDims<FILL>::NP;
+    const DevLine<double> &ln = a.ls.l[l];
+    double M0[4], pr0[6], N0 = 1.0;
+    profiles_at(sh.jm[0], ln, jj, pr0);
+    unno_rachkovsky(sh.jm[0], pr0[0], pr0[1], pr0[2], pr0[3], pr0[4], pr0[5], M0[0], M0[1],
+                    M0[2], M0[3]);
+    double Mm[4] = {M0[0], M0[1], M0[2], M0[3]};  // magnetic part of the base model
+    if constexpr (FILL) {
+        N0 = fill_n(sh.fp.l[l], ln, jj, sh.jm[0].vlos);
+        fill_mix(sh.alpha[0], sh.jm[0].S0 + sh.jm[0].muS1, N0, M0);
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        double Mk[4];
+        if (!((a.free_mask >> k) & 1u)) {
+            // a held coordinate: zero column, so A_kk = 0 and d_k = 0
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4)
+                J[k][s4] = 0.0;
+            continue;
+        }
+        if (k == GENESIS_NPAR) {
+            // alpha (fill only): the base model mixed at the perturbed alpha
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4)
+                Mk[s4] = Mm[s4];
+            fill_mix(sh.alpha[k + 1], sh.jm[0].S0 + sh.jm[0].muS1, N0, Mk);
+        } else {
+            const Model<double> &mk = sh.jm[k + 1];
+            if (k == 0 || (k >= 3 && k <= 5)) {
+                // B, v_los, Doppler width, damping: new profiles
+                stokes_at(mk, ln, jj, Mk[0], Mk[1], Mk[2], Mk[3]);
+            } else {
+                // the angles, eta0, S0, S1 leave every Voigt argument
+                // unchanged: the base profiles, the perturbed algebra
+                unno_rachkovsky(mk, pr0[0], pr0[1], pr0[2], pr0[3], pr0[4], pr0[5], Mk[0],
+                                Mk[1], Mk[2], Mk[3]);
+            }
+            if constexpr (FILL)
+                fill_mix(sh.alpha[0], mk.S0 + mk.muS1,
+                         k == 3 ? fill_n(sh.fp.l[l], ln, jj, mk.vlos) : N0, Mk);
+        }
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+            J[k][s4] = (Mk[s4] - M0[s4]) / (hx[k] * sig[s4]);
+    }
+    const Vec4<double> o = obs_s[ln.off + jj];
+    r[0] = (o.x - M0[0]) / sig[0];
+    r[1] = (o.y - M0[1]) / sig[1];
+    r[2] = (o.z - M0[2]) / sig[2];
+    r[3] = (o.w - M0[3]) / sig[3];
+}
+
+template <bool FILL>
 __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
 {
+    constexpr int NP = RefineDims<FILL>::NP, NC = RefineDims<FILL>::NC;
+    static_assert(NC <= 16, "the Gram matrix fits one 16 x 16 accumulator");
     code_shift<GENESIS_PAD_REFINE>();
     extern __shared__ __align__(16) unsigned char smem[];
     const int L = a.ls.L;
     Vec4<double> *obs_s = reinterpret_cast<Vec4<double> *>(smem);
-    __shared__ RefineShared sh;
-    const int tid = threadIdx.x;
-    const double inv_nu = 1.0 / (4.0 * L - GENESIS_NPAR);
+    __shared__ RefineShared<FILL> sh;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const double inv_nu = 1.0 / (4.0 * L - NP);
     const double h = 1e-7;
     for (int64_t p = blockIdx.x; p < a.npix; p += gridDim.x) {
+        const double mu = a.mu ? a.mu[p] : 1.0;
+        if constexpr (FILL)
+            if (tid == 0)
+                fill_setup(a.fc, a.ls.nlines, mu, sh.fp);
         double w2[4];
-        const int st = stage_pixel(a.obs + p * 4 * (int64_t)L, a.sigma + p * 4, L, obs_s, w2);
+        int st = stage_pixel(a.obs + p * 4 * (int64_t)L, a.sigma + p * 4, L, obs_s, w2);
+        if constexpr (FILL)
+            if (st == 0)
+                st = sh.fp.status;
         if (st != 0) {
             if (tid == 0) {
                 for (int j = 0; j < GENESIS_NPAR; ++j)
                     a.params_out[p * GENESIS_NPAR + j] = NAN;
+                if constexpr (FILL)
+                    a.alpha_out[p] = NAN;
                 a.chi2_out[p] = NAN;
                 if (a.iters_done)
                     a.iters_done[p] = 0;
@@ -1307,7 +1431,6 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
             __syncthreads();
             continue;
         }
-        const double mu = a.mu ? a.mu[p] : 1.0;
         const double sig[4] = {a.sigma[p * 4], a.sigma[p * 4 + 1], a.sigma[p * 4 + 2],
                                a.sigma[p * 4 + 3]};
         if (tid < GENESIS_NPAR) {
@@ -1315,26 +1438,27 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
             const double v = (pin - a.lo[tid]) / a.span[tid];
             sh.x[tid] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
         }
+        if constexpr (FILL)
+            if (tid == GENESIS_NPAR) {
+                const double v =
+                    (a.alpha_in[p] - a.fc.alpha_lo) / (a.fc.alpha_hi - a.fc.alpha_lo);
+                sh.x[GENESIS_NPAR] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+            }
         if (tid == 0)
             sh.lam = 1e-3;
         __syncthreads();
         {
-            double c[1] = {chi2_part(a, sh.x, mu, obs_s, w2)};
-            block_sum(c, sh);
+            const double c = block_sum1(chi2_part(a, sh, sh.x, mu, obs_s, w2), sh);
             if (tid == 0)
-                sh.chi2 = sh.tot[0];
+                sh.chi2 = c;
             __syncthreads();
         }
         int it = 0;
         for (; it < a.iterations; ++it) {
             // ---- Jacobian and normal equations
-            double acc[kNA + GENESIS_NPAR];
+            double hx[NP];
 #pragma unroll
-            for (int i = 0; i < kNA + GENESIS_NPAR; ++i)
-                acc[i] = 0.0;
-            double hx[GENESIS_NPAR];
-#pragma unroll
-            for (int j = 0; j < GENESIS_NPAR; ++j)
+            for (int j = 0; j < NP; ++j)
                 hx[j] = (sh.x[j] + h <= 1.0) ? h : -h;
             // the model at x (slot 0) and the nine forward-difference models
             // (slot k + 1), set up once per iteration for every wavelength
@@ -1345,73 +1469,76 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
                     xk[j] = sh.x[j] + (j == tid - 1 ? hx[j] : 0.0);
                 model_from_x(a, xk, mu, sh.jm[tid]);
             }
+            if constexpr (FILL)
+                if (tid == 0)
+                    for (int k = 0; k <= NP; ++k)
+                        sh.alpha[k] = alpha_of(a, sh.x[GENESIS_NPAR] +
+                                                      (k == NP ? hx[GENESIS_NPAR] : 0.0));
             __syncthreads();
+            v4f64 acc = {0.0, 0.0, 0.0, 0.0};
+            const int rrow = lane >> 4, rcol = lane & 15;
             for (int l = 0; l < a.ls.nlines; ++l) {
-                const DevLine<double> &ln = a.ls.l[l];
-                for (int jj = tid; jj < ln.nlam; jj += kRefineThreads) {
-                    double M0[4], Jm[GENESIS_NPAR][4], pr0[6];
-                    profiles_at(sh.jm[0], ln, jj, pr0);
-                    unno_rachkovsky(sh.jm[0], pr0[0], pr0[1], pr0[2], pr0[3], pr0[4], pr0[5],
-                                    M0[0], M0[1], M0[2], M0[3]);
-                    for (int k = 0; k < GENESIS_NPAR; ++k) {
-                        if (!((a.free_mask >> k) & 1u)) {
-                            // a held parameter: zero column, so A_kk = 0 and d_k = 0
+                const int nlam = a.ls.l[l].nlam;
+                for (int c0 = 0; c0 < nlam; c0 += kRefineThreads) {
+                    const int jj = c0 + tid;
+                    double J[NP][4], r[4];
+                    if (jj < nlam) {
+                        jacobian_rows<FILL>(a, sh, l, jj, hx, sig, obs_s, J, r);
+                    } else {
 #pragma unroll
-                            for (int s4 = 0; s4 < 4; ++s4)
-                                Jm[k][s4] = 0.0;
-                            continue;
-                        }
-                        double Mk[4];
-                        if (k == 0 || (k >= 3 && k <= 5)) {
-                            // B, v_los, Doppler width, damping: new profiles
-                            stokes_at(sh.jm[k + 1], ln, jj, Mk[0], Mk[1], Mk[2], Mk[3]);
-                        } else {
-                            // the angles, eta0, S0, S1 leave every Voigt argument
-                            // unchanged: the base profiles, the perturbed algebra
-                            unno_rachkovsky(sh.jm[k + 1], pr0[0], pr0[1], pr0[2], pr0[3],
-                                            pr0[4], pr0[5], Mk[0], Mk[1], Mk[2], Mk[3]);
-                        }
+                        for (int s4 = 0; s4 < 4; ++s4) {
+                            r[s4] = 0.0;
 #pragma unroll
-                        for (int s4 = 0; s4 < 4; ++s4)
-                            Jm[k][s4] = (Mk[s4] - M0[s4]) / (hx[k] * sig[s4]);
+                            for (int k = 0; k < NP; ++k)
+                                J[k][s4] = 0.0;
+                        }
                     }
-                    const Vec4<double> o = obs_s[ln.off + jj];
-                    const double r[4] = {(o.x - M0[0]) / sig[0], (o.y - M0[1]) / sig[1],
-                                         (o.z - M0[2]) / sig[2], (o.w - M0[3]) / sig[3]};
 #pragma unroll
                     for (int s4 = 0; s4 < 4; ++s4) {
-                        int q = 0;
+                        double *rw = sh.rows[wv];
 #pragma unroll
-                        for (int i = 0; i < GENESIS_NPAR; ++i) {
-#pragma unroll
-                            for (int j = i; j < GENESIS_NPAR; ++j)
-                                acc[q++] += Jm[i][s4] * Jm[j][s4];
+                        for (int k = 0; k < NP; ++k)
+                            rw[lane * NC + k] = J[k][s4];
+                        rw[lane * NC + NP] = r[s4];
+                        __syncthreads();
+#pragma unroll 4
+                        for (int t = 0; t < 16; ++t) {
+                            const double v = rcol < NC ? rw[(4 * t + rrow) * NC + rcol] : 0.0;
+                            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
                         }
-#pragma unroll
-                        for (int i = 0; i < GENESIS_NPAR; ++i)
-                            acc[kNA + i] += Jm[i][s4] * r[s4];
+                        __syncthreads();
                     }
                 }
             }
-            block_sum(acc, sh);
-            if (tid < kNA + GENESIS_NPAR)
-                sh.nrm[tid] = sh.tot[tid];
+            // accumulator element v of lane l: row l / 16 + 4 v, column l % 16
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = rrow + 4 * v;
+                if (i < NP && rcol < NC)
+                    sh.gram[wv][i][rcol] = acc[v];
+            }
+            __syncthreads();
+            for (int e = tid; e < NP * NC; e += kRefineThreads) {
+                double t = 0.0;
+                for (int w = 0; w < kRefineWaves; ++w)
+                    t += sh.gram[w][e / NC][e % NC];
+                sh.nrm[e / NC][e % NC] = t;
+            }
             __syncthreads();
             // ---- damped trials
             bool accepted = false;
             for (int trial = 0; trial < 10; ++trial) {
                 if (tid == 0) {
-                    double Mx[GENESIS_NPAR][GENESIS_NPAR], g[GENESIS_NPAR], d[GENESIS_NPAR];
-                    int q = 0;
-                    for (int i = 0; i < GENESIS_NPAR; ++i)
-                        for (int j = i; j < GENESIS_NPAR; ++j, ++q)
-                            Mx[i][j] = Mx[j][i] = sh.nrm[q];
-                    for (int i = 0; i < GENESIS_NPAR; ++i)
-                        g[i] = sh.nrm[kNA + i];
-                    for (int i = 0; i < GENESIS_NPAR; ++i) {
+                    double Mx[NP][NP], g[NP], d[NP];
+                    for (int i = 0; i < NP; ++i)
+                        for (int j = i; j < NP; ++j)
+                            Mx[i][j] = Mx[j][i] = sh.nrm[i][j];
+                    for (int i = 0; i < NP; ++i)
+                        g[i] = sh.nrm[i][NP];
+                    for (int i = 0; i < NP; ++i) {
                         const double aii = Mx[i][i];
                         if (aii == 0.0) {
-                            for (int j = 0; j < GENESIS_NPAR; ++j)
+                            for (int j = 0; j < NP; ++j)
                                 Mx[i][j] = Mx[j][i] = 0.0;
                             Mx[i][i] = 1.0;
                             g[i] = 0.0;
@@ -1419,9 +1546,9 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
                             Mx[i][i] = aii + sh.lam * aii;
                         }
                     }
-                    sh.flag = cholesky9(Mx, g, d) ? 1 : 0;
+                    sh.flag = cholesky_n<NP>(Mx, g, d) ? 1 : 0;
                     if (sh.flag)
-                        for (int j = 0; j < GENESIS_NPAR; ++j) {
+                        for (int j = 0; j < NP; ++j) {
                             const double v = sh.x[j] + d[j];
                             sh.xt[j] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
                         }
@@ -1433,13 +1560,12 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
                     __syncthreads();
                     continue;
                 }
-                double c[1] = {chi2_part(a, sh.xt, mu, obs_s, w2)};
-                block_sum(c, sh);
+                const double c = block_sum1(chi2_part(a, sh, sh.xt, mu, obs_s, w2), sh);
                 if (tid == 0) {
-                    if (sh.tot[0] < sh.chi2) {
-                        for (int j = 0; j < GENESIS_NPAR; ++j)
+                    if (c < sh.chi2) {
+                        for (int j = 0; j < NP; ++j)
                             sh.x[j] = sh.xt[j];
-                        sh.chi2 = sh.tot[0];
+                        sh.chi2 = c;
                         sh.lam = fmax(sh.lam / 10.0, 1e-12);
                         sh.flag = 2;
                     } else {
@@ -1458,6 +1584,8 @@ __global__ __launch_bounds__(kRefineThreads) void k_refine_f64(RefineArgs a)
         if (tid < GENESIS_NPAR)
             a.params_out[p * GENESIS_NPAR + tid] = a.lo[tid] + a.span[tid] * sh.x[tid];
         if (tid == 0) {
+            if constexpr (FILL)
+                a.alpha_out[p] = alpha_of(a, sh.x[GENESIS_NPAR]);
             a.chi2_out[p] = sh.chi2 * inv_nu;
             if (a.iters_done)
                 a.iters_done[p] = it;
@@ -1651,12 +1779,15 @@ int invert_dispatch(const Real *obs, const Real *sigma, const Real *mu, int64_t 
 }
 
 
+template <bool FILL>
 int refine_impl(const double *obs, const double *sigma, const double *mu, int64_t npix,
                 const me_line *lines, const me_grid *grids, int nlines, const me_bounds *bounds,
                 const double *params_in, int iterations, double *params_out, double *chi2_out,
                 int32_t *iters_done, void *stream, uint32_t free_mask = 0x1ffu,
-                bool zero_field = false)
+                bool zero_field = false, const me_fill *fill = nullptr,
+                const double *alpha_in = nullptr, double *alpha_out = nullptr)
 {
+    constexpr int NP = RefineDims<FILL>::NP;
     RefineArgs a{};
     if (int rc = pack_lines(lines, grids, nlines, a.ls))
         return rc;
@@ -1669,19 +1800,27 @@ int refine_impl(const double *obs, const double *sigma, const double *mu, int64_
         a.lo[j] = b.lo[j];
         a.span[j] = b.span[j];
     }
+    if constexpr (FILL) {
+        if (int rc = pack_fill(fill, nlines, a.fc))
+            return rc;
+        if (!(a.fc.alpha_hi > a.fc.alpha_lo))
+            return fail(ME_EINVAL, "refinement needs alpha_hi > alpha_lo");
+    }
     if (iterations < 0)
         return fail(ME_EINVAL, "iterations must be >= 0");
     if (npix < 0)
         return fail(ME_EINVAL, "npix must be >= 0");
-    if (4 * a.ls.L <= GENESIS_NPAR)
-        return fail(ME_EINVAL, "need 4 L > 9 wavelength samples for nu > 0");
+    if (4 * a.ls.L <= NP)
+        return fail(ME_EINVAL, "need 4 L > %d wavelength samples for nu > 0", NP);
     const size_t lds = sizeof(Vec4<double>) * (size_t)a.ls.L;
-    if (lds + sizeof(RefineShared) > kMaxLds)
+    if (lds + sizeof(RefineShared<FILL>) > kMaxLds)
         return fail(ME_ENOMEM, "observation of %d samples exceeds LDS", a.ls.L);
     if (npix == 0)
         return ME_OK;
     if (!obs || !sigma || !params_in || !params_out || !chi2_out)
         return fail(ME_EINVAL, "NULL array argument");
+    if (FILL && (!alpha_in || !alpha_out))
+        return fail(ME_EINVAL, "NULL alpha array");
     a.obs = obs;
     a.sigma = sigma;
     a.mu = mu;
@@ -1691,11 +1830,13 @@ int refine_impl(const double *obs, const double *sigma, const double *mu, int64_
     a.params_out = params_out;
     a.chi2_out = chi2_out;
     a.iters_done = iters_done;
-    a.free_mask = free_mask;
+    a.free_mask = free_mask & ((1u << NP) - 1u);
     a.zero_field = zero_field ? 1 : 0;
-    hipLaunchKernelGGL(k_refine_f64, dim3(grid_for(npix)), dim3(kRefineThreads), lds,
+    a.alpha_in = alpha_in;
+    a.alpha_out = alpha_out;
+    hipLaunchKernelGGL(k_refine_f64<FILL>, dim3(grid_for(npix)), dim3(kRefineThreads), lds,
                        as_stream(stream), a);
-    return check_launch("me_refine_f64");
+    return check_launch(FILL ? "me_refine_fill_f64" : "me_refine_f64");
 }
 }  // namespace
 
@@ -2172,8 +2313,20 @@ int me_refine_f64(const double *obs, const double *sigma, const double *mu, int6
                   const me_bounds *bounds, const double *params_in, int32_t iterations,
                   double *params_out, double *chi2_out, int32_t *iters_done, void *stream)
 {
-    return refine_impl(obs, sigma, mu, npix, lines, grids, nlines, bounds, params_in, iterations,
-                       params_out, chi2_out, iters_done, stream);
+    return refine_impl<false>(obs, sigma, mu, npix, lines, grids, nlines, bounds, params_in,
+                              iterations, params_out, chi2_out, iters_done, stream);
+}
+
+int me_refine_fill_f64(const double *obs, const double *sigma, const double *mu, int64_t npix,
+                       const me_line *lines, const me_grid *grids, int32_t nlines,
+                       const me_bounds *bounds, const me_fill *fill, const double *params_in,
+                       const double *alpha_in, int32_t iterations, uint32_t free_mask,
+                       double *params_out, double *alpha_out, double *chi2_out,
+                       int32_t *iters_done, void *stream)
+{
+    return refine_impl<true>(obs, sigma, mu, npix, lines, grids, nlines, bounds, params_in,
+                             iterations, params_out, chi2_out, iters_done, stream, free_mask,
+                             false, fill, alpha_in, alpha_out);
 }
 
 int me_prefit_f64(const double *obs, const double *sigma, const double *mu, int64_t npix,
@@ -2185,8 +2338,8 @@ int me_prefit_f64(const double *obs, const double *sigma, const double *mu, int6
         return fail(ME_EINVAL, "the non-magnetic pre-fit needs a box containing B = 0");
     // v_los, Doppler width, damping, eta0, S0, S1 free; B held at 0 (the angles
     // then do not enter the model)
-    return refine_impl(obs, sigma, mu, npix, lines, grids, nlines, bounds, params_in, iterations,
-                       params_out, chi2_out, iters_done, stream, 0x1f8u, true);
+    return refine_impl<false>(obs, sigma, mu, npix, lines, grids, nlines, bounds, params_in,
+                              iterations, params_out, chi2_out, iters_done, stream, 0x1f8u, true);
 }
 
 }  // extern "C"

@@ -168,3 +168,129 @@ def test_alpha_fixed_at_one_is_the_plain_merit():
     f1 = one["fitness"].cpu().numpy().astype(np.float64) * (4 * L - 10)
     f0 = plain["fitness"].cpu().numpy().astype(np.float64) * (4 * L - 9)
     assert np.allclose(f1, f0, rtol=2e-5, atol=0)
+
+
+# ---- FP64 Levenberg-Marquardt refinement of the fill model ----------------
+
+def _fill_refine_problem(npix, seed, noise, kind="slit"):
+    lines, grids, olines = _setup(kind)
+    gf, of = _fills(kind, 0.1, 1.0)
+    truth = si.draw_truth(npix, seed)
+    al = np.linspace(0.3, 0.95, npix)
+    mu = np.linspace(0.4, 1.0, npix)
+    obs = oracle.me_synth_fill(truth, al, olines, of, mu=mu)
+    sig = si.sigma_for(truth, mu=mu)
+    if noise:
+        obs = obs + sig[:, :, None] * si.std_normal(obs.shape, seed + 1)
+    rng = np.random.default_rng(seed + 2)
+    p0 = np.clip(truth + (HI - LO) * rng.normal(0, 0.01, truth.shape), LO, HI)
+    a0 = np.clip(al + rng.normal(0, 0.05, npix), 0.1, 1.0)
+    return lines, grids, olines, gf, of, truth, al, mu, obs, sig, p0, a0
+
+
+@pytest.mark.parametrize("noise", [False, True])
+def test_refine_fill_matches_oracle(noise):
+    # both fits reach the same minimum of the fill model's chi-square (the
+    # FP64 models differ by < 1e-10 I_c, the Gram matrices by rounding order)
+    (lines, grids, olines, gf, of, truth, al, mu, obs, sig, p0,
+     a0) = _fill_refine_problem(10, 21, noise)
+    f64 = torch.float64
+    r = g.me_refine_fill_f64(_t(obs, f64), _t(sig, f64), lines, grids, g.bounds(LO, HI), gf,
+                             _t(p0, f64), _t(a0, f64), iterations=40, mu=_t(mu, f64))
+    ref = oracle.lm_refine_fill(obs, sig, olines, LO, HI, of, p0, a0, 40, mu=mu)
+    gp, ga, gc = (r[k].cpu().numpy() for k in ("params", "alpha", "chi2"))
+    dx = np.abs(gp - ref["params"]) / (HI - LO)
+    same = (dx.max(axis=1) < 1e-6) & (np.abs(ga - ref["alpha"]) < 1e-6)
+    print("pixels at the oracle's minimum: %d / 10" % same.sum())
+    assert same.sum() >= 9
+    assert np.all(np.abs(gc[same] - ref["chi2"][same])
+                  <= 1e-7 * np.maximum(ref["chi2"][same], 1e-6))
+    # the reported chi-square is the oracle's merit at the returned (p, alpha)
+    m = oracle.me_synth_fill(gp, ga, olines, of, mu=mu)
+    L = m.shape[2]
+    direct = (((obs - m) / sig[:, :, None]) ** 2).sum(axis=(1, 2)) / (4 * L - 10)
+    assert np.allclose(gc, direct, rtol=1e-9, atol=1e-14)
+    if not noise:
+        ok = gc < 1e-12
+        assert ok.sum() >= 8
+        assert np.all(np.abs(ga[ok] - al[ok]) < 1e-6)
+
+
+def test_refine_fill_with_alpha_held_at_one_is_the_plain_refinement():
+    # at alpha = 1 the fill model is the Milne-Eddington vector, so holding
+    # alpha (bit 9 clear) gives the plain refinement's parameters to the bit
+    lines, grids, olines = _setup("slit")
+    gf, of = _fills("slit", 0.0, 1.0)
+    truth = si.draw_truth(16, 5)
+    obs = oracle.me_synth(truth, olines)
+    sig = si.sigma_for(truth)
+    rng = np.random.default_rng(6)
+    p0 = np.clip(truth + (HI - LO) * rng.normal(0, 0.01, truth.shape), LO, HI)
+    f64 = torch.float64
+    b = g.bounds(LO, HI)
+    plain = g.me_refine_f64(_t(obs, f64), _t(sig, f64), lines, grids, b, _t(p0, f64), 12)
+    fill = g.me_refine_fill_f64(_t(obs, f64), _t(sig, f64), lines, grids, b, gf, _t(p0, f64),
+                                _t(np.ones(16), f64), iterations=12, free_mask=0x1FF)
+    assert torch.equal(fill["params"], plain["params"])
+    assert torch.equal(fill["iters"], plain["iters"])
+    assert torch.all(fill["alpha"] == 1.0)
+    L = sum(gr.n for gr in grids)
+    assert torch.allclose(fill["chi2"] * (4 * L - 10), plain["chi2"] * (4 * L - 9), rtol=1e-12,
+                          atol=0)
+
+
+def test_refine_fill_edge_cases():
+    (lines, grids, olines, gf, of, truth, al, mu, obs, sig, p0,
+     a0) = _fill_refine_problem(4, 8, False, kind="tiny")
+    obs = obs.copy()
+    obs[1, 2, 3] = np.nan
+    f64 = torch.float64
+    b = g.bounds(LO, HI)
+    a0 = a0.copy()
+    a0[2] = 7.0                            # outside [alpha_lo, alpha_hi]: clamped
+    r = g.me_refine_fill_f64(_t(obs, f64), _t(sig, f64), lines, grids, b, gf, _t(truth, f64),
+                             _t(a0, f64), iterations=0, mu=_t(mu, f64))
+    assert np.isnan(r["params"][1].cpu().numpy()).all() and np.isnan(r["alpha"][1].item())
+    assert r["alpha"][2].item() == pytest.approx(1.0, abs=1e-12)
+    assert int(r["iters"][0].item()) == 0
+    # a field-free profile invalid at this mu: NaN, like a bad observation
+    bad_c = [np.array(a) for a in si.fill_coefficients("tiny")]
+    bad_c[1][0][0] = -1.0                  # width(mu) < 0 everywhere
+    bad = g.fill(0.1, 1.0, *bad_c)
+    r = g.me_refine_fill_f64(_t(obs, f64), _t(sig, f64), lines, grids, b, bad, _t(truth, f64),
+                             _t(a0, f64), iterations=2, mu=_t(mu, f64))
+    assert torch.isnan(r["chi2"]).all()
+    # arguments
+    with pytest.raises(g.GenesisError):
+        g.me_refine_fill_f64(_t(obs, f64), _t(sig, f64), lines, grids, b,
+                             g.fill(0.5, 0.5, *si.fill_coefficients("tiny")), _t(truth, f64),
+                             _t(a0, f64), iterations=2, mu=_t(mu, f64))
+    empty = g.me_refine_fill_f64(_t(obs[:0], f64), _t(sig[:0], f64), lines, grids, b, gf,
+                                 _t(truth[:0], f64), _t(a0[:0], f64), iterations=3)
+    assert empty["params"].shape == (0, 9)
+
+
+def test_ga_fill_then_refine_fill_pipeline():
+    # the FP32 fill-fraction search followed by the FP64 fill refinement on
+    # noise-free observations: the refinement lowers every chi-square and
+    # brings alpha and B closer to the truth
+    lines, grids, olines = _setup("slit")
+    gf, of = _fills("slit", 0.1, 1.0)
+    npix = 128
+    truth = si.draw_truth(npix, 30)
+    al = np.linspace(0.3, 0.95, npix)
+    obs = oracle.me_synth_fill(truth, al, olines, of)
+    sig = si.sigma_for(truth)
+    b = g.bounds(LO, HI)
+    ga = g.ga_invert(_t(obs, torch.float32), _t(sig, torch.float32), lines, grids, b,
+                     g.GAConfig(pop=128, generations=120, seed=3), fill=gf)
+    f64 = torch.float64
+    r = g.me_refine_fill_f64(_t(obs, f64), _t(sig, f64), lines, grids, b, gf,
+                             ga["params"].double(), ga["alpha"].double(), iterations=30)
+    c_ga = ga["chi2"].double().cpu().numpy()
+    c_r = r["chi2"].cpu().numpy()
+    assert np.all(c_r <= c_ga * 1.001 + 1e-6)
+    e_ga = np.abs(ga["alpha"].double().cpu().numpy() - al)
+    e_r = np.abs(r["alpha"].cpu().numpy() - al)
+    print("median |d alpha| GA %.3g, GA + refine %.3g" % (np.median(e_ga), np.median(e_r)))
+    assert np.median(e_r) < np.median(e_ga)
