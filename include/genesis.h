@@ -533,6 +533,19 @@ int mlp_features(const float *obs, int64_t npix, const me_grid *grids, int32_t n
 /* y [n][9] = network(x [n][1024]). */
 int mlp_forward(const float *master, const float *x, int64_t n, int32_t precision, float *y,
                 void *workspace, size_t ws_bytes, void *stream);
+/* mlp_forward for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels, with the workspace in a file-scope device array of the
+ * library (about 20 MiB per device, held until the process ends) instead of
+ * a workspace argument; it allocates nothing.  n must lie in [1,
+ * mlp_noalloc_max_rows()] (ME_EINVAL otherwise: split larger batches).  The
+ * caller still owns master, x [n][1024] and y [n][9] (device).  Every call
+ * on one device shares that device's array: calls that overlap on one
+ * device (different streams, or threads) race and must be serialised by the
+ * caller. */
+int64_t mlp_noalloc_max_rows(void);
+int mlp_forward_noalloc(const float *master, const float *x, int64_t n, int32_t precision,
+                        float *y, void *stream);
 /* Gradient of loss = mean_b sum_j d_bj^2, d = y - target (azimuth d taken
  * modulo 1), into grad [param_count]; *loss (device) receives the loss. */
 int mlp_grad(const float *master, const float *x, const float *target, int64_t batch,

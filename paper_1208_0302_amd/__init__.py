@@ -193,6 +193,8 @@ _SIGS = {
     "mlp_init": ([_vp, C.c_uint64, _vp], C.c_int),
     "mlp_features": ([_vp, _i64, _gp, _i32, _vp, _vp], C.c_int),
     "mlp_forward": ([_vp, _vp, _i64, _i32, _vp, _vp, C.c_size_t, _vp], C.c_int),
+    "mlp_noalloc_max_rows": ([], _i64),
+    "mlp_forward_noalloc": ([_vp, _vp, _i64, _i32, _vp, _vp], C.c_int),
     "mlp_grad": ([_vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp, C.c_size_t, _vp], C.c_int),
     "mlp_adam": ([_vp, _vp, _vp, _vp, _i32, C.c_float, _vp], C.c_int),
     "mlp_draw_examples": ([C.c_uint64, _i64, _i64, _bp, _vp, _vp, _vp], C.c_int),
@@ -819,6 +821,17 @@ class MLP:
         _check(lib().mlp_forward(_ptr(self.master), _ptr(x), n,
                                  self.precision if precision is None else precision, _ptr(y),
                                  _ptr(ws), nb, _stream(x)))
+        return y
+
+    def forward_noalloc(self, x, precision=None):
+        """forward() through mlp_forward_noalloc: the library's own device
+        scratch instead of a workspace (at most mlp_noalloc_max_rows() rows)."""
+        n = x.shape[0]
+        _dev(x, torch.float32, "x", (n, 1024))
+        y = torch.empty((n, NPAR), dtype=torch.float32, device=x.device)
+        _check(lib().mlp_forward_noalloc(_ptr(self.master), _ptr(x), n,
+                                         self.precision if precision is None else precision,
+                                         _ptr(y), _stream(x)))
         return y
 
     def compute_grad(self, x, target, precision=None):

@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "genesis_common.h"
@@ -634,6 +635,67 @@ Ws ws_layout(void *base, int64_t B)
     return w;
 }
 
+// The forward pass alone needs the BF16 weights, the input (FP32 and BF16),
+// the three hidden layers (pre-activation and activation) and the output, in
+// the same order as ws_layout places them.
+size_t fwd_bytes(int64_t B)
+{
+    return al(kParams * 2) + al(B * kIn * 4) + al(B * kIn * 2) +
+           3 * (al(B * kHid * 4) + al(B * kHid * 4)) + al(B * kOut * 4);
+}
+
+Ws fwd_layout(void *base, int64_t B)
+{
+    char *p = (char *)base;
+    Ws w{};
+    auto take = [&](size_t n) {
+        char *r = p;
+        p += al(n);
+        return (void *)r;
+    };
+    w.wbf = (uint16_t *)take(kParams * 2);
+    w.x = (float *)take(B * kIn * 4);
+    w.xb = (uint16_t *)take(B * kIn * 2);
+    for (int i = 0; i < 3; ++i) {
+        w.pre[i] = (float *)take(B * kHid * 4);
+        w.act[i] = take(B * kHid * 4);
+    }
+    w.out = (float *)take(B * kOut * 4);
+    return w;
+}
+
+// Scratch of mlp_forward_noalloc: one forward workspace of kNoAllocRows rows
+// per device, a file-scope device array.  Host code must not pass the array's
+// name to a kernel (that is a host-side stand-in, not a device address); it
+// uses the address hipGetSymbolAddress returns for the current device.
+constexpr int64_t kNoAllocRows = 1024;
+constexpr size_t kNoAllocBytes = (kParams * 2 + 255) / 256 * 256 + kNoAllocRows * kIn * 4 +
+                                 kNoAllocRows * kIn * 2 + 6 * kNoAllocRows * kHid * 4 +
+                                 (kNoAllocRows * kOut * 4 + 255) / 256 * 256;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices];
+std::once_flag g_scratch_once[kMaxDevices];
+hipError_t g_scratch_rc[kMaxDevices];
+
+// The scratch array's device address on the current device (set up once per
+// device, with that device current).
+int scratch_address(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return fail(ME_EHIP, "no current device (or device index >= %d)", kMaxDevices);
+    std::call_once(g_scratch_once[dev], [dev] {
+        g_scratch_rc[dev] = hipGetSymbolAddress(&g_scratch_ptr[dev], HIP_SYMBOL(scratch));
+    });
+    if (g_scratch_rc[dev] != hipSuccess || !g_scratch_ptr[dev])
+        return fail(ME_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                    hipGetErrorString(g_scratch_rc[dev]));
+    *out = g_scratch_ptr[dev];
+    return ME_OK;
+}
+
 // training area after the pass workspace: drawn parameters, targets, the
 // synthesised Stokes vectors and the gradient
 struct TrainWs {
@@ -841,6 +903,34 @@ int mlp_forward(const float *master, const float *x, int64_t n, int32_t precisio
         return fail(ME_ENOMEM, "workspace of %zu B too small for %lld rows", ws, (long long)n);
     const bool bf16 = precision == 0;
     Ws w = ws_layout(workspace, n);
+    hipStream_t st = as_stream(stream);
+    if (hipMemcpyAsync(w.x, x, n * kIn * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return fail(ME_EHIP, "copy failed");
+    if (int rc = forward(bf16, master, w, n, st))
+        return rc;
+    if (hipMemcpyAsync(y, w.out, n * kOut * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return fail(ME_EHIP, "copy failed");
+    return ME_OK;
+}
+
+int64_t mlp_noalloc_max_rows(void) { return kNoAllocRows; }
+
+int mlp_forward_noalloc(const float *master, const float *x, int64_t n, int32_t precision,
+                        float *y, void *stream)
+{
+    if (!master || !x || !y)
+        return fail(ME_EINVAL, "NULL argument");
+    if (n < 1 || n > kNoAllocRows)
+        return fail(ME_EINVAL, "mlp_forward_noalloc takes 1 to %lld rows per call, got %lld",
+                    (long long)kNoAllocRows, (long long)n);
+    void *base = nullptr;
+    if (int rc = scratch_address(&base))
+        return rc;
+    if (fwd_bytes(n) > kNoAllocBytes)
+        return fail(ME_ENOMEM, "internal: forward scratch of %zu B exceeds %zu B", fwd_bytes(n),
+                    kNoAllocBytes);
+    const bool bf16 = precision == 0;
+    const Ws w = fwd_layout(base, n);
     hipStream_t st = as_stream(stream);
     if (hipMemcpyAsync(w.x, x, n * kIn * 4, hipMemcpyDeviceToDevice, st) != hipSuccess)
         return fail(ME_EHIP, "copy failed");
