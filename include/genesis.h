@@ -600,12 +600,25 @@ int mlp_train(float *master, float *m, float *v, int32_t first_step, int32_t ste
  * than the whole budget.  The budget counts only what the session owns (the
  * resident populations), not the caller's input and output arrays.
  * Each gs_step waits on the device for the session's previous step, on
- * whatever stream that one ran, so steps may come on different streams. */
+ * whatever stream that one ran, so steps may come on different streams.
+ * cfg->synth_precision may select FP16 profile synthesis (damping bounds
+ * within [0, 1], as for ga_invert); gs_submit_fill serves the fill-fraction
+ * merit.  Requests of every kind share each launch. */
 int gs_create(size_t hbm_budget_bytes, int32_t gens_per_step, void **session);
 int gs_submit(void *session, const float *obs, const float *sigma, const float *mu, int64_t npix,
               const me_line *lines, const me_grid *grids, int32_t nlines,
               const me_bounds *bounds, const ga_config *cfg, float *best_params,
               float *best_chi2, int32_t *status, uint64_t *request_id);
+/* gs_submit for the fill-fraction merit of Sec. 5.2 (as ga_invert_fill):
+ * every individual takes its best alpha in [fill->alpha_lo, fill->alpha_hi]
+ * in closed form; best_alpha [npix] (device, caller-owned) receives the best
+ * individual's alpha.  Native synthesis only (ME_EINVAL with FP16).  A
+ * served tile equals ga_invert_fill of it bit for bit. */
+int gs_submit_fill(void *session, const float *obs, const float *sigma, const float *mu,
+                   int64_t npix, const me_line *lines, const me_grid *grids, int32_t nlines,
+                   const me_bounds *bounds, const ga_config *cfg, const me_fill *fill,
+                   float *best_params, float *best_alpha, float *best_chi2, int32_t *status,
+                   uint64_t *request_id);
 int gs_step(void *session, void *stream);
 /* Admission by compute as well as memory: with max_pixels > 0 a queued request
  * is admitted only while the resident pixels (plus its own) stay within

@@ -206,6 +206,8 @@ _SIGS = {
     "gs_create": ([C.c_size_t, _i32, C.POINTER(_vp)], C.c_int),
     "gs_submit": ([_vp, _vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _cp, _vp, _vp, _vp,
                    C.POINTER(C.c_uint64)], C.c_int),
+    "gs_submit_fill": ([_vp, _vp, _vp, _vp, _i64, _lp, _gp, _i32, _bp, _cp,
+                        C.POINTER(MeFill), _vp, _vp, _vp, _vp, C.POINTER(C.c_uint64)], C.c_int),
     "gs_step": ([_vp, _vp], C.c_int),
     "gs_set_max_resident_pixels": ([_vp, _i64], C.c_int),
     "gs_poll": ([_vp, C.c_uint64, C.POINTER(_i32)], C.c_int),
@@ -704,7 +706,11 @@ class ServingSession:
         if max_resident_pixels:
             _check(lib().gs_set_max_resident_pixels(self._h, int(max_resident_pixels)))
 
-    def submit(self, obs, sigma, lines, grids, bnds: MeBounds, cfg: GAConfig, mu=None):
+    def submit(self, obs, sigma, lines, grids, bnds: MeBounds, cfg: GAConfig, mu=None,
+               fill: MeFill = None):
+        """Queue a tile; cfg.synth_precision chooses FP16 profile synthesis,
+        `fill` the fill-fraction merit of Sec. 5.2 (the result then has
+        'alpha')."""
         npix = obs.shape[0]
         L = total_samples(grids)
         _dev(obs, torch.float32, "obs", (npix, 4, L))
@@ -716,9 +722,16 @@ class ServingSession:
         la, ga, nl = _lines(lines, grids)
         c = cfg.c(npix)
         rid = C.c_uint64()
-        _check(lib().gs_submit(self._h, _ptr(obs), _ptr(sigma), _ptr(mu), npix, la, ga, nl,
-                               C.byref(bnds), C.byref(c), _ptr(out["params"]), _ptr(out["chi2"]),
-                               _ptr(out["status"]), C.byref(rid)))
+        if fill is None:
+            _check(lib().gs_submit(self._h, _ptr(obs), _ptr(sigma), _ptr(mu), npix, la, ga, nl,
+                                   C.byref(bnds), C.byref(c), _ptr(out["params"]),
+                                   _ptr(out["chi2"]), _ptr(out["status"]), C.byref(rid)))
+        else:
+            out["alpha"] = torch.empty((npix,), dtype=torch.float32, device=obs.device)
+            _check(lib().gs_submit_fill(self._h, _ptr(obs), _ptr(sigma), _ptr(mu), npix, la, ga,
+                                        nl, C.byref(bnds), C.byref(c), C.byref(fill),
+                                        _ptr(out["params"]), _ptr(out["alpha"]),
+                                        _ptr(out["chi2"]), _ptr(out["status"]), C.byref(rid)))
         # the device reads the inputs and writes the outputs until the request
         # is done: keep them alive until it is released
         self._req[rid.value] = dict(out=out, keep=(obs, sigma, mu, cfg.seed_params,

@@ -481,18 +481,6 @@ struct InvertArgs : SynLines<SYN>, FillArgs<Real, FILL> {
     int32_t prio_mate;
 };
 
-// Issue priority of the calling wave, 0 (lowest) to 3; the instruction takes
-// an immediate, so the four values are four branches (uniform per wave).
-__device__ __forceinline__ void set_issue_priority(int r)
-{
-    switch (r & 3) {
-    case 0: __builtin_amdgcn_s_setprio(0); break;
-    case 1: __builtin_amdgcn_s_setprio(1); break;
-    case 2: __builtin_amdgcn_s_setprio(2); break;
-    default: __builtin_amdgcn_s_setprio(3); break;
-    }
-}
-
 // The whole of Algorithm 1 for one pixel per workgroup: the population
 // lives in LDS (two buffers: parents and children), lane i owns
 // individual i.
@@ -547,82 +535,31 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN, FILL> 
             continue;
         }
         const uint32_t pix = a.ga.pixel_base + (uint32_t)p;
-        const int gstride = GENESIS_NPAR * pop;
-        int cur = 0;  // offset of the current generation's gene buffer
-        if (active) {
-            uint32_t g0[GENESIS_NPAR];
-            initial_genes(pix, p, tid, a.ga, *s.box, g0);
-#pragma unroll
-            for (int j = 0; j < GENESIS_NPAR; ++j)
-                s.genes[j * pop + tid] = (uint16_t)g0[j];
-        }
-        Real f = (Real)0;
-        // one evaluation site: after a restart the loop comes back here with
-        // only the replaced lanes to evaluate
-        bool eval = active, restarted = false;
-        for (int t = 0;;) {
-            // In a launch that is resident all at once, a SIMD issues oldest
-            // first, so the first-dispatched workgroups run ahead and finish
-            // early and the launch ends on SIMDs holding one or two waves.
-            // Rotating the issue priority among the workgroups that share a
-            // CU every generation keeps their progress even.  It changes the
-            // issue order only, never a result.
-            if (a.prio_mate > 0)
-                set_issue_priority(t + (int)blockIdx.x + (int)blockIdx.x / a.prio_mate);
-            // evaluate generation t (each lane reads only its own genes)
-            if (eval) {
-                if constexpr (FILL) {
-                    Real al;
-                    f = evaluate_fill(s.genes + cur, pop, tid, *s.box, mu, a.ls, fp,
-                                      (Real)a.fc.alpha_lo, (Real)a.fc.alpha_hi, s.obs, w2, inv_nu,
-                                      al);
-                } else if constexpr (SYN == GENESIS_SYNTH_FP16) {
-                    f = evaluate_lds_h(s.genes + cur, pop, tid, *s.box, mu, a.ls, a.lh, s.obs,
-                                       w2, inv_nu);
-                } else {
-                    f = evaluate_lds(s.genes + cur, pop, tid, *s.box, mu, a.ls, s.obs, w2,
-                                     inv_nu);
-                }
-                s.fit[tid] = f;
-            }
-            __syncthreads();
-            if (!restarted && restart_due(a.ga, t, a.generations)) {
-                const int rank = active ? fitness_rank(s.fit, pop, tid) : 0;
-                __syncthreads();
-                uint32_t gr[GENESIS_NPAR];
-                eval = active && restart_genes(a.ga, pix, t, rank, gr);
-                if (eval)
-#pragma unroll
-                    for (int j = 0; j < GENESIS_NPAR; ++j)
-                        s.genes[cur + j * pop + tid] = (uint16_t)gr[j];
-                restarted = true;
-                continue;
-            }
-            if (t == a.generations)
-                break;
-            const int e = block_argmin(s.fit, pop, s.red_f, s.red_i);
-            if (active) {
-                LdsChild out{s.genes + (gstride - cur), pop, tid};
-                if (tid == 0) {
-                    for (int j = 0; j < GENESIS_NPAR; ++j)
-                        out.gene(j, s.genes[cur + j * pop + e], 0u);
-                } else {
-                    make_child(tid, pix, (uint32_t)(t + 1), s.fit, s.genes + cur, a.ga, out);
-                }
-            }
-            __syncthreads();
-            cur = gstride - cur;
-            ++t;
-            eval = active;
-            restarted = false;
-        }
-        const int e = block_argmin(s.fit, pop, s.red_f, s.red_i);
+        GenState<Real> gs = generation_zero(s, pop, tid, pix, p, a.ga);
+        // In a launch that is resident all at once, a SIMD issues oldest
+        // first, so the first-dispatched workgroups run ahead and finish
+        // early and the launch ends on SIMDs holding one or two waves.
+        // Rotating the issue priority among the workgroups that share a CU
+        // every generation (prio_mate) keeps their progress even.  It changes
+        // the issue order only, never a result.
+        generation_loop(s, pop, tid, pix, a.ga, a.generations, a.generations, a.prio_mate, gs,
+                        [&](const uint16_t *genes) -> Real {
+                            if constexpr (FILL) {
+                                Real al;
+                                return evaluate_fill(genes, pop, tid, *s.box, mu, a.ls, fp,
+                                                     (Real)a.fc.alpha_lo, (Real)a.fc.alpha_hi,
+                                                     s.obs, w2, inv_nu, al);
+                            } else if constexpr (SYN == GENESIS_SYNTH_FP16) {
+                                return evaluate_lds_h(genes, pop, tid, *s.box, mu, a.ls, a.lh,
+                                                      s.obs, w2, inv_nu);
+                            } else {
+                                return evaluate_lds(genes, pop, tid, *s.box, mu, a.ls, s.obs, w2,
+                                                    inv_nu);
+                            }
+                        });
+        double par[GENESIS_NPAR];
+        const int e = best_of(s, pop, gs, par);
         if (tid == 0) {
-            uint32_t gb[GENESIS_NPAR];
-            for (int j = 0; j < GENESIS_NPAR; ++j)
-                gb[j] = s.genes[cur + j * pop + e];
-            double par[GENESIS_NPAR];
-            decode(gb, *s.box, par);
             for (int j = 0; j < GENESIS_NPAR; ++j)
                 a.best_params[p * GENESIS_NPAR + j] = (Real)par[j];
             a.best_chi2[p] = s.fit[e];
@@ -638,6 +575,8 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN, FILL> 
             if (a.status)
                 a.status[p] = 0;
         }
+        const int cur = gs.cur;
+        const Real f = gs.f;
         if (active) {
             if (a.final_fitness)
                 a.final_fitness[p * pop + tid] = f;

@@ -171,6 +171,10 @@ struct FillConst {
     double depth[GENESIS_MAX_LINES][4], width[GENESIS_MAX_LINES][4], damp[GENESIS_MAX_LINES][4];
 };
 
+// The fill-fraction constants of a me_fill (host; checks the alpha range and
+// that the coefficients of the first nlines lines are finite).
+int pack_fill(const me_fill *fill, int nlines, FillConst &fc);
+
 template <typename Real>
 struct FillLine;
 template <>
@@ -449,6 +453,119 @@ __device__ __forceinline__ float evaluate_lds_h(const uint16_t *genes_s, int pop
     ModelH m;
     model_setup(par, mu, m);
     return chi2_of_h(m, ls, lh, obs_s, w2, inv_nu);
+}
+
+// Issue priority of the calling wave, 0 (lowest) to 3; the instruction takes
+// an immediate, so the four values are four branches (uniform per wave).
+__device__ __forceinline__ void set_issue_priority(int r)
+{
+    switch (r & 3) {
+    case 0: __builtin_amdgcn_s_setprio(0); break;
+    case 1: __builtin_amdgcn_s_setprio(1); break;
+    case 2: __builtin_amdgcn_s_setprio(2); break;
+    default: __builtin_amdgcn_s_setprio(3); break;
+    }
+}
+
+// Where a pixel's generation loop stands: generation g with its genes at
+// s.genes + cur; `eval` when this lane's individual still has to be
+// evaluated, `restarted` once generation g's restart (if due) is done.
+template <typename Real>
+struct GenState {
+    int g, cur;
+    bool eval, restarted;
+    Real f;  // this lane's fitness of generation g (once evaluated)
+};
+
+// The generation loop of Algorithm 1 for one pixel (one workgroup, lane i
+// owns individual i; parents and children in the two LDS gene buffers):
+// evaluate generation g, restart it when due (Sec. 5.6; the replaced lanes
+// come back here to be evaluated), and breed generation g + 1 (elite to slot
+// 0, selection, recombination, mutation), until generation g_to is evaluated
+// and restarted.  evaluate(genes) returns the calling lane's fitness of the
+// genes in buffer `genes`.  prio_mate > 0 rotates the waves' issue priority
+// every generation (the whole launch resident at once; see k_ga_invert).
+// On return s.fit holds generation g_to's fitness.  ga_invert and the
+// service run this same loop, so a served pixel is bit-identical to it.
+template <typename Real, typename Eval>
+__device__ __forceinline__ void generation_loop(const GaLds<Real> &s, int pop, int tid,
+                                                uint32_t pix, const GaConst &ga,
+                                                int generations, int g_to, int prio_mate,
+                                                GenState<Real> &st, Eval &&evaluate)
+{
+    const bool active = tid < pop;
+    const int gstride = GENESIS_NPAR * pop;
+    for (;;) {
+        if (prio_mate > 0)
+            set_issue_priority(st.g + (int)blockIdx.x + (int)blockIdx.x / prio_mate);
+        if (st.eval) {
+            st.f = evaluate(s.genes + st.cur);
+            s.fit[tid] = st.f;
+        }
+        __syncthreads();
+        if (!st.restarted && restart_due(ga, st.g, generations)) {
+            const int rank = active ? fitness_rank(s.fit, pop, tid) : 0;
+            __syncthreads();
+            uint32_t gr[GENESIS_NPAR];
+            st.eval = active && restart_genes(ga, pix, st.g, rank, gr);
+            if (st.eval)
+#pragma unroll
+                for (int j = 0; j < GENESIS_NPAR; ++j)
+                    s.genes[st.cur + j * pop + tid] = (uint16_t)gr[j];
+            st.restarted = true;
+            continue;
+        }
+        if (st.g == g_to)
+            break;
+        const int e = block_argmin(s.fit, pop, s.red_f, s.red_i);
+        if (active) {
+            LdsChild out{s.genes + (gstride - st.cur), pop, tid};
+            if (tid == 0) {
+                for (int j = 0; j < GENESIS_NPAR; ++j)
+                    out.gene(j, s.genes[st.cur + j * pop + e], 0u);
+            } else {
+                make_child(tid, pix, (uint32_t)(st.g + 1), s.fit, s.genes + st.cur, ga, out);
+            }
+        }
+        __syncthreads();
+        st.cur = gstride - st.cur;
+        ++st.g;
+        st.eval = active;
+        st.restarted = false;
+    }
+}
+
+// Generation 0 of one pixel into the first gene buffer (Algorithm 1,
+// "Create P0"), to be evaluated by generation_loop.
+template <typename Real>
+__device__ __forceinline__ GenState<Real> generation_zero(const GaLds<Real> &s, int pop, int tid,
+                                                         uint32_t pix, int64_t p,
+                                                         const GaConst &ga)
+{
+    if (tid < pop) {
+        uint32_t g0[GENESIS_NPAR];
+        initial_genes(pix, p, tid, ga, *s.box, g0);
+#pragma unroll
+        for (int j = 0; j < GENESIS_NPAR; ++j)
+            s.genes[j * pop + tid] = (uint16_t)g0[j];
+    }
+    return GenState<Real>{0, 0, tid < pop, false, (Real)0};
+}
+
+// The best individual of the current generation (elite rule: least fitness,
+// ties to the lower index, NaN last): its decoded parameters on thread 0.
+template <typename Real>
+__device__ __forceinline__ int best_of(const GaLds<Real> &s, int pop, const GenState<Real> &st,
+                                       double (&par)[GENESIS_NPAR])
+{
+    const int e = block_argmin(s.fit, pop, s.red_f, s.red_i);
+    if (threadIdx.x == 0) {
+        uint32_t gb[GENESIS_NPAR];
+        for (int j = 0; j < GENESIS_NPAR; ++j)
+            gb[j] = s.genes[st.cur + j * pop + e];
+        decode(gb, *s.box, par);
+    }
+    return e;
 }
 
 // FP16 strength table of packed lines (after pack_lines).

@@ -31,15 +31,20 @@ struct ReqDesc {
     uint16_t *genes;  // [npix][pop][9], session-owned
     float *fit;       // [npix][pop], session-owned
     float *best_params, *best_chi2;
+    float *best_alpha;  // [npix], fill-fraction requests only
     int32_t *status;
     int64_t npix;
     int32_t generations;  // G of the request
     int32_t gen_done;     // generations completed before this launch, -1 = not started
     int32_t gen_to;       // generation to reach in this launch
+    int32_t synth;        // GENESIS_SYNTH_NATIVE or GENESIS_SYNTH_FP16
+    int32_t fill;         // 1: the fill-fraction merit of Sec. 5.2 (fc)
     int32_t pad_;
     DevLines<float> ls;
+    DevLinesH lh;         // FP16 synthesis only
     Bounds b;
     GaConst ga;
+    FillConst fc;         // fill-fraction requests only
 };
 
 }  // namespace genesis
@@ -70,114 +75,98 @@ __global__ __launch_bounds__(1024) void k_ga_advance(const ReqDesc *__restrict__
     const GaLds<float> s = ga_lds<float>(smem, L, pop);
     const int tid = threadIdx.x;
     const bool active = tid < pop;
-    const float inv_nu = (float)(1.0 / (4.0 * L - GENESIS_NPAR));
+    // nu = 4L - 9, or 4L - 10 with the fill fraction as a tenth parameter
+    const float inv_nu = (float)(1.0 / (4.0 * L - (d.fill ? GENESIS_NPAR + 1 : GENESIS_NPAR)));
     const bool finish = d.gen_to == d.generations;
+    const double mu = d.mu ? (double)d.mu[p] : 1.0;
+    FillPix<float> &fp = *reinterpret_cast<FillPix<float> *>(s.fill);
 
-    if (tid == 0)
+    if (tid == 0) {
         stage_box(d.b, d.ga.pixel_bounds, p, *s.box);
+        if (d.fill)
+            fill_setup(d.fc, d.ls.nlines, mu, fp);
+    }
     float w2[4];
     int st = stage_pixel(d.obs + p * 4 * (int64_t)L, d.sigma + p * 4, L, s.obs, w2);
     if (st == 0 && d.ga.pixel_bounds)
-        st = box_status(*s.box, false);
+        st = box_status(*s.box, d.synth == GENESIS_SYNTH_FP16);
+    if (st == 0 && d.fill)
+        st = fp.status;
     if (st != 0) {
         if (finish && tid == 0) {
             for (int j = 0; j < GENESIS_NPAR; ++j)
                 d.best_params[p * GENESIS_NPAR + j] = NAN;
             d.best_chi2[p] = NAN;
+            if (d.fill)
+                d.best_alpha[p] = NAN;
             if (d.status)
                 d.status[p] = st;
         }
         return;
     }
-    const double mu = d.mu ? (double)d.mu[p] : 1.0;
     const uint32_t pix = d.ga.pixel_base + (uint32_t)p;
-    const int gstride = GENESIS_NPAR * pop;
-    int cur = 0;
-    float f = 0.0f;
-    // one evaluation site, as in k_ga_invert: generation g is evaluated, then
-    // restarted if due (the replaced lanes come back to be evaluated), then
-    // bred into generation g + 1 until gen_to is reached.  A resumed
-    // generation was saved after its restart.
-    int g = d.gen_done;
-    bool eval, restarted;
-    if (g < 0) {
-        if (active) {
-            uint32_t g0[GENESIS_NPAR];
-            initial_genes(pix, p, tid, d.ga, *s.box, g0);
-#pragma unroll
-            for (int j = 0; j < GENESIS_NPAR; ++j)
-                s.genes[j * pop + tid] = (uint16_t)g0[j];
-        }
-        g = 0;
-        eval = active;
-        restarted = false;
+    // a new request starts from generation 0; a resumed one from the
+    // generation saved at the end of the previous launch (after its restart)
+    GenState<float> gs;
+    if (d.gen_done < 0) {
+        gs = generation_zero(s, pop, tid, pix, p, d.ga);
     } else {
+        gs = GenState<float>{d.gen_done, 0, false, true, 0.0f};
         if (active) {
             const int64_t row = p * pop + tid;
 #pragma unroll
             for (int j = 0; j < GENESIS_NPAR; ++j)
                 s.genes[j * pop + tid] = d.genes[row * GENESIS_NPAR + j];
-            f = d.fit[row];
-            s.fit[tid] = f;
+            gs.f = d.fit[row];
+            s.fit[tid] = gs.f;
         }
-        eval = false;
-        restarted = true;
     }
-    for (;;) {
-        if (eval) {
-            f = evaluate_lds(s.genes + cur, pop, tid, *s.box, mu, d.ls, s.obs, w2, inv_nu);
-            s.fit[tid] = f;
-        }
-        __syncthreads();
-        if (!restarted && restart_due(d.ga, g, d.generations)) {
-            const int rank = active ? fitness_rank(s.fit, pop, tid) : 0;
-            __syncthreads();
-            uint32_t gr[GENESIS_NPAR];
-            eval = active && restart_genes(d.ga, pix, g, rank, gr);
-            if (eval)
-#pragma unroll
-                for (int j = 0; j < GENESIS_NPAR; ++j)
-                    s.genes[cur + j * pop + tid] = (uint16_t)gr[j];
-            restarted = true;
-            continue;
-        }
-        if (g == d.gen_to)
-            break;
-        const int e = block_argmin(s.fit, pop, s.red_f, s.red_i);
-        if (active) {
-            LdsChild out{s.genes + (gstride - cur), pop, tid};
-            if (tid == 0) {
-                for (int j = 0; j < GENESIS_NPAR; ++j)
-                    out.gene(j, s.genes[cur + j * pop + e], 0u);
-            } else {
-                make_child(tid, pix, (uint32_t)(g + 1), s.fit, s.genes + cur, d.ga, out);
-            }
-        }
-        __syncthreads();
-        cur = gstride - cur;
-        ++g;
-        eval = active;
-        restarted = false;
+    // the evaluation of the request's kind (uniform over the workgroup)
+    if (d.synth == GENESIS_SYNTH_FP16) {
+        generation_loop(s, pop, tid, pix, d.ga, d.generations, d.gen_to, 0, gs,
+                        [&](const uint16_t *genes) -> float {
+                            return evaluate_lds_h(genes, pop, tid, *s.box, mu, d.ls, d.lh, s.obs,
+                                                  w2, inv_nu);
+                        });
+    } else if (d.fill) {
+        generation_loop(s, pop, tid, pix, d.ga, d.generations, d.gen_to, 0, gs,
+                        [&](const uint16_t *genes) -> float {
+                            float al;
+                            return evaluate_fill(genes, pop, tid, *s.box, mu, d.ls, fp,
+                                                 (float)d.fc.alpha_lo, (float)d.fc.alpha_hi, s.obs,
+                                                 w2, inv_nu, al);
+                        });
+    } else {
+        generation_loop(s, pop, tid, pix, d.ga, d.generations, d.gen_to, 0, gs,
+                        [&](const uint16_t *genes) -> float {
+                            return evaluate_lds(genes, pop, tid, *s.box, mu, d.ls, s.obs, w2,
+                                                inv_nu);
+                        });
     }
     if (finish) {
-        const int e = block_argmin(s.fit, pop, s.red_f, s.red_i);
+        double par[GENESIS_NPAR];
+        const int e = best_of(s, pop, gs, par);
         if (tid == 0) {
-            uint32_t gb[GENESIS_NPAR];
-            for (int j = 0; j < GENESIS_NPAR; ++j)
-                gb[j] = s.genes[cur + j * pop + e];
-            double par[GENESIS_NPAR];
-            decode(gb, *s.box, par);
             for (int j = 0; j < GENESIS_NPAR; ++j)
                 d.best_params[p * GENESIS_NPAR + j] = (float)par[j];
             d.best_chi2[p] = s.fit[e];
+            if (d.fill) {
+                // the best individual's alpha, as ga_invert finds it
+                Model<float> m;
+                model_setup(par, mu, m);
+                float al;
+                (void)chi2_fill_of(m, d.ls, fp, (float)d.fc.alpha_lo, (float)d.fc.alpha_hi, s.obs,
+                                   w2, inv_nu, al);
+                d.best_alpha[p] = al;
+            }
             if (d.status)
                 d.status[p] = 0;
         }
     } else if (active) {
         const int64_t row = p * pop + tid;
         for (int j = 0; j < GENESIS_NPAR; ++j)
-            d.genes[row * GENESIS_NPAR + j] = s.genes[cur + j * pop + tid];
-        d.fit[row] = f;
+            d.genes[row * GENESIS_NPAR + j] = s.genes[gs.cur + j * pop + tid];
+        d.fit[row] = gs.f;
     }
 }
 
@@ -243,10 +232,15 @@ int gs_create(size_t hbm_budget_bytes, int32_t gens_per_step, void **session)
     return ME_OK;
 }
 
-int gs_submit(void *session, const float *obs, const float *sigma, const float *mu, int64_t npix,
-              const me_line *lines, const me_grid *grids, int32_t nlines,
-              const me_bounds *bounds, const ga_config *cfg, float *best_params,
-              float *best_chi2, int32_t *status, uint64_t *request_id)
+}  // extern "C"
+
+namespace {
+
+int submit_impl(void *session, const float *obs, const float *sigma, const float *mu,
+                int64_t npix, const me_line *lines, const me_grid *grids, int32_t nlines,
+                const me_bounds *bounds, const ga_config *cfg, const me_fill *fill,
+                float *best_params, float *best_alpha, float *best_chi2, int32_t *status,
+                uint64_t *request_id)
 {
     auto *s = static_cast<Session *>(session);
     if (!s || !request_id)
@@ -259,12 +253,27 @@ int gs_submit(void *session, const float *obs, const float *sigma, const float *
         return rc;
     if (int rc = pack_ga(cfg, d.ga))
         return rc;
-    if (cfg->synth_precision != GENESIS_SYNTH_NATIVE)
-        return fail(ME_EINVAL, "the service synthesises in FP32 (synth_precision must be 0)");
+    d.synth = cfg->synth_precision;
+    d.fill = fill ? 1 : 0;
+    if (d.synth == GENESIS_SYNTH_FP16) {
+        if (fill)
+            return fail(ME_EINVAL, "the fill fraction needs native synthesis (synth_precision 0)");
+        if (!(bounds->lo[5] >= 0.0 && bounds->hi[5] <= kHalfMaxDamping))
+            return fail(ME_EINVAL, "FP16 synthesis needs damping bounds within [0, %g]",
+                        kHalfMaxDamping);
+        pack_lines_h(d.ls, d.lh);
+    }
+    if (fill) {
+        if (int rc = pack_fill(fill, nlines, d.fc))
+            return rc;
+        if (!best_alpha)
+            return fail(ME_EINVAL, "best_alpha must not be NULL");
+    }
     if (npix < 1 || npix > kMaxGrid)
         return fail(ME_EINVAL, "npix must lie in [1, 2^30]");
-    if (4 * d.ls.L <= GENESIS_NPAR)
-        return fail(ME_EINVAL, "need 4 L > 9 wavelength samples for nu > 0");
+    if (4 * d.ls.L <= GENESIS_NPAR + d.fill)
+        return fail(ME_EINVAL, "need 4 L > %d wavelength samples for nu > 0",
+                    GENESIS_NPAR + d.fill);
     if (ga_lds_bytes<float>(d.ls.L, cfg->pop) > kMaxLds)
         return fail(ME_ENOMEM, "L = %d, pop = %d exceed LDS", d.ls.L, cfg->pop);
     if (!obs || !sigma || !best_params || !best_chi2)
@@ -276,6 +285,7 @@ int gs_submit(void *session, const float *obs, const float *sigma, const float *
     d.generations = cfg->generations;
     d.best_params = best_params;
     d.best_chi2 = best_chi2;
+    d.best_alpha = fill ? best_alpha : nullptr;
     d.status = status;
     r->npix = npix;
     r->generations = cfg->generations;
@@ -289,6 +299,31 @@ int gs_submit(void *session, const float *obs, const float *sigma, const float *
     (void)s->sched.submit(r);
     *request_id = r->id;
     return ME_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gs_submit(void *session, const float *obs, const float *sigma, const float *mu, int64_t npix,
+              const me_line *lines, const me_grid *grids, int32_t nlines,
+              const me_bounds *bounds, const ga_config *cfg, float *best_params,
+              float *best_chi2, int32_t *status, uint64_t *request_id)
+{
+    return submit_impl(session, obs, sigma, mu, npix, lines, grids, nlines, bounds, cfg, nullptr,
+                       best_params, nullptr, best_chi2, status, request_id);
+}
+
+int gs_submit_fill(void *session, const float *obs, const float *sigma, const float *mu,
+                   int64_t npix, const me_line *lines, const me_grid *grids, int32_t nlines,
+                   const me_bounds *bounds, const ga_config *cfg, const me_fill *fill,
+                   float *best_params, float *best_alpha, float *best_chi2, int32_t *status,
+                   uint64_t *request_id)
+{
+    if (!fill)
+        return fail(ME_EINVAL, "fill must not be NULL");
+    return submit_impl(session, obs, sigma, mu, npix, lines, grids, nlines, bounds, cfg, fill,
+                       best_params, best_alpha, best_chi2, status, request_id);
 }
 
 int gs_set_max_resident_pixels(void *session, int64_t max_pixels)

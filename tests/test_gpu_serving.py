@@ -242,3 +242,92 @@ def test_steps_on_alternating_streams():
     for r, rid in zip(reqs, ids):
         assert _same(sess.result(rid), _alone(r, cfg))
     sess.close()
+
+
+def _fill_request(npix, seed, lo=0.1, hi=1.0):
+    lines, grids, olines = [], [], []
+    for ln, n in si.line_set("slit"):
+        st, sp = si.grid(ln, n)
+        lines.append(g.line_from_terms(ln["lambda0"], ln["Jl"], ln["gl"], ln["Ju"], ln["gu"]))
+        grids.append(g.grid(st, sp, n))
+        olines.append(oracle.make_line(ln["lambda0"], ln["Jl"], ln["gl"], ln["Ju"], ln["gu"],
+                                       st, sp, n))
+    c = si.fill_coefficients("slit")
+    gf, of = g.fill(lo, hi, *c), oracle.make_fill(lo, hi, *c)
+    truth = si.draw_truth(npix, seed)
+    alpha = si.draw_alpha(npix, seed)
+    obs = oracle.me_synth_fill(truth, alpha, olines, of)
+    sig = si.sigma_for(truth)
+    obs = (obs + sig[:, :, None] * si.std_normal(obs.shape, seed)).astype(np.float32)
+    sig = sig.astype(np.float32)
+    obs[npix // 2, 0, 5] = np.nan
+    return (lines, grids, torch.tensor(obs, device=DEV), torch.tensor(sig, device=DEV), olines,
+            truth, gf, of)
+
+
+def test_fp16_and_fill_requests_equal_their_standalone_runs():
+    # the service runs ga_invert's own generation loop, so FP16-synthesis and
+    # fill-fraction requests, mixed with plain ones and arriving late, come
+    # out bit-identical to their standalone inversions
+    b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
+    r16 = _request("slit", 60, 11, bad=True)
+    c16 = g.GAConfig(pop=128, generations=17, seed=9, synth_precision=g.SYNTH_FP16)
+    rf = _fill_request(50, 12)
+    cf = g.GAConfig(pop=96, generations=13, seed=10, init_mode=1, restart_every=5)
+    rp = _request("tiny", 20, 13)
+    cp = g.GAConfig(pop=64, generations=11, seed=11)
+    sess = g.ServingSession(budget_bytes=1 << 30, gens_per_step=5)
+    ids = [sess.submit(rp[2], rp[3], rp[0], rp[1], b, cp)]
+    sess.step()
+    ids.append(sess.submit(r16[2], r16[3], r16[0], r16[1], b, c16))
+    ids.append(sess.submit(rf[2], rf[3], rf[0], rf[1], b, cf, fill=rf[6]))
+    _drain(sess, ids)
+    out_p, out_16, out_f = (sess.result(i) for i in ids)
+    assert _same(out_p, _alone(rp, cp))
+    assert _same(out_16, _alone(r16, c16))
+    alone_f = g.ga_invert(rf[2], rf[3], rf[0], rf[1], b, cf, fill=rf[6])
+    assert _same(out_f, alone_f)
+    assert torch.equal(out_f["alpha"].nan_to_num(-1), alone_f["alpha"].nan_to_num(-1))
+    # oracle leg of the fill request: status, and the reported chi-square and
+    # alpha are the oracle's fill merit and best alpha of the decoded genes
+    lines, grids, obs, sig, olines, truth, gf, of = rf
+    lo, hi = np.asarray(si.PRIOR_LO), np.asarray(si.PRIOR_HI)
+    st = out_f["status"].cpu().numpy()
+    ok = st == 0
+    assert st[~ok].tolist() == [1] and np.isnan(out_f["alpha"].cpu().numpy()[~ok]).all()
+    par = out_f["params"].cpu().numpy()[ok]
+    dec = oracle.decode(recover_genes(par, lo, hi), lo, hi)
+    o64 = obs.cpu().numpy().astype(np.float64)[ok]
+    s64 = sig.cpu().numpy().astype(np.float64)[ok]
+    ref, aref = oracle.chi2_fill(dec[:, None, :], o64, s64, olines, of)
+    chi = out_f["chi2"].cpu().numpy().astype(np.float64)[ok]
+    L = o64.shape[-1]
+    models = np.stack([oracle.me_synth_fill(dec[i:i + 1], aref[i], olines, of)[0]
+                       for i in range(len(dec))])
+    delta = FWD_TOL_F32 * ic_of(dec)[:, None, None]
+    rr = np.abs(o64 - models)
+    w2 = 1.0 / s64[:, :, None] ** 2
+    bound = (w2 * (2 * rr * delta + delta ** 2)).sum(axis=(1, 2)) / (4 * L - 10)
+    assert np.all(np.abs(chi - ref[:, 0]) <= bound + 1e-5 * ref[:, 0])
+    da = np.abs(out_f["alpha"].cpu().numpy()[ok] - aref[:, 0])
+    assert np.median(da) <= 1e-5 and da.max() <= 1e-3, da
+    # the FP16 request's oracle leg: status and decodable parameters (its
+    # fitness is the FP16 synthesis's, checked against the oracle in the FP16
+    # tests)
+    st16 = out_16["status"].cpu().numpy()
+    ref16 = oracle.ga_invert(r16[2].cpu().numpy().astype(np.float64),
+                             r16[3].cpu().numpy().astype(np.float64), r16[4], lo, hi, pop=2,
+                             generations=0, k=1, p_cross=0.0, p_mut=0.0, seed=0)["status"]
+    assert np.array_equal(st16, ref16)
+    sess.close()
+
+
+def test_service_rejects_fill_with_fp16():
+    b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
+    rf = _fill_request(8, 14)
+    sess = g.ServingSession(budget_bytes=1 << 30, gens_per_step=5)
+    with pytest.raises(g.GenesisError):
+        sess.submit(rf[2], rf[3], rf[0], rf[1], b,
+                    g.GAConfig(pop=32, generations=3, synth_precision=g.SYNTH_FP16), fill=rf[6])
+    assert sess.held() == 0
+    sess.close()
