@@ -29,3 +29,15 @@ def test_scheduler_against_mock_allocator(tmp_path):
     out = _run(["g++", "-std=c++17", "-Wall", "-Wextra", "-Werror"] + SAN +
                [os.path.join(HERE, "native", "test_scheduler.cpp")], tmp_path, "sched")
     assert "all checks passed" in out
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+def test_oracle_entry_points_under_sanitizers(tmp_path):
+    src = [os.path.join(ROOT, "oracle", f) for f in sorted(os.listdir(os.path.join(ROOT, "oracle")))
+           if f.endswith(".c")]
+    # serial build (the OpenMP pragmas are ignored): the sanitizers see one thread
+    out = _run(["gcc", "-std=gnu11", "-Wall", "-Wextra", "-Werror", "-Wno-unknown-pragmas"] + SAN +
+               ["-I", os.path.join(ROOT, "oracle"), os.path.join(HERE, "native",
+                                                                 "test_oracle_san.c")] +
+               src + ["-lm"], tmp_path, "oracle_san")
+    assert "all checks passed" in out
