@@ -52,37 +52,28 @@ PEAK_FP64_VALU = 78.6e12
 # with margin -- p90 |dB| 8.4 G after 5, 3.6 G after 10, 0.66 G after 50.
 REFINE_ITERS = 10
 
-# HBM bytes per launch of k_ga_invert<float> on the slit workload, from the
-# FETCH_SIZE and WRITE_SIZE counters scaled by a device copy of known size
-# (profiles/k_ga_invert_slit_counters.md).  Valid only for the sources they
-# were measured on: reported when the kernel's sources hash to this value.
-TRAFFIC_SLIT_BYTES = 204.12e6
-TRAFFIC_SOURCES = ("csrc/genesis.hip", "csrc/genesis_device.h", "csrc/genesis_common.h",
-                   "csrc/genesis_half.h", "csrc/voigt_rational.h", "csrc/weideman36.h",
-                   "build.py")
-TRAFFIC_SOURCES_SHA256 = "03882eacb494f62294dd370ce4cfd1b3c06fd3fde2fc50384c29072c383536cd"
+# HBM bytes per launch of k_ga_invert<float> from the FETCH_SIZE and
+# WRITE_SIZE counters scaled by a device copy of known size (profiles/
+# k_ga_invert_disc_counters.md): one full-disc block, and the slit row.  Valid
+# only for the machine code they were measured on: reported while the build's
+# code hash of that kernel (libgenesis_hip.layout.json) equals this one.
+TRAFFIC_DISC_BLOCK_BYTES = 18.859e9
+TRAFFIC_SLIT_BYTES = 230.78e6
+TRAFFIC_CODE_SHA256 = "2665b5d7b3eec37935ad84d7688ca5f935aa4b28d3acf7c4c5dbf8eb422758f6"
 
 
-# HBM bytes per launch of k_ga_invert<float> on one full-disc block, from the
-# same counters (profiles/k_ga_invert_disc_counters.md); None until measured
-# on the current sources.
-TRAFFIC_DISC_BLOCK_BYTES = None
-TRAFFIC_DISC_SOURCES_SHA256 = None
+def measured_traffic(nbytes):
+    """nbytes while the installed k_ga_invert<float> is the measured one, else None."""
+    from paper_1208_0302_amd import build as gbuild
+    rec = gbuild.layout().get("GENESIS_PAD_INVERT_F32", {})
+    if nbytes is None or TRAFFIC_CODE_SHA256 is None or \
+            rec.get("code_sha256") != TRAFFIC_CODE_SHA256:
+        return None
+    return nbytes
 
 
 def disc_traffic(edges):
-    if TRAFFIC_DISC_BLOCK_BYTES is None or kernel_sources_sha256() != TRAFFIC_DISC_SOURCES_SHA256:
-        return None
-    return TRAFFIC_DISC_BLOCK_BYTES
-
-
-def kernel_sources_sha256():
-    import hashlib
-    h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, "paper_1208_0302_amd", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+    return measured_traffic(TRAFFIC_DISC_BLOCK_BYTES)
 
 
 def workload(name):
@@ -1064,8 +1055,8 @@ def main():
         "layout": __import__("paper_1208_0302_amd.build", fromlist=["layout"]).layout(),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": (TRAFFIC_SLIT_BYTES if w["name"] == "slit" and dt == torch.float32
-                                 and kernel_sources_sha256() == TRAFFIC_SOURCES_SHA256 else None),
+                     "traffic": (measured_traffic(TRAFFIC_SLIT_BYTES)
+                                 if w["name"] == "slit" and dt == torch.float32 else None),
                      "kernel": "k_ga_invert<%s>" % ("float" if dt == torch.float32 else "double"),
                      "flop_per_eval": fpe, "evals_per_launch": evals},
     }

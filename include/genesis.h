@@ -322,7 +322,9 @@ int me_synth_fill_f64(const double *params, const double *alpha, int64_t n,
  * that minimum (nu = 4L - 10); the genes, operators and outputs are those of
  * ga_invert, plus best_alpha [npix], the best individual's alpha.  Status 4
  * (NaN outputs) for a pixel whose field-free profile is invalid at its mu.
- * Native synthesis only (ME_EINVAL for GENESIS_SYNTH_FP16). */
+ * cfg->synth_precision = GENESIS_SYNTH_FP16 synthesises the magnetic
+ * profiles in packed FP16 (the field-free profile, the mixture and the sums
+ * in FP32); the FP64 entry point takes native synthesis only. */
 int ga_invert_fill(const float *obs, const float *sigma, const float *mu, int64_t npix,
                    const me_line *lines, const me_grid *grids, int32_t nlines,
                    const me_bounds *bounds, const ga_config *cfg, const me_fill *fill,
@@ -612,7 +614,7 @@ int gs_submit(void *session, const float *obs, const float *sigma, const float *
 /* gs_submit for the fill-fraction merit of Sec. 5.2 (as ga_invert_fill):
  * every individual takes its best alpha in [fill->alpha_lo, fill->alpha_hi]
  * in closed form; best_alpha [npix] (device, caller-owned) receives the best
- * individual's alpha.  Native synthesis only (ME_EINVAL with FP16).  A
+ * individual's alpha; FP16 synthesis as in ga_invert_fill.  A
  * served tile equals ga_invert_fill of it bit for bit. */
 int gs_submit_fill(void *session, const float *obs, const float *sigma, const float *mu,
                    int64_t npix, const me_line *lines, const me_grid *grids, int32_t nlines,

@@ -45,6 +45,7 @@ PLACEMENT = {
     "GENESIS_PAD_INVERT_F16": r"k_ga_invertIfLi1ELb0E",
     "GENESIS_PAD_INVERT_F64": r"k_ga_invertIdLi0ELb0E",
     "GENESIS_PAD_FILL_F32": r"k_ga_invertIfLi0ELb1E",
+    "GENESIS_PAD_FILL_F16": r"k_ga_invertIfLi1ELb1E",
     "GENESIS_PAD_FILL_F64": r"k_ga_invertIdLi0ELb1E",
     "GENESIS_PAD_ADVANCE": r"k_ga_advance",
     "GENESIS_PAD_REFINE": r"k_refine_f64",
@@ -135,6 +136,28 @@ def _placement_one(co, pattern):
     return good, bad
 
 
+def code_sha256(cos, pattern):
+    """SHA-256 of the machine code of the kernels whose symbols match
+    `pattern` (their instruction encodings in symbol order): a record of
+    measurements of a kernel stays valid exactly while this is unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for co in cos:
+        table = subprocess.run([_llvm("llvm-objdump"), "-t", co], capture_output=True,
+                               text=True).stdout
+        syms = sorted(l.split()[-1] for l in table.splitlines()
+                      if " F .text" in l and re.search(pattern, l.split()[-1]))
+        for sym in syms:
+            out = subprocess.run([_llvm("llvm-objdump"), "-d", "--disassemble-symbols=" + sym,
+                                  co], capture_output=True, text=True).stdout
+            h.update(sym.encode())
+            for line in out.splitlines():
+                m = _ADDR.search(line)
+                if m:
+                    h.update(m.group(2).encode())
+    return h.hexdigest()
+
+
 def _compile(pads, verbose):
     tmp = SO + ".tmp%d" % os.getpid()
     cmd = [hipcc()] + HIPCC_FLAGS + ["-D%s=%d" % kv for kv in sorted(pads.items())] + \
@@ -176,10 +199,12 @@ def place(tmp, pads, verbose, workdir, compile_fn=None):
             if worse:
                 raise RuntimeError("code placement: the entry shift left more 8-byte loop "
                                    "instructions at 0 (mod 8) than at 4 in %s" % worse)
+        hashes = {k: code_sha256(co, p) for k, p in PLACEMENT.items()}
     except (subprocess.CalledProcessError, OSError) as e:
         return tmp, {"placement": "unchecked", "reason": str(e)}
     record = {"placement": "checked"}
-    record.update({k: {"shift": pads.get(k, 0), "good": counts[k][0], "bad": counts[k][1]}
+    record.update({k: {"shift": pads.get(k, 0), "good": counts[k][0], "bad": counts[k][1],
+                       "code_sha256": hashes[k]}
                    for k in PLACEMENT})
     return tmp, record
 

@@ -487,7 +487,9 @@ struct InvertArgs : SynLines<SYN>, FillArgs<Real, FILL> {
 template <typename Real, int SYN, bool FILL>
 __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN, FILL> a)
 {
-    code_shift<FILL ? (sizeof(Real) == 8 ? GENESIS_PAD_FILL_F64 : GENESIS_PAD_FILL_F32)
+    code_shift<FILL ? (sizeof(Real) == 8 ? GENESIS_PAD_FILL_F64
+                                         : SYN == GENESIS_SYNTH_FP16 ? GENESIS_PAD_FILL_F16
+                                                                     : GENESIS_PAD_FILL_F32)
                     : SYN == GENESIS_SYNTH_FP16
                           ? GENESIS_PAD_INVERT_F16
                           : (sizeof(Real) == 8 ? GENESIS_PAD_INVERT_F64 : GENESIS_PAD_INVERT_F32)>();
@@ -544,7 +546,13 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN, FILL> 
         // the issue order only, never a result.
         generation_loop(s, pop, tid, pix, a.ga, a.generations, a.generations, a.prio_mate, gs,
                         [&](const uint16_t *genes) -> Real {
-                            if constexpr (FILL) {
+                            if constexpr (FILL && SYN == GENESIS_SYNTH_FP16) {
+                                float al;
+                                return evaluate_fill_h(genes, pop, tid, *s.box, mu, a.ls, a.lh,
+                                                       fp, (float)a.fc.alpha_lo,
+                                                       (float)a.fc.alpha_hi, s.obs, w2, inv_nu,
+                                                       al);
+                            } else if constexpr (FILL) {
                                 Real al;
                                 return evaluate_fill(genes, pop, tid, *s.box, mu, a.ls, fp,
                                                      (Real)a.fc.alpha_lo, (Real)a.fc.alpha_hi,
@@ -563,8 +571,15 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN, FILL> 
             for (int j = 0; j < GENESIS_NPAR; ++j)
                 a.best_params[p * GENESIS_NPAR + j] = (Real)par[j];
             a.best_chi2[p] = s.fit[e];
-            if constexpr (FILL) {
+            if constexpr (FILL && SYN == GENESIS_SYNTH_FP16) {
                 // the best individual's alpha: the same evaluation again
+                ModelH m;
+                model_setup(par, mu, m);
+                float al;
+                (void)chi2_fill_of_h(m, a.ls, a.lh, fp, (float)a.fc.alpha_lo,
+                                     (float)a.fc.alpha_hi, s.obs, w2, inv_nu, al);
+                a.best_alpha[p] = al;
+            } else if constexpr (FILL) {
                 Model<Real> m;
                 model_setup(par, mu, m);
                 Real al;
@@ -2105,8 +2120,13 @@ int ga_invert_fill(const float *obs, const float *sigma, const float *mu, int64_
                    float *best_params, float *best_alpha, float *best_chi2, int32_t *status,
                    uint16_t *final_genes, float *final_fitness, void *stream)
 {
+    if (cfg && cfg->synth_precision == GENESIS_SYNTH_FP16)
+        return invert_impl<float, GENESIS_SYNTH_FP16, true>(
+            obs, sigma, mu, npix, lines, grids, nlines, bounds, cfg, best_params, best_chi2,
+            status, final_genes, final_fitness, stream, fill, best_alpha);
     if (cfg && cfg->synth_precision != GENESIS_SYNTH_NATIVE)
-        return fail(ME_EINVAL, "the fill fraction needs the native synthesis");
+        return fail(ME_EINVAL, "synth_precision = %d is not a GENESIS_SYNTH_* value",
+                    cfg->synth_precision);
     return invert_impl<float, GENESIS_SYNTH_NATIVE, true>(
         obs, sigma, mu, npix, lines, grids, nlines, bounds, cfg, best_params, best_chi2, status,
         final_genes, final_fitness, stream, fill, best_alpha);
@@ -2120,7 +2140,7 @@ int ga_invert_fill_f64(const double *obs, const double *sigma, const double *mu,
                        void *stream)
 {
     if (cfg && cfg->synth_precision != GENESIS_SYNTH_NATIVE)
-        return fail(ME_EINVAL, "the fill fraction needs the native synthesis");
+        return fail(ME_EINVAL, "FP16 synthesis is an option of the FP32 search");
     return invert_impl<double, GENESIS_SYNTH_NATIVE, true>(
         obs, sigma, mu, npix, lines, grids, nlines, bounds, cfg, best_params, best_chi2, status,
         final_genes, final_fitness, stream, fill, best_alpha);

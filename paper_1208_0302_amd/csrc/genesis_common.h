@@ -106,6 +106,9 @@ inline int pack_lines(const me_line *lines, const me_grid *grids, int nlines, De
 #ifndef GENESIS_PAD_INVERT_F64
 #define GENESIS_PAD_INVERT_F64 0
 #endif
+#ifndef GENESIS_PAD_FILL_F16
+#define GENESIS_PAD_FILL_F16 0
+#endif
 #ifndef GENESIS_PAD_FILL_F32
 #define GENESIS_PAD_FILL_F32 0
 #endif
@@ -281,12 +284,9 @@ struct FillSink {
     }
 };
 
-// chi-square at the model's best fill fraction, and that fraction.
-template <typename Real>
-__device__ __forceinline__ Real chi2_fill_of(const Model<Real> &m, const DevLines<Real> &ls,
-                                             const FillPix<Real> &fp, Real alo, Real ahi,
-                                             const Vec4<Real> *obs_s, const Real (&w2)[4],
-                                             Real inv_nu, Real &alpha)
+template <typename Real, typename M>
+__device__ __forceinline__ FillSink<Real> fill_sink(const M &m, const Vec4<Real> *obs_s,
+                                                    const Real (&w2)[4])
 {
     FillSink<Real> s;
     s.obs = obs_s;
@@ -295,6 +295,29 @@ __device__ __forceinline__ Real chi2_fill_of(const Model<Real> &m, const DevLine
     for (int k = 0; k < 4; ++k)
         s.w2[k] = w2[k];
     s.see = s.sed = s.sdd = (Real)0;
+    return s;
+}
+
+// The chi-square's minimum over alpha in [alo, ahi] from the sums, and that alpha.
+template <typename Real>
+__device__ __forceinline__ Real fill_minimum(const FillSink<Real> &s, Real alo, Real ahi,
+                                             Real inv_nu, Real &alpha)
+{
+    const Real bmin = (Real)1 - ahi, bmax = (Real)1 - alo;
+    Real beta = s.sdd > (Real)0 ? -s.sed / s.sdd : bmin;
+    beta = fmin(fmax(beta, bmin), bmax);
+    alpha = (Real)1 - beta;
+    return fma(beta, fma(beta, s.sdd, (Real)2 * s.sed), s.see) * inv_nu;
+}
+
+// chi-square at the model's best fill fraction, and that fraction.
+template <typename Real>
+__device__ __forceinline__ Real chi2_fill_of(const Model<Real> &m, const DevLines<Real> &ls,
+                                             const FillPix<Real> &fp, Real alo, Real ahi,
+                                             const Vec4<Real> *obs_s, const Real (&w2)[4],
+                                             Real inv_nu, Real &alpha)
+{
+    FillSink<Real> s = fill_sink<Real>(m, obs_s, w2);
     for (int l = 0; l < ls.nlines; ++l) {
         const DevLine<Real> &ln = ls.l[l];
         s.ln = &ln;
@@ -302,11 +325,25 @@ __device__ __forceinline__ Real chi2_fill_of(const Model<Real> &m, const DevLine
         s.vshift = m.vlos * ln.dop_kms;
         synth_line_range(m, ln, s, 0, ln.nlam);
     }
-    const Real bmin = (Real)1 - ahi, bmax = (Real)1 - alo;
-    Real beta = s.sdd > (Real)0 ? -s.sed / s.sdd : bmin;
-    beta = fmin(fmax(beta, bmin), bmax);
-    alpha = (Real)1 - beta;
-    return fma(beta, fma(beta, s.sdd, (Real)2 * s.sed), s.see) * inv_nu;
+    return fill_minimum(s, alo, ahi, inv_nu, alpha);
+}
+
+// The same with the magnetic profiles synthesised in packed FP16 (the
+// field-free profile, the mixture and the sums in FP32).
+__device__ __forceinline__ float chi2_fill_of_h(const ModelH &m, const DevLines<float> &ls,
+                                                const DevLinesH &lh, const FillPix<float> &fp,
+                                                float alo, float ahi, const Vec4<float> *obs_s,
+                                                const float (&w2)[4], float inv_nu, float &alpha)
+{
+    FillSink<float> s = fill_sink<float>(m, obs_s, w2);
+    for (int l = 0; l < ls.nlines; ++l) {
+        const DevLine<float> &ln = ls.l[l];
+        s.ln = &ln;
+        s.fl = &fp.l[l];
+        s.vshift = m.vlos * ln.dop_kms;
+        synth_line_range_h(m, ln, lh.w[l], s);
+    }
+    return fill_minimum(s, alo, ahi, inv_nu, alpha);
 }
 
 // LDS of the GA kernels: observation [L] x 4, fitness [pop], argmin
@@ -566,6 +603,25 @@ __device__ __forceinline__ int best_of(const GaLds<Real> &s, int pop, const GenS
         decode(gb, *s.box, par);
     }
     return e;
+}
+
+// FP16-synthesis variant of evaluate_fill.
+__device__ __forceinline__ float evaluate_fill_h(const uint16_t *genes_s, int pop, int i,
+                                                 const Bounds &b, double mu,
+                                                 const DevLines<float> &ls, const DevLinesH &lh,
+                                                 const FillPix<float> &fp, float alo, float ahi,
+                                                 const Vec4<float> *obs_s, const float (&w2)[4],
+                                                 float inv_nu, float &alpha)
+{
+    uint32_t g[GENESIS_NPAR];
+#pragma unroll
+    for (int j = 0; j < GENESIS_NPAR; ++j)
+        g[j] = genes_s[j * pop + i];
+    double par[GENESIS_NPAR];
+    decode(g, b, par);
+    ModelH m;
+    model_setup(par, mu, m);
+    return chi2_fill_of_h(m, ls, lh, fp, alo, ahi, obs_s, w2, inv_nu, alpha);
 }
 
 // FP16 strength table of packed lines (after pack_lines).

@@ -441,22 +441,9 @@ __device__ __forceinline__ void profiles_at(const Model<Real> &m, const DevLine<
 #pragma unroll
     for (int i = 0; i < 6; ++i)
         pr[i] = 0;
-    // compile-time component counts for the two patterns of the Fe I pair, so
-    // that the components' independent evaluation chains interleave (the sums
-    // are formed in the same order either way)
-    if (ln.nb == 4 && ln.np == 4 && ln.nr == 4) {
-        group<4>(m, ln, 0, 4, x0, zb, pr[0], pr[1]);
-        group<4>(m, ln, 4, 4, x0, zb, pr[2], pr[3]);
-        group<4>(m, ln, 8, 4, x0, zb, pr[4], pr[5]);
-    } else if (ln.nb == 1 && ln.np == 1 && ln.nr == 1) {
-        group<1>(m, ln, 0, 1, x0, zb, pr[0], pr[1]);
-        group<1>(m, ln, 1, 1, x0, zb, pr[2], pr[3]);
-        group<1>(m, ln, 2, 1, x0, zb, pr[4], pr[5]);
-    } else {
-        group<-1>(m, ln, 0, ln.nb, x0, zb, pr[0], pr[1]);
-        group<-1>(m, ln, ln.nb, ln.np, x0, zb, pr[2], pr[3]);
-        group<-1>(m, ln, ln.nb + ln.np, ln.nr, x0, zb, pr[4], pr[5]);
-    }
+    group<-1>(m, ln, 0, ln.nb, x0, zb, pr[0], pr[1]);
+    group<-1>(m, ln, ln.nb, ln.np, x0, zb, pr[2], pr[3]);
+    group<-1>(m, ln, ln.nb + ln.np, ln.nr, x0, zb, pr[4], pr[5]);
 }
 
 template <typename Real>

@@ -274,19 +274,26 @@ __device__ __forceinline__ void synth_line_h(const ModelH &m, const DevLine<floa
     }
 }
 
+// One line, with compile-time component counts for the two patterns of the
+// Fe I pair.
+template <typename Sink>
+__device__ __forceinline__ void synth_line_range_h(const ModelH &m, const DevLine<float> &ln,
+                                                   const half_t *wh, Sink &sink)
+{
+    if (ln.nb == 1 && ln.np == 1 && ln.nr == 1)
+        synth_line_h<1, 1, 1>(m, ln, wh, sink);
+    else if (ln.nb == 4 && ln.np == 4 && ln.nr == 4)
+        synth_line_h<4, 4, 4>(m, ln, wh, sink);
+    else
+        synth_line_h<-1, -1, -1>(m, ln, wh, sink);
+}
+
 template <typename Sink>
 __device__ __forceinline__ void synthesize_h(const ModelH &m, const DevLines<float> &ls,
                                              const DevLinesH &lh, Sink &sink)
 {
-    for (int l = 0; l < ls.nlines; ++l) {
-        const DevLine<float> &ln = ls.l[l];
-        if (ln.nb == 1 && ln.np == 1 && ln.nr == 1)
-            synth_line_h<1, 1, 1>(m, ln, lh.w[l], sink);
-        else if (ln.nb == 4 && ln.np == 4 && ln.nr == 4)
-            synth_line_h<4, 4, 4>(m, ln, lh.w[l], sink);
-        else
-            synth_line_h<-1, -1, -1>(m, ln, lh.w[l], sink);
-    }
+    for (int l = 0; l < ls.nlines; ++l)
+        synth_line_range_h(m, ls.l[l], lh.w[l], sink);
 }
 
 __device__ __forceinline__ float chi2_of_h(const ModelH &m, const DevLines<float> &ls,

@@ -122,7 +122,15 @@ __global__ __launch_bounds__(1024) void k_ga_advance(const ReqDesc *__restrict__
         }
     }
     // the evaluation of the request's kind (uniform over the workgroup)
-    if (d.synth == GENESIS_SYNTH_FP16) {
+    if (d.synth == GENESIS_SYNTH_FP16 && d.fill) {
+        generation_loop(s, pop, tid, pix, d.ga, d.generations, d.gen_to, 0, gs,
+                        [&](const uint16_t *genes) -> float {
+                            float al;
+                            return evaluate_fill_h(genes, pop, tid, *s.box, mu, d.ls, d.lh, fp,
+                                                   (float)d.fc.alpha_lo, (float)d.fc.alpha_hi,
+                                                   s.obs, w2, inv_nu, al);
+                        });
+    } else if (d.synth == GENESIS_SYNTH_FP16) {
         generation_loop(s, pop, tid, pix, d.ga, d.generations, d.gen_to, 0, gs,
                         [&](const uint16_t *genes) -> float {
                             return evaluate_lds_h(genes, pop, tid, *s.box, mu, d.ls, d.lh, s.obs,
@@ -152,11 +160,18 @@ __global__ __launch_bounds__(1024) void k_ga_advance(const ReqDesc *__restrict__
             d.best_chi2[p] = s.fit[e];
             if (d.fill) {
                 // the best individual's alpha, as ga_invert finds it
-                Model<float> m;
-                model_setup(par, mu, m);
                 float al;
-                (void)chi2_fill_of(m, d.ls, fp, (float)d.fc.alpha_lo, (float)d.fc.alpha_hi, s.obs,
-                                   w2, inv_nu, al);
+                if (d.synth == GENESIS_SYNTH_FP16) {
+                    ModelH m;
+                    model_setup(par, mu, m);
+                    (void)chi2_fill_of_h(m, d.ls, d.lh, fp, (float)d.fc.alpha_lo,
+                                         (float)d.fc.alpha_hi, s.obs, w2, inv_nu, al);
+                } else {
+                    Model<float> m;
+                    model_setup(par, mu, m);
+                    (void)chi2_fill_of(m, d.ls, fp, (float)d.fc.alpha_lo, (float)d.fc.alpha_hi,
+                                       s.obs, w2, inv_nu, al);
+                }
                 d.best_alpha[p] = al;
             }
             if (d.status)
@@ -256,8 +271,6 @@ int submit_impl(void *session, const float *obs, const float *sigma, const float
     d.synth = cfg->synth_precision;
     d.fill = fill ? 1 : 0;
     if (d.synth == GENESIS_SYNTH_FP16) {
-        if (fill)
-            return fail(ME_EINVAL, "the fill fraction needs native synthesis (synth_precision 0)");
         if (!(bounds->lo[5] >= 0.0 && bounds->hi[5] <= kHalfMaxDamping))
             return fail(ME_EINVAL, "FP16 synthesis needs damping bounds within [0, %g]",
                         kHalfMaxDamping);

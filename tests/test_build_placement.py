@@ -48,6 +48,7 @@ def _fake(tmp_path, monkeypatch, after):
     monkeypatch.setattr(B, "_code_objects", lambda so, wd: [so])
     monkeypatch.setattr(B, "placement",
                         lambda cos, pat: (10, 90) if cos[0].endswith("first.so") else after)
+    monkeypatch.setattr(B, "code_sha256", lambda cos, pat: "code of " + cos[0][-9:] + pat)
     return str(first), compile_fn, state
 
 
@@ -56,7 +57,9 @@ def test_shift_is_recorded(tmp_path, monkeypatch):
     out, rec = B.place(first, {k: 0 for k in B.PLACEMENT}, False, str(tmp_path), compile_fn)
     assert state["built"] == 1 and out.endswith("second.so")
     assert rec["placement"] == "checked"
-    assert all(rec[k] == {"shift": 1, "good": 90, "bad": 10} for k in B.PLACEMENT)
+    assert all(rec[k] == {"shift": 1, "good": 90, "bad": 10,
+                          "code_sha256": "code of second.so" + B.PLACEMENT[k]}
+               for k in B.PLACEMENT)
     assert all(v == 1 for v in state["pads"].values())
 
 
@@ -64,6 +67,28 @@ def test_shift_that_does_not_help_raises(tmp_path, monkeypatch):
     first, compile_fn, _ = _fake(tmp_path, monkeypatch, (40, 60))
     with pytest.raises(RuntimeError, match="placement"):
         B.place(first, {k: 0 for k in B.PLACEMENT}, False, str(tmp_path), compile_fn)
+
+
+def test_code_hash_follows_the_machine_code(tmp_path, monkeypatch):
+    # the hash covers the matching symbols' instruction encodings only
+    dumps = {"a.co": ("  0 g F .text 0 k_ga_invertIfLi0ELb0E\n  0 g F .text 0 k_other\n",
+                      "  s_mov_b32 s0, 1 // 000000001000: BE800081\n"),
+             "b.co": ("  0 g F .text 0 k_ga_invertIfLi0ELb0E\n",
+                      "  s_mov_b32 s0, 2 // 000000001000: BE800082\n")}
+
+    class R:
+        def __init__(self, out):
+            self.stdout = out
+
+    def run(cmd, **kw):
+        co = cmd[-1]
+        return R(dumps[co][0] if cmd[1] == "-t" else dumps[co][1])
+    monkeypatch.setattr(B.subprocess, "run", run)
+    monkeypatch.setattr(B, "_llvm", lambda tool: tool)
+    ha = B.code_sha256(["a.co"], r"k_ga_invertIfLi0ELb0E")
+    hb = B.code_sha256(["b.co"], r"k_ga_invertIfLi0ELb0E")
+    assert ha != hb and len(ha) == 64
+    assert ha == B.code_sha256(["a.co"], r"k_ga_invertIfLi0ELb0E")
 
 
 def test_layout_of_missing_record(tmp_path, monkeypatch):

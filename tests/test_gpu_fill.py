@@ -136,6 +136,49 @@ def test_fill_loop_f32_fitness_is_the_fill_merit():
     assert np.median(da) <= 1e-5 and da.max() <= 1e-3, da
 
 
+def test_fill_loop_fp16_fitness_is_its_fill_merit():
+    # FP16 profile synthesis with the fill fraction: every final fitness is the
+    # fill merit (closed-form best alpha) of me_synth_f16's Stokes vector of
+    # the decoded genes, and within the FP16 synthesis bound (5e-3 Ic per
+    # sample) of the oracle's fill merit
+    lines, grids, olines, gf, of, truth, alpha, obs, sig = _problem("slit", 6, 35, 0.1, 1.0)
+    cfg = g.GAConfig(pop=64, generations=6, seed=7, synth_precision=g.SYNTH_FP16)
+    r = g.ga_invert(_t(obs, torch.float32), _t(sig, torch.float32), lines, grids,
+                    g.bounds(LO, HI), cfg, want_population=True, fill=gf)
+    genes = r["genes"].cpu().numpy()
+    par = oracle.decode(genes.reshape(-1, 9), LO, HI)
+    M = g.me_synth(torch.tensor(par, dtype=torch.float32, device=DEV), lines, grids,
+                   fp16=True).cpu().numpy().astype(np.float64).reshape(6, 64, 4, -1)
+    L = M.shape[-1]
+    N = np.stack([np.concatenate([oracle.fill_profile(ln, fl, 1.0, p[3])
+                                  for ln, fl in zip(olines, of.line)]) for p in par])
+    N = N.reshape(6, 64, L)
+    ic = (par[:, 7] + par[:, 8]).reshape(6, 64, 1)
+    o = obs.astype(np.float32).astype(np.float64)[:, None]
+    w2 = 1.0 / sig.astype(np.float32).astype(np.float64)[:, None, :, None] ** 2
+    bvec = np.zeros_like(M)
+    bvec[:, :, 0] = ic * N
+    D, e = M - bvec, o - M
+    see, sed, sdd = ((w2 * e * e).sum(axis=(2, 3)), (w2 * e * D).sum(axis=(2, 3)),
+                     (w2 * D * D).sum(axis=(2, 3)))
+    beta = np.clip(-sed / sdd, 1.0 - of.alpha_hi, 1.0 - of.alpha_lo)
+    merit = (see + beta * (2 * sed + beta * sdd)) / (4 * L - 10)
+    fit = r["fitness"].cpu().numpy().astype(np.float64)
+    assert np.allclose(fit, merit, rtol=1e-3, atol=0)
+    e_best = np.argmin(fit, axis=1)
+    da = np.abs(r["alpha"].cpu().numpy() - (1.0 - beta)[np.arange(6), e_best])
+    assert da.max() <= 1e-3, da
+    # against the FP64 oracle's fill merit of the same genes
+    ref, aref = oracle.chi2_fill(par.reshape(6, 64, 9), o[:, 0], np.sqrt(1.0 / w2[:, 0, :, 0]),
+                                 olines, of)
+    models = np.stack([oracle.me_synth_fill(par.reshape(6, 64, 9)[q], aref[q], olines, of)
+                       for q in range(6)])
+    delta = 5e-3 * ic[..., None]
+    rr = np.abs(o - models)
+    bound = (w2 * (2 * rr * delta + delta ** 2)).sum(axis=(2, 3)) / (4 * L - 10)
+    assert np.all(np.abs(fit - ref) <= bound + 1e-5 * ref)
+
+
 def test_fill_status_and_rejections():
     lines, grids, olines, gf, of, truth, alpha, obs, sig = _problem("slit", 4, 33, 0.0, 1.0)
     o32, s32 = _t(obs, torch.float32), _t(sig, torch.float32)
@@ -148,7 +191,7 @@ def test_fill_status_and_rejections():
     assert r["status"].cpu().tolist() == [0, 0, 4, 4]
     assert torch.isnan(r["alpha"][2:]).all() and torch.isfinite(r["alpha"][:2]).all()
     with pytest.raises(g.GenesisError):
-        g.ga_invert(o32, s32, lines, grids, b,
+        g.ga_invert(_t(obs, torch.float64), _t(sig, torch.float64), lines, grids, b,
                     g.GAConfig(pop=16, generations=2, synth_precision=g.SYNTH_FP16), fill=gf)
     with pytest.raises(g.GenesisError):
         g.ga_invert(o32, s32, lines, grids, b, g.GAConfig(pop=16, generations=2),

@@ -322,12 +322,15 @@ def test_fp16_and_fill_requests_equal_their_standalone_runs():
     sess.close()
 
 
-def test_service_rejects_fill_with_fp16():
+def test_fp16_fill_request_equals_its_standalone_run():
     b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
-    rf = _fill_request(8, 14)
+    rf = _fill_request(40, 14)
+    cfg = g.GAConfig(pop=64, generations=12, seed=13, synth_precision=g.SYNTH_FP16)
     sess = g.ServingSession(budget_bytes=1 << 30, gens_per_step=5)
-    with pytest.raises(g.GenesisError):
-        sess.submit(rf[2], rf[3], rf[0], rf[1], b,
-                    g.GAConfig(pop=32, generations=3, synth_precision=g.SYNTH_FP16), fill=rf[6])
-    assert sess.held() == 0
+    rid = sess.submit(rf[2], rf[3], rf[0], rf[1], b, cfg, fill=rf[6])
+    _drain(sess, [rid])
+    out = sess.result(rid)
+    alone = g.ga_invert(rf[2], rf[3], rf[0], rf[1], b, cfg, fill=rf[6])
+    assert _same(out, alone)
+    assert torch.equal(out["alpha"].nan_to_num(-1), alone["alpha"].nan_to_num(-1))
     sess.close()
