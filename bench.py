@@ -393,7 +393,12 @@ def _heldout(args, g, si, net, lines, grids, b, stream, dev):
         *((n, one[n]) for n in SEED_STRATEGIES),
         ("four_seeds", dict(n_seeded=32, seed_jitter=512, seed_params=seeds)),
         ("four_seeds_polarity", dict(n_seeded=32, seed_jitter=512, seed_params=seeds_pol,
-                                     pixel_bounds=box_pol))) if n in wanted)
+                                     pixel_bounds=box_pol)),
+        # as Sec. 5.5 places them: each first guess once, exactly, among an
+        # otherwise random population
+        ("four_seeds_exact", dict(n_seeded=4, seed_jitter=0, seed_params=seeds)),
+        ("four_seeds_exact_polarity", dict(n_seeded=4, seed_jitter=0, seed_params=seeds_pol,
+                                           pixel_bounds=box_pol))) if n in wanted)
     table = []
     o64, s64 = obs.double(), sig.double()
     for gens in (0, 10, 25, 50, 100, 150, 200):
@@ -921,7 +926,7 @@ def main():
     ap.add_argument("--heldout", type=int, default=16384, help="proposal: held-out pixels")
     ap.add_argument("--strategies", default="random,seeded,physics,polarity_box,prefit_box,"
                     "physics_in_box,sobol,sobol_restart," + ",".join(SEED_STRATEGIES) +
-                    ",four_seeds,four_seeds_polarity",
+                    ",four_seeds,four_seeds_polarity,four_seeds_exact,four_seeds_exact_polarity",
                     help="proposal: initial-population strategies to compare")
     ap.add_argument("--chi2-target", type=float, default=1.2,
                     help="proposal: reduced chi-square target")
