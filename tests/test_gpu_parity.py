@@ -396,6 +396,32 @@ def test_f64_loop_tracks_the_oracle():
         assert abs(r["chi2"][p].item() - ref["chi2"][p]) <= tol[p]
 
 
+def test_tiny_workload_at_full_size_tracks_the_oracle():
+    """The single-line FP64 workload at its full size (64 pixels, population
+    64, 100 generations, seed 0) against the oracle's loop: every operator is
+    bit-exact, so final populations agree wherever no tournament met a
+    fitness near-tie on the way; allow a few such pixels and require the
+    median chi-square over all pixels to agree."""
+    lines, grids, olines, truth, obs, sig = _problem("tiny", 64, 0, dtype=np.float64)
+    b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
+    cfg = g.GAConfig(pop=64, generations=100, tournament_k=4, seed=0)
+    r = g.ga_invert(torch.tensor(obs, device=DEV), torch.tensor(sig, device=DEV), lines, grids,
+                    b, cfg, want_population=True)
+    ref = oracle.ga_invert(obs, sig, olines, si.PRIOR_LO, si.PRIOR_HI, pop=64, generations=100,
+                           k=4, p_cross=float(np.float32(0.85)), p_mut=float(np.float32(0.05)),
+                           seed=0, want_population=True)
+    same = np.array([np.array_equal(r["genes"][p].cpu().numpy(), ref["genes"][p])
+                     for p in range(64)])
+    c, cr = r["chi2"].cpu().numpy(), ref["chi2"]
+    print("identical final populations: %d / 64" % same.sum())
+    assert same.sum() >= 56
+    bp = r["params"].cpu().numpy()
+    models = oracle.me_synth(bp, olines)[:, None]
+    tol = _chi2_tol(obs, models, sig, _ic(truth), 4 * obs.shape[-1] - 9, FWD_TOL_F64)[:, 0]
+    assert np.all(np.abs(c[same] - cr[same]) <= tol[same])
+    assert abs(np.median(c) / np.median(cr) - 1) < 0.02
+
+
 @pytest.mark.parametrize("kind", ["tiny", "slit"])
 def test_loop_reduces_chi2_and_beats_truth_on_noisy_data(kind):
     lines, grids, olines, truth, obs, sig = _problem(kind, 16, 21)
