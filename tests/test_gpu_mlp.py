@@ -111,8 +111,9 @@ def test_gradient_fp32_matches_oracle(batch):
     assert np.all(_layer_errors(grad.cpu().numpy().astype(np.float64), gref) <= 1e-4)
 
 
-# 1000: the weight gradients split the batch into four k ranges, the last ragged
-@pytest.mark.parametrize("batch", [9, 256, 1000])
+# 1000: the weight gradients split the batch into eight k ranges, the last
+# ragged; 4096: the training batch (a full round of 128-row tiles)
+@pytest.mark.parametrize("batch", [9, 256, 1000, 4096])
 def test_gradient_bf16_matches_oracle(batch):
     net, p = _net(6)
     x = _x(batch, 3 * batch)
