@@ -551,8 +551,9 @@ def _proposal_report(args, g, si, batch, lr, wall, train_ms, losses, pass_flop, 
            "roofline": {"bound": "mfma", "achieved": pass_flop / pass_s / 1e12,
                         "peak": PEAK_BF16_MFMA / 1e12, "unit": "TFLOP/s",
                         "frac": pass_flop / pass_s / PEAK_BF16_MFMA, "traffic": None,
-                        "kernel": "mlp_grad pass (k_gemm_bf16 forward/backward products "
-                                  "with fused epilogues)",
+                        "kernel": "mlp_grad pass (ten launches: k_prep, k_mm forward, "
+                                  "output, backward and weight-gradient products, "
+                                  "k_grad_reduce)",
                         "flop_per_example": MLP_TRAIN_FLOP, "examples_per_launch": batch}}
     print(json.dumps(out), flush=True)
 
