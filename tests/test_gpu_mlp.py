@@ -113,7 +113,7 @@ def test_gradient_fp32_matches_oracle(batch):
 
 # 1000: the weight gradients split the batch into eight k ranges, the last
 # ragged; 4096: the training batch (a full round of 128-row tiles)
-@pytest.mark.parametrize("batch", [9, 256, 1000, 4096])
+@pytest.mark.parametrize("batch", [1, 9, 256, 1000, 4096])
 def test_gradient_bf16_matches_oracle(batch):
     net, p = _net(6)
     x = _x(batch, 3 * batch)
