@@ -22,11 +22,14 @@
  *   7 S0     source function at tau = 0
  *   8 S1     source function gradient (S1 = S0 * beta0 of Sec. 5)
  *
- * Parity of the genetic operators: the end-to-end inversion is a stochastic
- * heuristic and its result is "parity unpinned" (it is checked through
- * recovered-parameter accuracy, chi-square against the truth's chi-square and
- * determinism); the integer steps (Philox, tournament, crossover, mutation)
- * are pinned and compared bit-exactly.
+ * Parity of the genetic operators: the integer steps (Philox, tournament,
+ * crossover, mutation) are pinned and compared bit-exactly.  The end-to-end
+ * inversion is a stochastic heuristic whose general trajectory has no closed
+ * form; it is pinned by the special cases that have one (without crossover
+ * and mutation the loop only reselects generation 0, keeping its best; a
+ * tournament over the whole population breeds copies of generation 0's
+ * best), by determinism and resumption, and by recovered-parameter accuracy
+ * on synthetic truth.
  */
 #ifndef GENESIS_ORACLE_H
 #define GENESIS_ORACLE_H
