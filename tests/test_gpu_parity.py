@@ -396,6 +396,30 @@ def test_f64_loop_tracks_the_oracle():
         assert abs(r["chi2"][p].item() - ref["chi2"][p]) <= tol[p]
 
 
+@pytest.mark.parametrize("pc,k,pop", [(0.0, 3, 16), (0.0, 8, 8), (1.0, 8, 8)])
+def test_f64_loop_special_cases_match_the_oracle(pc, k, pop):
+    """The FP64 fused loop in the oracle's exactly pinned regimes (no
+    mutation; no crossover, or a tournament over the whole population):
+    final populations equal the oracle's, and they hold only generation-0
+    genotypes, or only copies of generation 0's best."""
+    lines, grids, olines, truth, obs, sig = _problem("tiny", 4, 4, dtype=np.float64)
+    b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
+    cfg = g.GAConfig(pop=pop, generations=6, tournament_k=k, p_cross=pc, p_mut=0.0, seed=5)
+    r = g.ga_invert(torch.tensor(obs, device=DEV), torch.tensor(sig, device=DEV), lines, grids,
+                    b, cfg, want_population=True)
+    kw = dict(pop=pop, k=k, p_cross=pc, p_mut=0.0, seed=5, want_population=True)
+    ref = oracle.ga_invert(obs, sig, olines, si.PRIOR_LO, si.PRIOR_HI, generations=6, **kw)
+    ref0 = oracle.ga_invert(obs, sig, olines, si.PRIOR_LO, si.PRIOR_HI, generations=0, **kw)
+    for p in range(4):
+        genes = r["genes"][p].cpu().numpy()
+        assert np.array_equal(genes, ref["genes"][p])
+        first = {tuple(x) for x in ref0["genes"][p].tolist()}
+        assert all(tuple(x) in first for x in genes.tolist())
+        if k == pop:
+            best = ref0["genes"][p][np.argmin(ref0["fitness"][p])]
+            assert np.array_equal(genes, np.broadcast_to(best, genes.shape))
+
+
 def test_tiny_workload_at_full_size_tracks_the_oracle():
     """The single-line FP64 workload at its full size (64 pixels, population
     64, 100 generations, seed 0) against the oracle's loop: every operator is
