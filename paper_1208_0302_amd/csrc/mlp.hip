@@ -90,6 +90,105 @@ __device__ __forceinline__ void epilogue(const GemmArgs &a, int m, int n, float 
     }
 }
 
+// FP32 reference-precision product on the VALU (gradient checks).
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs a)
+{
+    constexpr int BM = 64, BN = 64, BK = 16;
+    __shared__ float As[BK][BM + 1];
+    __shared__ float Bs[BK][BN + 1];
+    const float *A = a.A, *B = a.B;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int tid = threadIdx.x;
+    const int tm = (tid / 16) * 4, tn = (tid % 16) * 4;
+    float acc[4][4] = {};
+    for (int k0 = 0; k0 < a.K; k0 += BK) {
+        for (int e = tid; e < BM * BK; e += 256) {
+            const int c = e / BM, r = e % BM;
+            const int gm = m0 + r, gk = k0 + c;
+            As[c][r] = (gm < a.M && gk < a.K)
+                           ? (TA ? A[(int64_t)gk * a.lda + gm] : A[(int64_t)gm * a.lda + gk])
+                           : 0.0f;
+        }
+        for (int e = tid; e < BN * BK; e += 256) {
+            const int c = e / BN, r = e % BN;
+            const int gn = n0 + r, gk = k0 + c;
+            Bs[c][r] = (gn < a.N && gk < a.K)
+                           ? (TB ? B[(int64_t)gn * a.ldb + gk] : B[(int64_t)gk * a.ldb + gn])
+                           : 0.0f;
+        }
+        __syncthreads();
+        for (int k = 0; k < BK; ++k)
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = fmaf(As[k][tm + i], Bs[k][tn + j], acc[i][j]);
+        __syncthreads();
+    }
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j)
+            epilogue<EPI>(a, m0 + tm + i, n0 + tn + j, acc[i][j]);
+}
+
+// column sums: out[n] = sum_m in[m][n].  Block (64 columns) x (16 row
+// phases); thread (c, r) sums rows r, r + 16, ... in order, then the 16
+// partials are added in order: a fixed summation order for every launch.
+__global__ __launch_bounds__(1024) void k_colsum(const float *in, int M, int N, float *out)
+{
+    __shared__ float part[16][64];
+    const int c = threadIdx.x & 63, r = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + c;
+    float s = 0.0f;
+    if (n < N)
+        for (int m = r; m < M; m += 16)
+            s += in[(int64_t)m * N + n];
+    part[r][c] = s;
+    __syncthreads();
+    if (r == 0 && n < N) {
+        float t = 0.0f;
+        for (int i = 0; i < 16; ++i)
+            t += part[i][c];
+        out[n] = t;
+    }
+}
+
+// Loss: mean over the batch of sum_j d_j^2 with d = out - target, the azimuth
+// (j = 2) taken modulo 1 (its 180-degree period).  Writes dL/dout and the
+// per-sample loss.
+__global__ void k_loss(const float *out, const float *target, int B, float *dout,
+                       float *per_sample)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B)
+        return;
+    float s = 0.0f;
+    for (int j = 0; j < kOut; ++j) {
+        float d = out[b * kOut + j] - target[b * kOut + j];
+        if (j == 2)
+            d = d - rintf(d);
+        s = fmaf(d, d, s);
+        dout[b * kOut + j] = 2.0f * d / (float)B;
+    }
+    per_sample[b] = s;
+}
+
+// out = scale * sum in[0..n): 256 strided partial sums, then a fixed tree.
+__global__ __launch_bounds__(256) void k_sum(const float *in, int n, float scale, float *out)
+{
+    __shared__ float red[256];
+    float s = 0.0f;
+    for (int i = threadIdx.x; i < n; i += 256)
+        s += in[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        *out = red[0] * scale;
+}
+
 // ---- BF16 products on the matrix cores ------------------------------------
 //
 // Every product is C[M][N] = A[M][K] B[K][N], staged in LDS as [rows][k]
@@ -565,105 +664,6 @@ __global__ __launch_bounds__(256) void k_grad_reduce(ReduceArgs a)
         g[2] = s.z;
         g[3] = s.w;
     }
-}
-
-// FP32 reference-precision product on the VALU (gradient checks).
-template <bool TA, bool TB, int EPI>
-__global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs a)
-{
-    constexpr int BM = 64, BN = 64, BK = 16;
-    __shared__ float As[BK][BM + 1];
-    __shared__ float Bs[BK][BN + 1];
-    const float *A = a.A, *B = a.B;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-    const int tid = threadIdx.x;
-    const int tm = (tid / 16) * 4, tn = (tid % 16) * 4;
-    float acc[4][4] = {};
-    for (int k0 = 0; k0 < a.K; k0 += BK) {
-        for (int e = tid; e < BM * BK; e += 256) {
-            const int c = e / BM, r = e % BM;
-            const int gm = m0 + r, gk = k0 + c;
-            As[c][r] = (gm < a.M && gk < a.K)
-                           ? (TA ? A[(int64_t)gk * a.lda + gm] : A[(int64_t)gm * a.lda + gk])
-                           : 0.0f;
-        }
-        for (int e = tid; e < BN * BK; e += 256) {
-            const int c = e / BN, r = e % BN;
-            const int gn = n0 + r, gk = k0 + c;
-            Bs[c][r] = (gn < a.N && gk < a.K)
-                           ? (TB ? B[(int64_t)gn * a.ldb + gk] : B[(int64_t)gk * a.ldb + gn])
-                           : 0.0f;
-        }
-        __syncthreads();
-        for (int k = 0; k < BK; ++k)
-            for (int i = 0; i < 4; ++i)
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = fmaf(As[k][tm + i], Bs[k][tn + j], acc[i][j]);
-        __syncthreads();
-    }
-    for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j)
-            epilogue<EPI>(a, m0 + tm + i, n0 + tn + j, acc[i][j]);
-}
-
-// column sums: out[n] = sum_m in[m][n].  Block (64 columns) x (16 row
-// phases); thread (c, r) sums rows r, r + 16, ... in order, then the 16
-// partials are added in order: a fixed summation order for every launch.
-__global__ __launch_bounds__(1024) void k_colsum(const float *in, int M, int N, float *out)
-{
-    __shared__ float part[16][64];
-    const int c = threadIdx.x & 63, r = threadIdx.x >> 6;
-    const int n = blockIdx.x * 64 + c;
-    float s = 0.0f;
-    if (n < N)
-        for (int m = r; m < M; m += 16)
-            s += in[(int64_t)m * N + n];
-    part[r][c] = s;
-    __syncthreads();
-    if (r == 0 && n < N) {
-        float t = 0.0f;
-        for (int i = 0; i < 16; ++i)
-            t += part[i][c];
-        out[n] = t;
-    }
-}
-
-// Loss: mean over the batch of sum_j d_j^2 with d = out - target, the azimuth
-// (j = 2) taken modulo 1 (its 180-degree period).  Writes dL/dout and the
-// per-sample loss.
-__global__ void k_loss(const float *out, const float *target, int B, float *dout,
-                       float *per_sample)
-{
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B)
-        return;
-    float s = 0.0f;
-    for (int j = 0; j < kOut; ++j) {
-        float d = out[b * kOut + j] - target[b * kOut + j];
-        if (j == 2)
-            d = d - rintf(d);
-        s = fmaf(d, d, s);
-        dout[b * kOut + j] = 2.0f * d / (float)B;
-    }
-    per_sample[b] = s;
-}
-
-// out = scale * sum in[0..n): 256 strided partial sums, then a fixed tree.
-__global__ __launch_bounds__(256) void k_sum(const float *in, int n, float scale, float *out)
-{
-    __shared__ float red[256];
-    float s = 0.0f;
-    for (int i = threadIdx.x; i < n; i += 256)
-        s += in[i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h)
-            red[threadIdx.x] += red[threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        *out = red[0] * scale;
 }
 
 __global__ void k_adam(float *p, float *m, float *v, const float *g, int64_t n, float lr,
