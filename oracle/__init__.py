@@ -106,6 +106,7 @@ def lib():
             L.oracle_zeeman.argtypes = [C.c_double] * 4 + [_i32p, _dp, _dp, C.c_int]
             L.oracle_zeeman.restype = C.c_int
             L.oracle_me_synth.argtypes = [_dp, C.c_int64, _linep, C.c_int, _dp, _dp]
+            L.oracle_me_synth_lin.argtypes = [_dp, _dp, C.c_double, _linep, C.c_int, _dp]
             L.oracle_chi2.argtypes = [_dp, C.c_int64, C.c_int, _linep, C.c_int, _dp, _dp, _dp, _dp]
             L.oracle_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
             L.oracle_rng_word.argtypes = [C.c_uint64] + [C.c_uint32] * 5
@@ -242,6 +243,18 @@ def me_synth(params, lines, mu=None):
     m = None if mu is None else _f64(np.broadcast_to(mu, (n,)))
     lib().oracle_me_synth(_ptr(p, _dp), n, lp, len(lines),
                           None if m is None else _ptr(m, _dp), _ptr(out, _dp))
+    return out
+
+
+def me_synth_lin(params0, params, lines, mu=1.0):
+    """Stokes [4, L] of params [9] with every component's Faddeeva value taken
+    to first order about its value at params0 [9] (oracle_me_synth_lin)."""
+    p0 = np.ascontiguousarray(_f64(params0).reshape(NPAR))
+    p = np.ascontiguousarray(_f64(params).reshape(NPAR))
+    out = np.empty((4, total_samples(lines)), np.float64)
+    arr, lp = _lines_array(lines)
+    lib().oracle_me_synth_lin(_ptr(p0, _dp), _ptr(p, _dp), float(mu), lp, len(lines),
+                              _ptr(out, _dp))
     return out
 
 

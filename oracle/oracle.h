@@ -71,6 +71,16 @@ int oracle_zeeman(double Jl, double gl, double Ju, double gu,
 void oracle_me_synth(const double *par, int64_t n, const oracle_line *lines, int nlines,
                      const double *mu, double *out);
 
+/* One model par with every component's Faddeeva value taken to first order
+ * about its value at par0: w(z) ~ w(z0) + w'(z0)(z - z0), w' = -2 z w +
+ * 2 i / sqrt(pi), z = v + i a of the component at par, z0 at par0; the rest
+ * of the model (the propagation matrix and the Unno-Rachkovsky solution) is
+ * evaluated at par.  par0 = par gives oracle_me_synth bit for bit.  This is
+ * the model the refinement's Jacobian columns for B, v_los, the Doppler
+ * width and the damping difference (oracle_lm.c).  out [4][L]. */
+void oracle_me_synth_lin(const double *par0, const double *par, double mu,
+                         const oracle_line *lines, int nlines, double *out);
+
 /* Merit function (Sec. 5, chi-square equation) with w_i = 1/sigma_i:
  * chi2 = 1/nu sum_i sum_j (O - M)^2 / sigma_i^2, nu = 4L - 9.
  * par [npix][pop][9], obs [npix][4][L], sigma [npix][4], chi2 [npix][pop]. */

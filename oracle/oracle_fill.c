@@ -67,6 +67,25 @@ static int fill_profiles(const oracle_line *lines, int nlines, const oracle_fill
     return 0;
 }
 
+/* o [4][L] holds M(p); replace it by alpha M(p) + (1 - alpha) I_c N e (NaN
+ * and -1 where N is invalid).  N [L] is scratch. */
+int oracle__fill_mix(const double *p, double alpha, double mu, const oracle_line *lines,
+                     int nlines, const oracle_fill *fill, double *N, double *o)
+{
+    const int L = oracle__total_samples(lines, nlines);
+    if (fill_profiles(lines, nlines, fill, mu, p[3], N) != 0) {
+        for (int k = 0; k < 4 * L; ++k)
+            o[k] = NAN;
+        return -1;
+    }
+    const double ic = p[7] + mu * p[8];
+    for (int j = 0; j < L; ++j)
+        o[j] = alpha * o[j] + (1.0 - alpha) * ic * N[j];
+    for (int k = L; k < 4 * L; ++k)
+        o[k] *= alpha;
+    return 0;
+}
+
 int oracle_me_synth_fill(const double *par, const double *alpha, int64_t n,
                          const oracle_line *lines, int nlines, const double *mu,
                          const oracle_fill *fill, double *out)
@@ -75,21 +94,11 @@ int oracle_me_synth_fill(const double *par, const double *alpha, int64_t n,
     double *N = (double *)malloc(sizeof(double) * L);
     int rc = 0;
     for (int64_t i = 0; i < n; ++i) {
-        const double m = mu ? mu[i] : 1.0;
         const double *p = par + i * ORACLE_NPAR;
         double *o = out + i * 4 * L;
         oracle_me_synth(p, 1, lines, nlines, mu ? mu + i : NULL, o);
-        if (fill_profiles(lines, nlines, fill, m, p[3], N) != 0) {
+        if (oracle__fill_mix(p, alpha[i], mu ? mu[i] : 1.0, lines, nlines, fill, N, o) != 0)
             rc = -1;
-            for (int k = 0; k < 4 * L; ++k)
-                o[k] = NAN;
-            continue;
-        }
-        const double ic = p[7] + m * p[8], al = alpha[i];
-        for (int j = 0; j < L; ++j)
-            o[j] = al * o[j] + (1.0 - al) * ic * N[j];
-        for (int k = L; k < 4 * L; ++k)
-            o[k] *= al;
     }
     free(N);
     return rc;

@@ -10,7 +10,12 @@
  * kept inside [0, 1]:
  *   residuals r_i = (O_i - M_i(x)) / sigma_i over the 4L samples;
  *   Jacobian of the model by forward differences, step h = 1e-7 (taken
- *   backwards when x_j + h > 1): J_ij = (M_i(x + h e_j) - M_i(x)) / (h sigma_i);
+ *   backwards when x_j + h > 1): J_ij = (M_i(x + h e_j) - M_i(x)) / (h sigma_i),
+ *   where for B, v_los, the Doppler width and the damping, which move every
+ *   component's Faddeeva argument z = v + i a, M(x + h e_j) takes each
+ *   component's w to first order about its value at x (oracle_me_synth_lin):
+ *   one Faddeeva evaluation per component and sample serves all five models,
+ *   and the difference from the exact model is of order |dz|^2, about h^2;
  *   A = J^T J, g = J^T r;
  *   trial: solve (A + lambda diag(A)) d = g by Cholesky (a parameter with
  *   A_jj = 0 gets d_j = 0), x' = clamp(x + d, 0, 1); accept if
@@ -85,6 +90,30 @@ static void model_at(const lm_problem *P, const double *x, double *out)
     }
 }
 
+int oracle__fill_mix(const double *p, double alpha, double mu, const oracle_line *lines,
+                     int nlines, const oracle_fill *fill, double *N, double *o);
+
+/* model [4L] at normalised xs with every component's Faddeeva value taken to
+ * first order about its value at x (the fill profile and fraction exact) */
+static void model_lin(const lm_problem *P, const double *x, const double *xs, double *out)
+{
+    double p0[NP], p[NP];
+    to_params(x, P->lo, P->hi, p0);
+    to_params(xs, P->lo, P->hi, p);
+    oracle_me_synth_lin(p0, p, P->mu, P->lines, P->nlines, out);
+    if (P->fill) {
+        double *N = (double *)malloc(sizeof(double) * P->L);
+        oracle__fill_mix(p, to_alpha(P, xs), P->mu, P->lines, P->nlines, P->fill, N, out);
+        free(N);
+    }
+}
+
+/* coordinates that move the Faddeeva arguments: B, v_los, Doppler width, damping */
+static int moves_profiles(int j)
+{
+    return j == 0 || j == 3 || j == 4 || j == 5;
+}
+
 static double chi2_at(const lm_problem *P, const double *x, double *scratch)
 {
     double p[NP];
@@ -122,7 +151,10 @@ static void normal_equations(const lm_problem *P, const double *x, uint32_t free
         memcpy(xs, x, sizeof(double) * n);
         const double hj = (x[j] + h <= 1.0) ? h : -h;
         xs[j] += hj;
-        model_at(P, xs, m1);
+        if (moves_profiles(j))
+            model_lin(P, x, xs, m1);
+        else
+            model_at(P, xs, m1);
         for (int i = 0; i < R; ++i)
             J[i * n + j] = (m1[i] - m0[i]) / (hj * s[i / L]);
     }

@@ -204,62 +204,104 @@ static int total_samples(const oracle_line *lines, int nlines)
     return L;
 }
 
-/* One profile: out [4][L]. */
-static void synth_one(const double *par, double mu, const oracle_line *lines, int nlines, int L,
-                      double *out)
+/* Stokes vector at one sample from the group profiles phi (absorption) and
+ * psi (dispersion) of the blue, pi and red components (Sec. 5): the
+ * propagation matrix and the Unno-Rachkovsky solution for the model par. */
+static void stokes_from_profiles(const double *par, double mu, const double phi[3],
+                                 const double psi[3], double st[4])
 {
-    const double B = par[0];
     const double gam = par[1] * M_PI / 180.0;
     const double chi = par[2] * M_PI / 180.0;
-    const double vlos = par[3];
-    const double dopp = par[4];
-    const double a = par[5];
     const double eta0 = par[6];
     const double S0 = par[7];
     const double S1 = par[8];
-
     const double sg = sin(gam), cg = cos(gam);
     const double c2x = cos(2.0 * chi), s2x = sin(2.0 * chi);
+    const double pb = phi[0], pp = phi[1], pr = phi[2];
+    const double qb = psi[0], qp = psi[1], qr = psi[2];
+    const double etaI = 0.5 * eta0 * (pp * sg * sg + 0.5 * (pb + pr) * (1.0 + cg * cg));
+    const double etaQ = 0.5 * eta0 * (pp - 0.5 * (pb + pr)) * sg * sg * c2x;
+    const double etaU = 0.5 * eta0 * (pp - 0.5 * (pb + pr)) * sg * sg * s2x;
+    const double etaV = 0.5 * eta0 * (pr - pb) * cg;
+    const double rhoQ = 0.5 * eta0 * (qp - 0.5 * (qb + qr)) * sg * sg * c2x;
+    const double rhoU = 0.5 * eta0 * (qp - 0.5 * (qb + qr)) * sg * sg * s2x;
+    const double rhoV = 0.5 * eta0 * (qr - qb) * cg;
+    double K[4][4] = {
+        {1.0 + etaI, etaQ, etaU, etaV},
+        {etaQ, 1.0 + etaI, rhoV, -rhoU},
+        {etaU, -rhoV, 1.0 + etaI, rhoQ},
+        {etaV, rhoU, -rhoQ, 1.0 + etaI},
+    };
+    double e[4] = {1.0, 0.0, 0.0, 0.0}, x[4];
+    solve4(K, e, x);
+    st[0] = S0 + mu * S1 * x[0];
+    st[1] = mu * S1 * x[1];
+    st[2] = mu * S1 * x[2];
+    st[3] = mu * S1 * x[3];
+}
 
+/* Reduced wavelength of component c of a line at sample lam for the model
+ * par (Sec. 5: line centre shifted by v_los, Zeeman shift in units of the
+ * Doppler width). */
+static double component_v(const double *par, const oracle_line *ln, int c, double lam)
+{
+    const double lc = ln->lambda0 * (1.0 + par[3] / ORACLE_C_KMS);
+    const double dlb = ORACLE_ZEEMAN_K * ln->lambda0 * ln->lambda0 * par[0];
+    return (lam - lc - ln->shift[c] * dlb) / par[4];
+}
+
+/* One profile: out [4][L].  With par0 != NULL, each component's Faddeeva
+ * value is taken to first order about its value at par0:
+ *   w(z) ~ w(z0) + w'(z0) (z - z0),  w'(z) = -2 z w(z) + 2 i / sqrt(pi),
+ * z = v + i a of the component at par, z0 at par0 (the derivative of the
+ * Faddeeva function follows from its differential equation). */
+static void synth_one_from(const double *par0, const double *par, double mu,
+                           const oracle_line *lines, int nlines, int L, double *out)
+{
+    const double a = par[5];
     int off = 0;
     for (int l = 0; l < nlines; ++l) {
         const oracle_line *ln = &lines[l];
-        const double lc = ln->lambda0 * (1.0 + vlos / ORACLE_C_KMS);
-        const double dlb = ORACLE_ZEEMAN_K * ln->lambda0 * ln->lambda0 * B;
         for (int j = 0; j < ln->nlam; ++j) {
             const double lam = ln->start + (double)j * ln->step;
             double phi[3] = {0.0, 0.0, 0.0}, psi[3] = {0.0, 0.0, 0.0};
             for (int c = 0; c < ln->ncomp; ++c) {
-                const double v = (lam - lc - ln->shift[c] * dlb) / dopp;
+                const double v = component_v(par, ln, c, lam);
                 double H, Lf;
-                oracle_faddeeva(v, a, &H, &Lf);
+                if (!par0) {
+                    oracle_faddeeva(v, a, &H, &Lf);
+                } else {
+                    const double v0 = component_v(par0, ln, c, lam), a0 = par0[5];
+                    double H0, L0;
+                    oracle_faddeeva(v0, a0, &H0, &L0);
+                    const double complex z0 = v0 + I * a0, w0 = H0 + I * L0;
+                    const double complex dw = -2.0 * z0 * w0 + 2.0 * I / sqrt(M_PI);
+                    const double complex w = w0 + dw * ((v - v0) + I * (a - a0));
+                    H = creal(w);
+                    Lf = cimag(w);
+                }
                 phi[ln->q[c] + 1] += ln->strength[c] * H;
                 psi[ln->q[c] + 1] += ln->strength[c] * Lf;
             }
-            const double pb = phi[0], pp = phi[1], pr = phi[2];
-            const double qb = psi[0], qp = psi[1], qr = psi[2];
-            const double etaI = 0.5 * eta0 * (pp * sg * sg + 0.5 * (pb + pr) * (1.0 + cg * cg));
-            const double etaQ = 0.5 * eta0 * (pp - 0.5 * (pb + pr)) * sg * sg * c2x;
-            const double etaU = 0.5 * eta0 * (pp - 0.5 * (pb + pr)) * sg * sg * s2x;
-            const double etaV = 0.5 * eta0 * (pr - pb) * cg;
-            const double rhoQ = 0.5 * eta0 * (qp - 0.5 * (qb + qr)) * sg * sg * c2x;
-            const double rhoU = 0.5 * eta0 * (qp - 0.5 * (qb + qr)) * sg * sg * s2x;
-            const double rhoV = 0.5 * eta0 * (qr - qb) * cg;
-            double K[4][4] = {
-                {1.0 + etaI, etaQ, etaU, etaV},
-                {etaQ, 1.0 + etaI, rhoV, -rhoU},
-                {etaU, -rhoV, 1.0 + etaI, rhoQ},
-                {etaV, rhoU, -rhoQ, 1.0 + etaI},
-            };
-            double e[4] = {1.0, 0.0, 0.0, 0.0}, x[4];
-            solve4(K, e, x);
-            out[0 * L + off + j] = S0 + mu * S1 * x[0];
-            out[1 * L + off + j] = mu * S1 * x[1];
-            out[2 * L + off + j] = mu * S1 * x[2];
-            out[3 * L + off + j] = mu * S1 * x[3];
+            double st[4];
+            stokes_from_profiles(par, mu, phi, psi, st);
+            for (int s4 = 0; s4 < 4; ++s4)
+                out[s4 * L + off + j] = st[s4];
         }
         off += ln->nlam;
     }
+}
+
+static void synth_one(const double *par, double mu, const oracle_line *lines, int nlines, int L,
+                      double *out)
+{
+    synth_one_from(NULL, par, mu, lines, nlines, L, out);
+}
+
+void oracle_me_synth_lin(const double *par0, const double *par, double mu,
+                         const oracle_line *lines, int nlines, double *out)
+{
+    synth_one_from(par0, par, mu, lines, nlines, total_samples(lines, nlines), out);
 }
 
 void oracle_me_synth(const double *par, int64_t n, const oracle_line *lines, int nlines,

@@ -1288,6 +1288,52 @@ __device__ bool cholesky_n(double (&M)[N][N], const double (&g)[N], double (&d)[
     return true;
 }
 
+// Group profiles (h, l of blue, pi, red) at sample jj of the base model jm[0]
+// (pr[0], accumulated as profiles_at does) and of the four models that move
+// the Faddeeva arguments z = v + i a: jm[1] (B), jm[4] (v_los), jm[5]
+// (Doppler width), jm[6] (damping) (pr[1..4]), each component's w taken to
+// first order about its base value,
+//   w(z) ~ w(z0) + w'(z0) (z - z0),  w'(z) = -2 z w(z) + 2 i / sqrt(pi),
+// so one Faddeeva evaluation per component serves all five models.
+__device__ __forceinline__ void profiles_lin(const Model<double> *jm, const DevLine<double> &ln,
+                                             int jj, double (&pr)[5][6])
+{
+    const int mi[5] = {0, 1, 4, 5, 6};
+    double x0[5], zb[5], da[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const Model<double> &m = jm[mi[q]];
+        const double xb = (ln.off0 - m.vlos * ln.dop_kms) * m.inv_dop;
+        x0[q] = fma((double)jj, ln.step * m.inv_dop, xb);
+        zb[q] = ln.zee_G * m.B * m.inv_dop;
+        da[q] = m.a - jm[0].a;
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+            pr[q][i] = 0.0;
+    }
+    const double a0 = jm[0].a;
+    const int lim[4] = {0, ln.nb, ln.nb + ln.np, ln.nb + ln.np + ln.nr};
+#pragma unroll
+    for (int g = 0; g < 3; ++g) {
+        for (int c = lim[g]; c < lim[g + 1]; ++c) {
+            const double s = ln.s[c], w = ln.w[c];
+            const double v0 = fma(-s, zb[0], x0[0]);
+            double H, L;
+            voigt_f64(a0, v0, H, L);
+            const double dr = -2.0 * fma(v0, H, -(a0 * L));
+            const double di = fma(-2.0, fma(v0, L, a0 * H), 1.1283791670955125739);  // 2/sqrt(pi)
+            pr[0][2 * g] = fma(w, H, pr[0][2 * g]);
+            pr[0][2 * g + 1] = fma(w, L, pr[0][2 * g + 1]);
+#pragma unroll
+            for (int q = 1; q < 5; ++q) {
+                const double dv = fma(-s, zb[q], x0[q]) - v0;
+                pr[q][2 * g] = fma(w, H + fma(dr, dv, -(di * da[q])), pr[q][2 * g]);
+                pr[q][2 * g + 1] = fma(w, L + fma(di, dv, dr * da[q]), pr[q][2 * g + 1]);
+            }
+        }
+    }
+}
+
 // The weighted Jacobian rows J[k][s] (k < NP) and residuals r[s] of one sample
 // (zero when the thread has no sample).
 template <bool FILL>
@@ -1298,8 +1344,9 @@ __device__ __forceinline__ void jacobian_rows(const RefineArgs &a, const RefineS
 {
     constexpr int NP = RefineDims<FILL>::NP;
     const DevLine<double> &ln = a.ls.l[l];
-    double M0[4], pr0[6], N0 = 1.0;
-    profiles_at(sh.jm[0], ln, jj, pr0);
+    double M0[4], pl[5][6], N0 = 1.0;
+    profiles_lin(sh.jm, ln, jj, pl);
+    const double(&pr0)[6] = pl[0];
     unno_rachkovsky(sh.jm[0], pr0[0], pr0[1], pr0[2], pr0[3], pr0[4], pr0[5], M0[0], M0[1],
                     M0[2], M0[3]);
     double Mm[4] = {M0[0], M0[1], M0[2], M0[3]};  // magnetic part of the base model
@@ -1326,8 +1373,10 @@ __device__ __forceinline__ void jacobian_rows(const RefineArgs &a, const RefineS
         } else {
             const Model<double> &mk = sh.jm[k + 1];
             if (k == 0 || (k >= 3 && k <= 5)) {
-                // B, v_los, Doppler width, damping: new profiles
-                stokes_at(mk, ln, jj, Mk[0], Mk[1], Mk[2], Mk[3]);
+                // B, v_los, Doppler width, damping: the linearised profiles
+                const double(&pq)[6] = pl[k == 0 ? 1 : k - 1];
+                unno_rachkovsky(mk, pq[0], pq[1], pq[2], pq[3], pq[4], pq[5], Mk[0], Mk[1],
+                                Mk[2], Mk[3]);
             } else {
                 // the angles, eta0, S0, S1 leave every Voigt argument
                 // unchanged: the base profiles, the perturbed algebra

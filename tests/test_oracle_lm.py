@@ -25,6 +25,33 @@ def _start(truth, seed, scale=0.01):
     return np.clip(truth + (HI - LO) * rng.normal(0, scale, truth.shape), LO, HI)
 
 
+def test_linearised_synthesis_at_the_base_point_is_the_synthesis():
+    lines = _lines("slit")
+    for p in si.draw_truth(4, 8):
+        assert np.array_equal(oracle.me_synth_lin(p, p, lines, mu=0.7),
+                              oracle.me_synth(p[None], lines, mu=0.7)[0])
+
+
+@pytest.mark.parametrize("k", [0, 3, 4, 5])
+def test_linearised_synthesis_error_is_second_order(k):
+    # w(z0 + dz) - (w(z0) + w'(z0) dz) is O(dz^2): halving the step quarters
+    # the error, and the error is a small fraction of the first-order change
+    # (a wrong sign or constant in w', or v and a swapped, leaves an O(dz) error)
+    lines = _lines("slit")
+    for p0 in si.draw_truth(3, 9):
+        errs = []
+        for frac in (2e-3, 1e-3):
+            p = p0.copy()
+            p[k] = p0[k] + frac * (HI[k] - LO[k])
+            exact = oracle.me_synth(p[None], lines)[0]
+            lin = oracle.me_synth_lin(p0, p, lines)
+            change = np.abs(exact - oracle.me_synth(p0[None], lines)[0]).max()
+            err = np.abs(lin - exact).max()
+            assert err <= 0.05 * change
+            errs.append(err)
+        assert 3.0 <= errs[0] / errs[1] <= 5.0, errs
+
+
 def test_refine_never_increases_chi2_and_iteration_zero_is_identity():
     lines = _lines("tiny")
     truth = si.draw_truth(6, 1)
