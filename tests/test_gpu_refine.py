@@ -69,6 +69,31 @@ def test_refine_matches_oracle(noise):
         assert np.all(err[ok][~angles[ok]] < 1e-6)
 
 
+@pytest.mark.parametrize("iterations", [1, 3])
+def test_refine_iterates_follow_the_oracle(iterations):
+    # the same steps as the oracle (reading 20, linearised Jacobian columns
+    # included), not only the same minimum: after 1 and 3 iterations from a
+    # distant start the parameters equal the oracle's to 1e-4 of the step taken
+    # (the two FP64 models differ by ~1e-13, which the h = 1e-7 differences
+    # turn into ~1e-6 relative differences of the Jacobian)
+    lines, grids, olines = _setup("slit")
+    truth = si.draw_truth(10, 21)
+    obs = oracle.me_synth(truth, olines)
+    sig = si.sigma_for(truth)
+    obs = obs + sig[:, :, None] * si.std_normal(obs.shape, 21)
+    p0 = _start(truth, 22, 0.05)
+    r = g.me_refine_f64(_t(obs), _t(sig), lines, grids, g.bounds(LO, HI), _t(p0),
+                        iterations=iterations)
+    ref = oracle.lm_refine(obs, sig, olines, LO, HI, p0, iterations)
+    gp = r["params"].cpu().numpy()
+    step = np.abs(ref["params"] - p0).max(axis=1) / (HI - LO).max()
+    dx = (np.abs(gp - ref["params"]) / (HI - LO)).max(axis=1)
+    close = dx <= 1e-4 * step + 1e-9
+    print("iterations %d: pixels on the oracle's iterate %d / 10, max dx / step %.2e"
+          % (iterations, close.sum(), (dx / np.maximum(step, 1e-30)).max()))
+    assert close.sum() >= 9
+
+
 def test_refine_edge_cases():
     lines, grids, olines = _setup("tiny")
     truth = si.draw_truth(4, 3)
