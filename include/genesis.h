@@ -407,7 +407,10 @@ int me_seeds(const double *obs, const double *mu, int64_t npix, const me_line *l
  * machinery the paper uses for its non-magnetic pre-fit, Sec. 5.3, applied
  * here to the full model and the Sec. 5 chi-square).  In normalised
  * coordinates x_j = (p_j - lo_j)/(hi_j - lo_j), kept in [0, 1]: forward-
- * difference Jacobian (step 1e-7), normal equations, damped Cholesky steps
+ * difference Jacobian (step 1e-7; for B, v_los, the Doppler width and the
+ * damping the perturbed model takes each Zeeman component's Faddeeva value
+ * to first order about the current one, w(z0 + dz) ~ w(z0) + w'(z0) dz with
+ * w' = -2 z w + 2i/sqrt(pi)), normal equations, damped Cholesky steps
  * (lambda from 1e-3, /10 on success, x10 on failure, at most 10 trials per
  * iteration); stops after `iterations` or an iteration without progress.
  * params_in [npix][9] (need not lie inside the box: it is clamped);
