@@ -905,6 +905,33 @@ def disc_workload(args):
     return out
 
 
+def uncertainty_leg(g, w, obs, sig, obs64, sig64, lines, grids, b, cfg, popt, stream, reps=3):
+    """Sec. 6 uncertainties of the refined pixels, after the timed steps: the
+    initial steps from the final population of one more search (the same
+    seed, so the same population), then me_uncertainty_f64 timed with HIP
+    events on the launch stream."""
+    import torch
+    r = g.ga_invert(obs, sig, lines, grids, b, cfg, want_population=True)
+    steps = g.ga_population_steps(r["genes"], r["fitness"], b, popt)
+    u = g.me_uncertainty_f64(obs64, sig64, lines, grids, b, popt, steps)  # warm-up
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    torch.cuda.synchronize()
+    for e0, e1 in ev:
+        e0.record(stream)
+        u = g.me_uncertainty_f64(obs64, sig64, lines, grids, b, popt, steps)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    s = u["sigma"].cpu().numpy()
+    fin = np.isfinite(s).all(axis=1)
+    print("uncertainties done: %s ms" % np.round(ms, 3).tolist(), file=sys.stderr, flush=True)
+    return {"kernel": "k_uncert_f64", "pixels": w["npix"], "ms": float(ms.mean()),
+            "ms_min": float(ms.min()), "pixels_per_s": w["npix"] / (float(ms.mean()) / 1e3),
+            "finite_fraction": float(fin.mean()),
+            "median_sigma_B_G": float(np.median(s[fin, 0])) if fin.any() else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -913,6 +940,9 @@ def main():
     ap.add_argument("--workload", default="disc",
                     help="disc (default), slit, tiny, precision, serving, proposal, fill")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--uncertainty", action="store_true",
+                    help="slit, tiny: after the timed steps, also time the Sec. 6 uncertainties "
+                    "of the refined pixels (not part of a step)")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--rate", type=float, default=2.0, help="serving: requests per second")
     ap.add_argument("--window", type=float, default=20.0, help="serving: arrival window [s]")
@@ -1067,6 +1097,9 @@ def main():
                      "kernel": "k_ga_invert<%s>" % ("float" if dt == torch.float32 else "double"),
                      "flop_per_eval": fpe, "evals_per_launch": evals},
     }
+    if args.uncertainty:
+        out["uncertainty"] = uncertainty_leg(g, w, obs, sig, obs64, sig64, lines, grids, b, cfg,
+                                             ref["params"], stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, truth, w["lines"], args.cpu_budget,
                                            device_obs=obs64.cpu().numpy())
