@@ -20,7 +20,7 @@ SRCS = [os.path.join(HERE, "csrc", f) for f in ("genesis.hip", "serving.hip", "m
                                                  "uncert.hip")]
 DEPS = SRCS + [os.path.join(HERE, "csrc", f) for f in
                ("genesis_device.h", "genesis_common.h", "genesis_half.h", "voigt_rational.h",
-                "voigt_rational_h.h", "weideman36.h", "scheduler.h")] + \
+                "voigt_rational_h.h", "weideman36.h", "weideman28.h", "scheduler.h")] + \
        [os.path.join(ROOT, "include", "genesis.h")]
 
 HIPCC_FLAGS = [

@@ -192,10 +192,11 @@ __device__ __forceinline__ void voigt_acc_f32(const VoigtF32 &c, float v, float 
     l = fmaf(v * fmaf(ep, oq, -(op * eq)), wr, l);
 }
 
-// FP64: Weideman's expansion with N = 36 (error ~2e-15).
-__device__ __forceinline__ void voigt_f64(double a, double v, double &H, double &L)
+// FP64: Weideman's expansion with the N coefficients c and parameter WL.
+template <int N>
+__device__ __forceinline__ void weideman_w(const double (&c)[N], double WL, double a, double v,
+                                           double &H, double &L)
 {
-    const double WL = GENESIS_WD_L;
     // d = L - i z with z = v + i a  ->  d = (WL + a) - i v ; r = 1/d
     const double dr = WL + a, di = -v;
     const double inv = 1.0 / fma(dr, dr, di * di);
@@ -204,10 +205,10 @@ __device__ __forceinline__ void voigt_f64(double a, double v, double &H, double 
     const double nr = WL - a, ni = v;
     const double Zr = fma(nr, rr, -(ni * ri));
     const double Zi = fma(nr, ri, ni * rr);
-    double pr = genesis_wd_c[GENESIS_WD_N - 1], pi = 0.0;
+    double pr = c[N - 1], pi = 0.0;
 #pragma unroll
-    for (int n = GENESIS_WD_N - 2; n >= 0; --n) {
-        const double tr = fma(pr, Zr, fma(-pi, Zi, genesis_wd_c[n]));
+    for (int n = N - 2; n >= 0; --n) {
+        const double tr = fma(pr, Zr, fma(-pi, Zi, c[n]));
         const double ti = fma(pr, Zi, pi * Zr);
         pr = tr;
         pi = ti;
@@ -217,6 +218,12 @@ __device__ __forceinline__ void voigt_f64(double a, double v, double &H, double 
     const double ti = 2.0 * fma(pr, ri, pi * rr);
     H = fma(tr, rr, -(ti * ri));
     L = fma(tr, ri, ti * rr);
+}
+
+// The FP64 kernels' Faddeeva function: N = 36 (error ~2e-15).
+__device__ __forceinline__ void voigt_f64(double a, double v, double &H, double &L)
+{
+    weideman_w(genesis_wd36_c, GENESIS_WD36_L, a, v, H, L);
 }
 
 __device__ __forceinline__ void voigt_acc_f64(double a, double v, double w, double &h, double &l)
