@@ -219,13 +219,16 @@ __device__ __forceinline__ void sweep_sample(UncShared &sh, const DevLine<double
 }
 
 // chi2 (reduced) of the batch's slots into sh.f.  Each thread accumulates
-// its wavelengths' squared residuals per slot in its own LDS column.  W36:
+// its wavelengths' squared residuals per slot in its own LDS column; it reads
+// its samples of the observation obs_p [4][L] from memory (cached: the batch
+// count keeps them hot), so the observation's length is not bounded by LDS.
+// W36:
 // profiles with the forward model's N = 36 (the chi-square at the optimum, so
 // that it is the one the search and the refinement minimise).
 template <bool W36>
 __device__ __forceinline__ void eval_batch(const UncArgs &a, UncShared &sh,
-                                           const Vec4<double> *obs_s, const double (&w2)[4],
-                                           double inv_nu)
+                                           const double *__restrict__ obs_p,
+                                           const double (&w2)[4], double inv_nu)
 {
     const int ns = sh.nslots;
     const int tid = threadIdx.x;
@@ -234,7 +237,8 @@ __device__ __forceinline__ void eval_batch(const UncArgs &a, UncShared &sh,
     for (int l = 0; l < a.ls.nlines; ++l) {
         const DevLine<double> &ln = a.ls.l[l];
         for (int jj = tid; jj < ln.nlam; jj += kUncThreads) {
-            const Vec4<double> o = obs_s[ln.off + jj];
+            const int j = ln.off + jj, L = a.ls.L;
+            const Vec4<double> o{obs_p[j], obs_p[L + j], obs_p[2 * L + j], obs_p[3 * L + j]};
             if (ln.nb == 1 && ln.np == 1 && ln.nr == 1)
                 sweep_sample<1, 1, 1, W36>(sh, ln, jj, o, w2, ns, tid);
             else if (ln.nb == 4 && ln.np == 4 && ln.nr == 4)
@@ -264,7 +268,7 @@ __device__ __forceinline__ void eval_batch(const UncArgs &a, UncShared &sh,
 
 // Gradient at sh.q for the components in mask (LDS) into g (LDS).
 __device__ void gradient(const UncArgs &a, UncShared &sh, const int *mask, double *g,
-                         double mu, const Vec4<double> *obs_s, const double (&w2)[4],
+                         double mu, const double *__restrict__ obs_p, const double (&w2)[4],
                          double inv_nu)
 {
     const int tid = threadIdx.x;
@@ -308,7 +312,7 @@ __device__ void gradient(const UncArgs &a, UncShared &sh, const int *mask, doubl
             model_setup(x, mu, sh.mod[tid]);
         }
         __syncthreads();
-        eval_batch<false>(a, sh, obs_s, w2, inv_nu);
+        eval_batch<false>(a, sh, obs_p, w2, inv_nu);
         if (tid < GENESIS_NPAR && sh.in.live[tid]) {
             const int s = sh.slot_of[tid];
             const double t = sh.in.t[tid];
@@ -373,17 +377,36 @@ __device__ void sigmas(const UncShared &sh, double c, int M, double *out)
     }
 }
 
+// Status of a pixel's inputs (0 ok, 1 non-finite observation, 2 sigma <= 0
+// or non-finite) and its weights w2 = 1/sigma^2.
+__device__ __forceinline__ int check_pixel(const double *__restrict__ obs_p,
+                                           const double *__restrict__ sig_p, int L,
+                                           double (&w2)[4])
+{
+    int bad = 0;
+    for (int j = threadIdx.x; j < 4 * L; j += blockDim.x)
+        bad |= !isfinite(obs_p[j]);
+    bad = __syncthreads_or(bad);
+    int bad_sig = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const double sg = sig_p[s];
+        bad_sig |= !(sg > 0.0 && isfinite(sg));
+        w2[s] = 1.0 / (sg * sg);
+    }
+    return bad ? 1 : (bad_sig ? 2 : 0);
+}
+
 __global__ __launch_bounds__(kUncThreads) void k_uncert_f64(UncArgs a)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
     __shared__ UncShared sh;
     const int L = a.ls.L;
-    Vec4<double> *obs_s = reinterpret_cast<Vec4<double> *>(smem);
     const int tid = threadIdx.x;
     const double inv_nu = 1.0 / (4.0 * L - GENESIS_NPAR);
     for (int64_t p = blockIdx.x; p < a.npix; p += gridDim.x) {
         double w2[4];
-        int st = stage_pixel(a.obs + p * 4 * (int64_t)L, a.sigma + p * 4, L, obs_s, w2);
+        const double *obs_p = a.obs + p * 4 * (int64_t)L;
+        int st = check_pixel(obs_p, a.sigma + p * 4, L, w2);
         if (tid == 0) {
             for (int j = 0; j < GENESIS_NPAR; ++j)
                 st |= !isfinite(a.p_opt[p * GENESIS_NPAR + j]);
@@ -438,7 +461,7 @@ __global__ __launch_bounds__(kUncThreads) void k_uncert_f64(UncArgs a)
             sh.need_base = 0;
         }
         __syncthreads();
-        eval_batch<true>(a, sh, obs_s, w2, inv_nu);
+        eval_batch<true>(a, sh, obs_p, w2, inv_nu);
         if (tid == 0)
             sh.chi2 = sh.f[0];
         // Hessian columns
@@ -465,7 +488,7 @@ __global__ __launch_bounds__(kUncThreads) void k_uncert_f64(UncArgs a)
                             sh.q[j] -= t;
                     }
                     __syncthreads();
-                    gradient(a, sh, sh.out.live, side == 0 ? sh.gp : sh.gm, mu, obs_s, w2,
+                    gradient(a, sh, sh.out.live, side == 0 ? sh.gp : sh.gm, mu, obs_p, w2,
                              inv_nu);
                 }
                 if (tid < GENESIS_NPAR && sh.out.live[tid])
@@ -603,9 +626,6 @@ int me_uncertainty_f64(const double *obs, const double *sigma, const double *mu,
         return fail(ME_EINVAL, "npix must be >= 0");
     if (4 * a.ls.L <= GENESIS_NPAR)
         return fail(ME_EINVAL, "need 4 L > 9 wavelength samples for nu > 0");
-    const size_t lds = sizeof(Vec4<double>) * (size_t)a.ls.L;
-    if (lds + sizeof(UncShared) > kMaxLds)
-        return fail(ME_ENOMEM, "observation of %d samples exceeds LDS", a.ls.L);
     if (npix == 0)
         return ME_OK;
     if (!obs || !sigma || !params_opt || !steps || !sigma_params)
@@ -622,7 +642,7 @@ int me_uncertainty_f64(const double *obs, const double *sigma, const double *mu,
     a.hess = hessian;
     a.hess_err = hessian_err;
     a.steps_used = steps_used;
-    hipLaunchKernelGGL(k_uncert_f64, dim3(grid_for(npix)), dim3(kUncThreads), lds,
+    hipLaunchKernelGGL(k_uncert_f64, dim3(grid_for(npix)), dim3(kUncThreads), 0,
                        as_stream(stream), a);
     return check_launch("me_uncertainty_f64");
 }
