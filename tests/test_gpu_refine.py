@@ -234,3 +234,34 @@ def test_population_steps_bit_exact(dtype):
                                     torch.tensor(fit, device=DEV), b, _t(popt)).cpu().numpy()
         ref = oracle.population_steps(genes, fit.astype(np.float64), LO, HI, popt)
         assert np.array_equal(got, ref), pop
+
+
+def test_uncertainties_of_a_long_observation_are_invariant_to_replicating_the_line():
+    """Scale invariance of Sec. 6's sigma at an observation too long to stage
+    in LDS: repeating the line's samples k times multiplies the reduced merit
+    function by c = k (4L - 9) / (4kL - 9), so H and chi2(p_opt) scale by c
+    and sigma^2 = [H^-1]_jj chi2 / M does not change."""
+    ln = si.FE6302
+    n, k = 1200, 4
+    st, sp = si.grid(ln, n)
+    line = g.line_from_terms(ln["lambda0"], ln["Jl"], ln["gl"], ln["Ju"], ln["gu"])
+    oline = oracle.make_line(ln["lambda0"], ln["Jl"], ln["gl"], ln["Ju"], ln["gu"], st, sp, n)
+    truth, obs, sig = _noisy([oline], 3, 21)
+    steps = np.tile(0.01 * (HI - LO), (3, 1))
+    b = g.bounds(LO, HI)
+    one = g.me_uncertainty_f64(_t(obs), _t(sig), [line], [g.grid(st, sp, n)], b, _t(truth),
+                               _t(steps), want_hessian=True)
+    obs_k = np.concatenate([obs] * k, axis=2)
+    rep = g.me_uncertainty_f64(_t(obs_k), _t(sig), [line] * k, [g.grid(st, sp, n)] * k, b,
+                               _t(truth), _t(steps), want_hessian=True)
+    c = k * (4.0 * n - 9) / (4.0 * k * n - 9)
+    s1, sk = one["sigma"].cpu().numpy(), rep["sigma"].cpu().numpy()
+    assert np.array_equal(np.isfinite(s1), np.isfinite(sk))
+    ok = np.isfinite(s1)
+    assert ok.sum() >= 20
+    assert np.all(np.abs(sk[ok] - s1[ok]) <= 1e-3 * s1[ok])
+    H1, Hk = one["hessian"].cpu().numpy(), rep["hessian"].cpu().numpy()
+    for p in range(3):
+        d = np.abs(np.diag(H1[p]))
+        scale = np.sqrt(np.outer(d, d))
+        assert np.all(np.abs(Hk[p] - c * H1[p]) <= 1e-4 * scale + 1e-300)
