@@ -58,9 +58,9 @@ REFINE_ITERS = 10
 # k_ga_invert_disc_counters.md): one full-disc block, and the slit row.  Valid
 # only for the machine code they were measured on: reported while the build's
 # code hash of that kernel (libgenesis_hip.layout.json) equals this one.
-TRAFFIC_DISC_BLOCK_BYTES = 18.859e9
-TRAFFIC_SLIT_BYTES = 230.78e6
-TRAFFIC_CODE_SHA256 = "2665b5d7b3eec37935ad84d7688ca5f935aa4b28d3acf7c4c5dbf8eb422758f6"
+TRAFFIC_DISC_BLOCK_BYTES = 18.607e9
+TRAFFIC_SLIT_BYTES = 243.08e6
+TRAFFIC_CODE_SHA256 = "568e627056b42b8948b3f83600d315b51575a9ab2660813ccb14e1154b399a9b"
 
 
 def measured_traffic(nbytes):

@@ -477,9 +477,22 @@ struct InvertArgs : SynLines<SYN>, FillArgs<Real, FILL> {
     int32_t *status;
     uint16_t *final_genes;
     // > 0 when every workgroup of the launch is resident at once: the number
-    // of CUs, the dispatch stride between workgroups that share a CU
+    // of CUs
     int32_t prio_mate;
 };
+
+// Progress counters of single-round launches, one per XCD (workgroup b runs
+// on XCD b mod 8), 256 bytes apart; zeroed by k_progress_reset before each
+// such launch.  Launches that overlap on one device share them, which can
+// only change the issue order, never a result.
+constexpr int kProgressStride = 32;
+__device__ unsigned long long g_ga_progress[8 * kProgressStride];
+
+__global__ void k_progress_reset()
+{
+    if (threadIdx.x < 8)
+        g_ga_progress[threadIdx.x * kProgressStride] = 0ull;
+}
 
 // The whole of Algorithm 1 for one pixel per workgroup: the population
 // lives in LDS (two buffers: parents and children), lane i owns
@@ -541,10 +554,12 @@ __global__ __launch_bounds__(1024) void k_ga_invert(InvertArgs<Real, SYN, FILL> 
         // In a launch that is resident all at once, a SIMD issues oldest
         // first, so the first-dispatched workgroups run ahead and finish
         // early and the launch ends on SIMDs holding one or two waves.
-        // Rotating the issue priority among the workgroups that share a CU
-        // every generation (prio_mate) keeps their progress even.  It changes
-        // the issue order only, never a result.
-        generation_loop(s, pop, tid, pix, a.ga, a.generations, a.generations, a.prio_mate, gs,
+        // Raising the priority of the workgroups that lag their XCD's average
+        // generation keeps their progress even.  It changes the issue order
+        // only, never a result.
+        unsigned long long *progress =
+            a.prio_mate > 0 ? g_ga_progress + kProgressStride * (blockIdx.x & 7) : nullptr;
+        generation_loop(s, pop, tid, pix, a.ga, a.generations, a.generations, progress, gs,
                         [&](const uint16_t *genes) -> Real {
                             if constexpr (FILL && SYN == GENESIS_SYNTH_FP16) {
                                 float al;
@@ -1688,7 +1703,7 @@ int step_impl(const uint16_t *genes_in, const Real *fitness, int64_t npix, const
 
 // The number of CUs when all `nblocks` workgroups of `kernel` fit on the
 // device at once (occupancy at this block size and LDS), else 0.  A failed
-// query only turns the priority rotation off.
+// query only turns the progress-based issue priority off.
 int single_round_stride(const void *kernel, int block, size_t lds, int64_t nblocks)
 {
     int dev = 0, ncu = 0, per_cu = 0;
@@ -1752,6 +1767,8 @@ int invert_impl(const Real *obs, const Real *sigma, const Real *mu, int64_t npix
         pack_lines_h(a.ls, a.lh);
     a.prio_mate = single_round_stride((const void *)k_ga_invert<Real, SYN, FILL>,
                                       block_for_pop(cfg->pop), lds, npix);
+    if (a.prio_mate > 0)
+        hipLaunchKernelGGL(k_progress_reset, dim3(1), dim3(64), 0, as_stream(stream));
     hipLaunchKernelGGL((k_ga_invert<Real, SYN, FILL>), dim3(grid_for(npix)),
                        dim3(block_for_pop(cfg->pop)), lds, as_stream(stream), a);
     return check_launch("ga_invert");

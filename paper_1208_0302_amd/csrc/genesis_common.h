@@ -354,6 +354,7 @@ struct GaLds {
     Vec4<Real> *obs;
     Real *fit, *red_f;
     int *red_i;
+    unsigned long long *tick;  // the progress count seen by this workgroup (see generation_loop)
     uint16_t *genes;  // two buffers [9][pop] back to back
     Bounds *box;
     void *fill;       // FillPix<Real> of the pixel (fill-fraction kernels)
@@ -400,7 +401,7 @@ __host__ __device__ inline size_t ga_lds_bytes(int L, int pop)
 {
     size_t o = align16(sizeof(Vec4<Real>) * (size_t)L);
     o = align16(o + sizeof(Real) * (size_t)pop);
-    o += (sizeof(Real) + sizeof(int)) * 16;
+    o += (sizeof(Real) + sizeof(int)) * 16 + 16;
     o = align16(o + 2 * sizeof(uint16_t) * GENESIS_NPAR * (size_t)pop);
     o = align16(o + sizeof(Bounds));
     o = align16(o + sizeof(FillPix<Real>));
@@ -420,6 +421,8 @@ __device__ __forceinline__ GaLds<Real> ga_lds(unsigned char *base, int L, int po
     o += sizeof(Real) * 16;
     s.red_i = reinterpret_cast<int *>(base + o);
     o += sizeof(int) * 16;
+    s.tick = reinterpret_cast<unsigned long long *>(base + o);
+    o += 16;
     s.genes = reinterpret_cast<uint16_t *>(base + o);
     o = align16(o + 2 * sizeof(uint16_t) * GENESIS_NPAR * (size_t)pop);
     s.box = reinterpret_cast<Bounds *>(base + o);
@@ -520,26 +523,43 @@ struct GenState {
 // come back here to be evaluated), and breed generation g + 1 (elite to slot
 // 0, selection, recombination, mutation), until generation g_to is evaluated
 // and restarted.  evaluate(genes) returns the calling lane's fitness of the
-// genes in buffer `genes`.  prio_mate > 0 rotates the waves' issue priority
-// every generation (the whole launch resident at once; see k_ga_invert).
+// genes in buffer `genes`.  With a progress counter (the whole launch
+// resident at once; see k_ga_invert) each workgroup raises its waves' issue
+// priority while it lags the average generation of the workgroups on its XCD.
 // On return s.fit holds generation g_to's fitness.  ga_invert and the
 // service run this same loop, so a served pixel is bit-identical to it.
 template <typename Real, typename Eval>
 __device__ __forceinline__ void generation_loop(const GaLds<Real> &s, int pop, int tid,
                                                 uint32_t pix, const GaConst &ga,
-                                                int generations, int g_to, int prio_mate,
+                                                int generations, int g_to,
+                                                unsigned long long *progress,
                                                 GenState<Real> &st, Eval &&evaluate)
 {
     const bool active = tid < pop;
     const int gstride = GENESIS_NPAR * pop;
     for (;;) {
-        if (prio_mate > 0)
-            set_issue_priority(st.g + (int)blockIdx.x + (int)blockIdx.x / prio_mate);
+        // Progress: once per generation thread 0 adds to the counter (high
+        // word: workgroups started, low word: generations begun) and keeps
+        // the count it saw; at the next generation every wave sets its
+        // priority from how far this workgroup was behind the average then.
+        const bool count = progress != nullptr && !st.restarted;
+        if (count && st.g > 0) {
+            const unsigned long long t = *s.tick;
+            const long long started = (long long)(t >> 32), begun = (long long)(t & 0xffffffffu);
+            const long long d = begun - (long long)(st.g - 1) * started;
+            set_issue_priority(d >= started ? 3 : (2 * d >= started ? 2 : (d >= 0 ? 1 : 0)));
+        }
+        unsigned long long tick = 0;
+        if (count && tid == 0)
+            tick = __hip_atomic_fetch_add(progress, st.g == 0 ? (1ull << 32) + 1ull : 1ull,
+                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (st.eval) {
             st.f = evaluate(s.genes + st.cur);
             s.fit[tid] = st.f;
         }
         __syncthreads();
+        if (count && tid == 0)
+            *s.tick = tick;
         if (!st.restarted && restart_due(ga, st.g, generations)) {
             const int rank = active ? fitness_rank(s.fit, pop, tid) : 0;
             __syncthreads();

@@ -123,7 +123,7 @@ __global__ __launch_bounds__(1024) void k_ga_advance(const ReqDesc *__restrict__
     }
     // the evaluation of the request's kind (uniform over the workgroup)
     if (d.synth == GENESIS_SYNTH_FP16 && d.fill) {
-        generation_loop(s, pop, tid, pix, d.ga, d.generations, d.gen_to, 0, gs,
+        generation_loop(s, pop, tid, pix, d.ga, d.generations, d.gen_to, nullptr, gs,
                         [&](const uint16_t *genes) -> float {
                             float al;
                             return evaluate_fill_h(genes, pop, tid, *s.box, mu, d.ls, d.lh, fp,
@@ -131,13 +131,13 @@ __global__ __launch_bounds__(1024) void k_ga_advance(const ReqDesc *__restrict__
                                                    s.obs, w2, inv_nu, al);
                         });
     } else if (d.synth == GENESIS_SYNTH_FP16) {
-        generation_loop(s, pop, tid, pix, d.ga, d.generations, d.gen_to, 0, gs,
+        generation_loop(s, pop, tid, pix, d.ga, d.generations, d.gen_to, nullptr, gs,
                         [&](const uint16_t *genes) -> float {
                             return evaluate_lds_h(genes, pop, tid, *s.box, mu, d.ls, d.lh, s.obs,
                                                   w2, inv_nu);
                         });
     } else if (d.fill) {
-        generation_loop(s, pop, tid, pix, d.ga, d.generations, d.gen_to, 0, gs,
+        generation_loop(s, pop, tid, pix, d.ga, d.generations, d.gen_to, nullptr, gs,
                         [&](const uint16_t *genes) -> float {
                             float al;
                             return evaluate_fill(genes, pop, tid, *s.box, mu, d.ls, fp,
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(1024) void k_ga_advance(const ReqDesc *__restrict__
                                                  w2, inv_nu, al);
                         });
     } else {
-        generation_loop(s, pop, tid, pix, d.ga, d.generations, d.gen_to, 0, gs,
+        generation_loop(s, pop, tid, pix, d.ga, d.generations, d.gen_to, nullptr, gs,
                         [&](const uint16_t *genes) -> float {
                             return evaluate_lds(genes, pop, tid, *s.box, mu, d.ls, s.obs, w2,
                                                 inv_nu);

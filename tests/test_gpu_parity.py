@@ -340,11 +340,12 @@ def test_loop_determinism_pixel_base_and_status():
     assert r0["params"].shape == (0, 9)
 
 
-def test_issue_priority_rotation_leaves_results_unchanged():
+def test_issue_priority_leaves_results_unchanged():
     # A launch with more pixels than the device holds at once (16,384 one-wave
     # workgroups against 256 CUs x 16) keeps the default issue priority; one
-    # that fits (256 pixels) rotates it every generation.  Priority orders
-    # instruction issue only, so every pixel's result is the same either way.
+    # that fits (256 pixels) sets it every generation from the workgroup's
+    # lag behind its XCD's average progress.  Priority orders instruction
+    # issue only, so every pixel's result is the same either way.
     lines, grids, _ = _setup("tiny")
     npix = 16384
     truth = si.draw_truth(npix, 31)
