@@ -274,7 +274,12 @@ size_t ga_workspace_bytes(int64_t npix, const ga_config *cfg);
  * genotype of the last generation), best_chi2 [npix], status [npix]
  * (0 ok, 1 non-finite observation, 2 sigma <= 0 or non-finite, 3 invalid
  * pixel box (ga_config.pixel_bounds); outputs NaN for status != 0) -- status may be NULL; final_genes [npix][pop][9] and
- * final_fitness [npix][pop] may be NULL.  workspace/ws_bytes may be NULL/0. */
+ * final_fitness [npix][pop] may be NULL.  workspace/ws_bytes may be NULL/0.
+ * When every workgroup fits on the device at once, the call first zeroes a
+ * small per-device progress counter (a one-block kernel on `stream`) through
+ * which the workgroups steer their waves' issue priority; calls that overlap
+ * on one device share it, which changes the issue order only, never a
+ * result. */
 int ga_invert(const float *obs, const float *sigma, const float *mu, int64_t npix,
               const me_line *lines, const me_grid *grids, int32_t nlines,
               const me_bounds *bounds, const ga_config *cfg, float *best_params,
