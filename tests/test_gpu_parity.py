@@ -360,6 +360,34 @@ def test_issue_priority_leaves_results_unchanged():
         assert torch.equal(part[k], big[k][:256]), k
 
 
+def test_overlapping_single_round_launches_share_the_progress_counter_harmlessly():
+    # Two single-round launches queued on two streams may run at the same
+    # time and then share the device's progress counters: only the issue
+    # order changes, so each result equals the same launch run alone.
+    lines, grids, _ = _setup("tiny")
+    truth = si.draw_truth(512, 33)
+    obs = g.me_synth(torch.tensor(truth, dtype=torch.float32, device=DEV), lines, grids)
+    sig = torch.tensor(si.sigma_for(truth), dtype=torch.float32, device=DEV)
+    b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
+    halves = [(obs[:256].contiguous(), sig[:256].contiguous(),
+               g.GAConfig(pop=64, generations=40, seed=5)),
+              (obs[256:].contiguous(), sig[256:].contiguous(),
+               g.GAConfig(pop=64, generations=25, seed=6))]
+    alone = [g.ga_invert(o, s_, lines, grids, b, c, want_population=True) for o, s_, c in halves]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for st in streams:
+        st.wait_stream(torch.cuda.current_stream())
+    both = []
+    for st, (o, s_, c) in zip(streams, halves):
+        with torch.cuda.stream(st):
+            both.append(g.ga_invert(o, s_, lines, grids, b, c, want_population=True))
+    torch.cuda.synchronize()
+    for a, r in zip(alone, both):
+        for k in ("genes", "params", "chi2", "status"):
+            assert torch.equal(a[k], r[k]), k
+
+
 def test_loop_generation_zero_is_the_initial_population():
     lines, grids, olines, truth, obs, sig = _problem("tiny", 3, 6)
     b = g.bounds(si.PRIOR_LO, si.PRIOR_HI)
